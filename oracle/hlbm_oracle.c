@@ -1,0 +1,398 @@
+/*
+ * hlbm_oracle.c -- plain, slow, FP64 CPU oracle of the homogenized lattice BGK
+ * (HLBM) sweep.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
+ * this file: only tests/, the smoke check and the CPU-baseline leg of bench.py
+ * use it.  It shares no code, header, table or constant generator with the HIP
+ * library; the two agree only through the paper and the written readings of it.
+ *
+ * What it computes (Simonis et al., "Homogenized lattice Boltzmann methods for
+ * fluid flow through porous media -- part I"):
+ *   * Kinetic model: the BGK Boltzmann equation (Sec. 3.1, eq:BGKBE) whose
+ *     Maxwellian is replaced by the homogenized Maxwellian
+ *     M^eq = f^eq(n, varpi*u, T) with porosity control varpi = 1 - nu*tau/K
+ *     (Sec. 3.2, eq:porousVeloMaxwellian and eq:d-definition).  Here the caller
+ *     gives d = 1 - varpi in [0,1] per cell.
+ *   * Moments: density and velocity as zeroth and first velocity moments
+ *     (Sec. 3.1, Definition of moments).
+ *   * Lattice: the paper's Maxwellian has covariance (1/(3 eps^2)) I
+ *     (Sec. 3.3, Step 2, eq:homMaxwellianParametrized), i.e. c_s^2 = 1/3 in
+ *     lattice units (eps = 1).  The discrete velocity sets (D2Q9, D3Q19), the
+ *     second-order Hermite truncation of the Maxwellian, the Guo forcing term
+ *     and halfway bounce-back are textbook lattice Boltzmann pieces; part I of
+ *     the paper defers the lattice discretization to its sequel.
+ *
+ * State convention: populations are stored shifted, g_i = f_i - w_i*rho0, in
+ * structure-of-arrays order g[i*N + cell], cell = x + nx*(y + ny*z).  A state
+ * array holds the post-collision populations after a completed step; the
+ * initial state "from rest" is g = 0.
+ *
+ * One time step = pull streaming (oracle_stream) followed by collision of every
+ * fluid cell (oracle_collide).  The two are separate full-field passes so that
+ * each can be read against its definition on its own.
+ *
+ * Reported moments after n completed steps are those of the post-streaming,
+ * pre-collision populations at time n: rho = rho0 + sum g*, j = sum c g*,
+ * u = (j + F/2)/rho (Guo's half-force velocity).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { OR_PERIODIC = 0, OR_WALL = 1, OR_INLET_U = 2, OR_OUTLET_RHO = 3 };
+
+typedef struct {
+    int q;             /* 9 (planar D2Q9) or 19 (D3Q19) */
+    int nx, ny, nz;    /* nz = 1 for q = 9 */
+    double tau;        /* BGK relaxation time, > 1/2 */
+    double force[3];   /* body-force density F (lattice units) */
+    int bc_lo[3];      /* per axis: OR_PERIODIC, OR_WALL, OR_INLET_U, OR_OUTLET_RHO */
+    int bc_hi[3];
+    double inlet_u[3]; /* prescribed velocity on an OR_INLET_U face */
+    double outlet_rho; /* prescribed density on an OR_OUTLET_RHO face */
+    double rho0;       /* reference density of the shifted populations */
+} oracle_cfg;
+
+/* ------------------------------------------------------------------------ */
+/* Velocity sets.                                                            */
+/* The set is built from its definition rather than typed in as a table:     */
+/* every integer vector with components in {-1,0,1} (third component 0 for   */
+/* the planar set) whose squared length is at most 2.  Weights depend on the */
+/* squared length only: D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36.          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int q;
+    int c[19][3];
+    double w[19];
+    int opp[19];
+} lattice_t;
+
+static int build_lattice(int q, lattice_t *L)
+{
+    double wlen[3];
+    int zmax;
+    if (q == 9) {
+        wlen[0] = 4.0 / 9.0; wlen[1] = 1.0 / 9.0; wlen[2] = 1.0 / 36.0; zmax = 0;
+    } else if (q == 19) {
+        wlen[0] = 1.0 / 3.0; wlen[1] = 1.0 / 18.0; wlen[2] = 1.0 / 36.0; zmax = 1;
+    } else {
+        return -1;
+    }
+    int n = 0;
+    for (int cz = -zmax; cz <= zmax; ++cz)
+        for (int cy = -1; cy <= 1; ++cy)
+            for (int cx = -1; cx <= 1; ++cx) {
+                int len2 = cx * cx + cy * cy + cz * cz;
+                if (len2 > 2) continue;
+                L->c[n][0] = cx; L->c[n][1] = cy; L->c[n][2] = cz;
+                L->w[n] = wlen[len2];
+                ++n;
+            }
+    if (n != q) return -1;
+    L->q = q;
+    for (int i = 0; i < q; ++i) {
+        L->opp[i] = -1;
+        for (int k = 0; k < q; ++k)
+            if (L->c[k][0] == -L->c[i][0] && L->c[k][1] == -L->c[i][1] &&
+                L->c[k][2] == -L->c[i][2])
+                L->opp[i] = k;
+    }
+    return 0;
+}
+
+/* Exported so tests can map between this ordering and any other. */
+int oracle_lattice(int q, int *c, double *w)
+{
+    lattice_t L;
+    if (build_lattice(q, &L)) return -1;
+    for (int i = 0; i < q; ++i) {
+        c[3 * i + 0] = L.c[i][0]; c[3 * i + 1] = L.c[i][1]; c[3 * i + 2] = L.c[i][2];
+        w[i] = L.w[i];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry helpers                                                          */
+/* ------------------------------------------------------------------------ */
+static long cell_index(const oracle_cfg *cfg, int x, int y, int z)
+{
+    return (long)x + (long)cfg->nx * ((long)y + (long)cfg->ny * (long)z);
+}
+
+static void dims(const oracle_cfg *cfg, int n[3])
+{
+    n[0] = cfg->nx; n[1] = cfg->ny; n[2] = cfg->nz;
+}
+
+/* A wall face makes its first (lo) or last (hi) layer of cells solid. */
+static int in_wall_layer(const oracle_cfg *cfg, const int s[3])
+{
+    int n[3];
+    dims(cfg, n);
+    for (int a = 0; a < 3; ++a) {
+        if (cfg->bc_lo[a] == OR_WALL && s[a] == 0) return 1;
+        if (cfg->bc_hi[a] == OR_WALL && s[a] == n[a] - 1) return 1;
+    }
+    return 0;
+}
+
+static int is_solid(const oracle_cfg *cfg, int x, int y, int z)
+{
+    int s[3] = { x, y, z };
+    return in_wall_layer(cfg, s);
+}
+
+/* Second-order truncated Maxwellian of density rho and velocity u, c_s^2 = 1/3,
+ * returned shifted by w_i*rho0:
+ *   g_i^eq = w_i * [ (rho - rho0) + rho*(3 c.u + 9/2 (c.u)^2 - 3/2 u.u) ].    */
+static void equilibrium(const lattice_t *L, double rho0, double rho, const double u[3],
+                        double *geq)
+{
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < L->q; ++i) {
+        double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];
+        geq[i] = L->w[i] * ((rho - rho0) + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+}
+
+void oracle_equilibrium(int q, double rho0, double rho, const double *u, double *geq)
+{
+    lattice_t L;
+    if (build_lattice(q, &L)) return;
+    equilibrium(&L, rho0, rho, u, geq);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Collision of one fluid cell (pre-collision g* in, post-collision out).    */
+/*   rho = rho0 + sum g*,  j = sum c g*,  u = (j + F/2)/rho                   */
+/*   u_eq = (1 - d) u        -- homogenized Maxwellian, varpi = 1 - d         */
+/*   g^post = g* - (g* - g^eq(rho, u_eq))/tau + S                            */
+/*   S_i = (1 - 1/(2 tau)) w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)]  (Guo)      */
+/* ------------------------------------------------------------------------ */
+static void collide_cell(const lattice_t *L, const oracle_cfg *cfg, double d,
+                         const double *gpre, double *gpost)
+{
+    const double *F = cfg->force;
+    double drho = 0.0, j[3] = { 0.0, 0.0, 0.0 };
+    for (int i = 0; i < L->q; ++i) {
+        drho += gpre[i];
+        for (int a = 0; a < 3; ++a) j[a] += L->c[i][a] * gpre[i];
+    }
+    double rho = cfg->rho0 + drho;
+    double u[3], ueq[3];
+    for (int a = 0; a < 3; ++a) {
+        u[a] = (j[a] + 0.5 * F[a]) / rho;
+        ueq[a] = (1.0 - d) * u[a];
+    }
+    double geq[19];
+    equilibrium(L, cfg->rho0, rho, ueq, geq);
+    double pref = 1.0 - 0.5 / cfg->tau;
+    for (int i = 0; i < L->q; ++i) {
+        double cu = 0.0, cF = 0.0, uF = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            cu += L->c[i][a] * u[a];
+            cF += L->c[i][a] * F[a];
+            uF += u[a] * F[a];
+        }
+        double S = pref * L->w[i] * (3.0 * (cF - uF) + 9.0 * cu * cF);
+        gpost[i] = gpre[i] - (gpre[i] - geq[i]) / cfg->tau + S;
+    }
+}
+
+/* Single-cell collision, exported for the moment-property tests. */
+int oracle_collide_cell(const oracle_cfg *cfg, double d, const double *gpre, double *gpost)
+{
+    lattice_t L;
+    if (build_lattice(cfg->q, &L)) return -1;
+    collide_cell(&L, cfg, d, gpre, gpost);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pull streaming: g*_i(x) = g^post_i(x - c_i).                              */
+/*   * periodic axes wrap;                                                   */
+/*   * a source cell inside a wall layer is replaced by halfway bounce-back, */
+/*     g*_i(x) = g^post_opp(i)(x); this takes precedence on edges;           */
+/*   * a source beyond an open face (lowest such axis first) is replaced by   */
+/*     an equilibrium built from the cell's own post-collision state:         */
+/*       inlet : f^eq(rho_b, u_in) - w rho0, rho_b = rho0 + sum_j g^post_j(x) */
+/*       outlet: f^eq(rho_out, u_b) - w rho0, u_b = (sum_j c_j g^post_j(x))/rho_b */
+/* Solid cells get zero populations.                                         */
+/* ------------------------------------------------------------------------ */
+static void stream_cell(const lattice_t *L, const oracle_cfg *cfg, const double *post,
+                        double *pre, int x, int y, int z)
+{
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    const long cell = cell_index(cfg, x, y, z);
+    int n[3];
+    dims(cfg, n);
+    if (is_solid(cfg, x, y, z)) {
+        for (int i = 0; i < L->q; ++i) pre[i * N + cell] = 0.0;
+        return;
+    }
+    int X[3] = { x, y, z };
+    for (int i = 0; i < L->q; ++i) {
+        int s[3];
+        int open_axis = -1, open_side = 0;
+        for (int a = 0; a < 3; ++a) {
+            s[a] = X[a] - L->c[i][a];
+            if (s[a] < 0) {
+                if (cfg->bc_lo[a] == OR_PERIODIC) s[a] += n[a];
+                else if (open_axis < 0) { open_axis = a; open_side = -1; }
+            } else if (s[a] >= n[a]) {
+                if (cfg->bc_hi[a] == OR_PERIODIC) s[a] -= n[a];
+                else if (open_axis < 0) { open_axis = a; open_side = +1; }
+            }
+        }
+        if (in_wall_layer(cfg, s)) {
+            pre[i * N + cell] = post[(long)L->opp[i] * N + cell];
+            continue;
+        }
+        if (open_axis < 0) {
+            pre[i * N + cell] = post[(long)i * N + cell_index(cfg, s[0], s[1], s[2])];
+            continue;
+        }
+        int kind = open_side < 0 ? cfg->bc_lo[open_axis] : cfg->bc_hi[open_axis];
+        double rho_b = cfg->rho0, jb[3] = { 0.0, 0.0, 0.0 };
+        for (int k = 0; k < L->q; ++k) {
+            double gk = post[(long)k * N + cell];
+            rho_b += gk;
+            for (int a = 0; a < 3; ++a) jb[a] += L->c[k][a] * gk;
+        }
+        double geq[19];
+        if (kind == OR_INLET_U) {
+            equilibrium(L, cfg->rho0, rho_b, cfg->inlet_u, geq);
+        } else { /* OR_OUTLET_RHO */
+            double ub[3] = { jb[0] / rho_b, jb[1] / rho_b, jb[2] / rho_b };
+            equilibrium(L, cfg->rho0, cfg->outlet_rho, ub, geq);
+        }
+        pre[i * N + cell] = geq[i];
+    }
+}
+
+static int check_cfg(const oracle_cfg *cfg, lattice_t *L)
+{
+    if (build_lattice(cfg->q, L)) return -1;
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return -1;
+    if (cfg->q == 9 && cfg->nz != 1) return -1;
+    if (!(cfg->tau > 0.5)) return -1;
+    for (int a = 0; a < 3; ++a) {
+        int lo = cfg->bc_lo[a], hi = cfg->bc_hi[a];
+        if ((lo == OR_PERIODIC) != (hi == OR_PERIODIC)) return -1;
+        if (lo < 0 || lo > 3 || hi < 0 || hi > 3) return -1;
+    }
+    return 0;
+}
+
+int oracle_stream(const oracle_cfg *cfg, const double *post, double *pre, int nthreads)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    const int ny = cfg->ny, nz = cfg->nz, nx = cfg->nx;
+#pragma omp parallel for collapse(2) num_threads(nthreads) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) stream_cell(&L, cfg, post, pre, x, y, z);
+    return 0;
+}
+
+int oracle_collide(const oracle_cfg *cfg, const double *d, const double *pre, double *post,
+                   int nthreads)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    const int ny = cfg->ny, nz = cfg->nz, nx = cfg->nx, q = cfg->q;
+#pragma omp parallel for collapse(2) num_threads(nthreads) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long cell = cell_index(cfg, x, y, z);
+                double gin[19], gout[19];
+                if (is_solid(cfg, x, y, z)) {
+                    for (int i = 0; i < q; ++i) post[i * N + cell] = 0.0;
+                    continue;
+                }
+                for (int i = 0; i < q; ++i) gin[i] = pre[i * N + cell];
+                collide_cell(&L, cfg, d[cell], gin, gout);
+                for (int i = 0; i < q; ++i) post[i * N + cell] = gout[i];
+            }
+    return 0;
+}
+
+/* Moments of pre-collision populations: drho = rho - rho0 and u = (j + F/2)/rho,
+ * u stored as u[a*N + cell].  Solid cells report drho = 0, u = 0.            */
+int oracle_moments(const oracle_cfg *cfg, const double *pre, double *drho, double *u)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    for (int z = 0; z < cfg->nz; ++z)
+        for (int y = 0; y < cfg->ny; ++y)
+            for (int x = 0; x < cfg->nx; ++x) {
+                long cell = cell_index(cfg, x, y, z);
+                if (is_solid(cfg, x, y, z)) {
+                    drho[cell] = 0.0;
+                    for (int a = 0; a < 3; ++a) u[a * N + cell] = 0.0;
+                    continue;
+                }
+                double s = 0.0, j[3] = { 0.0, 0.0, 0.0 };
+                for (int i = 0; i < L.q; ++i) {
+                    double g = pre[i * N + cell];
+                    s += g;
+                    for (int a = 0; a < 3; ++a) j[a] += L.c[i][a] * g;
+                }
+                double rho = cfg->rho0 + s;
+                drho[cell] = s;
+                for (int a = 0; a < 3; ++a) u[a * N + cell] = (j[a] + 0.5 * cfg->force[a]) / rho;
+            }
+    return 0;
+}
+
+/* Advance the post-collision state g by nsteps (g is overwritten). */
+int oracle_run(const oracle_cfg *cfg, const double *d, int nsteps, double *g, int nthreads)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    double *pre = (double *)malloc(sizeof(double) * (size_t)L.q * (size_t)N);
+    if (!pre) return -2;
+    for (int t = 0; t < nsteps; ++t) {
+        oracle_stream(cfg, g, pre, nthreads);
+        oracle_collide(cfg, d, pre, g, nthreads);
+    }
+    free(pre);
+    return 0;
+}
+
+/* Moments at the current time level of a post-collision state: stream, then
+ * take moments (the state itself is not changed).                           */
+int oracle_observe(const oracle_cfg *cfg, const double *g, double *drho, double *u,
+                   int nthreads)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    double *pre = (double *)malloc(sizeof(double) * (size_t)L.q * (size_t)N);
+    if (!pre) return -2;
+    oracle_stream(cfg, g, pre, nthreads);
+    oracle_moments(cfg, pre, drho, u);
+    free(pre);
+    return 0;
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,218 @@
+"""ctypes marshalling for the FP64 oracle in ``hlbm_oracle.c``.
+
+Test infrastructure only (see the package docstring).  Arrays are numpy float64
+in the oracle's own population ordering, ``g[i, cell]`` with
+``cell = x + nx*(y + ny*z)``; :func:`lattice` returns that ordering.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+PERIODIC, WALL, INLET_U, OUTLET_RHO = 0, 1, 2, 3
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hlbm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile ``hlbm_oracle.c`` into ``liboracle.so`` (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=c11", "-Wall",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("q", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("tau", ctypes.c_double),
+        ("force", ctypes.c_double * 3),
+        ("bc_lo", ctypes.c_int * 3),
+        ("bc_hi", ctypes.c_int * 3),
+        ("inlet_u", ctypes.c_double * 3),
+        ("outlet_rho", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+    ]
+
+
+@dataclass
+class OracleConfig:
+    q: int
+    nx: int
+    ny: int
+    nz: int = 1
+    tau: float = 0.6
+    force: tuple = (0.0, 0.0, 0.0)
+    bc_lo: tuple = (PERIODIC, PERIODIC, PERIODIC)
+    bc_hi: tuple = (PERIODIC, PERIODIC, PERIODIC)
+    inlet_u: tuple = (0.0, 0.0, 0.0)
+    outlet_rho: float = 1.0
+    rho0: float = 1.0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def c_struct(self) -> _Cfg:
+        s = _Cfg()
+        s.q, s.nx, s.ny, s.nz = self.q, self.nx, self.ny, self.nz
+        s.tau = self.tau
+        s.force = (ctypes.c_double * 3)(*self.force)
+        s.bc_lo = (ctypes.c_int * 3)(*self.bc_lo)
+        s.bc_hi = (ctypes.c_int * 3)(*self.bc_hi)
+        s.inlet_u = (ctypes.c_double * 3)(*self.inlet_u)
+        s.outlet_rho = self.outlet_rho
+        s.rho0 = self.rho0
+        return s
+
+    def solid_mask(self) -> np.ndarray:
+        """Boolean mask of wall-layer cells, shape (nz, ny, nx)."""
+        m = np.zeros((self.nz, self.ny, self.nx), dtype=bool)
+        n = (self.nx, self.ny, self.nz)
+        for a in range(3):
+            ax = 2 - a  # numpy axis of lattice axis a
+            if self.bc_lo[a] == WALL:
+                sl = [slice(None)] * 3
+                sl[ax] = 0
+                m[tuple(sl)] = True
+            if self.bc_hi[a] == WALL:
+                sl = [slice(None)] * 3
+                sl[ax] = n[a] - 1
+                m[tuple(sl)] = True
+        return m
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        D = P(ctypes.c_double)
+        C = P(_Cfg)
+        lib.oracle_lattice.argtypes = [ctypes.c_int, P(ctypes.c_int), D]
+        lib.oracle_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, D, D]
+        lib.oracle_equilibrium.restype = None
+        lib.oracle_collide_cell.argtypes = [C, ctypes.c_double, D, D]
+        lib.oracle_stream.argtypes = [C, D, D, ctypes.c_int]
+        lib.oracle_collide.argtypes = [C, D, D, D, ctypes.c_int]
+        lib.oracle_moments.argtypes = [C, D, D, D]
+        lib.oracle_run.argtypes = [C, D, ctypes.c_int, D, ctypes.c_int]
+        lib.oracle_observe.argtypes = [C, D, D, D, ctypes.c_int]
+        lib.oracle_max_threads.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} rejected its arguments (rc={rc})")
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def lattice(q: int):
+    """Return (c[q,3] int, w[q] float64) in the oracle's ordering."""
+    c = np.zeros((q, 3), dtype=np.int32)
+    w = np.zeros(q, dtype=np.float64)
+    _check(_load().oracle_lattice(q, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w)),
+           "lattice")
+    return c.astype(np.int64), w
+
+
+def equilibrium(q: int, rho: float, u, rho0: float = 1.0) -> np.ndarray:
+    uu = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(3))
+    geq = np.zeros(q, dtype=np.float64)
+    _load().oracle_equilibrium(q, rho0, rho, _dp(uu), _dp(geq))
+    return geq
+
+
+def collide_cell(cfg: OracleConfig, d: float, gpre) -> np.ndarray:
+    gin = np.ascontiguousarray(np.asarray(gpre, dtype=np.float64))
+    gout = np.zeros(cfg.q, dtype=np.float64)
+    s = cfg.c_struct()
+    _check(_load().oracle_collide_cell(ctypes.byref(s), float(d), _dp(gin), _dp(gout)),
+           "collide_cell")
+    return gout
+
+
+def _state(cfg: OracleConfig, g):
+    if g is None:
+        return np.zeros((cfg.q, cfg.ncells), dtype=np.float64)
+    g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(cfg.q, cfg.ncells))
+    return g.copy()
+
+
+def _field(cfg: OracleConfig, d):
+    d = np.ascontiguousarray(np.asarray(d, dtype=np.float64).reshape(cfg.ncells))
+    return d
+
+
+def stream(cfg: OracleConfig, post, nthreads: int = 1) -> np.ndarray:
+    post = _state(cfg, post)
+    pre = np.zeros_like(post)
+    s = cfg.c_struct()
+    _check(_load().oracle_stream(ctypes.byref(s), _dp(post), _dp(pre), nthreads), "stream")
+    return pre
+
+
+def collide(cfg: OracleConfig, d, pre, nthreads: int = 1) -> np.ndarray:
+    pre = _state(cfg, pre)
+    post = np.zeros_like(pre)
+    dd = _field(cfg, d)
+    s = cfg.c_struct()
+    _check(_load().oracle_collide(ctypes.byref(s), _dp(dd), _dp(pre), _dp(post), nthreads),
+           "collide")
+    return post
+
+
+def moments(cfg: OracleConfig, pre):
+    """Moments of pre-collision populations -> (drho[N], u[3, N])."""
+    pre = _state(cfg, pre)
+    drho = np.zeros(cfg.ncells)
+    u = np.zeros((3, cfg.ncells))
+    s = cfg.c_struct()
+    _check(_load().oracle_moments(ctypes.byref(s), _dp(pre), _dp(drho), _dp(u)), "moments")
+    return drho, u
+
+
+def run(cfg: OracleConfig, d, nsteps: int, g=None, nthreads: int = 1) -> np.ndarray:
+    """Advance the post-collision state ``g`` (default: rest) by ``nsteps``."""
+    g = _state(cfg, g)
+    dd = _field(cfg, d)
+    s = cfg.c_struct()
+    _check(_load().oracle_run(ctypes.byref(s), _dp(dd), int(nsteps), _dp(g), nthreads), "run")
+    return g
+
+
+def observe(cfg: OracleConfig, g, nthreads: int = 1):
+    """Moments (drho[N], u[3, N]) at the time level of post-collision state ``g``."""
+    g = _state(cfg, g)
+    drho = np.zeros(cfg.ncells)
+    u = np.zeros((3, cfg.ncells))
+    s = cfg.c_struct()
+    _check(_load().oracle_observe(ctypes.byref(s), _dp(g), _dp(drho), _dp(u), nthreads),
+           "observe")
+    return drho, u
