@@ -1,0 +1,230 @@
+"""Throughput of the fused HLBM stream-collide sweep on one MI355X.
+
+Workload: D3Q19 homogenized lattice BGK on a 512^3 fully periodic box, porosity
+control d from a regular 16^3 array of spheres (cell edge 32, radius 10)
+smoothed by a periodic Gaussian (sigma = 2), tau = 0.6, body force 1e-6 along x,
+from rest.  A "step" is one fused pull-stream + collide sweep over all cells.
+
+The headline form stores populations in FP32 (FP32 arithmetic).  The FP16- and
+BF16-shifted storage forms (FP32 arithmetic) run on the same workload and are
+reported beside it with their speed-up and their relative L2 error against the
+FP64 oracle.  The error is exact to evaluate at full size: the workload is
+32-periodic, so every 32^3 tile equals a 32^3 run of one obstacle cell, which
+the oracle computes (as part of the timed CPU-baseline sample).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+N_EDGE = 512
+TAU = 0.6
+FORCE = (1e-6, 0.0, 0.0)
+SCALE_16 = 2.0 ** 24
+ALG_BYTES = {"f32": 19 * 4 * 2 + 4, "f16s": 19 * 2 * 2 + 2, "bf16s": 19 * 2 * 2 + 2}
+COUNTERS = os.path.join(ROOT, "profiles", "sweep_d3q19_f32_512_counters.json")
+SWEEP_SRC = os.path.join(ROOT, "paper_2310_14746_amd", "csrc", "sweep.hip")
+METRIC = "MLUPS and % HBM roofline, D3Q19 HLBM 512^3; FP16-storage vs FP32 at stated L2 error"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rel_l2_drho(dr, dr_ref, u_ref):
+    floor = np.linalg.norm((u_ref ** 2).sum(axis=0) * 3.0)
+    return float(np.linalg.norm(dr - dr_ref) / max(np.linalg.norm(dr_ref), floor))
+
+
+def time_form(hlbm, storage, d_tile, steps, warmup):
+    import torch
+    reps = N_EDGE // 32
+    dt = np.float32 if storage == "f32" else np.float16
+    d = np.tile(d_tile.astype(dt), (reps, reps, reps))
+    sim = hlbm.HLBM(hlbm.D3Q19, storage, (N_EDGE,) * 3, tau=TAU, force=FORCE,
+                    store_scale=SCALE_16 if storage != "f32" else 1.0)
+    try:
+        sim.set_porosity(d)
+        del d
+        log(f"{storage}: warmup {warmup}")
+        sim.step(warmup)
+        sim.sync()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.step(steps)
+        e1.record(sim.stream)
+        e1.synchronize()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        log(f"{storage}: {steps} steps in {ms:.1f} ms")
+        drho, u, tot = sim.moments("f64", totals=True)
+        dr_t = drho[:32, :32, :32].cpu().numpy().ravel()
+        u_t = u[:, :32, :32, :32].cpu().numpy().reshape(3, -1)
+        # every 32^3 tile identical (exact periodicity of the workload)
+        r = N_EDGE // 32
+        v = drho.reshape(r, 32, r, 32, r, 32)
+        tiles_equal = bool((v == v[:1, :, :1, :, :1, :]).all().item())
+        del drho, u, v
+        torch.cuda.empty_cache()
+        return ms, dr_t, u_t, tot, tiles_equal
+    finally:
+        sim.close()
+
+
+def counters_traffic(n_cells):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current sweep source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    info = json.load(open(COUNTERS))
+    h = hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()
+    if info.get("sweep_sha256") != h or info.get("cells") != n_cells:
+        return None
+    return info.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(steps_total):
+    """Oracle on a 64^3 crop (2^3 obstacle cells; exact by periodicity) -> MLUPS."""
+    import oracle
+    from paper_2310_14746_amd import inputs
+    nt = max(1, min(16, os.cpu_count() or 1))
+    n = 64
+    d = inputs.round_to(inputs.sphere_array(n), "f32").ravel()
+    cfg = oracle.OracleConfig(q=19, nx=n, ny=n, nz=n, tau=TAU, force=FORCE)
+    log(f"oracle: {n}^3 x {steps_total} steps on {nt} threads")
+    t0 = time.perf_counter()
+    g = oracle.run(cfg, d, steps_total, nthreads=nt)
+    secs = time.perf_counter() - t0
+    dr, u = oracle.observe(cfg, g, nthreads=nt)
+    dr = dr.reshape(n, n, n)[:32, :32, :32].ravel()
+    u = u.reshape(3, n, n, n)[:, :32, :32, :32].reshape(3, -1)
+    return {
+        "value": n ** 3 * steps_total / secs / 1e6,
+        "unit": "MLUPS",
+        "cores": nt,
+        "kind": "oracle",
+        "sample": f"FP64 oracle, {n}^3 periodic crop of the same workload (2^3 obstacle cells, "
+                  f"exact by 32-periodicity), {steps_total} steps, {secs:.1f} s",
+    }, dr, u
+
+
+def oracle_tile(d_tile, steps):
+    """FP64 oracle on one 32^3 obstacle cell (untimed reference for an input rounding)."""
+    import oracle
+    nt = max(1, min(16, os.cpu_count() or 1))
+    cfg = oracle.OracleConfig(q=19, nx=32, ny=32, nz=32, tau=TAU, force=FORCE)
+    g = oracle.run(cfg, d_tile.ravel(), steps, nthreads=nt)
+    return oracle.observe(cfg, g, nthreads=nt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--forms", default="f32,f16s,bf16s")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_14746_amd import hlbm, inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    hlbm.load()
+    d_tile = inputs.sphere_array_tile()
+    n_cells = N_EDGE ** 3
+    forms = [f for f in args.forms.split(",") if f]
+    results = {}
+    for f in forms:
+        tile = inputs.round_to(d_tile, "f32" if f == "f32" else "f16")
+        ms, dr, u, tot, teq = time_form(hlbm, f, tile, args.steps, args.warmup)
+        results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq)
+
+    cpu, refs = None, {}
+    if not args.no_cpu_baseline:
+        cpu, dr_o, u_o = cpu_baseline(args.steps + args.warmup)
+        refs["f32"] = (dr_o, u_o)
+        if any(f != "f32" for f in forms):
+            refs["f16"] = oracle_tile(inputs.round_to(d_tile, "f16"), args.steps + args.warmup)
+
+    head = forms[0]
+    ms_step = results[head]["ms"] / args.steps
+    mlups = n_cells * args.steps / (results[head]["ms"] * 1e-3) / 1e6
+    achieved = ALG_BYTES[head] * n_cells / (ms_step * 1e-3) / 1e9
+    traffic = counters_traffic(n_cells) if head == "f32" else None
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"D3Q19 HLBM {N_EDGE}^3 periodic, 16^3 sphere array (r=10, edge 32, "
+                        f"sigma=2), tau={TAU}, F=1e-6 x, {head} storage, A/B buffers",
+            "cells": n_cells,
+            "storage": head,
+            "parallelism": "1 GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_cell": ALG_BYTES[head],
+        },
+        "cpu_baseline": cpu,
+        "forms": {},
+    }
+    for f in forms:
+        r = results[f]
+        ent = {
+            "mlups": round(n_cells * args.steps / (r["ms"] * 1e-3) / 1e6, 1),
+            "ms_per_step": round(r["ms"] / args.steps, 4),
+            "alg_GBs": round(ALG_BYTES[f] * n_cells * args.steps / (r["ms"] * 1e-3) / 1e9, 1),
+            "speedup_vs_" + head: round(results[head]["ms"] / r["ms"], 3),
+            "tiles_identical": r["tiles_equal"],
+            "mass_excess_total": float(r["tot"][0]),
+        }
+        ref = refs.get("f32" if f == "f32" else "f16")
+        if ref is not None:
+            ent["rel_l2_u_vs_fp64"] = float("%.3e" % rel_l2(r["u"], ref[1]))
+            ent["rel_l2_drho_vs_fp64"] = float("%.3e" % rel_l2_drho(r["dr"], ref[0], ref[1]))
+        line["forms"][f] = ent
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * hlbm.h -- C ABI of the MI355X (gfx950) homogenized lattice Boltzmann sweep.
+ *
+ * The library advances a lattice BGK discretization of the homogenized BGK
+ * Boltzmann equation (HBGKBE) of Simonis et al., "Homogenized lattice Boltzmann
+ * methods for fluid flow through porous media -- part I" (Sec. 3.2,
+ * eq:HBGKBE): the BGK collision relaxes toward the homogenized Maxwellian
+ * M^eq = f^eq(n, varpi*u, T) whose velocity argument is scaled by the porosity
+ * control varpi = 1 - nu*tau/K (eq:porousVeloMaxwellian, eq:d-definition).
+ * Per cell the caller supplies d = 1 - varpi in [0, 1]: d = 0 is free fluid
+ * (plain BGK, varpi = 1), d = 1 drives the equilibrium velocity to zero.  The
+ * resulting per-step momentum loss (1/tau)(1 - varpi) rho u is the Darcy /
+ * Brinkman drag of the target equations (Sec. 3.3 Step 1, eq:momentumHLBM).
+ *
+ * One step is a fused pull-stream + collide sweep over every cell:
+ *   g*_i(x) = g_i(x - c_i)                        (pull streaming)
+ *   rho = rho0 + sum g*_i, j = sum c_i g*_i, u = (j + F/2)/rho
+ *   u_eq = (1 - d(x)) u                           (porosity shift)
+ *   g_i <- g*_i - (g*_i - g^eq_i(rho, u_eq))/tau + S_i(u, F)   (BGK + Guo)
+ * with shifted populations g_i = f_i - w_i rho0, the second-order Maxwellian
+ * (c_s^2 = 1/3, from the covariance 1/(3 eps^2) I of Sec. 3.3 Step 2 at
+ * eps = 1) and lattice viscosity nu = (tau - 1/2)/3.
+ *
+ * Conventions
+ *   * Every call returns an int status: HLBM_OK (0) or a negative code; no
+ *     call aborts or throws.  hlbm_last_error() returns a message for the
+ *     last failure on the calling thread.
+ *   * Lattice units (dx = dt = 1).  Cell index = x + nx*(y + ny*z).
+ *   * Device pointers are HIP device addresses on the current device; host
+ *     pointers belong to the caller and are only read or written during the
+ *     call.
+ *   * Work is enqueued on the stream named in the config (NULL = default
+ *     stream).  hlbm_step only enqueues; hlbm_moments, hlbm_get_state and
+ *     hlbm_sync wait for the stream, and an asynchronous device fault
+ *     surfaces there as HLBM_EDEVICE.
+ *   * A context is not thread-safe; distinct contexts may be used from
+ *     distinct threads.
+ */
+#ifndef HLBM_H
+#define HLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HLBM_ABI_VERSION 1
+
+typedef struct hlbm_ctx hlbm_ctx;
+
+/* Status codes. */
+enum {
+    HLBM_OK = 0,
+    HLBM_EINVAL = -1,       /* invalid argument (NULL, range, NaN, tau <= 1/2, ...) */
+    HLBM_ENOMEM = -2,       /* device or host allocation failed */
+    HLBM_EDEVICE = -3,      /* HIP runtime or kernel error */
+    HLBM_EUNSUPPORTED = -4, /* combination of options not provided */
+    HLBM_ESTATE = -5,       /* call out of order (e.g. step before porosity) */
+    HLBM_ENUMERIC = -6      /* non-finite value in a result */
+};
+
+/* Velocity sets (textbook lattices; c_s^2 = 1/3). */
+enum { HLBM_D2Q9 = 9, HLBM_D3Q19 = 19 };
+
+/* Population storage in HBM.  All forms store shifted populations
+ * g = f - w*rho0.  F64: f64 storage and arithmetic.  F32: f32 storage and
+ * arithmetic.  F16S / BF16S: 16-bit storage of s*g (s = store_scale, a power of
+ * two) with f32 arithmetic, round to nearest even on store. */
+enum { HLBM_F64 = 0, HLBM_F32 = 1, HLBM_F16S = 2, HLBM_BF16S = 3 };
+
+/* Buffer pattern: two population buffers swapped every step (AB). */
+enum { HLBM_AB = 0 };
+
+/* Face kinds, per axis and side.  HLBM_PERIODIC must be used on both sides of
+ * an axis or on neither.  HLBM_WALL makes the first (lo) or last (hi) layer of
+ * cells solid, with halfway bounce-back at the fluid-solid link (no-slip,
+ * u = 0 on the boundary, Sec. 2.4 eq:targetEBTL). */
+enum { HLBM_PERIODIC = 0, HLBM_WALL = 1, HLBM_INLET_U = 2, HLBM_OUTLET_RHO = 3 };
+
+/* Element types of caller arrays. */
+enum { HLBM_DT_F64 = 0, HLBM_DT_F32 = 1, HLBM_DT_F16 = 2 };
+
+typedef struct {
+    int lattice;         /* HLBM_D2Q9 or HLBM_D3Q19 */
+    int storage;         /* HLBM_F64, HLBM_F32, HLBM_F16S, HLBM_BF16S */
+    int pattern;         /* HLBM_AB */
+    int nx, ny, nz;      /* cells per axis; nz = 1 for D2Q9; nx*ny*nz < 2^32 */
+    double tau;          /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3 */
+    double force[3];     /* body-force density F (lattice units) */
+    int bc_lo[3];        /* face kind of the lo side of x, y, z */
+    int bc_hi[3];        /* face kind of the hi side of x, y, z */
+    double inlet_u[3];   /* velocity of HLBM_INLET_U faces */
+    double outlet_rho;   /* density of HLBM_OUTLET_RHO faces */
+    double rho0;         /* reference density of the shifted populations (1) */
+    double store_scale;  /* power of two s for F16S/BF16S; ignored otherwise */
+    int external_memory; /* 1: caller binds population/porosity memory */
+    int block_x;         /* threads per block along x (multiple of 64, <= 1024); 0 = auto */
+    void *hip_stream;    /* hipStream_t for all work of this context, NULL = default */
+} hlbm_config;
+
+/* Library ABI version (HLBM_ABI_VERSION). */
+int hlbm_version(void);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *hlbm_last_error(void);
+
+/* Fill *cfg with defaults: D3Q19, F32, AB, 32^3 periodic, tau = 0.6, F = 0,
+ * rho0 = 1, store_scale = 1, library-owned memory, default stream. */
+int hlbm_config_default(hlbm_config *cfg);
+
+/* Velocity set of `lattice` in the library's population order: c[3*i + a]
+ * (integer components) and w[i].  Arrays hold at least 3*Q and Q entries.
+ * Used to map states between orderings; the populations in
+ * hlbm_get_state/hlbm_set_state follow this order. */
+int hlbm_lattice_info(int lattice, int *c, double *w);
+
+/* Bytes of one population buffer and of the porosity field for *cfg. */
+int hlbm_required_bytes(const hlbm_config *cfg, size_t *pop_bytes, size_t *porosity_bytes);
+
+/* Validate *cfg and create a context.  Unless cfg->external_memory is set the
+ * library allocates both population buffers and the porosity field in device
+ * memory.  The state starts at rest (g = 0: rho = rho0, u = 0 before the
+ * half-force shift), step counter 0.  EINVAL on a bad field, EUNSUPPORTED on an
+ * unsupported combination, ENOMEM if allocation fails. */
+int hlbm_create(const hlbm_config *cfg, hlbm_ctx **out);
+
+/* Use caller-owned device memory (e.g. torch tensors) for the two population
+ * buffers and the porosity field, each of hlbm_required_bytes() size and at
+ * least 256-byte aligned.  The memory must outlive the context.  Resets the
+ * state to rest and the step counter to 0; the porosity must be set again. */
+int hlbm_bind_buffers(hlbm_ctx *ctx, void *pop_a, void *pop_b, void *porosity);
+
+/* Wait for outstanding work, free library-owned memory, destroy the context.
+ * NULL is accepted.  Returns EDEVICE if outstanding work had failed (the
+ * context is still destroyed). */
+int hlbm_destroy(hlbm_ctx *ctx);
+
+/* Set the porosity control d = 1 - varpi per cell (eq:d-definition; varpi > 1
+ * is excluded by the paper, Sec. 3.2, and varpi < 0 lies outside the model),
+ * N = nx*ny*nz values, x fastest, of type `dtype` (HLBM_DT_*), on the device
+ * if on_device else on the host.  Values are rounded to nearest even into the
+ * storage's porosity type (f64, f32, or f16 for the 16-bit forms).  Any NaN or
+ * value outside [0, 1] -> EINVAL and the field is left unset.  Synchronous. */
+int hlbm_set_porosity(hlbm_ctx *ctx, const void *d, int dtype, int on_device);
+
+/* Enqueue `nsteps` >= 0 fused stream-collide sweeps.  ESTATE if the porosity
+ * was never set.  Asynchronous. */
+int hlbm_step(hlbm_ctx *ctx, int nsteps);
+
+/* Number of completed (enqueued) steps. */
+int hlbm_get_step(const hlbm_ctx *ctx, long long *step);
+
+/* Moments at the current time level n: those of the post-streaming,
+ * pre-collision populations (Sec. 3.1 moment definitions):
+ *   drho[cell]   = rho - rho0 = sum_i g*_i
+ *   u[a*N+cell]  = (sum_i c_ia g*_i + F_a/2) / rho,   a = 0, 1, 2
+ * (u[2*N..] = 0 for D2Q9).  Solid cells report 0.  dtype HLBM_DT_F64 or
+ * HLBM_DT_F32; on_device selects device or host arrays.  Either array may be
+ * NULL.  If totals != NULL it receives FP64 sums over fluid cells:
+ * totals[0] = sum (rho - rho0), totals[1..3] = sum rho*u_a (computed on the
+ * device in FP64: wavefront reduction, per-block partials, one fixed-order
+ * second pass).  Waits for the stream; EDEVICE on a device fault, ENUMERIC if
+ * a total is not finite. */
+int hlbm_moments(hlbm_ctx *ctx, void *drho, void *u, int dtype, int on_device, double *totals);
+
+/* Size in bytes of a raw state snapshot (one population buffer). */
+int hlbm_state_bytes(const hlbm_ctx *ctx, size_t *bytes);
+
+/* Copy the current post-collision populations (storage element type, library
+ * population order, g[i*N + cell]) to `dst` (device if on_device) and the step
+ * counter to *step (may be NULL).  Waits for the stream. */
+int hlbm_get_state(hlbm_ctx *ctx, void *dst, int on_device, long long *step);
+
+/* Replace the current state by a snapshot taken with hlbm_get_state and set
+ * the step counter.  Resuming from a snapshot reproduces the original run
+ * bit for bit.  Waits for the stream. */
+int hlbm_set_state(hlbm_ctx *ctx, const void *src, int on_device, long long step);
+
+/* Reset to rest (g = 0) and step 0; the porosity field is kept. */
+int hlbm_reset(hlbm_ctx *ctx);
+
+/* Wait for all work of the context; EDEVICE on a device fault. */
+int hlbm_sync(hlbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HLBM_H */

@@ -1,0 +1,46 @@
+// Internal declarations shared by the kernels (sweep.hip) and the C-ABI host
+// code (api.hip).  Not installed; the public interface is include/hlbm.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hlbm {
+
+// Per-launch constants of the sweep, passed by value in the kernel arguments.
+struct Params {
+    int nx, ny, nz;
+    uint32_t N;          // cells = nx*ny*nz (< 2^32)
+    double omega;        // 1/tau
+    double pref;         // 1 - 1/(2 tau), Guo source prefactor
+    double F[3];         // body-force density
+    double rho0;         // reference density of the shifted populations
+    double scale;        // 16-bit storage scale s (power of two), else 1
+    double inv_scale;    // 1/s
+    int bc_lo[3];        // face kinds (HLBM_PERIODIC, HLBM_WALL, ...)
+    int bc_hi[3];
+    double inlet_u[3];
+    double outlet_rho;
+};
+
+enum BcMode { BC_PERIODIC = 0, BC_GENERAL = 1 };
+
+// Launch geometry shared by every per-cell kernel: blocks of `bx` threads
+// along x, grid (ceil(nx/bx), ny, nz).
+struct Launch {
+    dim3 grid, block;
+    uint32_t nblocks;
+};
+Launch cell_launch(const Params& p, int bx);
+
+// Kernel launchers (sweep.hip).  All return the launch status.
+hipError_t launch_sweep(int q, int storage, int bcmode, const Params& p, const void* src,
+                        void* dst, const void* dfield, int bx, hipStream_t s);
+hipError_t launch_moments(int q, int storage, int bcmode, const Params& p, const void* src,
+                          void* drho, void* u, int out_f64, double* partials, int bx,
+                          hipStream_t s);
+hipError_t launch_reduce4(const double* partials, uint32_t nblocks, double* out, hipStream_t s);
+hipError_t launch_porosity_convert(int in_dtype, const void* in, int storage, void* out,
+                                   uint32_t n, int* block_flags, int* flag_out, hipStream_t s);
+
+}  // namespace hlbm

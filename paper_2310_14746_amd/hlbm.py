@@ -1,0 +1,300 @@
+"""Thin ctypes binding of the C-ABI in ``include/hlbm.h`` (``libhlbm.so``).
+
+Only argument marshalling lives here: every step of the sweep runs in the HIP
+kernels of the library.  PyTorch supplies device memory (population buffers and
+the porosity field are torch tensors bound with ``hlbm_bind_buffers``) and the
+stream (torch's current stream).  If the library has not been built, loading
+fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhlbm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "hlbm.h")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
+D2Q9, D3Q19 = 9, 19
+F64, F32, F16S, BF16S = 0, 1, 2, 3
+AB = 0
+PERIODIC, WALL, INLET_U, OUTLET_RHO = 0, 1, 2, 3
+DT_F64, DT_F32, DT_F16 = 0, 1, 2
+
+STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S}
+_STORE_ELEM = {F64: 8, F32: 4, F16S: 2, BF16S: 2}
+_POROSITY_DTYPE = {F64: "f64", F32: "f32", F16S: "f16", BF16S: "f16"}
+
+
+class HLBMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"hlbm error {code}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int),
+        ("storage", ctypes.c_int),
+        ("pattern", ctypes.c_int),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("tau", ctypes.c_double),
+        ("force", ctypes.c_double * 3),
+        ("bc_lo", ctypes.c_int * 3),
+        ("bc_hi", ctypes.c_int * 3),
+        ("inlet_u", ctypes.c_double * 3),
+        ("outlet_rho", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("store_scale", ctypes.c_double),
+        ("external_memory", ctypes.c_int),
+        ("block_x", ctypes.c_int),
+        ("hip_stream", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def declared_functions() -> list:
+    """Names of the functions declared in include/hlbm.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(hlbm_\w+)\s*\(", text, flags=re.M)
+
+
+def load() -> ctypes.CDLL:
+    """Load libhlbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2310_14746_amd.build` "
+            "(the HIP library is the only compute path)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "hlbm_version": ([], i),
+        "hlbm_last_error": ([], ctypes.c_char_p),
+        "hlbm_config_default": ([P(Config)], i),
+        "hlbm_lattice_info": ([i, P(ctypes.c_int), P(ctypes.c_double)], i),
+        "hlbm_required_bytes": ([P(Config), P(ctypes.c_size_t), P(ctypes.c_size_t)], i),
+        "hlbm_create": ([P(Config), P(vp)], i),
+        "hlbm_bind_buffers": ([vp, vp, vp, vp], i),
+        "hlbm_destroy": ([vp], i),
+        "hlbm_set_porosity": ([vp, vp, i, i], i),
+        "hlbm_step": ([vp, i], i),
+        "hlbm_get_step": ([vp, P(ctypes.c_longlong)], i),
+        "hlbm_moments": ([vp, vp, vp, i, i, P(ctypes.c_double)], i),
+        "hlbm_state_bytes": ([vp, P(ctypes.c_size_t)], i),
+        "hlbm_get_state": ([vp, vp, i, P(ctypes.c_longlong)], i),
+        "hlbm_set_state": ([vp, vp, i, ctypes.c_longlong], i),
+        "hlbm_reset": ([vp], i),
+        "hlbm_sync": ([vp], i),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        msg = load().hlbm_last_error()
+        raise HLBMError(rc, msg.decode() if msg else "")
+
+
+def lattice_info(q: int):
+    """(c[q,3], w[q]) in the library's population order."""
+    c = (ctypes.c_int * (3 * q))()
+    w = (ctypes.c_double * q)()
+    _check(load().hlbm_lattice_info(q, c, w))
+    return np.array(c, dtype=np.int64).reshape(q, 3), np.array(w)
+
+
+def make_config(lattice: int = D3Q19, storage="f32", shape=(32, 32, 32), tau: float = 0.6,
+                force=(0.0, 0.0, 0.0), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), inlet_u=(0.0, 0.0, 0.0),
+                outlet_rho: float = 1.0, rho0: float = 1.0, store_scale: float = 1.0,
+                block_x: int = 0, external_memory: int = 0, stream: Optional[int] = None) -> Config:
+    cfg = Config()
+    _check(load().hlbm_config_default(ctypes.byref(cfg)))
+    cfg.lattice = int(lattice)
+    cfg.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    cfg.pattern = AB
+    nx, ny, nz = (tuple(shape) + (1,))[:3] if len(shape) == 2 else tuple(shape)
+    cfg.nx, cfg.ny, cfg.nz = int(nx), int(ny), int(nz)
+    cfg.tau = float(tau)
+    cfg.force = (ctypes.c_double * 3)(*[float(v) for v in force])
+    cfg.bc_lo = (ctypes.c_int * 3)(*[int(v) for v in bc_lo])
+    cfg.bc_hi = (ctypes.c_int * 3)(*[int(v) for v in bc_hi])
+    cfg.inlet_u = (ctypes.c_double * 3)(*[float(v) for v in inlet_u])
+    cfg.outlet_rho = float(outlet_rho)
+    cfg.rho0 = float(rho0)
+    cfg.store_scale = float(store_scale)
+    cfg.block_x = int(block_x)
+    cfg.external_memory = int(external_memory)
+    cfg.hip_stream = stream
+    return cfg
+
+
+class HLBM:
+    """One lattice (context).  Device memory comes from torch tensors.
+
+    ``shape`` is (nx, ny, nz); fields returned by :meth:`moments` have shape
+    (nz, ny, nx) for drho and (3, nz, ny, nx) for u.
+    """
+
+    def __init__(self, lattice: int = D3Q19, storage="f32", shape=(32, 32, 32), tau=0.6,
+                 force=(0.0, 0.0, 0.0), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0),
+                 inlet_u=(0.0, 0.0, 0.0), outlet_rho=1.0, rho0=1.0, store_scale=1.0,
+                 block_x=0, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        lib = load()
+        self.cfg = make_config(lattice, storage, shape, tau, force, bc_lo, bc_hi, inlet_u,
+                               outlet_rho, rho0, store_scale, block_x, external_memory=1,
+                               stream=self.stream.cuda_stream)
+        self.q = self.cfg.lattice
+        self.storage = self.cfg.storage
+        self.shape = (self.cfg.nx, self.cfg.ny, self.cfg.nz)
+        self.N = self.cfg.nx * self.cfg.ny * self.cfg.nz
+        pb, db = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib.hlbm_required_bytes(ctypes.byref(self.cfg), ctypes.byref(pb), ctypes.byref(db)))
+        self.pop_bytes = pb.value
+        with torch.cuda.device(self.device):
+            self._pop_a = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+            self._pop_b = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+            self._dfield = torch.empty(max(db.value, 1), dtype=torch.uint8, device=self.device)
+        ctx = ctypes.c_void_p()
+        _check(lib.hlbm_create(ctypes.byref(self.cfg), ctypes.byref(ctx)))
+        self.ctx = ctx
+        _check(lib.hlbm_bind_buffers(self.ctx, self._pop_a.data_ptr(), self._pop_b.data_ptr(),
+                                     self._dfield.data_ptr()))
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            rc = load().hlbm_destroy(self.ctx)
+            self.ctx = None
+            _check(rc)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- porosity ----------------------------------------------------------
+    def set_porosity(self, d):
+        """d = 1 - varpi per cell: numpy array (host) or torch tensor (host or device)."""
+        t = self.torch
+        if isinstance(d, t.Tensor):
+            dd = d.contiguous()
+            dtype = {t.float64: DT_F64, t.float32: DT_F32, t.float16: DT_F16}[dd.dtype]
+            if dd.numel() != self.N:
+                raise ValueError("porosity needs nx*ny*nz values")
+            on_dev = 1 if dd.is_cuda else 0
+            if on_dev:
+                _check(load().hlbm_set_porosity(self.ctx, dd.data_ptr(), dtype, 1))
+            else:
+                arr = dd.numpy()
+                _check(load().hlbm_set_porosity(self.ctx, arr.ctypes.data, dtype, 0))
+            return
+        arr = np.ascontiguousarray(d)
+        if arr.size != self.N:
+            raise ValueError("porosity needs nx*ny*nz values")
+        dtype = {np.dtype(np.float64): DT_F64, np.dtype(np.float32): DT_F32,
+                 np.dtype(np.float16): DT_F16}[arr.dtype]
+        _check(load().hlbm_set_porosity(self.ctx, arr.ctypes.data, dtype, 0))
+
+    @property
+    def porosity_dtype(self) -> str:
+        return _POROSITY_DTYPE[self.storage]
+
+    # -- stepping ----------------------------------------------------------
+    def step(self, n: int = 1):
+        _check(load().hlbm_step(self.ctx, int(n)))
+
+    @property
+    def step_count(self) -> int:
+        s = ctypes.c_longlong()
+        _check(load().hlbm_get_step(self.ctx, ctypes.byref(s)))
+        return s.value
+
+    def sync(self):
+        _check(load().hlbm_sync(self.ctx))
+
+    def reset(self):
+        _check(load().hlbm_reset(self.ctx))
+
+    # -- observation -------------------------------------------------------
+    def moments(self, dtype: str = "f64", device: bool = True, totals: bool = False):
+        """(drho, u[, totals]) at the current time level as torch tensors."""
+        t = self.torch
+        tdt = t.float64 if dtype == "f64" else t.float32
+        cdt = DT_F64 if dtype == "f64" else DT_F32
+        nx, ny, nz = self.shape
+        tot = (ctypes.c_double * 4)()
+        if device:
+            drho = t.empty((nz, ny, nx), dtype=tdt, device=self.device)
+            u = t.empty((3, nz, ny, nx), dtype=tdt, device=self.device)
+            _check(load().hlbm_moments(self.ctx, drho.data_ptr(), u.data_ptr(), cdt, 1, tot))
+        else:
+            drho = t.empty((nz, ny, nx), dtype=tdt)
+            u = t.empty((3, nz, ny, nx), dtype=tdt)
+            _check(load().hlbm_moments(self.ctx, drho.data_ptr(), u.data_ptr(), cdt, 0, tot))
+        if totals:
+            return drho, u, np.array(tot)
+        return drho, u
+
+    def totals(self) -> np.ndarray:
+        """FP64 [sum(rho - rho0), sum rho u_x, sum rho u_y, sum rho u_z] over fluid cells."""
+        tot = (ctypes.c_double * 4)()
+        _check(load().hlbm_moments(self.ctx, None, None, DT_F64, 1, tot))
+        return np.array(tot)
+
+    # -- state -------------------------------------------------------------
+    def get_state(self):
+        """(raw state bytes as a uint8 device tensor, step)."""
+        t = self.torch
+        buf = t.empty(self.pop_bytes, dtype=t.uint8, device=self.device)
+        s = ctypes.c_longlong()
+        _check(load().hlbm_get_state(self.ctx, buf.data_ptr(), 1, ctypes.byref(s)))
+        return buf, s.value
+
+    def set_state(self, buf, step: int):
+        if buf.numel() != self.pop_bytes:
+            raise ValueError("state size mismatch")
+        _check(load().hlbm_set_state(self.ctx, buf.contiguous().data_ptr(), 1 if buf.is_cuda else 0,
+                                     int(step)))
+
+    def state_f64(self, store_scale: Optional[float] = None) -> np.ndarray:
+        """Current post-collision populations as float64 g[i, cell] (library order)."""
+        t = self.torch
+        buf, _ = self.get_state()
+        raw = buf.cpu()
+        if self.storage == F64:
+            v = raw.view(t.float64).numpy().astype(np.float64)
+        elif self.storage == F32:
+            v = raw.view(t.float32).numpy().astype(np.float64)
+        elif self.storage == F16S:
+            v = raw.view(t.float16).to(t.float64).numpy() / self.cfg.store_scale
+        else:
+            v = raw.view(t.bfloat16).to(t.float64).numpy() / self.cfg.store_scale
+        return v.reshape(self.q, self.N)

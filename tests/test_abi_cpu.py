@@ -1,0 +1,96 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/hlbm.h, and validates configurations (no compute calls)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2310_14746_amd import hlbm
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return hlbm.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = hlbm.declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.hlbm_version() == 1
+
+
+def test_header_matches_binding_struct():
+    # hlbm_config field order in the header equals the ctypes mirror
+    import re
+    text = open(hlbm.HEADER).read()
+    body = text[text.index("typedef struct {"):text.index("} hlbm_config;")]
+    fields = re.findall(r"^\s*(?:int|double|void)\s*\*?\s*(\w+)", body, flags=re.M)
+    names = []
+    for line in body.splitlines():
+        m = re.match(r"^\s*(int|double|void)\s*\*?\s*([\w\s,\[\]0-9]+);", line)
+        if m:
+            for part in m.group(2).split(","):
+                names.append(re.sub(r"\[.*\]", "", part).strip())
+    assert names == [f[0] for f in hlbm.Config._fields_], (names, fields)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_lattice_tables_match_oracle_set(orc, q):
+    c, w = hlbm.lattice_info(q)
+    co, wo = orc.lattice(q)
+    perm = [int(np.nonzero((co == ci).all(axis=1))[0][0]) for ci in c]
+    assert sorted(perm) == list(range(q))
+    assert np.allclose(w, wo[perm], rtol=0, atol=1e-17)
+    # opposite of i is i+1 for odd i, i-1 for even i > 0
+    for i in range(1, q):
+        j = i + 1 if i % 2 else i - 1
+        assert (c[j] == -c[i]).all()
+
+
+def _rb(cfg):
+    pb, db = ctypes.c_size_t(), ctypes.c_size_t()
+    return hlbm.load().hlbm_required_bytes(ctypes.byref(cfg), ctypes.byref(pb), ctypes.byref(db)), pb.value, db.value
+
+
+def test_required_bytes():
+    rc, pb, db = _rb(hlbm.make_config(19, "f32", (256, 256, 256)))
+    assert rc == 0 and pb == 19 * 4 * 256 ** 3 and db == 4 * 256 ** 3
+    rc, pb, db = _rb(hlbm.make_config(19, "f16s", (64, 32, 16), store_scale=4096.0))
+    assert rc == 0 and pb == 19 * 2 * 64 * 32 * 16 and db == 2 * 64 * 32 * 16
+    rc, pb, db = _rb(hlbm.make_config(9, "f64", (128, 64, 1), bc_lo=(0, 1, 0), bc_hi=(0, 1, 0)))
+    assert rc == 0 and pb == 9 * 8 * 128 * 64 and db == 8 * 128 * 64
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(tau=0.5), hlbm.EINVAL),
+    (dict(tau=float("nan")), hlbm.EINVAL),
+    (dict(shape=(0, 4, 4)), hlbm.EINVAL),
+    (dict(lattice=15), hlbm.EINVAL),
+    (dict(storage=7), hlbm.EINVAL),
+    (dict(bc_lo=(1, 0, 0), bc_hi=(0, 0, 0)), hlbm.EINVAL),
+    (dict(bc_lo=(5, 0, 0), bc_hi=(5, 0, 0)), hlbm.EINVAL),
+    (dict(storage="f16s", store_scale=3000.0), hlbm.EINVAL),
+    (dict(storage="bf16s", store_scale=0.0), hlbm.EINVAL),
+    (dict(block_x=96), hlbm.EINVAL),
+    (dict(force=(float("inf"), 0, 0)), hlbm.EINVAL),
+    (dict(shape=(2048, 2048, 512)), hlbm.EUNSUPPORTED),
+    (dict(shape=(8, 70000, 4)), hlbm.EUNSUPPORTED),
+    (dict(lattice=9, shape=(8, 8, 2)), hlbm.EINVAL),
+    (dict(bc_lo=(1, 0, 0), bc_hi=(1, 0, 0), shape=(2, 8, 8)), hlbm.EINVAL),
+])
+def test_config_validation(kw, code):
+    args = dict(lattice=19, storage="f32", shape=(16, 16, 16))
+    args.update(kw)
+    rc, _, _ = _rb(hlbm.make_config(**args))
+    assert rc == code
+    assert hlbm.load().hlbm_last_error().decode()
+
+
+def test_null_arguments(lib):
+    assert lib.hlbm_required_bytes(None, None, None) == hlbm.EINVAL
+    assert lib.hlbm_create(None, None) == hlbm.EINVAL
+    assert lib.hlbm_step(None, 1) == hlbm.EINVAL
+    assert lib.hlbm_destroy(None) == hlbm.OK
+    assert lib.hlbm_lattice_info(19, None, None) == hlbm.EINVAL
