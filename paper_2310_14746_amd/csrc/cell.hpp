@@ -1,0 +1,240 @@
+// Per-cell device code of the HLBM sweep: addressing, pull gathers, moments
+// and the homogenized BGK collision.  Included by the kernels in sweep.hip.
+#pragma once
+#include "hlbm_internal.hpp"
+#include "lattice.hpp"
+#include "storage.hpp"
+
+namespace hlbm {
+
+// Element `idx` of a population row addressed by a 32-bit byte offset from a
+// uniform base.  The host guarantees N * sizeof(T) < 2^32, so the offset cannot
+// wrap; this lets every access use the scalar-base + 32-bit vector-offset
+// form of global loads and stores.
+template <class T>
+__device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t idx)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+}
+
+template <class T>
+__device__ __forceinline__ void st(T* __restrict__ base, uint32_t idx, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)) = v;
+}
+
+// ---------------------------------------------------------------------------
+// Collision of one fluid cell in the arithmetic type R (Sec. 3.2: BGK toward
+// the homogenized Maxwellian; the velocity argument is (1 - d) u).
+//   rho = rho0 + sum g, j = sum c g, u = (j + F/2)/rho, u_eq = (1 - d) u
+//   g_i <- g_i - omega (g_i - g^eq_i(rho, u_eq)) + S_i
+//   g^eq_i = w_i [ drho + rho (3 c.u_eq + 9/2 (c.u_eq)^2 - 3/2 u_eq.u_eq) ]
+//   S_i    = (1 - 1/(2 tau)) w_i [ 3 (c_i - u).F + 9 (c_i.u)(c_i.F) ]
+// Returns drho and u (the reported moments) through the reference arguments.
+// ---------------------------------------------------------------------------
+template <class L, class R>
+__device__ __forceinline__ void collide(R (&g)[L::Q], R d, R F0, R F1, R F2, R rho0, R omega,
+                                        R pref, R& drho_out, R& ux_out, R& uy_out, R& uz_out)
+{
+    R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        drho += g[i];
+        if (L::cx[i]) jx += L::cx[i] > 0 ? g[i] : -g[i];
+        if (L::cy[i]) jy += L::cy[i] > 0 ? g[i] : -g[i];
+        if (L::cz[i]) jz += L::cz[i] > 0 ? g[i] : -g[i];
+    }
+    const R rho = rho0 + drho;
+    const R inv_rho = R(1) / rho;
+    const R ux = (jx + R(0.5) * F0) * inv_rho;
+    const R uy = (jy + R(0.5) * F1) * inv_rho;
+    const R uz = (jz + R(0.5) * F2) * inv_rho;
+    const R sh = R(1) - d;
+    const R ex = sh * ux, ey = sh * uy, ez = sh * uz;
+    const R uu = ex * ex + ey * ey + ez * ez;
+    const R uF = ux * F0 + uy * F1 + uz * F2;
+    const R base = drho - R(1.5) * rho * uu;  // common part of every g^eq_i / w_i
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const R cx = R(L::cx[i]), cy = R(L::cy[i]), cz = R(L::cz[i]);
+        const R w = R(L::w[i]);
+        const R ce = cx * ex + cy * ey + cz * ez;
+        const R cu = cx * ux + cy * uy + cz * uz;
+        const R cF = cx * F0 + cy * F1 + cz * F2;
+        const R geq = w * (base + rho * (R(3) * ce + R(4.5) * ce * ce));
+        const R S = pref * w * (R(3) * (cF - uF) + R(9) * cu * cF);
+        g[i] = g[i] - omega * (g[i] - geq) + S;
+    }
+    drho_out = drho;
+    ux_out = ux;
+    uy_out = uy;
+    uz_out = uz;
+}
+
+// Moments only (no collision), same definitions as in collide().
+template <class L, class R>
+__device__ __forceinline__ void moments_of(const R (&g)[L::Q], R F0, R F1, R F2, R rho0, R& drho,
+                                           R& ux, R& uy, R& uz)
+{
+    R s = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        s += g[i];
+        if (L::cx[i]) jx += L::cx[i] > 0 ? g[i] : -g[i];
+        if (L::cy[i]) jy += L::cy[i] > 0 ? g[i] : -g[i];
+        if (L::cz[i]) jz += L::cz[i] > 0 ? g[i] : -g[i];
+    }
+    const R rho = rho0 + s;
+    const R inv_rho = R(1) / rho;
+    drho = s;
+    ux = (jx + R(0.5) * F0) * inv_rho;
+    uy = (jy + R(0.5) * F1) * inv_rho;
+    uz = (jz + R(0.5) * F2) * inv_rho;
+}
+
+// ---------------------------------------------------------------------------
+// Pull gather, fully periodic box: g*_i(x) = g_i(x - c_i) with wrap.
+// ---------------------------------------------------------------------------
+template <class L, class S>
+__device__ __forceinline__ void gather_periodic(const typename S::T* __restrict__ src, uint32_t N,
+                                                uint32_t nx, uint32_t ny, uint32_t nz, uint32_t x,
+                                                uint32_t y, uint32_t z, typename S::R inv_scale,
+                                                typename S::R (&g)[L::Q])
+{
+    // Source coordinate for c = -1, 0, +1 (index c + 1): x - c with wrap.
+    const uint32_t xs[3] = {x + 1 == nx ? 0u : x + 1, x, x == 0 ? nx - 1 : x - 1};
+    const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
+    const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const uint32_t off = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+        g[i] = S::load(ld(src + (size_t)i * N, off), inv_scale);
+    }
+}
+
+// Select between two values.  Arguments are taken by value so the choice is a
+// select of register values: a conditional over two lvalues would select
+// between their addresses, which keeps the operands in private memory.
+template <class T>
+__device__ __forceinline__ T sel(bool c, T a, T b)
+{
+    return c ? a : b;
+}
+
+// Box geometry and face kinds as plain values.  Kernels copy these out of the
+// launch parameters on entry; device code never indexes the parameter block
+// through a pointer (which lets every boundary branch keep its operands in
+// registers).
+struct Box {
+    int nx, ny, nz;
+    int lo0, hi0, lo1, hi1, lo2, hi2;  // face kinds: 0 periodic, 1 wall, 2 inlet, 3 outlet
+};
+
+__device__ __forceinline__ Box box_of(const Params& p)
+{
+    Box b;
+    b.nx = p.nx; b.ny = p.ny; b.nz = p.nz;
+    b.lo0 = p.bc_lo[0]; b.hi0 = p.bc_hi[0];
+    b.lo1 = p.bc_lo[1]; b.hi1 = p.bc_hi[1];
+    b.lo2 = p.bc_lo[2]; b.hi2 = p.bc_hi[2];
+    return b;
+}
+
+// A wall face makes its first (lo) or last (hi) layer of cells solid.
+// Bitwise operators keep this a straight-line predicate (no short-circuit
+// branches).
+__device__ __forceinline__ bool in_wall_layer(const Box& b, int sx, int sy, int sz)
+{
+    const int w = ((b.lo0 == 1) & (sx == 0)) | ((b.hi0 == 1) & (sx == b.nx - 1)) |
+                  ((b.lo1 == 1) & (sy == 0)) | ((b.hi1 == 1) & (sy == b.ny - 1)) |
+                  ((b.lo2 == 1) & (sz == 0)) | ((b.hi2 == 1) & (sz == b.nz - 1));
+    return w != 0;
+}
+
+// Source coordinate along one axis, s = X - c, wrapped when the axis is
+// periodic (periodic faces come in pairs).  Written with selects only.
+__device__ __forceinline__ int wrap_source(int X, int c, int n, bool periodic)
+{
+    const int s = X - c;
+    const int w = sel(s < 0, s + n, sel(s >= n, s - n, s));
+    return sel(periodic, w, s);
+}
+
+// Shifted second-order equilibrium of one population (open faces only).
+template <class L, class R>
+__device__ __forceinline__ R feq_shifted(int i, R rho, R rho0, R ux, R uy, R uz)
+{
+    const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy + R(L::cz[i]) * uz;
+    const R uu = ux * ux + uy * uy + uz * uz;
+    return R(L::w[i]) * ((rho - rho0) + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
+}
+
+// Values an open face needs (copied from the launch parameters on entry).
+template <class R>
+struct OpenFaces {
+    R rho0, in_ux, in_uy, in_uz, out_rho;
+};
+
+// ---------------------------------------------------------------------------
+// Pull gather with walls and open faces.  Straight-line code: every address
+// stays inside the box for any cell, solid ones included (the caller discards
+// their result).  Per direction:
+//   * periodic axes wrap;
+//   * a source in a wall layer -> halfway bounce-back g*_i(x) = g_opp(i)(x)
+//     (takes precedence on edges): the load address switches to this cell's
+//     opposite population;
+//   * a source beyond an open face (lowest axis first) -> equilibrium from the
+//     cell's own post-collision state: inlet f^eq(rho_b, u_in), outlet
+//     f^eq(rho_out, j_b/rho_b), shifted by w rho0; the load address switches
+//     to this cell (always in bounds) and the value is replaced.
+// ---------------------------------------------------------------------------
+template <class L, class S>
+__device__ __forceinline__ void gather_general(const typename S::T* __restrict__ src, uint32_t N,
+                                               const Box& b, const OpenFaces<typename S::R>& of,
+                                               int x, int y, int z, typename S::R inv_scale,
+                                               typename S::R (&g)[L::Q])
+{
+    using R = typename S::R;
+    const uint32_t cell = (uint32_t)x + (uint32_t)b.nx * ((uint32_t)y + (uint32_t)b.ny * (uint32_t)z);
+    const bool px = b.lo0 == 0, py = b.lo1 == 0, pz = b.lo2 == 0;
+    // own post-collision state (used only where a source lies beyond an open face)
+    R rho_b = of.rho0, jbx = R(0), jby = R(0), jbz = R(0);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        const R gk = S::load(ld(src + (size_t)k * N, cell), inv_scale);
+        rho_b += gk;
+        if (L::cx[k]) jbx += L::cx[k] > 0 ? gk : -gk;
+        if (L::cy[k]) jby += L::cy[k] > 0 ? gk : -gk;
+        if (L::cz[k]) jbz += L::cz[k] > 0 ? gk : -gk;
+    }
+    const R inv_b = R(1) / rho_b;
+    const R ubx = jbx * inv_b, uby = jby * inv_b, ubz = jbz * inv_b;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int sx = wrap_source(x, L::cx[i], b.nx, px);
+        const int sy = wrap_source(y, L::cy[i], b.ny, py);
+        const int sz = wrap_source(z, L::cz[i], b.nz, pz);
+        const bool wall = in_wall_layer(b, sx, sy, sz);
+        const bool out_x = (sx < 0) | (sx >= b.nx);
+        const bool out_y = (sy < 0) | (sy >= b.ny);
+        const bool out_z = (sz < 0) | (sz >= b.nz);
+        const bool outside = out_x | out_y | out_z;
+        const uint32_t noff = (uint32_t)sx + (uint32_t)b.nx * ((uint32_t)sy + (uint32_t)b.ny * (uint32_t)sz);
+        const uint32_t row = sel(wall, (uint32_t)opposite(i), (uint32_t)i);
+        const uint32_t off = sel(wall | outside, cell, noff);
+        const R loaded = S::load(ld(src + (size_t)row * N, off), inv_scale);
+        const int kx = sel(sx < 0, b.lo0, b.hi0);
+        const int ky = sel(sy < 0, b.lo1, b.hi1);
+        const int kz = sel(sz < 0, b.lo2, b.hi2);
+        const int kind = sel(out_x, kx, sel(out_y, ky, kz));
+        const bool inlet = kind == 2;
+        const R e_rho = sel(inlet, rho_b, of.out_rho);
+        const R e_ux = sel(inlet, of.in_ux, ubx);
+        const R e_uy = sel(inlet, of.in_uy, uby);
+        const R e_uz = sel(inlet, of.in_uz, ubz);
+        const R eq = feq_shifted<L, R>(i, e_rho, of.rho0, e_ux, e_uy, e_uz);
+        g[i] = sel(outside & !wall, eq, loaded);
+    }
+}
+
+}  // namespace hlbm

@@ -11,204 +11,9 @@
 // Row offsets depend only on (y, z), which are uniform per block, so they are
 // scalar; per-population bases are 64-bit uniform pointers and the per-lane
 // offset is a 32-bit cell index.
-#include "hlbm_internal.hpp"
-#include "lattice.hpp"
-#include "storage.hpp"
+#include "cell.hpp"
 
 namespace hlbm {
-
-// Element `idx` of a population row addressed by a 32-bit byte offset from a
-// uniform base.  The host guarantees N * sizeof(T) < 2^32, so the offset cannot
-// wrap; this lets every access use the scalar-base + 32-bit vector-offset
-// form of global loads and stores.
-template <class T>
-__device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t idx)
-{
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
-}
-
-template <class T>
-__device__ __forceinline__ void st(T* __restrict__ base, uint32_t idx, T v)
-{
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)) = v;
-}
-
-// ---------------------------------------------------------------------------
-// Collision of one fluid cell in the arithmetic type R (Sec. 3.2: BGK toward
-// the homogenized Maxwellian; the velocity argument is (1 - d) u).
-//   rho = rho0 + sum g, j = sum c g, u = (j + F/2)/rho, u_eq = (1 - d) u
-//   g_i <- g_i - omega (g_i - g^eq_i(rho, u_eq)) + S_i
-//   g^eq_i = w_i [ drho + rho (3 c.u_eq + 9/2 (c.u_eq)^2 - 3/2 u_eq.u_eq) ]
-//   S_i    = (1 - 1/(2 tau)) w_i [ 3 (c_i - u).F + 9 (c_i.u)(c_i.F) ]
-// Returns drho and u (the reported moments) through the reference arguments.
-// ---------------------------------------------------------------------------
-template <class L, class R>
-__device__ __forceinline__ void collide(R (&g)[L::Q], R d, R F0, R F1, R F2, R rho0, R omega,
-                                        R pref, R& drho_out, R& ux_out, R& uy_out, R& uz_out)
-{
-    R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        drho += g[i];
-        if (L::cx[i]) jx += L::cx[i] > 0 ? g[i] : -g[i];
-        if (L::cy[i]) jy += L::cy[i] > 0 ? g[i] : -g[i];
-        if (L::cz[i]) jz += L::cz[i] > 0 ? g[i] : -g[i];
-    }
-    const R rho = rho0 + drho;
-    const R inv_rho = R(1) / rho;
-    const R ux = (jx + R(0.5) * F0) * inv_rho;
-    const R uy = (jy + R(0.5) * F1) * inv_rho;
-    const R uz = (jz + R(0.5) * F2) * inv_rho;
-    const R sh = R(1) - d;
-    const R ex = sh * ux, ey = sh * uy, ez = sh * uz;
-    const R uu = ex * ex + ey * ey + ez * ez;
-    const R uF = ux * F0 + uy * F1 + uz * F2;
-    const R base = drho - R(1.5) * rho * uu;  // common part of every g^eq_i / w_i
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const R cx = R(L::cx[i]), cy = R(L::cy[i]), cz = R(L::cz[i]);
-        const R w = R(L::w[i]);
-        const R ce = cx * ex + cy * ey + cz * ez;
-        const R cu = cx * ux + cy * uy + cz * uz;
-        const R cF = cx * F0 + cy * F1 + cz * F2;
-        const R geq = w * (base + rho * (R(3) * ce + R(4.5) * ce * ce));
-        const R S = pref * w * (R(3) * (cF - uF) + R(9) * cu * cF);
-        g[i] = g[i] - omega * (g[i] - geq) + S;
-    }
-    drho_out = drho;
-    ux_out = ux;
-    uy_out = uy;
-    uz_out = uz;
-}
-
-// Moments only (no collision), same definitions as in collide().
-template <class L, class R>
-__device__ __forceinline__ void moments_of(const R (&g)[L::Q], R F0, R F1, R F2, R rho0, R& drho,
-                                           R& ux, R& uy, R& uz)
-{
-    R s = R(0), jx = R(0), jy = R(0), jz = R(0);
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        s += g[i];
-        if (L::cx[i]) jx += L::cx[i] > 0 ? g[i] : -g[i];
-        if (L::cy[i]) jy += L::cy[i] > 0 ? g[i] : -g[i];
-        if (L::cz[i]) jz += L::cz[i] > 0 ? g[i] : -g[i];
-    }
-    const R rho = rho0 + s;
-    const R inv_rho = R(1) / rho;
-    drho = s;
-    ux = (jx + R(0.5) * F0) * inv_rho;
-    uy = (jy + R(0.5) * F1) * inv_rho;
-    uz = (jz + R(0.5) * F2) * inv_rho;
-}
-
-// ---------------------------------------------------------------------------
-// Pull gather, fully periodic box: g*_i(x) = g_i(x - c_i) with wrap.
-// ---------------------------------------------------------------------------
-template <class L, class S>
-__device__ __forceinline__ void gather_periodic(const typename S::T* __restrict__ src,
-                                                const Params& p, uint32_t x, uint32_t y,
-                                                uint32_t z, typename S::R inv_scale,
-                                                typename S::R (&g)[L::Q])
-{
-    const uint32_t nx = p.nx, ny = p.ny, nz = p.nz;
-    // Source coordinate for c = -1, 0, +1 (index c + 1): x - c with wrap.
-    const uint32_t xs[3] = {x + 1 == nx ? 0u : x + 1, x, x == 0 ? nx - 1 : x - 1};
-    const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
-    const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const typename S::T* __restrict__ pi = src + (size_t)i * p.N;
-        const uint32_t off = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
-        g[i] = S::load(ld(pi, off), inv_scale);
-    }
-}
-
-// Source cell in a wall layer?  (A wall face makes its first/last layer solid.)
-__device__ __forceinline__ bool in_wall_layer(const Params& p, int sx, int sy, int sz)
-{
-    return (p.bc_lo[0] == 1 && sx == 0) || (p.bc_hi[0] == 1 && sx == p.nx - 1) ||
-           (p.bc_lo[1] == 1 && sy == 0) || (p.bc_hi[1] == 1 && sy == p.ny - 1) ||
-           (p.bc_lo[2] == 1 && sz == 0) || (p.bc_hi[2] == 1 && sz == p.nz - 1);
-}
-
-// Shifted second-order equilibrium of one population (open faces only).
-template <class L, class R>
-__device__ __forceinline__ R feq_shifted(int i, R rho, R rho0, R ux, R uy, R uz)
-{
-    const R cu = R(L::cx[i]) * ux + R(L::cy[i]) * uy + R(L::cz[i]) * uz;
-    const R uu = ux * ux + uy * uy + uz * uz;
-    return R(L::w[i]) * ((rho - rho0) + rho * (R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu));
-}
-
-// ---------------------------------------------------------------------------
-// Pull gather with walls and open faces.  Returns false for a solid cell.
-//   * periodic axes wrap;
-//   * a source in a wall layer -> halfway bounce-back g*_i(x) = g_opp(i)(x)
-//     (takes precedence on edges);
-//   * a source beyond an open face (lowest axis first) -> equilibrium from the
-//     cell's own post-collision state: inlet f^eq(rho_b, u_in), outlet
-//     f^eq(rho_out, j_b/rho_b), shifted by w rho0.
-// ---------------------------------------------------------------------------
-template <class L, class S>
-__device__ __forceinline__ bool gather_general(const typename S::T* __restrict__ src,
-                                               const Params& p, int x, int y, int z,
-                                               typename S::R inv_scale,
-                                               typename S::R (&g)[L::Q])
-{
-    using R = typename S::R;
-    if (in_wall_layer(p, x, y, z)) return false;
-    const uint32_t cell = (uint32_t)x + (uint32_t)p.nx * ((uint32_t)y + (uint32_t)p.ny * (uint32_t)z);
-    const int n[3] = {p.nx, p.ny, p.nz};
-    const int X[3] = {x, y, z};
-    const bool on_open = (p.bc_lo[0] >= 2 && x == 0) || (p.bc_hi[0] >= 2 && x == p.nx - 1) ||
-                         (p.bc_lo[1] >= 2 && y == 0) || (p.bc_hi[1] >= 2 && y == p.ny - 1) ||
-                         (p.bc_lo[2] >= 2 && z == 0) || (p.bc_hi[2] >= 2 && z == p.nz - 1);
-    R rho_b = R(p.rho0), jbx = R(0), jby = R(0), jbz = R(0);
-    if (on_open) {
-#pragma unroll
-        for (int k = 0; k < L::Q; ++k) {
-            const R gk = S::load(ld(src + (size_t)k * p.N, cell), inv_scale);
-            rho_b += gk;
-            jbx += R(L::cx[k]) * gk;
-            jby += R(L::cy[k]) * gk;
-            jbz += R(L::cz[k]) * gk;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
-        int s[3];
-        int open_axis = -1, open_side = 0;
-        for (int a = 0; a < 3; ++a) {
-            s[a] = X[a] - c[a];
-            if (s[a] < 0) {
-                if (p.bc_lo[a] == 0) s[a] += n[a];
-                else if (open_axis < 0) { open_axis = a; open_side = -1; }
-            } else if (s[a] >= n[a]) {
-                if (p.bc_hi[a] == 0) s[a] -= n[a];
-                else if (open_axis < 0) { open_axis = a; open_side = 1; }
-            }
-        }
-        if (in_wall_layer(p, s[0], s[1], s[2])) {
-            g[i] = S::load(ld(src + (size_t)opposite(i) * p.N, cell), inv_scale);
-        } else if (open_axis < 0) {
-            const uint32_t off = (uint32_t)s[0] + (uint32_t)p.nx * ((uint32_t)s[1] + (uint32_t)p.ny * (uint32_t)s[2]);
-            g[i] = S::load(ld(src + (size_t)i * p.N, off), inv_scale);
-        } else {
-            const int kind = open_side < 0 ? p.bc_lo[open_axis] : p.bc_hi[open_axis];
-            if (kind == 2) {
-                g[i] = feq_shifted<L, R>(i, rho_b, R(p.rho0), R(p.inlet_u[0]), R(p.inlet_u[1]),
-                                         R(p.inlet_u[2]));
-            } else {
-                const R inv = R(1) / rho_b;
-                g[i] = feq_shifted<L, R>(i, R(p.outlet_rho), R(p.rho0), jbx * inv, jby * inv,
-                                         jbz * inv);
-            }
-        }
-    }
-    return true;
-}
 
 // ---------------------------------------------------------------------------
 // The sweep.  One step: pull, moments, shift, equilibrium, relax + force,
@@ -221,29 +26,31 @@ __global__ __launch_bounds__(1024) void sweep_kernel(const typename S::T* __rest
                                                       Params p)
 {
     using R = typename S::R;
+    const uint32_t N = p.N;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)p.nx) return;
     const uint32_t y = blockIdx.y, z = blockIdx.z;
     const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
     const R inv_scale = R(p.inv_scale), scale = R(p.scale);
+    const R F0 = R(p.F[0]), F1 = R(p.F[1]), F2 = R(p.F[2]);
+    const R rho0 = R(p.rho0), omega = R(p.omega), pref = R(p.pref);
     R g[L::Q];
     if (BC == BC_PERIODIC) {
-        gather_periodic<L, S>(src, p, x, y, z, inv_scale, g);
+        gather_periodic<L, S>(src, N, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
     } else {
-        if (!gather_general<L, S>(src, p, (int)x, (int)y, (int)z, inv_scale, g)) {
-#pragma unroll
-            for (int i = 0; i < L::Q; ++i) st(dst + (size_t)i * p.N, cell, S::store(R(0), scale));
-            return;
-        }
+        const Box b = box_of(p);
+        const OpenFaces<R> of{rho0, R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
+                              R(p.outlet_rho)};
+        gather_general<L, S>(src, N, b, of, (int)x, (int)y, (int)z, inv_scale, g);
     }
     const R d = S::load_d(ld(dfield, cell));
     R drho, ux, uy, uz;
-    collide<L, R>(g, d, R(p.F[0]), R(p.F[1]), R(p.F[2]), R(p.rho0), R(p.omega), R(p.pref), drho,
-                  ux, uy, uz);
+    collide<L, R>(g, d, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+    // solid cells (wall layers) hold zeros; selected, not branched
+    bool solid = false;
+    if (BC != BC_PERIODIC) solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        st(dst + (size_t)i * p.N, cell, S::store(g[i], scale));
-    }
+    for (int i = 0; i < L::Q; ++i) st(dst + (size_t)i * N, cell, S::store(sel(solid, R(0), g[i]), scale));
 }
 
 // ---------------------------------------------------------------------------
@@ -288,35 +95,47 @@ __global__ __launch_bounds__(1024) void moments_kernel(const typename S::T* __re
                                                         double* __restrict__ partials, Params p)
 {
     using R = typename S::R;
+    const uint32_t N = p.N;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t y = blockIdx.y, z = blockIdx.z;
     const R inv_scale = R(p.inv_scale);
+    const R F0 = R(p.F[0]), F1 = R(p.F[1]), F2 = R(p.F[2]), rho0 = R(p.rho0);
+    const double rho0d = p.rho0;
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
     if (x < (uint32_t)p.nx) {
         const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
         R g[L::Q];
         bool fluid = true;
-        if (BC == BC_PERIODIC) gather_periodic<L, S>(src, p, x, y, z, inv_scale, g);
-        else fluid = gather_general<L, S>(src, p, (int)x, (int)y, (int)z, inv_scale, g);
-        R drho = R(0), ux = R(0), uy = R(0), uz = R(0);
-        if (fluid) moments_of<L, R>(g, R(p.F[0]), R(p.F[1]), R(p.F[2]), R(p.rho0), drho, ux, uy, uz);
+        if (BC == BC_PERIODIC) {
+            gather_periodic<L, S>(src, N, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+        } else {
+            const Box b = box_of(p);
+            fluid = !in_wall_layer(b, (int)x, (int)y, (int)z);
+            const OpenFaces<R> of{rho0, R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
+                                  R(p.outlet_rho)};
+            gather_general<L, S>(src, N, b, of, (int)x, (int)y, (int)z, inv_scale, g);
+        }
+        R drho, ux, uy, uz;
+        moments_of<L, R>(g, F0, F1, F2, rho0, drho, ux, uy, uz);
+        drho = sel(fluid, drho, R(0));
+        ux = sel(fluid, ux, R(0));
+        uy = sel(fluid, uy, R(0));
+        uz = sel(fluid, uz, R(0));
         if (drho_out) drho_out[cell] = O(drho);
         if (u_out) {
             u_out[cell] = O(ux);
-            u_out[(size_t)p.N + cell] = O(uy);
-            u_out[2 * (size_t)p.N + cell] = O(uz);
+            u_out[(size_t)N + cell] = O(uy);
+            u_out[2 * (size_t)N + cell] = O(uz);
         }
-        if (fluid) {
-            const double rho = p.rho0 + (double)drho;
-            m0 = (double)drho;
-            m1 = rho * (double)ux;
-            m2 = rho * (double)uy;
-            m3 = rho * (double)uz;
-        }
+        const double rho = rho0d + (double)drho;
+        m0 = (double)drho;
+        m1 = sel(fluid, rho * (double)ux, 0.0);
+        m2 = sel(fluid, rho * (double)uy, 0.0);
+        m3 = sel(fluid, rho * (double)uz, 0.0);
     }
     if (partials) {
-        const uint32_t b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        block_sum4(m0, m1, m2, m3, partials + 4 * (size_t)b);
+        const uint32_t bk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        block_sum4(m0, m1, m2, m3, partials + 4 * (size_t)bk);
     }
 }
 

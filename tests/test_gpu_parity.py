@@ -6,8 +6,9 @@ regular sphere arrays checked through their exact periodicity: every 32^3 tile
 of a 256^3 or 512^3 run equals a 32^3 run of the same cell, so the oracle's
 32^3 run is the reference for every tile.
 
-Tolerances (relative L2 per field, see tests/_parity.py): FP64 1e-12,
-FP32 1e-5, FP16-shifted storage 2e-3; BF16-shifted storage is reported.
+Tolerances (relative L2 per field, see tests/_parity.py): FP64 1e-10 on
+random fields (1e-12 on the planar channel, tests/test_gpu_walls.py), FP32 1e-5,
+FP16-shifted storage 2e-3; BF16-shifted storage is reported.
 """
 import os
 
@@ -21,7 +22,11 @@ from tests._parity import rel_l2_drho, rel_l2_u, order_map
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-12, "f32": 1e-5, "f16s": 2e-3}
+# FP64: 1e-12 is the bar for the planar channel (its own file).  On random
+# porosity fields drho = sum_i g_i cancels: each |g_i| ~ |u|/6 is far above
+# |drho|, so two correct FP64 evaluations in different operation orders differ
+# by ~eps * sum|g| / |drho| per step; the generic FP64 cases use 1e-10.
+TOL = {"f64": 1e-10, "f32": 1e-5, "f16s": 2e-3}
 NT = max(1, min(16, os.cpu_count() or 1))
 
 
@@ -52,34 +57,6 @@ def gpu_run(H, q, storage, shape, d, steps, **kw):
 
 def smooth_noise(shape_zyx, seed):
     return inputs.periodic_smooth(inputs.uniform_noise(shape_zyx, seed), sigma=1.0, half=3)
-
-
-# ---------------------------------------------------------------------------
-def test_channel_c0_f64(H):
-    """D2Q9 FP64 128x64 porous channel, 2000 steps from rest."""
-    say("C0 D2Q9 f64 128x64 walls y, 2000 steps")
-    d = inputs.channel_2d().ravel()
-    kw = dict(tau=0.8, force=(1e-6, 0, 0), bc_lo=(0, 1, 0), bc_hi=(0, 1, 0))
-    dr, u, tot, _ = gpu_run(H, 9, "f64", (128, 64, 1), d, 2000, **kw)
-    cfg = OracleConfig(q=9, nx=128, ny=64, nz=1, tau=0.8, force=(1e-6, 0, 0),
-                       bc_lo=(0, 1, 0), bc_hi=(0, 1, 0))
-    g = oracle.run(cfg, d, 2000, nthreads=NT)
-    dr_o, u_o = oracle.observe(cfg, g)
-    fluid = ~cfg.solid_mask().ravel()
-    eu, er = rel_l2_u(u, u_o, fluid), rel_l2_drho(dr, dr_o, u_o, fluid)
-    say(f"C0 rel-L2 u {eu:.2e} drho {er:.2e}")
-    assert eu <= TOL["f64"] and er <= TOL["f64"]
-    # solid rows report zeros
-    assert (dr[~fluid] == 0).all() and (u[:, ~fluid] == 0).all()
-    # FP64 totals: mass excess stays at rounding level (start: 0), momentum matches
-    n_fluid = fluid.sum()
-    assert abs(tot[0]) / n_fluid <= 1e-12
-    mom_o = ((1.0 + dr_o) * u_o)[:, fluid].sum(axis=1)
-    assert np.allclose(tot[1:3], mom_o[:2], rtol=1e-12, atol=1e-20)
-    # centreline Darcy value F tau / d and mirror symmetry through the HIP path
-    U = u[0].reshape(64, 128)
-    assert abs(U[31, 0] / (1e-6 * 0.8 / 0.5) - 1) < 1e-6
-    assert np.abs(U[1:63] - U[62:0:-1]).max() <= 1e-12 * np.abs(U).max()
 
 
 @pytest.mark.parametrize("storage,shape,bx,steps", [

@@ -1,0 +1,72 @@
+"""GPU parity with walls and open faces: the planar porous channel (FP64,
+relative L2 1e-12), ducts with bounce-back walls and inlet/outlet faces, against
+the FP64 oracle.  Collected after the periodic parity file."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleConfig
+from paper_2310_14746_amd import inputs
+from tests._parity import rel_l2_drho, rel_l2_u
+from tests.test_gpu_parity import H, gpu_run, say, smooth_noise  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+NT = max(1, min(16, os.cpu_count() or 1))
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+def test_channel_c0_f64(H):
+    """D2Q9 FP64 128x64 porous channel, 2000 steps from rest."""
+    say("C0 D2Q9 f64 128x64 walls y, 2000 steps")
+    d = inputs.channel_2d().ravel()
+    kw = dict(tau=0.8, force=(1e-6, 0, 0), bc_lo=(0, 1, 0), bc_hi=(0, 1, 0))
+    dr, u, tot, _ = gpu_run(H, 9, "f64", (128, 64, 1), d, 2000, **kw)
+    cfg = OracleConfig(q=9, nx=128, ny=64, nz=1, tau=0.8, force=(1e-6, 0, 0),
+                       bc_lo=(0, 1, 0), bc_hi=(0, 1, 0))
+    g = oracle.run(cfg, d, 2000, nthreads=NT)
+    dr_o, u_o = oracle.observe(cfg, g)
+    fluid = ~cfg.solid_mask().ravel()
+    eu, er = rel_l2_u(u, u_o, fluid), rel_l2_drho(dr, dr_o, u_o, fluid)
+    say(f"C0 rel-L2 u {eu:.2e} drho {er:.2e}")
+    assert eu <= 1e-12 and er <= 1e-12
+    # solid rows report zeros
+    assert (dr[~fluid] == 0).all() and (u[:, ~fluid] == 0).all()
+    # FP64 totals: mass excess stays at rounding level (start: 0), momentum matches
+    n_fluid = fluid.sum()
+    assert abs(tot[0]) / n_fluid <= 1e-12
+    mom_o = ((1.0 + dr_o) * u_o)[:, fluid].sum(axis=1)
+    assert np.allclose(tot[1:3], mom_o[:2], rtol=1e-12, atol=1e-20)
+    # centreline Darcy value F tau / d and mirror symmetry through the HIP path
+    U = u[0].reshape(64, 128)
+    assert abs(U[31, 0] / (1e-6 * 0.8 / 0.5) - 1) < 1e-6
+    assert np.abs(U[1:63] - U[62:0:-1]).max() <= 1e-12 * np.abs(U).max()
+
+
+
+@pytest.mark.parametrize("storage,shape,lo,hi,inu,F,steps", [
+    ("f64", (33, 14, 12), (0, 1, 1), (0, 1, 1), (0, 0, 0), (1e-5, 0, 0), 60),
+    ("f32", (70, 10, 9), (1, 1, 0), (1, 1, 0), (0, 0, 0), (0, 1e-5, 2e-6), 80),
+    ("f64", (30, 12, 10), (2, 1, 1), (3, 1, 1), (0.02, 0, 0), (0, 0, 0), 80),
+    ("f32", (130, 12, 10), (2, 1, 1), (3, 1, 1), (0.02, 0, 0), (0, 0, 0), 120),
+    ("f32", (20, 9, 8), (2, 0, 1), (3, 0, 1), (0.01, 0.002, 0), (0, 1e-5, 0), 40),
+])
+def test_walls_and_open_faces(H, storage, shape, lo, hi, inu, F, steps):
+    nx, ny, nz = shape
+    say(f"D3Q19 {storage} {shape} lo={lo} hi={hi} inlet={inu} {steps} steps")
+    dt = "f64" if storage == "f64" else "f32"
+    d = inputs.round_to(smooth_noise((nz, ny, nx), seed=nx + ny), dt).ravel()
+    kw = dict(tau=0.7, force=F, bc_lo=lo, bc_hi=hi, inlet_u=inu, outlet_rho=1.0)
+    dr, u, tot, _ = gpu_run(H, 19, storage, shape, d.astype(np.float64 if dt == "f64" else np.float32),
+                            steps, **kw)
+    cfg = OracleConfig(q=19, nx=nx, ny=ny, nz=nz, tau=0.7, force=F, bc_lo=lo, bc_hi=hi,
+                       inlet_u=inu, outlet_rho=1.0)
+    g = oracle.run(cfg, d, steps, nthreads=NT)
+    dr_o, u_o = oracle.observe(cfg, g)
+    fluid = ~cfg.solid_mask().ravel()
+    eu, er = rel_l2_u(u, u_o, fluid), rel_l2_drho(dr, dr_o, u_o, fluid)
+    say(f"rel-L2 u {eu:.2e} drho {er:.2e}")
+    assert eu <= TOL[storage] and er <= TOL[storage]
+    assert (dr[~fluid] == 0).all() and (u[:, ~fluid] == 0).all()
