@@ -36,4 +36,18 @@ struct D3Q19 {
 
 __host__ __device__ constexpr int opposite(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
+// Index of the axis velocity +e_a (sign > 0) or -e_a (sign < 0) in lattice L.
+template <class L>
+__host__ __device__ constexpr int axis_velocity(int a, int sign)
+{
+    for (int i = 1; i < L::Q; ++i) {
+        const int c[3] = {L::cx[i], L::cy[i], L::cz[i]};
+        bool ok = c[a] == sign;
+        for (int b = 0; b < 3; ++b)
+            if (b != a && c[b] != 0) ok = false;
+        if (ok) return i;
+    }
+    return -1;
+}
+
 }  // namespace hlbm
