@@ -44,3 +44,20 @@ def order_map(c_from, c_to):
         k = int(np.nonzero((c_to == ci).all(axis=1))[0][0])
         perm.append(k)
     return np.array(perm)
+
+
+def quantization_floor(pre, c, scale, mantissa_bits, min_exp=None):
+    """Relative-L2 floor that storing the pulled populations `pre[q, N]` in a
+    binary float format with `mantissa_bits` explicit bits (scaled by `scale`)
+    puts on one read of drho and of u: RMS of the sum of per-population
+    round-to-nearest errors (variance ulp^2/12 each), over the field norm.
+    Returns (floor_drho_abs_norm, floor_u_abs_norm) as L2 norms."""
+    v = np.abs(np.asarray(pre, dtype=np.float64) * scale)
+    e = np.floor(np.log2(np.maximum(v, 1e-300)))
+    if min_exp is not None:
+        e = np.maximum(e, min_exp)
+    ulp = np.where(v > 0, 2.0 ** (e - mantissa_bits), 0.0) / scale
+    var = ulp ** 2 / 12.0
+    f_rho = np.sqrt(var.sum())
+    f_u = np.sqrt(sum((c[:, a:a + 1] ** 2 * var).sum() for a in range(3)))
+    return f_rho, f_u
