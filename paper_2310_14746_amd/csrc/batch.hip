@@ -1,0 +1,340 @@
+// Batched sweep: many independent periodic boxes (porous unit cells of uneven
+// sizes, each with its own tau and force) advanced together by one persistent
+// kernel that runs every step of a call, with a grid-wide barrier between
+// steps.
+//
+// Layout: the items' cells are packed one after another, x fastest inside an
+// item, and each population row spans all items: buf[i*Ntot + base_k + local].
+// The packed cells are cut into tiles of TILE consecutive cells that never
+// straddle two items (a tile's tail past the item's end is masked).  Block b
+// owns the contiguous tile range [b*T/G, (b+1)*T/G): neighbouring rows of one
+// item stay in the same block, hence in the same CU's L1 and XCD's L2.
+//
+// The grid is sized to the number of blocks that can be resident at once.
+// The barrier waits with a bounded spin; if the bound is exceeded (a block was
+// never scheduled) or another block reported an error, every block leaves the
+// kernel at its next barrier and the host sees the error flag, so the kernel
+// always ends.
+#include "cell.hpp"
+
+namespace hlbm {
+
+// Quotient of l by d via a 32-bit multiply-high, exact for l * d < 2^32
+// (checked on the host for every item).
+__device__ __forceinline__ uint32_t div_magic(uint32_t l, uint32_t magic) { return __umulhi(l, magic); }
+
+__device__ __forceinline__ bool grid_barrier(unsigned* __restrict__ counter, unsigned target,
+                                             int* __restrict__ err, unsigned spin_limit)
+{
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(counter, 1u);
+        int good = 1;
+        unsigned spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                good = 0;
+                break;
+            }
+            if (++spins > spin_limit) {
+                atomicOr(err, 1);
+                good = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+__global__ void batch_reset_kernel(unsigned* counter, int* err)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *counter = 0u;
+        *err = 0;
+    }
+}
+
+// One cell of one item: periodic pull inside the item's box, collision,
+// store.  `l` is the cell's index inside the item.
+template <class S>
+__device__ __forceinline__ void batch_cell(const typename S::T* __restrict__ src,
+                                           typename S::T* __restrict__ dst,
+                                           const typename S::D* __restrict__ dfield, uint32_t Ntot,
+                                           const BatchItem& it, uint32_t l, typename S::R rho0,
+                                           typename S::R scale, typename S::R inv_scale)
+{
+    using R = typename S::R;
+    using L = D3Q19;
+    const uint32_t t = div_magic(l, it.mx);
+    const uint32_t x = l - t * it.nx;
+    const uint32_t z = div_magic(t, it.my);
+    const uint32_t y = t - z * it.ny;
+    R g[L::Q];
+    gather_periodic<L, S>(src, Ntot, it.base, it.nx, it.ny, it.nz, x, y, z, inv_scale, g);
+    const uint32_t cell = it.base + l;
+    const R d = S::load_d(ld(dfield, cell));
+    R drho, ux, uy, uz;
+    collide<L, R>(g, d, R(it.F[0]), R(it.F[1]), R(it.F[2]), rho0, R(it.omega), R(it.pref), drho, ux,
+                  uy, uz);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) st(dst + (size_t)i * Ntot, cell, S::store(g[i], scale));
+}
+
+template <class S>
+__global__ __launch_bounds__(TILE) void batch_persistent_kernel(
+    typename S::T* __restrict__ buf_a, typename S::T* __restrict__ buf_b,
+    const typename S::D* __restrict__ dfield, const BatchItem* __restrict__ items,
+    const uint32_t* __restrict__ tile_item, uint32_t ntiles, uint32_t Ntot, int nsteps,
+    int start_in_b, double rho0_d, double scale_d, unsigned* __restrict__ counter,
+    int* __restrict__ err, unsigned spin_limit)
+{
+    using R = typename S::R;
+    const R rho0 = R(rho0_d), scale = R(scale_d), inv_scale = R(1.0 / scale_d);
+    const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint32_t t_begin = blockIdx.x * per;
+    const uint32_t t_end = min(ntiles, t_begin + per);
+    for (int s = 0; s < nsteps; ++s) {
+        const bool from_b = ((s + start_in_b) & 1) != 0;
+        const typename S::T* __restrict__ src = from_b ? buf_b : buf_a;
+        typename S::T* __restrict__ dst = from_b ? buf_a : buf_b;
+        for (uint32_t t = t_begin; t < t_end; ++t) {
+            const BatchItem it = items[tile_item[t]];
+            const uint32_t l = (t - it.tile0) * TILE + threadIdx.x;
+            if (l < it.cells) batch_cell<S>(src, dst, dfield, Ntot, it, l, rho0, scale, inv_scale);
+        }
+        if (s + 1 < nsteps && !grid_barrier(counter, (unsigned)(s + 1) * gridDim.x, err, spin_limit))
+            return;
+    }
+}
+
+// One launch per step over all tiles (no barrier); used for the non-persistent
+// form and as the reference the persistent form must match bit for bit.
+template <class S>
+__global__ __launch_bounds__(TILE) void batch_step_kernel(
+    const typename S::T* __restrict__ src, typename S::T* __restrict__ dst,
+    const typename S::D* __restrict__ dfield, const BatchItem* __restrict__ items,
+    const uint32_t* __restrict__ tile_item, uint32_t Ntot, double rho0_d, double scale_d)
+{
+    using R = typename S::R;
+    const uint32_t t = blockIdx.x;
+    const BatchItem it = items[tile_item[t]];
+    const uint32_t l = (t - it.tile0) * TILE + threadIdx.x;
+    if (l < it.cells)
+        batch_cell<S>(src, dst, dfield, Ntot, it, l, R(rho0_d), R(scale_d), R(1.0 / scale_d));
+}
+
+// Moments of every item at the current time level: one block per tile writes
+// FP64 partials (sum drho, sum rho u); optionally the fields of one item.
+template <class S>
+__global__ __launch_bounds__(TILE) void batch_moments_kernel(
+    const typename S::T* __restrict__ src, const BatchItem* __restrict__ items,
+    const uint32_t* __restrict__ tile_item, uint32_t Ntot, double rho0_d, double scale_d,
+    double* __restrict__ partials, int sel_item, double* __restrict__ drho_out,
+    double* __restrict__ u_out)
+{
+    using R = typename S::R;
+    using L = D3Q19;
+    const uint32_t t = blockIdx.x;
+    const uint32_t k = tile_item[t];
+    const BatchItem it = items[k];
+    const uint32_t l = (t - it.tile0) * TILE + threadIdx.x;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    if (l < it.cells) {
+        const uint32_t q = div_magic(l, it.mx);
+        const uint32_t x = l - q * it.nx;
+        const uint32_t z = div_magic(q, it.my);
+        const uint32_t y = q - z * it.ny;
+        R g[L::Q];
+        gather_periodic<L, S>(src, Ntot, it.base, it.nx, it.ny, it.nz, x, y, z, R(1.0 / scale_d), g);
+        R drho, ux, uy, uz;
+        moments_of<L, R>(g, R(it.F[0]), R(it.F[1]), R(it.F[2]), R(rho0_d), drho, ux, uy, uz);
+        const double rho = rho0_d + (double)drho;
+        m0 = (double)drho;
+        m1 = rho * (double)ux;
+        m2 = rho * (double)uy;
+        m3 = rho * (double)uz;
+        if ((int)k == sel_item && drho_out) {
+            drho_out[l] = (double)drho;
+            u_out[l] = (double)ux;
+            u_out[(size_t)it.cells + l] = (double)uy;
+            u_out[2 * (size_t)it.cells + l] = (double)uz;
+        }
+    }
+    block_sum4(m0, m1, m2, m3, partials + 4 * (size_t)t);
+}
+
+// Per-item totals: block k sums the partials of item k's tiles in order.
+__global__ __launch_bounds__(256) void batch_item_reduce_kernel(const double* __restrict__ partials,
+                                                                const BatchItem* __restrict__ items,
+                                                                double* __restrict__ totals)
+{
+    const BatchItem it = items[blockIdx.x];
+    const uint32_t nt = (it.cells + TILE - 1) / TILE;
+    double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+    for (uint32_t j = threadIdx.x; j < nt; j += blockDim.x) {
+        const double* p = partials + 4 * (size_t)(it.tile0 + j);
+        a += p[0];
+        b += p[1];
+        c += p[2];
+        d += p[3];
+    }
+    block_sum4(a, b, c, d, totals + 4 * (size_t)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <class S>
+static hipError_t persistent_dispatch(const BatchLaunch& b, void* buf_a, void* buf_b, const void* dfield,
+                                      int nsteps, int start_in_b, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b.counter, b.err);
+    hipLaunchKernelGGL((batch_persistent_kernel<S>), dim3(b.grid), dim3(TILE), 0, s,
+                       static_cast<typename S::T*>(buf_a), static_cast<typename S::T*>(buf_b),
+                       static_cast<const typename S::D*>(dfield), b.items, b.tile_item, b.ntiles,
+                       b.Ntot, nsteps, start_in_b, b.rho0, b.scale, b.counter, b.err, b.spin_limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_persistent(int storage, const BatchLaunch& b, void* buf_a, void* buf_b,
+                                   const void* dfield, int nsteps, int start_in_b, hipStream_t s)
+{
+    switch (storage) {
+    case StoreF32::code: return persistent_dispatch<StoreF32>(b, buf_a, buf_b, dfield, nsteps, start_in_b, s);
+    case StoreF16S::code: return persistent_dispatch<StoreF16S>(b, buf_a, buf_b, dfield, nsteps, start_in_b, s);
+    case StoreBF16S::code: return persistent_dispatch<StoreBF16S>(b, buf_a, buf_b, dfield, nsteps, start_in_b, s);
+    case StoreF64::code: return persistent_dispatch<StoreF64>(b, buf_a, buf_b, dfield, nsteps, start_in_b, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class S>
+static hipError_t step_dispatch(const BatchLaunch& b, const void* src, void* dst, const void* dfield,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_step_kernel<S>), dim3(b.ntiles), dim3(TILE), 0, s,
+                       static_cast<const typename S::T*>(src), static_cast<typename S::T*>(dst),
+                       static_cast<const typename S::D*>(dfield), b.items, b.tile_item, b.Ntot,
+                       b.rho0, b.scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_step(int storage, const BatchLaunch& b, const void* src, void* dst,
+                             const void* dfield, hipStream_t s)
+{
+    switch (storage) {
+    case StoreF32::code: return step_dispatch<StoreF32>(b, src, dst, dfield, s);
+    case StoreF16S::code: return step_dispatch<StoreF16S>(b, src, dst, dfield, s);
+    case StoreBF16S::code: return step_dispatch<StoreBF16S>(b, src, dst, dfield, s);
+    case StoreF64::code: return step_dispatch<StoreF64>(b, src, dst, dfield, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class S>
+static hipError_t moments_dispatch(const BatchLaunch& b, const void* src, double* partials,
+                                   int sel_item, double* drho, double* u, double* totals,
+                                   hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_moments_kernel<S>), dim3(b.ntiles), dim3(TILE), 0, s,
+                       static_cast<const typename S::T*>(src), b.items, b.tile_item, b.Ntot, b.rho0,
+                       b.scale, partials, sel_item, drho, u);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_item_reduce_kernel, dim3(b.n_items), dim3(256), 0, s, partials, b.items,
+                       totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_moments(int storage, const BatchLaunch& b, const void* src, double* partials,
+                                int sel_item, double* drho, double* u, double* totals, hipStream_t s)
+{
+    switch (storage) {
+    case StoreF32::code: return moments_dispatch<StoreF32>(b, src, partials, sel_item, drho, u, totals, s);
+    case StoreF16S::code: return moments_dispatch<StoreF16S>(b, src, partials, sel_item, drho, u, totals, s);
+    case StoreBF16S::code: return moments_dispatch<StoreBF16S>(b, src, partials, sel_item, drho, u, totals, s);
+    case StoreF64::code: return moments_dispatch<StoreF64>(b, src, partials, sel_item, drho, u, totals, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// An executable graph of two kernel nodes (barrier reset, then the persistent
+// kernel for `nsteps` steps), built from explicit nodes so that it can be
+// launched on any stream, the legacy default stream included.  No memset
+// nodes: the reset is a kernel.
+template <class S>
+static hipError_t graph_dispatch(const BatchLaunch& b, void* buf_a, void* buf_b, const void* dfield,
+                                 int nsteps, int start_in_b, hipGraphExec_t* out)
+{
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    unsigned* counter = b.counter;
+    int* err = b.err;
+    void* reset_args[] = {&counter, &err};
+    hipKernelNodeParams rp = {};
+    rp.func = reinterpret_cast<void*>(batch_reset_kernel);
+    rp.gridDim = dim3(1);
+    rp.blockDim = dim3(64);
+    rp.sharedMemBytes = 0;
+    rp.kernelParams = reset_args;
+    rp.extra = nullptr;
+    hipGraphNode_t n_reset = nullptr, n_run = nullptr;
+    e = hipGraphAddKernelNode(&n_reset, g, nullptr, 0, &rp);
+    auto* pa = static_cast<typename S::T*>(buf_a);
+    auto* pb = static_cast<typename S::T*>(buf_b);
+    auto* pd = static_cast<const typename S::D*>(dfield);
+    const BatchItem* items = b.items;
+    const uint32_t* tile_item = b.tile_item;
+    uint32_t ntiles = b.ntiles, Ntot = b.Ntot;
+    double rho0 = b.rho0, scale = b.scale;
+    unsigned spin = b.spin_limit;
+    void* run_args[] = {&pa, &pb, &pd, &items, &tile_item, &ntiles, &Ntot, &nsteps,
+                        &start_in_b, &rho0, &scale, &counter, &err, &spin};
+    hipKernelNodeParams kp = {};
+    kp.func = reinterpret_cast<void*>(batch_persistent_kernel<S>);
+    kp.gridDim = dim3(b.grid);
+    kp.blockDim = dim3(TILE);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = run_args;
+    kp.extra = nullptr;
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&n_run, g, &n_reset, 1, &kp);
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
+}
+
+hipError_t build_batch_graph(int storage, const BatchLaunch& b, void* buf_a, void* buf_b,
+                             const void* dfield, int nsteps, int start_in_b, hipGraphExec_t* out)
+{
+    switch (storage) {
+    case StoreF32::code: return graph_dispatch<StoreF32>(b, buf_a, buf_b, dfield, nsteps, start_in_b, out);
+    case StoreF16S::code: return graph_dispatch<StoreF16S>(b, buf_a, buf_b, dfield, nsteps, start_in_b, out);
+    case StoreBF16S::code: return graph_dispatch<StoreBF16S>(b, buf_a, buf_b, dfield, nsteps, start_in_b, out);
+    case StoreF64::code: return graph_dispatch<StoreF64>(b, buf_a, buf_b, dfield, nsteps, start_in_b, out);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_occupancy(int storage, int* blocks_per_cu)
+{
+    switch (storage) {
+    case StoreF32::code:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF32>, TILE, 0);
+    case StoreF16S::code:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF16S>, TILE, 0);
+    case StoreBF16S::code:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreBF16S>, TILE, 0);
+    case StoreF64::code:
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF64>, TILE, 0);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hlbm

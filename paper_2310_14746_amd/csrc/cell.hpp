@@ -135,13 +135,14 @@ __device__ __forceinline__ void moments_of(const R (&g)[L::Q], R F0, R F1, R F2,
 }
 
 // ---------------------------------------------------------------------------
-// Pull gather, fully periodic box: g*_i(x) = g_i(x - c_i) with wrap.
+// Pull gather, fully periodic box: g*_i(x) = g_i(x - c_i) with wrap.  The box
+// starts at cell `base` of the population rows (0 for a single lattice).
 // ---------------------------------------------------------------------------
 template <class L, class S>
 __device__ __forceinline__ void gather_periodic(const typename S::T* __restrict__ src, uint32_t N,
-                                                uint32_t nx, uint32_t ny, uint32_t nz, uint32_t x,
-                                                uint32_t y, uint32_t z, typename S::R inv_scale,
-                                                typename S::R (&g)[L::Q])
+                                                uint32_t base, uint32_t nx, uint32_t ny, uint32_t nz,
+                                                uint32_t x, uint32_t y, uint32_t z,
+                                                typename S::R inv_scale, typename S::R (&g)[L::Q])
 {
     // Source coordinate for c = -1, 0, +1 (index c + 1): x - c with wrap.
     const uint32_t xs[3] = {x + 1 == nx ? 0u : x + 1, x, x == 0 ? nx - 1 : x - 1};
@@ -149,7 +150,7 @@ __device__ __forceinline__ void gather_periodic(const typename S::T* __restrict_
     const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const uint32_t off = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+        const uint32_t off = base + xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
         g[i] = S::load(ld(src + (size_t)i * N, off), inv_scale);
     }
 }
@@ -276,6 +277,40 @@ __device__ __forceinline__ void gather_general(const typename S::T* __restrict__
         const R e_uz = sel(inlet, of.in_uz, ubz);
         const R eq = feq_shifted<L, R>(i, e_rho, of.rho0, e_ux, e_uy, e_uz);
         g[i] = sel(outside & !wall, eq, loaded);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 block reduction of 4 values (wavefront shuffle, then across waves in
+// LDS).  Thread 0 writes the block's partials.  Fixed order -> deterministic.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ void block_sum4(double a, double b, double c, double d, double* out)
+{
+    __shared__ double red[16][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    d = wave_sum(d);
+    if (lane == 0) {
+        red[wid][0] = a;
+        red[wid][1] = b;
+        red[wid][2] = c;
+        red[wid][3] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int nw = (blockDim.x + 63) >> 6;
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
     }
 }
 

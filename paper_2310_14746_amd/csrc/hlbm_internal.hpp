@@ -43,4 +43,42 @@ hipError_t launch_reduce4(const double* partials, uint32_t nblocks, double* out,
 hipError_t launch_porosity_convert(int in_dtype, const void* in, int storage, void* out,
                                    uint32_t n, int* block_flags, int* flag_out, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Batched periodic boxes
+// ---------------------------------------------------------------------------
+constexpr int TILE = 256;  // cells per tile (one block of the batched kernels)
+
+// One item of a batch, as read by the kernels.
+struct BatchItem {
+    uint32_t base;    // first cell of the item in the packed arrays
+    uint32_t cells;   // nx*ny*nz
+    uint32_t tile0;   // first tile of the item
+    uint32_t nx, ny, nz;
+    uint32_t mx, my;  // ceil(2^32/nx), ceil(2^32/ny): quotients by multiply-high
+    double omega, pref;
+    double F[3];
+};
+
+// Everything a batched launch needs besides the population buffers.
+struct BatchLaunch {
+    const BatchItem* items;     // device, n_items
+    const uint32_t* tile_item;  // device, ntiles
+    uint32_t n_items, ntiles, Ntot;
+    double rho0, scale;
+    unsigned* counter;          // device barrier counter
+    int* err;                   // device error flag
+    unsigned spin_limit;
+    int grid;                   // resident blocks of the persistent kernel
+};
+
+hipError_t launch_batch_persistent(int storage, const BatchLaunch& b, void* buf_a, void* buf_b,
+                                   const void* dfield, int nsteps, int start_in_b, hipStream_t s);
+hipError_t launch_batch_step(int storage, const BatchLaunch& b, const void* src, void* dst,
+                             const void* dfield, hipStream_t s);
+hipError_t launch_batch_moments(int storage, const BatchLaunch& b, const void* src, double* partials,
+                                int sel_item, double* drho, double* u, double* totals, hipStream_t s);
+hipError_t batch_occupancy(int storage, int* blocks_per_cu);
+hipError_t build_batch_graph(int storage, const BatchLaunch& b, void* buf_a, void* buf_b,
+                             const void* dfield, int nsteps, int start_in_b, hipGraphExec_t* out);
+
 }  // namespace hlbm

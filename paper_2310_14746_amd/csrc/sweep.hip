@@ -36,7 +36,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(const typename S::T* __rest
     const R rho0 = R(p.rho0), omega = R(p.omega), pref = R(p.pref);
     R g[L::Q];
     if (BC == BC_PERIODIC) {
-        gather_periodic<L, S>(src, N, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+        gather_periodic<L, S>(src, N, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
     } else {
         const Box b = box_of(p);
         const OpenFaces<R> of{rho0, R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
@@ -51,40 +51,6 @@ __global__ __launch_bounds__(1024) void sweep_kernel(const typename S::T* __rest
     if (BC != BC_PERIODIC) solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) st(dst + (size_t)i * N, cell, S::store(sel(solid, R(0), g[i]), scale));
-}
-
-// ---------------------------------------------------------------------------
-// FP64 block reduction of 4 values (wavefront shuffle, then across waves in
-// LDS).  Thread 0 writes the block's partials.  Fixed order -> deterministic.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    return v;
-}
-
-__device__ void block_sum4(double a, double b, double c, double d, double* out)
-{
-    __shared__ double red[16][4];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    a = wave_sum(a);
-    b = wave_sum(b);
-    c = wave_sum(c);
-    d = wave_sum(d);
-    if (lane == 0) {
-        red[wid][0] = a;
-        red[wid][1] = b;
-        red[wid][2] = c;
-        red[wid][3] = d;
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        const int nw = (blockDim.x + 63) >> 6;
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
-        out[threadIdx.x] = s;
-    }
 }
 
 // Moments at the current time level (gather + moments, no collision).
@@ -107,7 +73,7 @@ __global__ __launch_bounds__(1024) void moments_kernel(const typename S::T* __re
         R g[L::Q];
         bool fluid = true;
         if (BC == BC_PERIODIC) {
-            gather_periodic<L, S>(src, N, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+            gather_periodic<L, S>(src, N, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
         } else {
             const Box b = box_of(p);
             fluid = !in_wall_layer(b, (int)x, (int)y, (int)z);

@@ -38,7 +38,9 @@ def test_channel_c0_f64(H):
     n_fluid = fluid.sum()
     assert abs(tot[0]) / n_fluid <= 1e-12
     mom_o = ((1.0 + dr_o) * u_o)[:, fluid].sum(axis=1)
-    assert np.allclose(tot[1:3], mom_o[:2], rtol=1e-12, atol=1e-20)
+    assert np.isclose(tot[1], mom_o[0], rtol=1e-12, atol=0)
+    # u_y is zero in exact arithmetic: its total is rounding noise on both sides
+    assert abs(tot[2]) <= 1e-12 * abs(tot[1]) and abs(mom_o[1]) <= 1e-12 * abs(mom_o[0])
     # centreline Darcy value F tau / d and mirror symmetry through the HIP path
     U = u[0].reshape(64, 128)
     assert abs(U[31, 0] / (1e-6 * 0.8 / 0.5) - 1) < 1e-6
