@@ -53,13 +53,13 @@ def rel_l2_drho(dr, dr_ref, u_ref):
     return float(np.linalg.norm(dr - dr_ref) / max(np.linalg.norm(dr_ref), floor))
 
 
-def time_form(hlbm, storage, d_tile, steps, warmup):
+def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0):
     import torch
     reps = N_EDGE // 32
     dt = np.float32 if storage == "f32" else np.float16
     d = np.tile(d_tile.astype(dt), (reps, reps, reps))
     sim = hlbm.HLBM(hlbm.D3Q19, storage, (N_EDGE,) * 3, tau=TAU, force=FORCE,
-                    store_scale=SCALE_16 if storage != "f32" else 1.0)
+                    store_scale=SCALE_16 if storage != "f32" else 1.0, block_x=block_x)
     try:
         sim.set_porosity(d)
         del d
@@ -88,6 +88,53 @@ def time_form(hlbm, storage, d_tile, steps, warmup):
         return ms, dr_t, u_t, tot, tiles_equal
     finally:
         sim.close()
+
+
+def copy_reference(gib=4.0, reps=10):
+    """Device-to-device copy bandwidth of a plain copy kernel (torch copy_),
+    counted as bytes read + bytes written: what HBM sustains for streaming."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * 4 * n, "ms": round(ms, 4), "GBs": round(2 * 4 * n / (ms * 1e-3) / 1e9, 1)}
+
+
+def summarize_profile(path):
+    """Per-kernel duration summary of a rocprofv3 --kernel-trace output
+    (SQLite results database or kernel_stats CSV) under `path`."""
+    import glob
+    import sqlite3
+    dbs = glob.glob(os.path.join(path, "**", "*.db"), recursive=True)
+    rows = []
+    if dbs:
+        con = sqlite3.connect(dbs[0])
+        rows = con.execute("select name, count(*), avg(end-start), min(end-start), max(end-start), "
+                           "sum(end-start) from kernels group by name order by sum(end-start) desc").fetchall()
+    else:
+        import csv
+        for f in glob.glob(os.path.join(path, "**", "*kernel_stats.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]), float(r["MinNs"]),
+                             float(r["MaxNs"]), float(r["TotalDurationNs"])))
+    out = ["| kernel | calls | avg us | min us | max us | total ms |", "|---|---|---|---|---|---|"]
+    for name, calls, avg, mn, mx, tot in rows:
+        out.append(f"| `{name.split('(')[0]}` | {calls} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | "
+                   f"{mx / 1e3:.1f} | {tot / 1e6:.2f} |")
+    return "\n".join(out)
 
 
 def counters_traffic(n_cells):
@@ -143,7 +190,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--forms", default="f32,f16s,bf16s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-reference", action="store_true")
+    ap.add_argument("--block-x", type=int, default=-1,
+                    help="threads per block along x (-1: tuned value, 0: library default)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="print a per-kernel summary of a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
+    if args.summarize_profile:
+        print(summarize_profile(args.summarize_profile))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -159,10 +214,13 @@ def main():
     n_cells = N_EDGE ** 3
     forms = [f for f in args.forms.split(",") if f]
     results = {}
+    from paper_2310_14746_amd import tune
     for f in forms:
         tile = inputs.round_to(d_tile, "f32" if f == "f32" else "f16")
-        ms, dr, u, tot, teq = time_form(hlbm, f, tile, args.steps, args.warmup)
-        results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq)
+        bx = args.block_x if args.block_x >= 0 else tune.lookup(hlbm.D3Q19, f, (N_EDGE,) * 3)
+        ms, dr, u, tot, teq = time_form(hlbm, f, tile, args.steps, args.warmup, block_x=bx)
+        results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq, block_x=bx)
+    copy_ref = None if args.no_copy_reference else copy_reference()
 
     cpu, refs = None, {}
     if not args.no_cpu_baseline:
@@ -204,6 +262,8 @@ def main():
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
             "alg_bytes_per_cell": ALG_BYTES[head],
+            "copy_reference_GBs": copy_ref["GBs"] if copy_ref else None,
+            "frac_of_copy": round(achieved / copy_ref["GBs"], 4) if copy_ref else None,
         },
         "cpu_baseline": cpu,
         "forms": {},
@@ -216,6 +276,7 @@ def main():
             "alg_GBs": round(ALG_BYTES[f] * n_cells * args.steps / (r["ms"] * 1e-3) / 1e9, 1),
             "speedup_vs_" + head: round(results[head]["ms"] / r["ms"], 3),
             "tiles_identical": r["tiles_equal"],
+            "block_x": r["block_x"],
             "mass_excess_total": float(r["tot"][0]),
         }
         ref = refs.get("f32" if f == "f32" else "f16")

@@ -11,7 +11,7 @@
 
 #include <new>
 
-#include "../../include/hlbm.h"
+#include "hlbm.h"
 #include "hlbm_internal.hpp"
 #include "lattice.hpp"
 
