@@ -149,6 +149,51 @@ def counters_traffic(n_cells):
     return info.get("hbm_bytes_per_launch")
 
 
+def time_batched(hlbm, steps=2000, seed=0):
+    """256 homogenized periodic unit cells (edges 32..96), one graph launch of
+    the persistent kernel for all steps, and the same work as one launch per
+    step; algorithmic bytes as for the FP32 sweep."""
+    import torch
+    from paper_2310_14746_amd import inputs
+    spec = inputs.batch_items(256, seed=seed)
+    items = [dict(shape=(e, e, e), tau=t, force=(1e-6, 0, 0)) for e, _, t in spec]
+    log("batched: building 256 unit-cell fields")
+    fields = {}
+    out = {"workload": "256 periodic D3Q19 unit cells, edges {32,48,64,80,96}, phi U[0.1,0.9], "
+                       f"tau U[0.55,1.0], F=1e-6, FP32, seed {seed}", "steps": steps}
+    for mode in ("graph", "per_step"):
+        b = hlbm.HLBMBatch(items, "f32", mode=mode)
+        try:
+            for k, (e, phi, _) in enumerate(spec):
+                if (e, phi) not in fields:
+                    fields[(e, phi)] = inputs.round_to(inputs.batch_item_field(e, phi), "f32").astype(np.float32).ravel()
+                b.set_porosity(k, fields[(e, phi)])
+            b.step(2)
+            b.sync()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(b.stream)
+            b.step(steps)
+            e1.record(b.stream)
+            b.sync()
+            ms = e0.elapsed_time(e1)
+            _, cells = b.info()
+            tot = b.totals()
+        finally:
+            b.close()
+        log(f"batched {mode}: {steps} steps in {ms:.0f} ms")
+        out["cells"] = cells
+        out[mode] = {"ms": round(ms, 1), "mlups": round(cells * steps / (ms * 1e-3) / 1e6, 1),
+                     "alg_GBs": round(156 * cells * steps / (ms * 1e-3) / 1e9, 1)}
+        if mode == "graph":
+            cells_k = np.array([e ** 3 for e, _, _ in spec], dtype=float)
+            nu = (np.array([t for _, _, t in spec]) - 0.5) / 3.0
+            k = nu * (tot[:, 1] / cells_k) / 1e-6
+            out["permeability"] = {"min": float(k.min()), "median": float(np.median(k)),
+                                   "max": float(k.max()), "all_finite_positive": bool((k > 0).all() and np.isfinite(k).all())}
+    return out
+
+
 def cpu_baseline(steps_total):
     """Oracle on a 64^3 crop (2^3 obstacle cells; exact by periodicity) -> MLUPS."""
     import oracle
@@ -191,6 +236,7 @@ def main():
     ap.add_argument("--forms", default="f32,f16s,bf16s")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-reference", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--block-x", type=int, default=-1,
                     help="threads per block along x (-1: tuned value, 0: library default)")
     ap.add_argument("--summarize-profile", metavar="DIR",
@@ -221,6 +267,7 @@ def main():
         ms, dr, u, tot, teq = time_form(hlbm, f, tile, args.steps, args.warmup, block_x=bx)
         results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq, block_x=bx)
     copy_ref = None if args.no_copy_reference else copy_reference()
+    batched = None if args.no_batched else time_batched(hlbm)
 
     cpu, refs = None, {}
     if not args.no_cpu_baseline:
@@ -267,6 +314,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "forms": {},
+        "batched": batched,
     }
     for f in forms:
         r = results[f]

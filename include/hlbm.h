@@ -180,8 +180,62 @@ int hlbm_set_state(hlbm_ctx *ctx, const void *src, int on_device, long long step
 /* Reset to rest (g = 0) and step 0; the porosity field is kept. */
 int hlbm_reset(hlbm_ctx *ctx);
 
-/* Wait for all work of the context; EDEVICE on a device fault. */
+/* Wait for all work of the context; EDEVICE on a device fault (and, for a
+ * batch, if a grid barrier of the persistent kernel timed out). */
 int hlbm_sync(hlbm_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Batched periodic boxes.
+ *
+ * Many independent fully periodic D3Q19 boxes -- for instance porous unit
+ * cells of uneven sizes and porosities, each with its own tau and force --
+ * held in one context and advanced together.  Every item evolves exactly as a
+ * single context of the same configuration would (bit for bit); items do not
+ * interact.  The cells of all items are packed one after another (x fastest
+ * inside an item) and each population row spans all items.
+ *
+ * hlbm_step advances every item.  Modes:
+ *   HLBM_BATCH_GRAPH      (default) one executable HIP graph per call: a
+ *                         reset node, then one persistent kernel that runs all
+ *                         steps with a grid-wide barrier between them;
+ *   HLBM_BATCH_PERSISTENT the same persistent kernel launched directly;
+ *   HLBM_BATCH_PER_STEP   one kernel launch per step.
+ * The persistent kernel is sized to the blocks that fit on the GPU at once.
+ * Its barrier waits with a bounded spin; if the bound is hit, every block
+ * leaves and the next syncing call returns HLBM_EDEVICE.
+ * hlbm_get_state / hlbm_set_state / hlbm_reset / hlbm_get_step work on the
+ * packed state; hlbm_set_porosity and hlbm_moments return
+ * HLBM_EUNSUPPORTED for a batch (use the calls below).
+ * ------------------------------------------------------------------------ */
+enum { HLBM_BATCH_GRAPH = 0, HLBM_BATCH_PERSISTENT = 1, HLBM_BATCH_PER_STEP = 2 };
+
+/* Create a batch of n_items >= 1 boxes.  items[k] gives box k's nx, ny, nz
+ * (each in [2, 1024], with nx*ny*nz*max(nx, ny) < 2^32), tau and force; all
+ * items must use HLBM_D3Q19, the same storage, HLBM_AB and periodic faces on
+ * every axis.  rho0, store_scale, block_x and hip_stream are taken from
+ * items[0]; external_memory must be 0 (the library allocates).  The packed
+ * cell count times the element size must stay below 4 GiB.  State at rest. */
+int hlbm_create_batch(const hlbm_config *items, int n_items, hlbm_ctx **out);
+
+/* Number of items and total packed cells of a batch (EINVAL if not a batch). */
+int hlbm_batch_info(const hlbm_ctx *ctx, int *n_items, size_t *total_cells);
+
+/* Select how hlbm_step advances a batch (HLBM_BATCH_*). */
+int hlbm_batch_set_mode(hlbm_ctx *ctx, int mode);
+
+/* Porosity control d = 1 - varpi of one item (nx*ny*nz values, x fastest),
+ * same rules as hlbm_set_porosity.  Every item must be set before stepping. */
+int hlbm_batch_set_porosity(hlbm_ctx *ctx, int item, const void *d, int dtype, int on_device);
+
+/* Moments of a batch at the current time level (definitions as for
+ * hlbm_moments), FP64.  If drho or u is not NULL they receive the fields of
+ * `item` (drho[nx*ny*nz], u[3][nx*ny*nz]); on_device selects device or host
+ * arrays.  If totals is not NULL it receives, for every item k,
+ * totals[4k] = sum (rho - rho0), totals[4k+1..4k+3] = sum rho u_a, in FP64
+ * (block partials per tile, then one fixed-order pass per item).  Waits for
+ * the stream. */
+int hlbm_batch_moments(hlbm_ctx *ctx, int item, double *drho, double *u, int on_device,
+                       double *totals);
 
 #ifdef __cplusplus
 }

@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "hlbm.h"
 #include "hlbm_internal.hpp"
@@ -40,6 +41,21 @@ struct hlbm_ctx {
     int* flags_dev;    // per-block flags of the porosity check
     uint32_t flags_blocks;
     int* flag_out;
+    // batch of periodic boxes (hlbm_create_batch)
+    bool batch;
+    int n_items;
+    int batch_mode;
+    std::vector<hlbm::BatchItem> items;
+    std::vector<char> item_porosity;
+    hlbm::BatchItem* items_dev;
+    uint32_t* tile_item_dev;
+    double* tile_partials;
+    double* item_totals_dev;
+    unsigned* bar_counter;
+    int* bar_err;
+    hlbm::BatchLaunch bl;
+    hipGraphExec_t gexec[2];
+    int gsteps[2];
 };
 
 namespace {
@@ -183,6 +199,49 @@ int zero_state(hlbm_ctx* c)
     }
     c->cur = 0;
     c->step = 0;
+    return HLBM_OK;
+}
+
+int batch_check_barrier(hlbm_ctx* c)
+{
+    int err = 0;
+    hipError_t e = hipMemcpy(&err, c->bar_err, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the barrier flag");
+    if (err) return fail(HLBM_EDEVICE, "a grid barrier of the persistent batch kernel timed out");
+    return HLBM_OK;
+}
+
+int batch_step(hlbm_ctx* c, int nsteps)
+{
+    if (nsteps == 0) return HLBM_OK;
+    hipError_t e = hipSuccess;
+    const int storage = c->cfg.storage;
+    if (c->batch_mode == HLBM_BATCH_PER_STEP) {
+        for (int t = 0; t < nsteps && e == hipSuccess; ++t) {
+            e = hlbm::launch_batch_step(storage, c->bl, c->pop[c->cur], c->pop[c->cur ^ 1], c->dfield,
+                                        c->stream);
+            if (e == hipSuccess) c->cur ^= 1;
+        }
+    } else if (c->batch_mode == HLBM_BATCH_PERSISTENT) {
+        e = hlbm::launch_batch_persistent(storage, c->bl, c->pop[0], c->pop[1], c->dfield, nsteps, c->cur,
+                                          c->stream);
+        if (e == hipSuccess) c->cur ^= (nsteps & 1);
+    } else {
+        const int k = c->cur;
+        if (!c->gexec[k] || c->gsteps[k] != nsteps) {
+            if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+            c->gexec[k] = nullptr;
+            c->gsteps[k] = -1;
+            e = hlbm::build_batch_graph(storage, c->bl, c->pop[0], c->pop[1], c->dfield, nsteps, k,
+                                        &c->gexec[k]);
+            if (e != hipSuccess) return hip_fail(e, "building the batch graph");
+            c->gsteps[k] = nsteps;
+        }
+        e = hipGraphLaunch(c->gexec[k], c->stream);
+        if (e == hipSuccess) c->cur ^= (nsteps & 1);
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch step launch");
+    c->step += nsteps;
     return HLBM_OK;
 }
 
@@ -330,6 +389,14 @@ int hlbm_destroy(hlbm_ctx* c)
     if (c->totals_dev) (void)hipFree(c->totals_dev);
     if (c->flags_dev) (void)hipFree(c->flags_dev);
     if (c->flag_out) (void)hipFree(c->flag_out);
+    for (int k = 0; k < 2; ++k)
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->items_dev) (void)hipFree(c->items_dev);
+    if (c->tile_item_dev) (void)hipFree(c->tile_item_dev);
+    if (c->tile_partials) (void)hipFree(c->tile_partials);
+    if (c->item_totals_dev) (void)hipFree(c->item_totals_dev);
+    if (c->bar_counter) (void)hipFree(c->bar_counter);
+    if (c->bar_err) (void)hipFree(c->bar_err);
     delete c;
     return rc;
 }
@@ -338,6 +405,7 @@ int hlbm_set_porosity(hlbm_ctx* c, const void* d, int dtype, int on_device)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
+    if (c->batch) return fail(HLBM_EUNSUPPORTED, "use hlbm_batch_set_porosity for a batch");
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (!d) return fail(HLBM_EINVAL, "porosity array is NULL");
     if (dtype < HLBM_DT_F64 || dtype > HLBM_DT_F16) return fail(HLBM_EINVAL, "unknown dtype %d", dtype);
@@ -378,6 +446,7 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
     if (nsteps < 0) return fail(HLBM_EINVAL, "nsteps must be >= 0");
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (!c->porosity_set) return fail(HLBM_ESTATE, "porosity not set");
+    if (c->batch) return batch_step(c, nsteps);
     for (int t = 0; t < nsteps; ++t) {
         hipError_t e = hlbm::launch_sweep(c->q, c->cfg.storage, c->bcmode, c->p, c->pop[c->cur],
                                           c->pop[c->cur ^ 1], c->dfield, c->bx, c->stream);
@@ -401,6 +470,7 @@ int hlbm_moments(hlbm_ctx* c, void* drho, void* u, int dtype, int on_device, dou
 {
     int rc = check_ctx(c);
     if (rc) return rc;
+    if (c->batch) return fail(HLBM_EUNSUPPORTED, "use hlbm_batch_moments for a batch");
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (dtype != HLBM_DT_F64 && dtype != HLBM_DT_F32) return fail(HLBM_EINVAL, "dtype must be F64 or F32");
     const size_t osz = dtype == HLBM_DT_F64 ? 8 : 4;
@@ -495,6 +565,235 @@ int hlbm_sync(hlbm_ctx* c)
     if (rc) return rc;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "sync");
+    if (c->batch) return batch_check_barrier(c);
+    return HLBM_OK;
+}
+
+int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
+{
+    if (!out) return fail(HLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!items) return fail(HLBM_EINVAL, "items is NULL");
+    if (n_items < 1 || n_items > 65536) return fail(HLBM_EINVAL, "n_items must be in [1, 65536]");
+    const int storage = items[0].storage;
+    unsigned long long ntot = 0, ntiles = 0, max_cells = 0;
+    for (int k = 0; k < n_items; ++k) {
+        const hlbm_config* it = &items[k];
+        int rc = validate_config(it);
+        if (rc) return fail(rc, "item %d: %s", k, hlbm_last_error());
+        if (it->lattice != HLBM_D3Q19) return fail(HLBM_EUNSUPPORTED, "item %d: batches use D3Q19", k);
+        if (it->storage != storage) return fail(HLBM_EINVAL, "item %d: all items share one storage", k);
+        for (int a = 0; a < 3; ++a)
+            if (it->bc_lo[a] != HLBM_PERIODIC || it->bc_hi[a] != HLBM_PERIODIC)
+                return fail(HLBM_EUNSUPPORTED, "item %d: batch items are fully periodic", k);
+        if (it->nx < 2 || it->ny < 2 || it->nz < 2 || it->nx > 1024 || it->ny > 1024 || it->nz > 1024)
+            return fail(HLBM_EINVAL, "item %d: each edge must be in [2, 1024]", k);
+        const unsigned long long cells = (unsigned long long)it->nx * it->ny * it->nz;
+        const unsigned long long mxy = it->nx > it->ny ? it->nx : it->ny;
+        if (cells * mxy >= (1ull << 32))
+            return fail(HLBM_EUNSUPPORTED, "item %d: nx*ny*nz*max(nx,ny) must be < 2^32", k);
+        ntot += cells;
+        ntiles += (cells + hlbm::TILE - 1) / hlbm::TILE;
+        if (cells > max_cells) max_cells = cells;
+    }
+    if (items[0].external_memory) return fail(HLBM_EUNSUPPORTED, "a batch allocates its own memory");
+    if (ntot * elem_bytes(storage) >= (1ull << 32))
+        return fail(HLBM_EUNSUPPORTED, "packed cells x element size must be < 4 GiB");
+    hlbm_ctx* c = new (std::nothrow) hlbm_ctx();
+    if (!c) return fail(HLBM_ENOMEM, "host allocation of the context failed");
+    c->cfg = items[0];
+    c->batch = true;
+    c->n_items = n_items;
+    c->batch_mode = HLBM_BATCH_GRAPH;
+    c->q = 19;
+    c->bcmode = hlbm::BC_PERIODIC;
+    fill_params(&items[0], &c->p);
+    c->p.nx = (int)ntot;
+    c->p.ny = 1;
+    c->p.nz = 1;
+    c->p.N = (uint32_t)ntot;
+    c->bx = 256;
+    c->elem = elem_bytes(storage);
+    c->delem = porosity_elem_bytes(storage);
+    c->pop_bytes = (size_t)ntot * 19 * c->elem;
+    c->stream = static_cast<hipStream_t>(items[0].hip_stream);
+    c->own_mem = true;
+    c->gsteps[0] = c->gsteps[1] = -1;
+    c->items.resize(n_items);
+    c->item_porosity.assign(n_items, 0);
+    std::vector<uint32_t> tile_item((size_t)ntiles);
+    uint32_t base = 0, tile0 = 0;
+    for (int k = 0; k < n_items; ++k) {
+        const hlbm_config* it = &items[k];
+        hlbm::BatchItem& b = c->items[k];
+        b.base = base;
+        b.nx = it->nx;
+        b.ny = it->ny;
+        b.nz = it->nz;
+        b.cells = (uint32_t)it->nx * it->ny * it->nz;
+        b.tile0 = tile0;
+        b.mx = (uint32_t)(((1ull << 32) + it->nx - 1) / it->nx);
+        b.my = (uint32_t)(((1ull << 32) + it->ny - 1) / it->ny);
+        b.omega = 1.0 / it->tau;
+        b.pref = 1.0 - 0.5 / it->tau;
+        for (int a = 0; a < 3; ++a) b.F[a] = it->force[a];
+        const uint32_t nt = (b.cells + hlbm::TILE - 1) / hlbm::TILE;
+        for (uint32_t j = 0; j < nt; ++j) tile_item[tile0 + j] = (uint32_t)k;
+        base += b.cells;
+        tile0 += nt;
+    }
+    hipError_t e = hipMalloc(&c->pop[0], c->pop_bytes);
+    if (e == hipSuccess) e = hipMalloc(&c->pop[1], c->pop_bytes);
+    if (e == hipSuccess) e = hipMalloc(&c->dfield, (size_t)ntot * c->delem);
+    if (e == hipSuccess) e = hipMalloc(&c->items_dev, sizeof(hlbm::BatchItem) * n_items);
+    if (e == hipSuccess) e = hipMalloc(&c->tile_item_dev, sizeof(uint32_t) * (size_t)ntiles);
+    if (e == hipSuccess) e = hipMalloc(&c->tile_partials, sizeof(double) * 4 * (size_t)ntiles);
+    if (e == hipSuccess) e = hipMalloc(&c->item_totals_dev, sizeof(double) * 4 * (size_t)n_items);
+    if (e == hipSuccess) e = hipMalloc(&c->bar_counter, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc(&c->bar_err, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&c->flags_dev, sizeof(int) * (size_t)((max_cells + 255) / 256));
+    if (e == hipSuccess) e = hipMalloc(&c->flag_out, sizeof(int));
+    if (e != hipSuccess) {
+        hlbm_destroy(c);
+        return fail(HLBM_ENOMEM, "device allocation for the batch failed: %s", hipGetErrorString(e));
+    }
+    c->flags_blocks = (uint32_t)((max_cells + 255) / 256);
+    e = hipMemcpy(c->items_dev, c->items.data(), sizeof(hlbm::BatchItem) * n_items, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->tile_item_dev, tile_item.data(), sizeof(uint32_t) * (size_t)ntiles, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(c->bar_err, 0, sizeof(int));
+    int per_cu = 0, cus = 0;
+    if (e == hipSuccess) e = hlbm::batch_occupancy(storage, &per_cu);
+    int dev = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        hlbm_destroy(c);
+        return hip_fail(e, "batch set-up");
+    }
+    long long grid = (long long)per_cu * cus;
+    if (grid > (long long)ntiles) grid = (long long)ntiles;
+    if (grid < 1) grid = 1;
+    c->bl.items = c->items_dev;
+    c->bl.tile_item = c->tile_item_dev;
+    c->bl.n_items = (uint32_t)n_items;
+    c->bl.ntiles = (uint32_t)ntiles;
+    c->bl.Ntot = (uint32_t)ntot;
+    c->bl.rho0 = c->p.rho0;
+    c->bl.scale = c->p.scale;
+    c->bl.counter = c->bar_counter;
+    c->bl.err = c->bar_err;
+    c->bl.spin_limit = 1u << 20;
+    c->bl.grid = (int)grid;
+    c->bound = true;
+    int rc = zero_state(c);
+    if (rc) {
+        hlbm_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return HLBM_OK;
+}
+
+int hlbm_batch_info(const hlbm_ctx* c, int* n_items, size_t* total_cells)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!c->batch) return fail(HLBM_EINVAL, "not a batch context");
+    if (n_items) *n_items = c->n_items;
+    if (total_cells) *total_cells = c->p.N;
+    return HLBM_OK;
+}
+
+int hlbm_batch_set_mode(hlbm_ctx* c, int mode)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!c->batch) return fail(HLBM_EINVAL, "not a batch context");
+    if (mode < HLBM_BATCH_GRAPH || mode > HLBM_BATCH_PER_STEP) return fail(HLBM_EINVAL, "unknown batch mode %d", mode);
+    c->batch_mode = mode;
+    return HLBM_OK;
+}
+
+int hlbm_batch_set_porosity(hlbm_ctx* c, int item, const void* d, int dtype, int on_device)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!c->batch) return fail(HLBM_EINVAL, "not a batch context");
+    if (item < 0 || item >= c->n_items) return fail(HLBM_EINVAL, "item %d out of range", item);
+    if (!d) return fail(HLBM_EINVAL, "porosity array is NULL");
+    if (dtype < HLBM_DT_F64 || dtype > HLBM_DT_F16) return fail(HLBM_EINVAL, "unknown dtype %d", dtype);
+    const hlbm::BatchItem& it = c->items[item];
+    const size_t in_elem = dtype == HLBM_DT_F64 ? 8 : (dtype == HLBM_DT_F32 ? 4 : 2);
+    const size_t n = it.cells;
+    const void* src = d;
+    void* tmp = nullptr;
+    hipError_t e;
+    if (!on_device) {
+        e = hipMalloc(&tmp, n * in_elem);
+        if (e != hipSuccess) return fail(HLBM_ENOMEM, "staging allocation: %s", hipGetErrorString(e));
+        e = hipMemcpyAsync(tmp, d, n * in_elem, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(tmp);
+            return hip_fail(e, "porosity upload");
+        }
+        src = tmp;
+    }
+    void* out = static_cast<char*>(c->dfield) + (size_t)it.base * c->delem;
+    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, out, (uint32_t)n, c->flags_dev,
+                                      c->flag_out, c->stream);
+    int flag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, c->flag_out, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "porosity conversion");
+    if (flag) {
+        c->item_porosity[item] = 0;
+        c->porosity_set = false;
+        return fail(HLBM_EINVAL, "item %d: porosity values must be finite and in [0, 1]", item);
+    }
+    c->item_porosity[item] = 1;
+    bool all = true;
+    for (int k = 0; k < c->n_items; ++k) all = all && c->item_porosity[k];
+    c->porosity_set = all;
+    return HLBM_OK;
+}
+
+int hlbm_batch_moments(hlbm_ctx* c, int item, double* drho, double* u, int on_device, double* totals)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!c->batch) return fail(HLBM_EINVAL, "not a batch context");
+    const bool fields = drho || u;
+    if (fields && (item < 0 || item >= c->n_items)) return fail(HLBM_EINVAL, "item %d out of range", item);
+    if (fields && (!drho || !u)) return fail(HLBM_EINVAL, "give both drho and u, or neither");
+    const size_t n = fields ? c->items[item].cells : 0;
+    double* ddr = drho;
+    double* du = u;
+    void* tmp = nullptr;
+    hipError_t e;
+    if (fields && !on_device) {
+        e = hipMalloc(&tmp, 4 * n * sizeof(double));
+        if (e != hipSuccess) return fail(HLBM_ENOMEM, "staging allocation: %s", hipGetErrorString(e));
+        ddr = static_cast<double*>(tmp);
+        du = ddr + n;
+    }
+    e = hlbm::launch_batch_moments(c->cfg.storage, c->bl, c->pop[c->cur], c->tile_partials,
+                                   fields ? item : -1, fields ? ddr : nullptr, fields ? du : nullptr,
+                                   c->item_totals_dev, c->stream);
+    if (e == hipSuccess && totals)
+        e = hipMemcpyAsync(totals, c->item_totals_dev, 4 * sizeof(double) * c->n_items,
+                           hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && tmp) e = hipMemcpyAsync(drho, ddr, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && tmp) e = hipMemcpyAsync(u, du, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "batch moments");
+    rc = batch_check_barrier(c);
+    if (rc) return rc;
+    if (totals)
+        for (int k = 0; k < 4 * c->n_items; ++k)
+            if (!isfinite(totals[k])) return fail(HLBM_ENUMERIC, "non-finite total (item %d)", k / 4);
     return HLBM_OK;
 }
 

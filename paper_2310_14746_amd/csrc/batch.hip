@@ -27,9 +27,13 @@ __device__ __forceinline__ bool grid_barrier(unsigned* __restrict__ counter, uns
                                              int* __restrict__ err, unsigned spin_limit)
 {
     __shared__ int ok;
+    // Every wave releases its own stores at device scope (waits for them and
+    // writes back its L2) before the block barrier; a workgroup barrier alone
+    // does not wait for other waves' stores, and the step's results must be
+    // visible to blocks on every XCD.
+    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
         atomicAdd(counter, 1u);
         int good = 1;
         unsigned spins = 0;

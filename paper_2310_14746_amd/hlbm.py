@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libhlbm.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "hlbm.h")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
+BATCH_GRAPH, BATCH_PERSISTENT, BATCH_PER_STEP = 0, 1, 2
+BATCH_MODES = {"graph": BATCH_GRAPH, "persistent": BATCH_PERSISTENT, "per_step": BATCH_PER_STEP}
 D2Q9, D3Q19 = 9, 19
 F64, F32, F16S, BF16S = 0, 1, 2, 3
 AB = 0
@@ -72,6 +74,10 @@ def load() -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime; import it first so that libhlbm.so binds
+    # to that same runtime (one runtime per process: the library and torch
+    # exchange device pointers and streams).
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
             f"{LIB_PATH} is missing: build it with `python -m paper_2310_14746_amd.build` "
@@ -97,6 +103,11 @@ def load() -> ctypes.CDLL:
         "hlbm_set_state": ([vp, vp, i, ctypes.c_longlong], i),
         "hlbm_reset": ([vp], i),
         "hlbm_sync": ([vp], i),
+        "hlbm_create_batch": ([P(Config), i, P(vp)], i),
+        "hlbm_batch_info": ([vp, P(ctypes.c_int), P(ctypes.c_size_t)], i),
+        "hlbm_batch_set_mode": ([vp, i], i),
+        "hlbm_batch_set_porosity": ([vp, i, vp, i, i], i),
+        "hlbm_batch_moments": ([vp, i, vp, vp, i, P(ctypes.c_double)], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -298,3 +309,122 @@ class HLBM:
         else:
             v = raw.view(t.bfloat16).to(t.float64).numpy() / self.cfg.store_scale
         return v.reshape(self.q, self.N)
+
+
+def _host_or_device(d, n, torch):
+    """(pointer, dtype code, on_device, keepalive) for a porosity array."""
+    if isinstance(d, torch.Tensor):
+        dd = d.contiguous()
+        if dd.numel() != n:
+            raise ValueError(f"porosity needs {n} values")
+        code = {torch.float64: DT_F64, torch.float32: DT_F32, torch.float16: DT_F16}[dd.dtype]
+        if dd.is_cuda:
+            return dd.data_ptr(), code, 1, dd
+        arr = dd.numpy()
+        return arr.ctypes.data, code, 0, arr
+    arr = np.ascontiguousarray(d)
+    if arr.size != n:
+        raise ValueError(f"porosity needs {n} values")
+    code = {np.dtype(np.float64): DT_F64, np.dtype(np.float32): DT_F32,
+            np.dtype(np.float16): DT_F16}[arr.dtype]
+    return arr.ctypes.data, code, 0, arr
+
+
+class HLBMBatch:
+    """Many independent periodic D3Q19 boxes advanced together.
+
+    ``items`` is a sequence of dicts with keys ``shape`` (nx, ny, nz), ``tau``
+    and ``force``.  The library owns the packed device memory; torch supplies
+    the stream.
+    """
+
+    def __init__(self, items, storage="f32", store_scale=1.0, rho0=1.0, mode="graph",
+                 device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        lib = load()
+        n = len(items)
+        arr = (Config * n)()
+        for k, it in enumerate(items):
+            c = make_config(D3Q19, storage, it["shape"], it["tau"], it.get("force", (0, 0, 0)),
+                            rho0=rho0, store_scale=store_scale, stream=self.stream.cuda_stream)
+            arr[k] = c
+        self.items = [dict(shape=tuple(int(v) for v in it["shape"]), tau=float(it["tau"]),
+                           force=tuple(float(v) for v in it.get("force", (0, 0, 0))))
+                      for it in items]
+        ctx = ctypes.c_void_p()
+        _check(lib.hlbm_create_batch(arr, n, ctypes.byref(ctx)))
+        self.ctx = ctx
+        self.n_items = n
+        self.set_mode(mode)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            rc = load().hlbm_destroy(self.ctx)
+            self.ctx = None
+            _check(rc)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def info(self):
+        n, cells = ctypes.c_int(), ctypes.c_size_t()
+        _check(load().hlbm_batch_info(self.ctx, ctypes.byref(n), ctypes.byref(cells)))
+        return n.value, cells.value
+
+    def set_mode(self, mode):
+        _check(load().hlbm_batch_set_mode(self.ctx, BATCH_MODES[mode] if isinstance(mode, str)
+                                          else int(mode)))
+
+    def set_porosity(self, item: int, d):
+        nx, ny, nz = self.items[item]["shape"]
+        ptr, code, on_dev, keep = _host_or_device(d, nx * ny * nz, self.torch)
+        _check(load().hlbm_batch_set_porosity(self.ctx, int(item), ptr, code, on_dev))
+        del keep
+
+    def step(self, n: int = 1):
+        _check(load().hlbm_step(self.ctx, int(n)))
+
+    def sync(self):
+        _check(load().hlbm_sync(self.ctx))
+
+    @property
+    def step_count(self) -> int:
+        s = ctypes.c_longlong()
+        _check(load().hlbm_get_step(self.ctx, ctypes.byref(s)))
+        return s.value
+
+    def moments(self, item: int):
+        """(drho (nz,ny,nx), u (3,nz,ny,nx)) of one item, FP64 device tensors."""
+        t = self.torch
+        nx, ny, nz = self.items[item]["shape"]
+        drho = t.empty((nz, ny, nx), dtype=t.float64, device=self.device)
+        u = t.empty((3, nz, ny, nx), dtype=t.float64, device=self.device)
+        _check(load().hlbm_batch_moments(self.ctx, int(item), drho.data_ptr(), u.data_ptr(), 1, None))
+        return drho, u
+
+    def totals(self) -> np.ndarray:
+        """FP64 [sum(rho - rho0), sum rho u_x, sum rho u_y, sum rho u_z] per item."""
+        tot = (ctypes.c_double * (4 * self.n_items))()
+        _check(load().hlbm_batch_moments(self.ctx, -1, None, None, 1, tot))
+        return np.array(tot).reshape(self.n_items, 4)
+
+    def get_state(self):
+        t = self.torch
+        nb = ctypes.c_size_t()
+        _check(load().hlbm_state_bytes(self.ctx, ctypes.byref(nb)))
+        buf = t.empty(nb.value, dtype=t.uint8, device=self.device)
+        s = ctypes.c_longlong()
+        _check(load().hlbm_get_state(self.ctx, buf.data_ptr(), 1, ctypes.byref(s)))
+        return buf, s.value

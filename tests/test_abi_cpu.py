@@ -94,3 +94,50 @@ def test_null_arguments(lib):
     assert lib.hlbm_step(None, 1) == hlbm.EINVAL
     assert lib.hlbm_destroy(None) == hlbm.OK
     assert lib.hlbm_lattice_info(19, None, None) == hlbm.EINVAL
+
+
+def _batch_rc(items):
+    import ctypes as C
+    n = len(items)
+    arr = (hlbm.Config * n)(*items)
+    ctx = C.c_void_p()
+    return hlbm.load().hlbm_create_batch(arr, n, C.byref(ctx))
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(lattice=9, shape=(8, 8, 1)), hlbm.EUNSUPPORTED),
+    (dict(storage="f64"), hlbm.EINVAL),          # storage differs from item 0
+    (dict(bc_lo=(1, 0, 0), bc_hi=(1, 0, 0)), hlbm.EUNSUPPORTED),
+    (dict(shape=(1, 8, 8)), hlbm.EINVAL),
+    (dict(shape=(2000, 8, 8)), hlbm.EINVAL),
+    (dict(shape=(1000, 1000, 8)), hlbm.EUNSUPPORTED),   # multiply-high quotient bound
+    (dict(tau=0.4), hlbm.EINVAL),
+])
+def test_batch_validation(change, code):
+    base = dict(lattice=19, storage="f32", shape=(32, 32, 32), tau=0.7)
+    bad = dict(base)
+    bad.update(change)
+    assert _batch_rc([hlbm.make_config(**base), hlbm.make_config(**bad)]) == code
+    assert hlbm.load().hlbm_last_error().decode()
+
+
+def test_batch_null_and_count(lib):
+    import ctypes as C
+    ctx = C.c_void_p()
+    assert lib.hlbm_create_batch(None, 1, C.byref(ctx)) == hlbm.EINVAL
+    arr = (hlbm.Config * 1)(hlbm.make_config(19, "f32", (16, 16, 16)))
+    assert lib.hlbm_create_batch(arr, 0, C.byref(ctx)) == hlbm.EINVAL
+    assert lib.hlbm_batch_set_mode(None, 0) == hlbm.EINVAL
+
+
+def test_batch_quotient_by_multiply_high():
+    """The kernels divide by nx and ny with a 32-bit multiply-high by
+    ceil(2^32/n); exact whenever l*n < 2^32, which the library checks."""
+    for n in (2, 3, 7, 32, 48, 64, 80, 96, 255, 1000, 1024):
+        m = ((1 << 32) + n - 1) // n
+        lmax = min((1 << 32) // n - 1, 50_000_000)
+        ls = np.unique(np.concatenate([np.arange(0, min(lmax, 200_000)),
+                                       np.random.default_rng(n).integers(0, lmax, 200_000),
+                                       np.array([lmax])])).astype(np.uint64)
+        q = (ls * np.uint64(m)) >> np.uint64(32)
+        assert np.array_equal(q, ls // np.uint64(n)), n

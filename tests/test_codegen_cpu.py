@@ -20,15 +20,16 @@ from paper_2310_14746_amd import build as hbuild
 
 @pytest.fixture(scope="module")
 def asm():
-    with tempfile.TemporaryDirectory() as tmp:
-        out = os.path.join(tmp, "sweep.s")
-        cmd = [hbuild.hipcc(), *[f for f in hbuild.HIPCC_FLAGS if f != "-fPIC"],
-               "--cuda-device-only", "-S", os.path.join(hbuild.CSRC, "sweep.hip"), "-o", out]
-        subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
-        text = open(out).read()
     funcs = {}
-    for m in re.finditer(r"^(_Z\w+):.*?\n(.*?)^\.Lfunc_end", text, flags=re.S | re.M):
-        funcs[m.group(1)] = m.group(2)
+    with tempfile.TemporaryDirectory() as tmp:
+        for src in ("sweep.hip", "batch.hip"):
+            out = os.path.join(tmp, src + ".s")
+            cmd = [hbuild.hipcc(), *[f for f in hbuild.HIPCC_FLAGS if f != "-fPIC"],
+                   "--cuda-device-only", "-S", os.path.join(hbuild.CSRC, src), "-o", out]
+            subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
+            text = open(out).read()
+            for m in re.finditer(r"^(_Z\w+):.*?\n(.*?)^\.Lfunc_end", text, flags=re.S | re.M):
+                funcs[m.group(1)] = m.group(2)
     assert funcs
     return funcs
 
@@ -47,8 +48,27 @@ def test_sweep_kernels_are_straight_line(asm):
 
 def test_no_private_memory_in_sweep_and_moments(asm):
     for name, body in {**_kernels(asm, "_ZN4hlbm12sweep_kernel"),
-                       **_kernels(asm, "_ZN4hlbm14moments_kernel")}.items():
+                       **_kernels(asm, "_ZN4hlbm14moments_kernel"),
+                       **_kernels(asm, "_ZN4hlbm23batch_persistent_kernel"),
+                       **_kernels(asm, "_ZN4hlbm17batch_step_kernel")}.items():
         assert not re.search(r"^\s+(scratch_|buffer_store|buffer_load)", body, flags=re.M), name
+
+
+def test_persistent_barrier_releases_every_wave(asm):
+    """Each wave writes back (device-scope release) before the block barrier
+    that precedes the arrival count, so stores of every wave are visible to
+    blocks on other XCDs after the grid barrier."""
+    kern = _kernels(asm, "_ZN4hlbm23batch_persistent_kernel")
+    assert len(kern) == 4
+    for name, body in kern.items():
+        lines = [l.strip() for l in body.splitlines()]
+        idx = [i for i, l in enumerate(lines) if l.startswith("global_atomic_add")]
+        assert idx, name
+        # the block barrier before the arrival atomic is preceded by wbl2 + vmcnt(0)
+        bar = max(i for i in range(idx[0]) if lines[i].startswith("s_barrier"))
+        window = lines[max(0, bar - 6):bar]
+        assert any(l.startswith("buffer_wbl2") for l in window), name
+        assert any(l.startswith("s_waitcnt vmcnt(0)") for l in window), name
 
 
 def test_no_scalar_cache_writes(asm):

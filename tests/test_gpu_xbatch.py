@@ -1,0 +1,190 @@
+"""GPU tests of batched periodic boxes (persistent kernel with grid barrier,
+graph launch, per-step launches).  Collected after the other GPU tests.
+
+* every mode gives the same bits;
+* an item evolves bit for bit as a single context of the same configuration;
+* an item matches the FP64 oracle to the FP32 bar;
+* the full workload (256 homogenized unit cells, edges 32..96, 2000 steps)
+  runs in one graph launch and gives positive, finite permeabilities.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleConfig
+from paper_2310_14746_amd import inputs
+from tests._parity import rel_l2_drho, rel_l2_u
+
+pytestmark = pytest.mark.gpu
+NT = max(1, min(16, os.cpu_count() or 1))
+
+
+def say(msg):
+    print(f"[gpu-batch] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2310_14746_amd import hlbm
+    hlbm.load()
+    return hlbm
+
+
+ITEMS = [
+    dict(shape=(32, 32, 32), tau=0.6, force=(1e-5, 0, 0)),
+    dict(shape=(48, 40, 24), tau=0.9, force=(0, 2e-5, 0)),
+    dict(shape=(20, 36, 28), tau=0.55, force=(1e-5, 1e-5, 0)),   # ragged last tile
+    dict(shape=(64, 8, 12), tau=0.75, force=(0, 0, 3e-5)),
+]
+
+
+def _fields(items, seed=0):
+    out = []
+    for k, it in enumerate(items):
+        nx, ny, nz = it["shape"]
+        d = inputs.periodic_smooth(inputs.uniform_noise((nz, ny, nx), seed + k), 1.0, 3)
+        out.append(inputs.round_to(d, "f32").astype(np.float32).ravel())
+    return out
+
+
+def _run_batch(H, items, fields, steps, mode):
+    b = H.HLBMBatch(items, "f32", mode=mode)
+    try:
+        for k, d in enumerate(fields):
+            b.set_porosity(k, d)
+        b.step(steps)
+        b.sync()
+        st, s = b.get_state()
+        mom = [tuple(t.cpu().numpy() for t in b.moments(k)) for k in range(len(items))]
+        return st.cpu().numpy(), mom, b.totals()
+    finally:
+        b.close()
+
+
+def _run_single(H, it, d, steps):
+    sim = H.HLBM(19, "f32", it["shape"], tau=it["tau"], force=it["force"])
+    try:
+        sim.set_porosity(d)
+        sim.step(steps)
+        drho, u, tot = sim.moments("f64", totals=True)
+        st, _ = sim.get_state()
+        return st.cpu().numpy(), (drho.cpu().numpy(), u.cpu().numpy()), tot
+    finally:
+        sim.close()
+
+
+def test_single_item_batch_equals_single_context(H):
+    it = dict(shape=(40, 24, 16), tau=0.7, force=(1e-5, 0, 0))
+    d = _fields([it], 7)[0]
+    ref_state, _, _ = _run_single(H, it, d, 30)
+    for mode in ("per_step", "persistent", "graph"):
+        say(f"one item, mode {mode}")
+        st, _, _ = _run_batch(H, [it], [d], 30, mode)
+        assert np.array_equal(st, ref_state), mode
+
+
+def test_modes_bitwise_and_items_match_single_contexts(H):
+    fields = _fields(ITEMS, 3)
+    steps = 41
+    ref = None
+    for mode in ("per_step", "persistent", "graph"):
+        say(f"{len(ITEMS)} items, mode {mode}, {steps} steps")
+        st, mom, tot = _run_batch(H, ITEMS, fields, steps, mode)
+        if ref is None:
+            ref = (st, mom, tot)
+        else:
+            assert np.array_equal(st, ref[0]), mode
+            assert np.array_equal(tot, ref[2]), mode
+    for k, it in enumerate(ITEMS):
+        _, (dr, u), tot_s = _run_single(H, it, fields[k], steps)
+        assert np.array_equal(ref[1][k][0], dr) and np.array_equal(ref[1][k][1], u), k
+        assert np.allclose(ref[2][k], tot_s, rtol=1e-12, atol=1e-18), k
+
+
+def test_graph_relaunch_and_odd_even_steps(H):
+    """Graph cached per (steps, start buffer): 7 + 7 + 3 steps == 17 per-step."""
+    fields = _fields(ITEMS[:2], 5)
+    b = H.HLBMBatch(ITEMS[:2], "f32", mode="graph")
+    try:
+        for k, d in enumerate(fields):
+            b.set_porosity(k, d)
+        for n in (7, 7, 3):
+            b.step(n)
+        b.sync()
+        assert b.step_count == 17
+        st = b.get_state()[0].cpu().numpy()
+    finally:
+        b.close()
+    st2, _, _ = _run_batch(H, ITEMS[:2], fields, 17, "per_step")
+    assert np.array_equal(st, st2)
+
+
+def test_batch_item_vs_oracle(H):
+    it = dict(shape=(32, 32, 32), tau=0.7, force=(1e-6, 0, 0))
+    d = inputs.round_to(inputs.batch_item_field(32, 0.5), "f32").astype(np.float32).ravel()
+    items = [ITEMS[1], it, ITEMS[2]]
+    fields = _fields(items, 9)
+    fields[1] = d
+    steps = 300
+    say("item vs oracle, 300 steps")
+    _, mom, _ = _run_batch(H, items, fields, steps, "graph")
+    cfg = OracleConfig(q=19, nx=32, ny=32, nz=32, tau=0.7, force=(1e-6, 0, 0))
+    g = oracle.run(cfg, d.astype(np.float64), steps, nthreads=NT)
+    dr_o, u_o = oracle.observe(cfg, g)
+    eu = rel_l2_u(mom[1][1], u_o)
+    er = rel_l2_drho(mom[1][0], dr_o, u_o)
+    say(f"rel-L2 u {eu:.2e} drho {er:.2e}")
+    assert eu <= 1e-5 and er <= 1e-5
+
+
+def test_unit_cell_workload_full_size(H):
+    """256 homogenized unit cells (edges 32..96, phi in [0.1, 0.9], tau in
+    [0.55, 1]), body force 1e-6, 2000 steps in one graph launch."""
+    import torch
+    spec = inputs.batch_items(256, seed=0)
+    items = [dict(shape=(e, e, e), tau=t, force=(1e-6, 0, 0)) for e, _, t in spec]
+    say("building 256 unit-cell fields")
+    fields = [inputs.round_to(inputs.batch_item_field(e, phi), "f32").astype(np.float32).ravel()
+              for e, phi, _ in spec]
+    b = H.HLBMBatch(items, "f32", mode="graph")
+    try:
+        for k, d in enumerate(fields):
+            b.set_porosity(k, d)
+        say("2000 steps, one graph launch")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        b.step(2000)
+        e1.record(b.stream)
+        b.sync()
+        ms = e0.elapsed_time(e1)
+        n, cells = b.info()
+        say(f"{cells} cells x 2000 steps in {ms:.0f} ms: {cells * 2000 / ms / 1e3:.0f} MLUPS")
+        tot = b.totals()
+        k32 = next(k for k, (e, _, _) in enumerate(spec) if e == 32)
+        dr, u = (t.cpu().numpy() for t in b.moments(k32))
+    finally:
+        b.close()
+    assert np.isfinite(tot).all()
+    cells_k = np.array([e ** 3 for e, _, _ in spec], dtype=float)
+    nu = (np.array([t for _, _, t in spec]) - 0.5) / 3.0
+    k_darcy = nu * (tot[:, 1] / cells_k) / 1e-6        # k = nu <u_x> / g, rho0 = 1
+    assert (k_darcy > 0).all()
+    # permeability decreases with solid fraction at fixed edge (monotone trend)
+    for e in (32, 64, 96):
+        sel = [i for i, (ee, _, _) in enumerate(spec) if ee == e]
+        phis = np.array([spec[i][1] for i in sel])
+        ks = k_darcy[sel] / nu[sel]
+        assert np.corrcoef(phis, ks)[0, 1] > 0.5
+    # one 32^3 item against the FP64 oracle at full length
+    cfg = OracleConfig(q=19, nx=32, ny=32, nz=32, tau=spec[k32][2], force=(1e-6, 0, 0))
+    g = oracle.run(cfg, fields[k32].astype(np.float64), 2000, nthreads=NT)
+    dr_o, u_o = oracle.observe(cfg, g)
+    eu, er = rel_l2_u(u, u_o), rel_l2_drho(dr, dr_o, u_o)
+    say(f"item {k32} (32^3) vs oracle after 2000 steps: u {eu:.2e} drho {er:.2e}")
+    assert eu <= 1e-5 and er <= 1e-5
