@@ -19,6 +19,10 @@ from .oracle import (  # noqa: F401
     run,
     stream,
     collide,
+    collide_adjoint,
+    stream_adjoint,
+    moments_adjoint,
+    gradient,
     PERIODIC,
     WALL,
     INLET_U,

@@ -396,3 +396,257 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================== */
+/* Discrete adjoint (reverse mode) of the sweep, for gradients with respect  */
+/* to the porosity control d.  The forward map of one step is               */
+/*   y_t = S(x_{t-1})  (pull streaming, linear except at open faces)         */
+/*   x_t = C(y_t, d)   (cell-local collision)                                */
+/* and an objective J observes the moments M(S(x_T)).  The reverse sweep     */
+/* applies the transposed Jacobians in the opposite order.  Everything here  */
+/* is written from those definitions: the collision's Jacobian is formed    */
+/* explicitly, entry by entry, and streaming is transposed as a scatter.     */
+/* ======================================================================== */
+
+/* Shifted equilibrium derivatives at (rho, v): d geq_i / d rho and d geq_i / d v_a. */
+static void equilibrium_derivs(const lattice_t *L, double rho, const double v[3], int i,
+                               double *d_rho, double d_v[3])
+{
+    double cv = L->c[i][0] * v[0] + L->c[i][1] * v[1] + L->c[i][2] * v[2];
+    double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    *d_rho = L->w[i] * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
+    for (int a = 0; a < 3; ++a)
+        d_v[a] = L->w[i] * rho * (3.0 * L->c[i][a] + 9.0 * cv * L->c[i][a] - 3.0 * v[a]);
+}
+
+/* Transposed collision Jacobian of one fluid cell.  Given the pre-collision
+ * populations and the adjoint of the post-collision ones, returns the adjoint
+ * of the pre-collision populations and the derivative of <post_bar, post>
+ * with respect to d.                                                         */
+static void collide_cell_adjoint(const lattice_t *L, const oracle_cfg *cfg, double d,
+                                 const double *pre, const double *post_bar, double *pre_bar,
+                                 double *d_bar)
+{
+    const int q = L->q;
+    const double *F = cfg->force;
+    const double om = 1.0 / cfg->tau, pref = 1.0 - 0.5 / cfg->tau;
+    double s = 0.0, j[3] = { 0.0, 0.0, 0.0 };
+    for (int i = 0; i < q; ++i) {
+        s += pre[i];
+        for (int a = 0; a < 3; ++a) j[a] += L->c[i][a] * pre[i];
+    }
+    double rho = cfg->rho0 + s, u[3], v[3];
+    for (int a = 0; a < 3; ++a) {
+        u[a] = (j[a] + 0.5 * F[a]) / rho;
+        v[a] = (1.0 - d) * u[a];
+    }
+    /* explicit Jacobian J[i][k] = d post_i / d pre_k and Jd[i] = d post_i / d d */
+    double J[19][19], Jd[19];
+    for (int i = 0; i < q; ++i) {
+        double dg_rho, dg_v[3];
+        equilibrium_derivs(L, rho, v, i, &dg_rho, dg_v);
+        double cF = L->c[i][0] * F[0] + L->c[i][1] * F[1] + L->c[i][2] * F[2];
+        double dS_u[3];
+        for (int a = 0; a < 3; ++a) dS_u[a] = pref * L->w[i] * (-3.0 * F[a] + 9.0 * L->c[i][a] * cF);
+        for (int k = 0; k < q; ++k) {
+            double du[3], dv[3];
+            for (int a = 0; a < 3; ++a) {
+                du[a] = (L->c[k][a] - u[a]) / rho;
+                dv[a] = (1.0 - d) * du[a];
+            }
+            double dgeq = dg_rho + dg_v[0] * dv[0] + dg_v[1] * dv[1] + dg_v[2] * dv[2];
+            double dS = dS_u[0] * du[0] + dS_u[1] * du[1] + dS_u[2] * du[2];
+            J[i][k] = (i == k ? 1.0 - om : 0.0) + om * dgeq + dS;
+        }
+        Jd[i] = om * (dg_v[0] * (-u[0]) + dg_v[1] * (-u[1]) + dg_v[2] * (-u[2]));
+    }
+    double db = 0.0;
+    for (int k = 0; k < q; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < q; ++i) acc += J[i][k] * post_bar[i];
+        pre_bar[k] = acc;
+    }
+    for (int i = 0; i < q; ++i) db += Jd[i] * post_bar[i];
+    *d_bar += db;
+}
+
+int oracle_collide_adjoint(const oracle_cfg *cfg, const double *d, const double *pre,
+                           const double *post_bar, double *pre_bar, double *d_bar, int nthreads)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    const int ny = cfg->ny, nz = cfg->nz, nx = cfg->nx, q = cfg->q;
+#pragma omp parallel for collapse(2) num_threads(nthreads) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long cell = cell_index(cfg, x, y, z);
+                if (is_solid(cfg, x, y, z)) {
+                    for (int i = 0; i < q; ++i) pre_bar[i * N + cell] = 0.0;
+                    continue;
+                }
+                double gin[19], pb[19], gb[19];
+                for (int i = 0; i < q; ++i) {
+                    gin[i] = pre[i * N + cell];
+                    pb[i] = post_bar[i * N + cell];
+                }
+                collide_cell_adjoint(&L, cfg, d[cell], gin, pb, gb, &d_bar[cell]);
+                for (int i = 0; i < q; ++i) pre_bar[i * N + cell] = gb[i];
+            }
+    return 0;
+}
+
+/* Transpose of pull streaming at post-collision state `post`, written as a
+ * scatter: every pre-collision population sends its adjoint to whatever it
+ * was read from.  post_bar is overwritten.  Single-threaded (scatter).     */
+int oracle_stream_adjoint(const oracle_cfg *cfg, const double *post, const double *pre_bar,
+                          double *post_bar)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    int n[3];
+    dims(cfg, n);
+    memset(post_bar, 0, sizeof(double) * (size_t)L.q * (size_t)N);
+    for (int z = 0; z < cfg->nz; ++z)
+        for (int y = 0; y < cfg->ny; ++y)
+            for (int x = 0; x < cfg->nx; ++x) {
+                if (is_solid(cfg, x, y, z)) continue;
+                const long cell = cell_index(cfg, x, y, z);
+                int X[3] = { x, y, z };
+                double rho_b = cfg->rho0, jb[3] = { 0.0, 0.0, 0.0 };
+                for (int k = 0; k < L.q; ++k) {
+                    double gk = post[(long)k * N + cell];
+                    rho_b += gk;
+                    for (int a = 0; a < 3; ++a) jb[a] += L.c[k][a] * gk;
+                }
+                for (int i = 0; i < L.q; ++i) {
+                    const double gbar = pre_bar[(long)i * N + cell];
+                    int s[3];
+                    int open_axis = -1, open_side = 0;
+                    for (int a = 0; a < 3; ++a) {
+                        s[a] = X[a] - L.c[i][a];
+                        if (s[a] < 0) {
+                            if (cfg->bc_lo[a] == OR_PERIODIC) s[a] += n[a];
+                            else if (open_axis < 0) { open_axis = a; open_side = -1; }
+                        } else if (s[a] >= n[a]) {
+                            if (cfg->bc_hi[a] == OR_PERIODIC) s[a] -= n[a];
+                            else if (open_axis < 0) { open_axis = a; open_side = +1; }
+                        }
+                    }
+                    if (in_wall_layer(cfg, s)) {
+                        post_bar[(long)L.opp[i] * N + cell] += gbar;
+                    } else if (open_axis < 0) {
+                        post_bar[(long)i * N + cell_index(cfg, s[0], s[1], s[2])] += gbar;
+                    } else {
+                        int kind = open_side < 0 ? cfg->bc_lo[open_axis] : cfg->bc_hi[open_axis];
+                        if (kind == OR_INLET_U) {
+                            /* pre_i = feq_i(rho_b, u_in): depends on every own population via rho_b */
+                            double dr, dv[3];
+                            equilibrium_derivs(&L, rho_b, cfg->inlet_u, i, &dr, dv);
+                            for (int k = 0; k < L.q; ++k) post_bar[(long)k * N + cell] += gbar * dr;
+                        } else {
+                            /* pre_i = feq_i(rho_out, j_b/rho_b) */
+                            double ub[3] = { jb[0] / rho_b, jb[1] / rho_b, jb[2] / rho_b };
+                            double dr, dv[3];
+                            equilibrium_derivs(&L, cfg->outlet_rho, ub, i, &dr, dv);
+                            for (int k = 0; k < L.q; ++k) {
+                                double acc = 0.0;
+                                for (int a = 0; a < 3; ++a) acc += dv[a] * (L.c[k][a] - ub[a]) / rho_b;
+                                post_bar[(long)k * N + cell] += gbar * acc;
+                            }
+                        }
+                    }
+                }
+            }
+    return 0;
+}
+
+/* Transpose of the moments observation at pre-collision populations `pre`:
+ * pre_bar = d/dpre of sum_cells (drho_bar*drho + u_bar.u).                   */
+int oracle_moments_adjoint(const oracle_cfg *cfg, const double *pre, const double *drho_bar,
+                           const double *u_bar, double *pre_bar)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    for (int z = 0; z < cfg->nz; ++z)
+        for (int y = 0; y < cfg->ny; ++y)
+            for (int x = 0; x < cfg->nx; ++x) {
+                const long cell = cell_index(cfg, x, y, z);
+                if (is_solid(cfg, x, y, z)) {
+                    for (int k = 0; k < L.q; ++k) pre_bar[(long)k * N + cell] = 0.0;
+                    continue;
+                }
+                double s = 0.0, j[3] = { 0.0, 0.0, 0.0 };
+                for (int k = 0; k < L.q; ++k) {
+                    double g = pre[(long)k * N + cell];
+                    s += g;
+                    for (int a = 0; a < 3; ++a) j[a] += L.c[k][a] * g;
+                }
+                double rho = cfg->rho0 + s, u[3];
+                for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * cfg->force[a]) / rho;
+                for (int k = 0; k < L.q; ++k) {
+                    double acc = drho_bar[cell];
+                    for (int a = 0; a < 3; ++a) acc += u_bar[a * N + cell] * (L.c[k][a] - u[a]) / rho;
+                    pre_bar[(long)k * N + cell] = acc;
+                }
+            }
+    return 0;
+}
+
+/* Gradient of J = J(moments after nsteps from rest) with respect to d, given
+ * dJ/d(drho) and dJ/du at that time level.  Checkpoints every `every` steps
+ * and recomputes each segment on the way back.  d_bar is accumulated (+=).  */
+int oracle_gradient(const oracle_cfg *cfg, const double *d, int nsteps, int every,
+                    const double *drho_bar, const double *u_bar, double *d_bar, int nthreads)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    if (nsteps < 0 || every < 1) return -1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    const size_t S = (size_t)L.q * (size_t)N;
+    const int ncp = nsteps / every + 1;
+    double *cps = (double *)calloc((size_t)ncp * S, sizeof(double));
+    double *seg = (double *)malloc((size_t)(every + 1) * S * sizeof(double));
+    double *pre = (double *)malloc(S * sizeof(double));
+    double *xbar = (double *)malloc(S * sizeof(double));
+    double *ybar = (double *)malloc(S * sizeof(double));
+    double *x = (double *)calloc(S, sizeof(double));
+    if (!cps || !seg || !pre || !xbar || !ybar || !x) {
+        free(cps); free(seg); free(pre); free(xbar); free(ybar); free(x);
+        return -2;
+    }
+    /* forward with checkpoints: cps[m] = state after m*every steps */
+    for (int t = 0; t < nsteps; ++t) {
+        if (t % every == 0) memcpy(cps + (size_t)(t / every) * S, x, S * sizeof(double));
+        oracle_stream(cfg, x, pre, nthreads);
+        oracle_collide(cfg, d, pre, x, nthreads);
+    }
+    if (nsteps % every == 0) memcpy(cps + (size_t)(nsteps / every) * S, x, S * sizeof(double));
+    /* observation adjoint at the final time level */
+    oracle_stream(cfg, x, pre, nthreads);
+    oracle_moments_adjoint(cfg, pre, drho_bar, u_bar, ybar);
+    oracle_stream_adjoint(cfg, x, ybar, xbar);
+    /* reverse over segments */
+    for (int m = (nsteps - 1) / every; m >= 0 && nsteps > 0; --m) {
+        const int t0 = m * every;
+        const int t1 = (t0 + every < nsteps) ? t0 + every : nsteps;
+        memcpy(seg, cps + (size_t)m * S, S * sizeof(double));
+        for (int t = t0; t < t1; ++t) {
+            oracle_stream(cfg, seg + (size_t)(t - t0) * S, pre, nthreads);
+            oracle_collide(cfg, d, pre, seg + (size_t)(t - t0 + 1) * S, nthreads);
+        }
+        for (int t = t1; t > t0; --t) {
+            /* step t: y_t = S(x_{t-1}), x_t = C(y_t, d) */
+            const double *xprev = seg + (size_t)(t - 1 - t0) * S;
+            oracle_stream(cfg, xprev, pre, nthreads);
+            oracle_collide_adjoint(cfg, d, pre, xbar, ybar, d_bar, nthreads);
+            oracle_stream_adjoint(cfg, xprev, ybar, xbar);
+        }
+    }
+    free(cps); free(seg); free(pre); free(xbar); free(ybar); free(x);
+    return 0;
+}

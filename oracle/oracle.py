@@ -216,3 +216,67 @@ def observe(cfg: OracleConfig, g, nthreads: int = 1):
     _check(_load().oracle_observe(ctypes.byref(s), _dp(g), _dp(drho), _dp(u), nthreads),
            "observe")
     return drho, u
+
+
+# ---------------------------------------------------------------------------
+# Discrete adjoint
+# ---------------------------------------------------------------------------
+def _adj_load():
+    lib = _load()
+    if not getattr(lib, "_adj_ready", False):
+        P = ctypes.POINTER
+        D = P(ctypes.c_double)
+        C = P(_Cfg)
+        lib.oracle_collide_adjoint.argtypes = [C, D, D, D, D, D, ctypes.c_int]
+        lib.oracle_stream_adjoint.argtypes = [C, D, D, D]
+        lib.oracle_moments_adjoint.argtypes = [C, D, D, D, D]
+        lib.oracle_gradient.argtypes = [C, D, ctypes.c_int, ctypes.c_int, D, D, D, ctypes.c_int]
+        lib._adj_ready = True
+    return lib
+
+
+def collide_adjoint(cfg: OracleConfig, d, pre, post_bar, nthreads: int = 1):
+    """(pre_bar, d_bar) of one collision pass."""
+    pre = _state(cfg, pre)
+    pb = _state(cfg, post_bar)
+    out = np.zeros_like(pre)
+    dbar = np.zeros(cfg.ncells)
+    s = cfg.c_struct()
+    _check(_adj_load().oracle_collide_adjoint(ctypes.byref(s), _dp(_field(cfg, d)), _dp(pre),
+                                              _dp(pb), _dp(out), _dp(dbar), nthreads),
+           "collide_adjoint")
+    return out, dbar
+
+
+def stream_adjoint(cfg: OracleConfig, post, pre_bar):
+    post = _state(cfg, post)
+    yb = _state(cfg, pre_bar)
+    out = np.zeros_like(post)
+    s = cfg.c_struct()
+    _check(_adj_load().oracle_stream_adjoint(ctypes.byref(s), _dp(post), _dp(yb), _dp(out)),
+           "stream_adjoint")
+    return out
+
+
+def moments_adjoint(cfg: OracleConfig, pre, drho_bar, u_bar):
+    pre = _state(cfg, pre)
+    db = np.ascontiguousarray(np.asarray(drho_bar, dtype=np.float64).reshape(cfg.ncells))
+    ub = np.ascontiguousarray(np.asarray(u_bar, dtype=np.float64).reshape(3, cfg.ncells))
+    out = np.zeros_like(pre)
+    s = cfg.c_struct()
+    _check(_adj_load().oracle_moments_adjoint(ctypes.byref(s), _dp(pre), _dp(db), _dp(ub),
+                                              _dp(out)), "moments_adjoint")
+    return out
+
+
+def gradient(cfg: OracleConfig, d, nsteps: int, drho_bar, u_bar, every: int = 10,
+             nthreads: int = 1) -> np.ndarray:
+    """d/dd of <drho_bar, drho> + <u_bar, u> at the moments after nsteps from rest."""
+    db = np.ascontiguousarray(np.asarray(drho_bar, dtype=np.float64).reshape(cfg.ncells))
+    ub = np.ascontiguousarray(np.asarray(u_bar, dtype=np.float64).reshape(3, cfg.ncells))
+    out = np.zeros(cfg.ncells)
+    s = cfg.c_struct()
+    _check(_adj_load().oracle_gradient(ctypes.byref(s), _dp(_field(cfg, d)), int(nsteps),
+                                       int(every), _dp(db), _dp(ub), _dp(out), nthreads),
+           "gradient")
+    return out
