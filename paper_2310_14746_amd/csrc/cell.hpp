@@ -5,6 +5,13 @@
 #include "lattice.hpp"
 #include "storage.hpp"
 
+// Multiply-add fusion only inside one source expression.  The default lets the
+// code generator fuse across expressions, and its choices then depend on the
+// surrounding kernel; with this setting every kernel that runs the same cell
+// code (the single-lattice sweep, the batched step and the persistent batch)
+// rounds identically, so their results agree bit for bit.
+#pragma clang fp contract(on)
+
 namespace hlbm {
 
 // Element `idx` of a population row addressed by a 32-bit byte offset from a
