@@ -36,7 +36,9 @@ FORCE = (1e-6, 0.0, 0.0)
 SCALE_16 = 2.0 ** 24
 ALG_BYTES = {"f32": 19 * 4 * 2 + 4, "f16s": 19 * 2 * 2 + 2, "bf16s": 19 * 2 * 2 + 2}
 COUNTERS = os.path.join(ROOT, "profiles", "sweep_d3q19_f32_512_counters.json")
-SWEEP_SRC = os.path.join(ROOT, "paper_2310_14746_amd", "csrc", "sweep.hip")
+# sources the FP32 sweep kernel is compiled from (counters are valid for them only)
+SWEEP_SRCS = [os.path.join(ROOT, "paper_2310_14746_amd", "csrc", f)
+              for f in ("sweep.hip", "cell.hpp", "lattice.hpp", "storage.hpp", "hlbm_internal.hpp")]
 METRIC = "MLUPS and % HBM roofline, D3Q19 HLBM 512^3; FP16-storage vs FP32 at stated L2 error"
 
 
@@ -137,16 +139,77 @@ def summarize_profile(path):
     return "\n".join(out)
 
 
+def sweep_sources_sha256():
+    h = hashlib.sha256()
+    for f in SWEEP_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def counters_traffic(n_cells):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current sweep source."""
+    was taken on the current sweep sources."""
     if not os.path.exists(COUNTERS):
         return None
     info = json.load(open(COUNTERS))
-    h = hashlib.sha256(open(SWEEP_SRC, "rb").read()).hexdigest()
-    if info.get("sweep_sha256") != h or info.get("cells") != n_cells:
+    if info.get("sweep_sources_sha256") != sweep_sources_sha256() or info.get("cells") != n_cells:
         return None
     return info.get("hbm_bytes_per_launch")
+
+
+SWEEP_F32 = "hlbm::sweep_kernel<hlbm::D3Q19, hlbm::StoreF32, 0>"
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def summarize_counters(fetch_dir, write_dir, n_cells=N_EDGE ** 3):
+    """HBM traffic of the FP32 512^3 sweep from two rocprofv3 --pmc runs of
+    bench.py (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch).  Each counter is
+    scaled by what it reads for the 4 GiB device copy that the same run makes
+    (copy_reference: 4 GiB read, 4 GiB written).  Writes the JSON record bench
+    reads and returns a markdown summary."""
+    import csv
+    import glob
+
+    def per_dispatch(path, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"]
+                key = ("sweep" if name.startswith("void " + SWEEP_F32) else
+                       "copy" if name.startswith(COPY_KERNEL) and int(r["Grid_Size"]) > 4096 else None)
+                if key:
+                    vals.setdefault(key, []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
+
+    fetch, nf = per_dispatch(fetch_dir, "FETCH_SIZE")
+    write, nw = per_dispatch(write_dir, "WRITE_SIZE")
+    copy_bytes = 4.0 * 2 ** 30
+    f_scale = copy_bytes / (fetch["copy"] * 1024)
+    w_scale = copy_bytes / (write["copy"] * 1024)
+    rd = fetch["sweep"] * 1024 * f_scale
+    wr = write["sweep"] * 1024 * w_scale
+    alg_rd, alg_wr = n_cells * (19 * 4 + 4), n_cells * 19 * 4
+    info = {
+        "kernel": SWEEP_F32, "cells": n_cells, "sweep_sources_sha256": sweep_sources_sha256(),
+        "fetch_kib_per_dispatch": round(fetch["sweep"], 1), "write_kib_per_dispatch": round(write["sweep"], 1),
+        "fetch_scale_from_copy": round(f_scale, 5), "write_scale_from_copy": round(w_scale, 5),
+        "hbm_read_bytes_per_launch": round(rd), "hbm_write_bytes_per_launch": round(wr),
+        "hbm_bytes_per_launch": round(rd + wr),
+        "algorithmic_bytes_per_launch": alg_rd + alg_wr,
+        "dispatches": {"fetch": nf, "write": nw},
+    }
+    json.dump(info, open(COUNTERS, "w"), indent=1)
+    return "\n".join([
+        "| quantity | read | write | total |", "|---|---|---|---|",
+        f"| counter, KiB per dispatch | {fetch['sweep']:.1f} (FETCH_SIZE) | {write['sweep']:.1f} (WRITE_SIZE) | |",
+        f"| copy calibration (4 GiB copy) | x{f_scale:.4f} | x{w_scale:.4f} | |",
+        f"| HBM bytes per launch | {rd / 1e9:.3f} GB | {wr / 1e9:.3f} GB | {(rd + wr) / 1e9:.3f} GB |",
+        f"| algorithmic bytes per launch | {alg_rd / 1e9:.3f} GB | {alg_wr / 1e9:.3f} GB | "
+        f"{(alg_rd + alg_wr) / 1e9:.3f} GB |",
+        f"| HBM / algorithmic | {rd / alg_rd:.4f} | {wr / alg_wr:.4f} | {(rd + wr) / (alg_rd + alg_wr):.4f} |",
+    ])
 
 
 def time_batched(hlbm, steps=2000, seed=0):
@@ -194,6 +257,56 @@ def time_batched(hlbm, steps=2000, seed=0):
     return out
 
 
+ADJ_BYTES = 19 * 8 * 2 + 19 * 4 + 4 + 16  # adjoint kernel, FP32 forward: lam in/out, x, d, dJ/dd r+w
+
+
+def time_gradient(hlbm, steps=500, every=50, seed=0):
+    """Differentiation workload: D3Q19 128x64x64 channel, inlet u = 0.02,
+    outlet rho = 1, walls in y and z, d ~ U[0,1), FP32 forward / FP64 adjoint,
+    500 steps with a checkpoint every 50; gradient of the channel objective
+    through torch.autograd (forward with tape, objective, backward)."""
+    import torch
+    from paper_2310_14746_amd import inputs
+    from paper_2310_14746_amd.autograd import channel_objective, moments_of_porosity
+    shape = (128, 64, 64)
+    nx, ny, nz = shape
+    cells = nx * ny * nz
+    kw = dict(tau=0.6, bc_lo=(2, 1, 1), bc_hi=(3, 1, 1), inlet_u=(0.02, 0, 0), outlet_rho=1.0)
+    sim = hlbm.HLBM(19, "f32", shape, **kw)
+    try:
+        d = torch.tensor(inputs.uniform_noise((nz, ny, nx), seed), dtype=torch.float64,
+                         device=sim.device, requires_grad=True)
+        times = []
+        for rep in range(4):
+            d.grad = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            drho, u = moments_of_porosity(d, sim, steps, every)
+            J = channel_objective(drho, u, d, kw["tau"])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            J.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if rep:
+                times.append((t1 - t0, t2 - t1))
+        fwd = float(np.median([a for a, _ in times]))
+        bwd = float(np.median([b for _, b in times]))
+        replays = steps - (steps + every - 1) // every
+        moved = cells * (steps * ADJ_BYTES + replays * 156)
+        tape = sim.tape_info()["device_bytes"]
+    finally:
+        sim.close()
+    log(f"gradient: forward {fwd * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms")
+    return {"workload": "D3Q19 128x64x64 channel, inlet u=0.02, outlet rho=1, walls y/z, d~U[0,1) seed 0, "
+                        "tau=0.6, 500 steps, checkpoint every 50, FP32 forward / FP64 adjoint, "
+                        "J = pressure drop + 0.1 dissipation",
+            "forward_ms": round(fwd * 1e3, 2), "backward_ms": round(bwd * 1e3, 2),
+            "backward_alg_GBs": round(moved / bwd / 1e9, 1),
+            "adjoint_bytes_per_cell_step": ADJ_BYTES, "replay_steps": replays,
+            "tape_MiB": round(tape / 2 ** 20, 1)}
+
+
 def cpu_baseline(steps_total):
     """Oracle on a 64^3 crop (2^3 obstacle cells; exact by periodicity) -> MLUPS."""
     import oracle
@@ -237,13 +350,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-reference", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true")
     ap.add_argument("--block-x", type=int, default=-1,
                     help="threads per block along x (-1: tuned value, 0: library default)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the sweep's HBM traffic record from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print a per-kernel summary of a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile))
+        return
+    if args.summarize_counters:
+        print(summarize_counters(*args.summarize_counters))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -268,6 +387,7 @@ def main():
         results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq, block_x=bx)
     copy_ref = None if args.no_copy_reference else copy_reference()
     batched = None if args.no_batched else time_batched(hlbm)
+    gradient = None if args.no_gradient else time_gradient(hlbm)
 
     cpu, refs = None, {}
     if not args.no_cpu_baseline:
@@ -315,6 +435,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": {},
         "batched": batched,
+        "gradient": gradient,
     }
     for f in forms:
         r = results[f]

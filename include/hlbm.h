@@ -184,6 +184,77 @@ int hlbm_reset(hlbm_ctx *ctx);
  * batch, if a grid barrier of the persistent kernel timed out). */
 int hlbm_sync(hlbm_ctx *ctx);
 
+/* Diagnostics taken inside the sweep.  With every > 0, each hlbm_step sweep
+ * that starts from a time level n with n % every == 0 also reduces the moments
+ * it forms (those of time level n, as hlbm_moments would report them) to FP64
+ * totals over fluid cells -- sum (rho - rho0), sum rho u_x, sum rho u_y,
+ * sum rho u_z -- by a wavefront reduction, per-block partials and a
+ * fixed-order two-pass sum, and appends them to a device log of `capacity`
+ * records; further records are dropped (and counted) until the log is read.
+ * The totals equal those hlbm_moments returns at that time level, bit for
+ * bit.  every = 0 switches this off and frees the log.  Waits for the stream. */
+int hlbm_set_diagnostics(hlbm_ctx *ctx, int every, int capacity);
+
+/* Move up to max_records records, oldest first, into out[5*k ...]:
+ * (n, sum (rho - rho0), sum rho u_x, sum rho u_y, sum rho u_z), n stored as a
+ * double.  *count receives the records written; *dropped (may be NULL) the
+ * records lost since the last read (log full, or beyond max_records).  The log
+ * is emptied.  ENUMERIC if a total is not finite (records are still written).
+ * Waits for the stream. */
+int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *count,
+                          long long *dropped);
+
+/* ------------------------------------------------------------------------
+ * Discrete adjoint (reverse mode) for gradients with respect to the porosity
+ * control d (the optimization variable of the homogenized model: varpi is a
+ * design field, Sec. 3.2).
+ *
+ * The gradient is that of the discrete scheme itself: one step is pull
+ * streaming S followed by the cell-local collision C(., d), and an objective
+ * J observes the moments (drho, u) of the current time level (definitions as
+ * for hlbm_moments).  Given dJ/d(drho) and dJ/du at the current time level,
+ * hlbm_adjoint_step applies the transposed Jacobians of the last `nsteps`
+ * steps in reverse order, carrying FP64 adjoint populations, and adds
+ *   sum over those steps of (dJ/dx_t) . dC(y_t, d)/dd
+ * to dJ_dd: the derivative of J with respect to d through those steps (the
+ * state before them held fixed).  Explicit dependences of J on d are the
+ * caller's to add.
+ *
+ * The forward states are recovered from a tape: with a tape set, hlbm_step
+ * stores the state every `every` steps (checkpoints); the reverse sweep
+ * recomputes each segment of `every` steps from its checkpoint.  The tape
+ * records from the state current when it is set and restarts at the current
+ * state whenever the state or the porosity changes otherwise (hlbm_set_state,
+ * hlbm_reset, hlbm_set_porosity, hlbm_bind_buffers).
+ *
+ * Single contexts only (a batch returns EUNSUPPORTED).  Requires
+ * nx*ny*nz*8 < 4 GiB.
+ * ------------------------------------------------------------------------ */
+
+/* Allocate a tape for up to `max_steps` forward steps with a checkpoint every
+ * `every` >= 1 steps, and start recording at the current state.  Device memory:
+ * (max_steps/every + 1) checkpoints and every-1 replay states, each one
+ * population buffer, plus two FP64 adjoint buffers of Q*N doubles.  every = 0
+ * frees the tape.  hlbm_step returns EINVAL (and does nothing) if it would
+ * take the recorded steps past max_steps.  Waits for the stream. */
+int hlbm_set_tape(hlbm_ctx *ctx, int every, int max_steps);
+
+/* The tape's every and max_steps (0 when none), the steps recorded since its
+ * origin, and its device bytes.  Any output may be NULL. */
+int hlbm_tape_info(const hlbm_ctx *ctx, int *every, int *max_steps, long long *recorded,
+                   size_t *device_bytes);
+
+/* Reverse sweep over the last nsteps recorded steps (0 <= nsteps <= recorded).
+ * dJ_drho[N] and dJ_du[3][N] (x fastest, u component-major as in
+ * hlbm_moments; entries of solid cells are ignored) are FP64 cotangents of the
+ * moments at the current time level; dJ_dd[N] (FP64) is accumulated (+=).
+ * All three arrays are device memory if on_device, else host memory.  The
+ * current state and the step counter are unchanged.  ESTATE without a tape;
+ * EINVAL for nsteps outside the recorded range or a NULL array.  Waits for
+ * the stream. */
+int hlbm_adjoint_step(hlbm_ctx *ctx, int nsteps, const double *dJ_drho, const double *dJ_du,
+                      double *dJ_dd, int on_device);
+
 /* ------------------------------------------------------------------------
  * Batched periodic boxes.
  *

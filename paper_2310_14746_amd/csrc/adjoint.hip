@@ -1,0 +1,388 @@
+// Discrete adjoint of the sweep (reverse mode) for gradients of an objective
+// of the moments with respect to the porosity control d = 1 - varpi.
+//
+// One forward step is y_t = S(x_{t-1}) (pull streaming) followed by
+// x_t = C(y_t, d) (the homogenized BGK collision of Sec. 3.2, cell-local), and
+// the objective observes the moments M(S(x_T)).  The reverse sweep carries the
+// adjoint of the pre-collision populations, lambda_t = dJ/dy_t, in FP64:
+//
+//   lambda_{T+1} = M^T (dJ/drho, dJ/du)                         (seed kernel)
+//   lambda_t     = C_y(y_t, d)^T S^T lambda_{t+1},
+//   dJ/dd       += C_d(y_t, d)^T S^T lambda_{t+1}              (adjoint kernel)
+//
+// for t = T, T-1, ...  Both kernels are per-cell gathers with the sweep's
+// launch geometry:
+//   * S^T as a gather.  Pull streaming reads population k of cell x + c_k, so
+//     its transpose reads the adjoint of population k at x + c_k.  Where the
+//     forward rule at x for direction opp(k) bounced back, the transpose reads
+//     this cell's own opp(k) adjoint; where it took an open-face equilibrium
+//     built from this cell's post-collision state, the transpose adds that
+//     equilibrium's derivative.  The classification per direction is the
+//     forward gather's own (same helpers), with +c_k in place of -c_k.
+//   * C^T by the chain rule through the moments: with A = sum_i pb_i g^eq_i
+//     and B = sum_i pb_i S_i, the adjoint needs only the weighted moments
+//     P0 = sum w pb, P1 = sum w c pb, P2 = sum w c c pb of the incoming adjoint
+//     pb, not the 19x19 Jacobian.
+//   * The post-collision moments of this cell at step t, needed by the
+//     open-face derivatives, follow from y_t by the collision's balance laws
+//     (mass kept, momentum (1 - omega) j + omega rho u_eq + (1 - 1/(2 tau)) F),
+//     so x_t itself is never read.
+//
+// Layout: adjoint populations are FP64 rows lam[k*N + cell] (the forward
+// state's layout); dJ/dd is one FP64 value per cell, accumulated.  Blocks
+// hold at most 256 threads (the FP64 adjoint needs more registers than a
+// 1024-thread block leaves per thread); the launchers clamp the block width.
+#include "cell.hpp"
+
+namespace hlbm {
+
+// FP64 moments of the pre-collision populations gathered at one cell.
+struct Moms {
+    double s, jx, jy, jz;
+};
+
+template <class L, class R>
+__device__ __forceinline__ Moms moments_f64(const R (&g)[L::Q])
+{
+    Moms m{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double gi = (double)g[i];
+        m.s += gi;
+        if (L::cx[i]) m.jx += L::cx[i] > 0 ? gi : -gi;
+        if (L::cy[i]) m.jy += L::cy[i] > 0 ? gi : -gi;
+        if (L::cz[i]) m.jz += L::cz[i] > 0 ? gi : -gi;
+    }
+    return m;
+}
+
+// Gather of the forward pre-collision populations y at (x, y, z) from the
+// post-collision state `src`, reduced at once to FP64 moments.
+template <class L, class S, int BC>
+__device__ __forceinline__ Moms forward_moments(const typename S::T* __restrict__ src, const Params& p,
+                                                uint32_t x, uint32_t y, uint32_t z)
+{
+    using R = typename S::R;
+    const R inv_scale = R(p.inv_scale);
+    R g[L::Q];
+    if (BC == BC_PERIODIC) {
+        gather_periodic<L, S>(src, p.N, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+    } else {
+        const Box b = box_of(p);
+        const OpenFaces<R> of{R(p.rho0), R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
+                              R(p.outlet_rho)};
+        gather_general<L, S>(src, p.N, b, of, (int)x, (int)y, (int)z, inv_scale, g);
+    }
+    return moments_f64<L, R>(g);
+}
+
+// ---------------------------------------------------------------------------
+// Seed: lambda_k = dJ/ddrho + sum_a dJ/du_a (c_ka - u_a)/rho at the moments'
+// time level (drho = sum g, u = (j + F/2)/rho).  Solid cells get zeros.
+// ---------------------------------------------------------------------------
+template <class L, class S, int BC>
+__global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* __restrict__ src,
+                                                            const double* __restrict__ drho_bar,
+                                                            const double* __restrict__ u_bar,
+                                                            double* __restrict__ lam, Params p)
+{
+    const uint32_t N = p.N;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (uint32_t)p.nx) return;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
+    const Moms m = forward_moments<L, S, BC>(src, p, x, y, z);
+    const double inv_rho = 1.0 / (p.rho0 + m.s);
+    const double ux = (m.jx + 0.5 * p.F[0]) * inv_rho;
+    const double uy = (m.jy + 0.5 * p.F[1]) * inv_rho;
+    const double uz = (m.jz + 0.5 * p.F[2]) * inv_rho;
+    const double rb = ld(drho_bar, cell);
+    const double bx = ld(u_bar, cell) * inv_rho;
+    const double by = ld(u_bar + N, cell) * inv_rho;
+    const double bz = ld(u_bar + 2 * (size_t)N, cell) * inv_rho;
+    const double base = rb - (bx * ux + by * uy + bz * uz);
+    bool solid = false;
+    if (BC != BC_PERIODIC) solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        const double v = base + double(L::cx[k]) * bx + double(L::cy[k]) * by + double(L::cz[k]) * bz;
+        st(lam + (size_t)k * N, cell, sel(solid, 0.0, v));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// S^T: adjoint of the post-collision populations of this cell from the
+// adjoint of the next step's pre-collision populations.
+// ---------------------------------------------------------------------------
+template <class L>
+__device__ __forceinline__ void stream_adjoint_periodic(const double* __restrict__ lam, uint32_t N,
+                                                        const Params& p, uint32_t x, uint32_t y,
+                                                        uint32_t z, double (&pb)[L::Q])
+{
+    const uint32_t nx = p.nx, ny = p.ny, nz = p.nz;
+    // x + c for c = -1, 0, +1 (index c + 1), wrapped
+    const uint32_t xs[3] = {x == 0 ? nx - 1 : x - 1, x, x + 1 == nx ? 0u : x + 1};
+    const uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y + 1 == ny ? 0u : y + 1};
+    const uint32_t zs[3] = {z == 0 ? nz - 1 : z - 1, z, z + 1 == nz ? 0u : z + 1};
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        const uint32_t off = xs[L::cx[k] + 1] + nx * (ys[L::cy[k] + 1] + ny * zs[L::cz[k] + 1]);
+        pb[k] = ld(lam + (size_t)k * N, off);
+    }
+}
+
+// Walls and open faces.  `rho_b`, (ubx, uby, ubz) are this cell's
+// post-collision density and velocity j_b/rho_b at the forward step whose
+// open-face equilibria are being differentiated.
+template <class L>
+__device__ __forceinline__ void stream_adjoint_general(const double* __restrict__ lam, uint32_t N,
+                                                       const Params& p, int x, int y, int z,
+                                                       double rho_b, double ubx, double uby,
+                                                       double ubz, double (&pb)[L::Q])
+{
+    const Box b = box_of(p);
+    const uint32_t cell = (uint32_t)x + (uint32_t)b.nx * ((uint32_t)y + (uint32_t)b.ny * (uint32_t)z);
+    const bool px = b.lo0 == 0, py = b.lo1 == 0, pz = b.lo2 == 0;
+    const double uix = p.inlet_u[0], uiy = p.inlet_u[1], uiz = p.inlet_u[2];
+    const double uin2 = uix * uix + uiy * uiy + uiz * uiz;
+    const double rout = p.outlet_rho;
+    double a_in = 0.0, bvx = 0.0, bvy = 0.0, bvz = 0.0;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        // neighbour x + c_k = x - c_opp(k): the forward source of direction opp(k) at x
+        const int sx = wrap_source(x, -L::cx[k], b.nx, px);
+        const int sy = wrap_source(y, -L::cy[k], b.ny, py);
+        const int sz = wrap_source(z, -L::cz[k], b.nz, pz);
+        const bool wall = in_wall_layer(b, sx, sy, sz);
+        const bool out_x = (sx < 0) | (sx >= b.nx);
+        const bool out_y = (sy < 0) | (sy >= b.ny);
+        const bool out_z = (sz < 0) | (sz >= b.nz);
+        const bool outside = out_x | out_y | out_z;
+        const bool own = wall | outside;
+        const uint32_t noff = (uint32_t)sx + (uint32_t)b.nx * ((uint32_t)sy + (uint32_t)b.ny * (uint32_t)sz);
+        const uint32_t row = sel(own, (uint32_t)opposite(k), (uint32_t)k);
+        const uint32_t off = sel(own, cell, noff);
+        const double v = ld(lam + (size_t)row * N, off);
+        const bool open = outside & !wall;
+        pb[k] = sel(open, 0.0, v);
+        // open face: v is the adjoint of this cell's pre-collision population
+        // i = opp(k), which the forward step took from an equilibrium
+        const int kx = sel(sx < 0, b.lo0, b.hi0);
+        const int ky = sel(sy < 0, b.lo1, b.hi1);
+        const int kz = sel(sz < 0, b.lo2, b.hi2);
+        const int kind = sel(out_x, kx, sel(out_y, ky, kz));
+        const bool inlet = kind == 2;
+        const int i = opposite(k);
+        const double w = L::w[i];
+        const double cix = L::cx[i], ciy = L::cy[i], ciz = L::cz[i];
+        const double cin = cix * uix + ciy * uiy + ciz * uiz;
+        // inlet f^eq(rho_b, u_in): d/d rho_b
+        const double d_in = w * (1.0 + 3.0 * cin + 4.5 * cin * cin - 1.5 * uin2);
+        a_in += sel(open & inlet, v * d_in, 0.0);
+        // outlet f^eq(rho_out, u_b): d/d u_b
+        const double cub = cix * ubx + ciy * uby + ciz * ubz;
+        const double wv = sel(open & !inlet, v * w * rout, 0.0);
+        bvx += wv * (3.0 * cix + 9.0 * cub * cix - 3.0 * ubx);
+        bvy += wv * (3.0 * ciy + 9.0 * cub * ciy - 3.0 * uby);
+        bvz += wv * (3.0 * ciz + 9.0 * cub * ciz - 3.0 * ubz);
+    }
+    // rho_b depends on every own population with weight 1, u_b = j_b/rho_b
+    const double inv_b = 1.0 / rho_b;
+    const double common = a_in - (bvx * ubx + bvy * uby + bvz * ubz) * inv_b;
+    const double gx = bvx * inv_b, gy = bvy * inv_b, gz = bvz * inv_b;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k)
+        pb[k] += common + double(L::cx[k]) * gx + double(L::cy[k]) * gy + double(L::cz[k]) * gz;
+}
+
+// ---------------------------------------------------------------------------
+// C^T of one fluid cell.  In: the FP64 moments of y, d, and pb = adjoint of
+// the post-collision populations.  Out: pb overwritten with the adjoint of
+// the pre-collision populations; returns this step's dJ/dd contribution.
+//   u = (j + F/2)/rho, v = (1 - d) u
+//   dA/drho = P0 (1 - 3/2 v.v) + 3 P1.v + 9/2 v.P2.v
+//   dA/dv   = rho (3 P1 + 9 P2 v - 3 P0 v)
+//   dB/du   = (1 - 1/(2 tau)) (9 P2 F - 3 P0 F)
+//   ubar    = omega (1 - d) dA/dv + dB/du
+//   pre_k   = (1 - omega) pb_k + omega dA/drho - ubar.u/rho + c_k.ubar/rho
+//   dJ/dd  += -omega dA/dv . u
+// ---------------------------------------------------------------------------
+template <class L>
+__device__ __forceinline__ double collide_adjoint(const Moms& m, double d, const Params& p,
+                                                  double (&pb)[L::Q])
+{
+    const double om = p.omega, pref = p.pref;
+    const double F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
+    const double rho = p.rho0 + m.s, inv_rho = 1.0 / rho;
+    const double ux = (m.jx + 0.5 * F0) * inv_rho;
+    const double uy = (m.jy + 0.5 * F1) * inv_rho;
+    const double uz = (m.jz + 0.5 * F2) * inv_rho;
+    const double sh = 1.0 - d;
+    const double vx = sh * ux, vy = sh * uy, vz = sh * uz;
+    double P0 = 0.0, Px = 0.0, Py = 0.0, Pz = 0.0;
+    double Pxx = 0.0, Pyy = 0.0, Pzz = 0.0, Pxy = 0.0, Pxz = 0.0, Pyz = 0.0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double wp = L::w[i] * pb[i];
+        P0 += wp;
+        if (L::cx[i]) Px += L::cx[i] > 0 ? wp : -wp;
+        if (L::cy[i]) Py += L::cy[i] > 0 ? wp : -wp;
+        if (L::cz[i]) Pz += L::cz[i] > 0 ? wp : -wp;
+        if (L::cx[i]) Pxx += wp;
+        if (L::cy[i]) Pyy += wp;
+        if (L::cz[i]) Pzz += wp;
+        if (L::cx[i] * L::cy[i]) Pxy += L::cx[i] * L::cy[i] > 0 ? wp : -wp;
+        if (L::cx[i] * L::cz[i]) Pxz += L::cx[i] * L::cz[i] > 0 ? wp : -wp;
+        if (L::cy[i] * L::cz[i]) Pyz += L::cy[i] * L::cz[i] > 0 ? wp : -wp;
+    }
+    const double Pvx = Pxx * vx + Pxy * vy + Pxz * vz;
+    const double Pvy = Pxy * vx + Pyy * vy + Pyz * vz;
+    const double Pvz = Pxz * vx + Pyz * vy + Pzz * vz;
+    const double vv = vx * vx + vy * vy + vz * vz;
+    const double A_rho = P0 * (1.0 - 1.5 * vv) + 3.0 * (Px * vx + Py * vy + Pz * vz) +
+                         4.5 * (vx * Pvx + vy * Pvy + vz * Pvz);
+    const double Avx = rho * (3.0 * Px + 9.0 * Pvx - 3.0 * vx * P0);
+    const double Avy = rho * (3.0 * Py + 9.0 * Pvy - 3.0 * vy * P0);
+    const double Avz = rho * (3.0 * Pz + 9.0 * Pvz - 3.0 * vz * P0);
+    const double PFx = Pxx * F0 + Pxy * F1 + Pxz * F2;
+    const double PFy = Pxy * F0 + Pyy * F1 + Pyz * F2;
+    const double PFz = Pxz * F0 + Pyz * F1 + Pzz * F2;
+    const double ubx = om * sh * Avx + pref * (9.0 * PFx - 3.0 * F0 * P0);
+    const double uby = om * sh * Avy + pref * (9.0 * PFy - 3.0 * F1 * P0);
+    const double ubz = om * sh * Avz + pref * (9.0 * PFz - 3.0 * F2 * P0);
+    const double rbar = om * A_rho - (ubx * ux + uby * uy + ubz * uz) * inv_rho;
+    const double jbx = ubx * inv_rho, jby = uby * inv_rho, jbz = ubz * inv_rho;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k)
+        pb[k] = (1.0 - om) * pb[k] + rbar + double(L::cx[k]) * jbx + double(L::cy[k]) * jby +
+                double(L::cz[k]) * jbz;
+    return -om * (Avx * ux + Avy * uy + Avz * uz);
+}
+
+// ---------------------------------------------------------------------------
+// One reverse step t: lam_out = lambda_t from lam_in = lambda_{t+1}, with the
+// forward state x_{t-1} in `xprev`; dbar += this step's dJ/dd.
+// ---------------------------------------------------------------------------
+template <class L, class S, int BC>
+__global__ __launch_bounds__(256) void adjoint_kernel(const double* __restrict__ lam_in,
+                                                       double* __restrict__ lam_out,
+                                                       const typename S::T* __restrict__ xprev,
+                                                       const typename S::D* __restrict__ dfield,
+                                                       double* __restrict__ dbar, Params p)
+{
+    const uint32_t N = p.N;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (uint32_t)p.nx) return;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
+    const Moms m = forward_moments<L, S, BC>(xprev, p, x, y, z);
+    const double d = (double)S::load_d(ld(dfield, cell));
+    double pb[L::Q];
+    bool solid = false;
+    if (BC == BC_PERIODIC) {
+        stream_adjoint_periodic<L>(lam_in, N, p, x, y, z, pb);
+    } else {
+        // post-collision moments of this cell at step t (balance laws)
+        const double rho = p.rho0 + m.s, inv_rho = 1.0 / rho;
+        const double om = p.omega, sh = 1.0 - d;
+        const double jbx = (1.0 - om) * m.jx + om * sh * (m.jx + 0.5 * p.F[0]) + p.pref * p.F[0];
+        const double jby = (1.0 - om) * m.jy + om * sh * (m.jy + 0.5 * p.F[1]) + p.pref * p.F[1];
+        const double jbz = (1.0 - om) * m.jz + om * sh * (m.jz + 0.5 * p.F[2]) + p.pref * p.F[2];
+        stream_adjoint_general<L>(lam_in, N, p, (int)x, (int)y, (int)z, rho, jbx * inv_rho,
+                                  jby * inv_rho, jbz * inv_rho, pb);
+        solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
+    }
+    const double dd = collide_adjoint<L>(m, d, p, pb);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) st(lam_out + (size_t)k * N, cell, sel(solid, 0.0, pb[k]));
+    const double acc = ld(dbar, cell);
+    st(dbar, cell, acc + sel(solid, 0.0, dd));
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <class L, class S>
+static hipError_t seed_dispatch_bc(int bcmode, const Params& p, const void* src, const double* drho_bar,
+                                   const double* u_bar, double* lam, int bx, hipStream_t s)
+{
+    const Launch l = cell_launch(p, bx < 256 ? bx : 256);
+    auto* a = static_cast<const typename S::T*>(src);
+    if (bcmode == BC_PERIODIC)
+        hipLaunchKernelGGL((adjoint_seed_kernel<L, S, BC_PERIODIC>), l.grid, l.block, 0, s, a, drho_bar,
+                           u_bar, lam, p);
+    else
+        hipLaunchKernelGGL((adjoint_seed_kernel<L, S, BC_GENERAL>), l.grid, l.block, 0, s, a, drho_bar,
+                           u_bar, lam, p);
+    return hipGetLastError();
+}
+
+template <class L, class S>
+static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const double* lam_in, double* lam_out,
+                                      const void* xprev, const void* dfield, double* dbar, int bx,
+                                      hipStream_t s)
+{
+    const Launch l = cell_launch(p, bx < 256 ? bx : 256);
+    auto* a = static_cast<const typename S::T*>(xprev);
+    auto* d = static_cast<const typename S::D*>(dfield);
+    if (bcmode == BC_PERIODIC)
+        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC>), l.grid, l.block, 0, s, lam_in, lam_out, a,
+                           d, dbar, p);
+    else
+        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL>), l.grid, l.block, 0, s, lam_in, lam_out, a,
+                           d, dbar, p);
+    return hipGetLastError();
+}
+
+template <class L>
+static hipError_t seed_dispatch_store(int storage, int bcmode, const Params& p, const void* src,
+                                      const double* drho_bar, const double* u_bar, double* lam, int bx,
+                                      hipStream_t s)
+{
+    switch (storage) {
+    case StoreF64::code: return seed_dispatch_bc<L, StoreF64>(bcmode, p, src, drho_bar, u_bar, lam, bx, s);
+    case StoreF32::code: return seed_dispatch_bc<L, StoreF32>(bcmode, p, src, drho_bar, u_bar, lam, bx, s);
+    case StoreF16S::code: return seed_dispatch_bc<L, StoreF16S>(bcmode, p, src, drho_bar, u_bar, lam, bx, s);
+    case StoreBF16S::code: return seed_dispatch_bc<L, StoreBF16S>(bcmode, p, src, drho_bar, u_bar, lam, bx, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class L>
+static hipError_t adjoint_dispatch_store(int storage, int bcmode, const Params& p, const double* lam_in,
+                                         double* lam_out, const void* xprev, const void* dfield,
+                                         double* dbar, int bx, hipStream_t s)
+{
+    switch (storage) {
+    case StoreF64::code:
+        return adjoint_dispatch_bc<L, StoreF64>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+    case StoreF32::code:
+        return adjoint_dispatch_bc<L, StoreF32>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+    case StoreF16S::code:
+        return adjoint_dispatch_bc<L, StoreF16S>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+    case StoreBF16S::code:
+        return adjoint_dispatch_bc<L, StoreBF16S>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, const void* src,
+                               const double* drho_bar, const double* u_bar, double* lam, int bx,
+                               hipStream_t s)
+{
+    if (q == 9) return seed_dispatch_store<D2Q9>(storage, bcmode, p, src, drho_bar, u_bar, lam, bx, s);
+    if (q == 19) return seed_dispatch_store<D3Q19>(storage, bcmode, p, src, drho_bar, u_bar, lam, bx, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint(int q, int storage, int bcmode, const Params& p, const double* lam_in,
+                          double* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
+                          hipStream_t s)
+{
+    if (q == 9) return adjoint_dispatch_store<D2Q9>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+    if (q == 19)
+        return adjoint_dispatch_store<D3Q19>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace hlbm

@@ -38,9 +38,8 @@ struct hlbm_ctx {
     double* partials;  // FP64 per-block partials for the totals
     uint32_t partials_blocks;
     double* totals_dev;
-    int* flags_dev;    // per-block flags of the porosity check
-    uint32_t flags_blocks;
-    int* flag_out;
+    double* reduce_stage;  // first-pass results of the two-pass reduction
+    int* flag_out;         // porosity check flag
     // batch of periodic boxes (hlbm_create_batch)
     bool batch;
     int n_items;
@@ -56,6 +55,24 @@ struct hlbm_ctx {
     hlbm::BatchLaunch bl;
     hipGraphExec_t gexec[2];
     int gsteps[2];
+    // adjoint tape (hlbm_set_tape): checkpoints of the state every `every`
+    // steps since step `tape_origin`, a replay segment and two FP64 adjoint
+    // population buffers
+    int tape_every;
+    int tape_max;
+    long long tape_origin;
+    int tape_ncp;
+    char* tape_cps;
+    char* tape_seg;
+    double* tape_lam[2];
+    // in-sweep diagnostics (hlbm_set_diagnostics): FP64 totals of the time
+    // levels n with n % diag_every == 0, appended to a device log
+    int diag_every;
+    int diag_cap;
+    int diag_count;
+    long long diag_dropped;
+    double* diag_log;
+    std::vector<long long> diag_steps;
 };
 
 namespace {
@@ -202,6 +219,31 @@ int zero_state(hlbm_ctx* c)
     return HLBM_OK;
 }
 
+void tape_free(hlbm_ctx* c)
+{
+    if (c->tape_cps) (void)hipFree(c->tape_cps);
+    if (c->tape_seg) (void)hipFree(c->tape_seg);
+    for (int k = 0; k < 2; ++k)
+        if (c->tape_lam[k]) (void)hipFree(c->tape_lam[k]);
+    c->tape_cps = nullptr;
+    c->tape_seg = nullptr;
+    c->tape_lam[0] = c->tape_lam[1] = nullptr;
+    c->tape_every = 0;
+    c->tape_max = 0;
+    c->tape_ncp = 0;
+}
+
+// Start recording at the current state: checkpoint 0 is the current state.
+int tape_restart(hlbm_ctx* c)
+{
+    if (!c->tape_every) return HLBM_OK;
+    c->tape_origin = c->step;
+    hipError_t e = hipMemcpyAsync(c->tape_cps, c->pop[c->cur], c->pop_bytes, hipMemcpyDeviceToDevice,
+                                  c->stream);
+    if (e != hipSuccess) return hip_fail(e, "tape checkpoint");
+    return HLBM_OK;
+}
+
 int batch_check_barrier(hlbm_ctx* c)
 {
     int err = 0;
@@ -339,15 +381,13 @@ int hlbm_create(const hlbm_config* cfg, hlbm_ctx** out)
             return rc;
         }
     }
-    const uint32_t nfl = (c->p.N + 255) / 256;
-    hipError_t e = hipMalloc(&c->flags_dev, sizeof(int) * (size_t)nfl);
-    if (e == hipSuccess) e = hipMalloc(&c->flag_out, sizeof(int));
+    hipError_t e = hipMalloc(&c->flag_out, sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&c->totals_dev, 4 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&c->reduce_stage, 4 * sizeof(double) * hlbm::REDUCE_STAGE);
     if (e != hipSuccess) {
         hlbm_destroy(c);
         return fail(HLBM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
     }
-    c->flags_blocks = nfl;
     rc = ensure_partials(c, hlbm::cell_launch(c->p, c->bx).nblocks);
     if (rc) {
         hlbm_destroy(c);
@@ -371,7 +411,9 @@ int hlbm_bind_buffers(hlbm_ctx* c, void* pop_a, void* pop_b, void* porosity)
     c->dfield = porosity;
     c->bound = true;
     c->porosity_set = false;
-    return zero_state(c);
+    rc = zero_state(c);
+    if (rc) return rc;
+    return tape_restart(c);
 }
 
 int hlbm_destroy(hlbm_ctx* c)
@@ -387,10 +429,12 @@ int hlbm_destroy(hlbm_ctx* c)
     }
     if (c->partials) (void)hipFree(c->partials);
     if (c->totals_dev) (void)hipFree(c->totals_dev);
-    if (c->flags_dev) (void)hipFree(c->flags_dev);
+    if (c->reduce_stage) (void)hipFree(c->reduce_stage);
     if (c->flag_out) (void)hipFree(c->flag_out);
+    if (c->diag_log) (void)hipFree(c->diag_log);
     for (int k = 0; k < 2; ++k)
         if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    tape_free(c);
     if (c->items_dev) (void)hipFree(c->items_dev);
     if (c->tile_item_dev) (void)hipFree(c->tile_item_dev);
     if (c->tile_partials) (void)hipFree(c->tile_partials);
@@ -424,8 +468,8 @@ int hlbm_set_porosity(hlbm_ctx* c, const void* d, int dtype, int on_device)
         }
         src = tmp;
     }
-    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, c->dfield, (uint32_t)n,
-                                      c->flags_dev, c->flag_out, c->stream);
+    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, c->dfield, (uint32_t)n, c->flag_out,
+                                      c->stream);
     int flag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, c->flag_out, sizeof(int), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -436,7 +480,7 @@ int hlbm_set_porosity(hlbm_ctx* c, const void* d, int dtype, int on_device)
         return fail(HLBM_EINVAL, "porosity values must be finite and in [0, 1]");
     }
     c->porosity_set = true;
-    return HLBM_OK;
+    return tape_restart(c);
 }
 
 int hlbm_step(hlbm_ctx* c, int nsteps)
@@ -447,10 +491,32 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (!c->porosity_set) return fail(HLBM_ESTATE, "porosity not set");
     if (c->batch) return batch_step(c, nsteps);
+    if (c->tape_every && c->step - c->tape_origin + nsteps > c->tape_max)
+        return fail(HLBM_EINVAL, "the tape holds %d steps; %lld recorded, %d more requested", c->tape_max,
+                    c->step - c->tape_origin, nsteps);
     for (int t = 0; t < nsteps; ++t) {
-        hipError_t e = hlbm::launch_sweep(c->q, c->cfg.storage, c->bcmode, c->p, c->pop[c->cur],
-                                          c->pop[c->cur ^ 1], c->dfield, c->bx, c->stream);
+        hipError_t e;
+        if (c->tape_every) {
+            const long long rel = c->step - c->tape_origin;
+            if (rel > 0 && rel % c->tape_every == 0) {
+                e = hipMemcpyAsync(c->tape_cps + (size_t)(rel / c->tape_every) * c->pop_bytes, c->pop[c->cur],
+                                   c->pop_bytes, hipMemcpyDeviceToDevice, c->stream);
+                if (e != hipSuccess) return hip_fail(e, "tape checkpoint");
+            }
+        }
+        const bool diag = c->diag_every && c->step % c->diag_every == 0;
+        const bool record = diag && c->diag_count < c->diag_cap;
+        if (diag && !record) c->diag_dropped += 1;
+        e = hlbm::launch_sweep(c->q, c->cfg.storage, c->bcmode, c->p, c->pop[c->cur], c->pop[c->cur ^ 1],
+                               c->dfield, c->bx, c->stream, record ? c->partials : nullptr);
+        if (e == hipSuccess && record)
+            e = hlbm::launch_reduce4(c->partials, hlbm::cell_launch(c->p, c->bx).nblocks, c->reduce_stage,
+                                     c->diag_log + 4 * (size_t)c->diag_count, c->stream);
         if (e != hipSuccess) return hip_fail(e, "sweep launch");
+        if (record) {
+            c->diag_steps.push_back(c->step);
+            c->diag_count += 1;
+        }
         c->cur ^= 1;
         c->step += 1;
     }
@@ -497,7 +563,8 @@ int hlbm_moments(hlbm_ctx* c, void* drho, void* u, int dtype, int on_device, dou
     }
     e = hlbm::launch_moments(c->q, c->cfg.storage, c->bcmode, c->p, c->pop[c->cur], ddr, du,
                              dtype == HLBM_DT_F64, partials, c->bx, c->stream);
-    if (e == hipSuccess && totals) e = hlbm::launch_reduce4(partials, l.nblocks, c->totals_dev, c->stream);
+    if (e == hipSuccess && totals)
+        e = hlbm::launch_reduce4(partials, l.nblocks, c->reduce_stage, c->totals_dev, c->stream);
     if (e == hipSuccess && totals)
         e = hipMemcpyAsync(totals, c->totals_dev, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess && tmp && drho)
@@ -548,7 +615,7 @@ int hlbm_set_state(hlbm_ctx* c, const void* src, int on_device, long long step)
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "set_state");
     c->step = step;
-    return HLBM_OK;
+    return tape_restart(c);
 }
 
 int hlbm_reset(hlbm_ctx* c)
@@ -556,7 +623,176 @@ int hlbm_reset(hlbm_ctx* c)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
-    return zero_state(c);
+    rc = zero_state(c);
+    if (rc) return rc;
+    return tape_restart(c);
+}
+
+int hlbm_set_diagnostics(hlbm_ctx* c, int every, int capacity)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->batch) return fail(HLBM_EUNSUPPORTED, "use hlbm_batch_moments for a batch");
+    if (every < 0 || capacity < 0) return fail(HLBM_EINVAL, "every and capacity must be >= 0");
+    if (every > 0 && capacity < 1) return fail(HLBM_EINVAL, "capacity must be >= 1");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "set_diagnostics: outstanding work failed");
+    if (c->diag_log) (void)hipFree(c->diag_log);
+    c->diag_log = nullptr;
+    c->diag_every = 0;
+    c->diag_cap = 0;
+    c->diag_count = 0;
+    c->diag_dropped = 0;
+    c->diag_steps.clear();
+    if (every == 0) return HLBM_OK;
+    e = hipMalloc(&c->diag_log, 4 * sizeof(double) * (size_t)capacity);
+    if (e != hipSuccess) return fail(HLBM_ENOMEM, "diagnostics log: %s", hipGetErrorString(e));
+    c->diag_every = every;
+    c->diag_cap = capacity;
+    return ensure_partials(c, hlbm::cell_launch(c->p, c->bx).nblocks);
+}
+
+int hlbm_read_diagnostics(hlbm_ctx* c, double* out, int max_records, int* count, long long* dropped)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!count) return fail(HLBM_EINVAL, "count is NULL");
+    if (max_records < 0 || (max_records > 0 && !out)) return fail(HLBM_EINVAL, "bad output array");
+    const int n = c->diag_count < max_records ? c->diag_count : max_records;
+    std::vector<double> tmp(4 * (size_t)(n > 0 ? n : 1));
+    hipError_t e = hipSuccess;
+    if (n > 0)
+        e = hipMemcpyAsync(tmp.data(), c->diag_log, 4 * sizeof(double) * (size_t)n, hipMemcpyDeviceToHost,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "read_diagnostics");
+    for (int k = 0; k < n; ++k) {
+        out[5 * k] = (double)c->diag_steps[k];
+        for (int j = 0; j < 4; ++j) {
+            out[5 * k + 1 + j] = tmp[4 * (size_t)k + j];
+            if (!isfinite(tmp[4 * (size_t)k + j])) rc = HLBM_ENUMERIC;
+        }
+    }
+    *count = n;
+    if (dropped) *dropped = c->diag_dropped + (c->diag_count - n);
+    c->diag_count = 0;
+    c->diag_dropped = 0;
+    c->diag_steps.clear();
+    if (rc) return fail(rc, "a diagnostic total is not finite");
+    return HLBM_OK;
+}
+
+int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->batch) return fail(HLBM_EUNSUPPORTED, "a batch has no adjoint");
+    if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
+    if (every < 0 || max_steps < 0) return fail(HLBM_EINVAL, "every and max_steps must be >= 0");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "set_tape: outstanding work failed");
+    tape_free(c);
+    if (every == 0) return HLBM_OK;
+    if ((unsigned long long)c->p.N * sizeof(double) >= (1ull << 32))
+        return fail(HLBM_EUNSUPPORTED, "the adjoint needs nx*ny*nz*8 bytes < 4 GiB per population row");
+    const int ncp = max_steps / every + 1;
+    const size_t lam_bytes = (size_t)c->p.N * (size_t)c->q * sizeof(double);
+    e = hipMalloc(&c->tape_cps, (size_t)ncp * c->pop_bytes);
+    if (e == hipSuccess && every > 1) e = hipMalloc(&c->tape_seg, (size_t)(every - 1) * c->pop_bytes);
+    if (e == hipSuccess) e = hipMalloc(&c->tape_lam[0], lam_bytes);
+    if (e == hipSuccess) e = hipMalloc(&c->tape_lam[1], lam_bytes);
+    if (e != hipSuccess) {
+        tape_free(c);
+        return fail(HLBM_ENOMEM, "tape allocation (%d checkpoints of %zu bytes): %s", ncp, c->pop_bytes,
+                    hipGetErrorString(e));
+    }
+    c->tape_every = every;
+    c->tape_max = max_steps;
+    c->tape_ncp = ncp;
+    return tape_restart(c);
+}
+
+int hlbm_tape_info(const hlbm_ctx* c, int* every, int* max_steps, long long* recorded, size_t* device_bytes)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (every) *every = c->tape_every;
+    if (max_steps) *max_steps = c->tape_max;
+    if (recorded) *recorded = c->tape_every ? c->step - c->tape_origin : 0;
+    if (device_bytes) {
+        size_t b = 0;
+        if (c->tape_every)
+            b = (size_t)(c->tape_ncp + c->tape_every - 1) * c->pop_bytes +
+                2 * (size_t)c->p.N * (size_t)c->q * sizeof(double);
+        *device_bytes = b;
+    }
+    return HLBM_OK;
+}
+
+int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const double* dJ_du, double* dJ_dd,
+                      int on_device)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->batch) return fail(HLBM_EUNSUPPORTED, "a batch has no adjoint");
+    if (!c->tape_every) return fail(HLBM_ESTATE, "no tape: call hlbm_set_tape before the forward steps");
+    if (!c->porosity_set) return fail(HLBM_ESTATE, "porosity not set");
+    if (!dJ_drho || !dJ_du || !dJ_dd) return fail(HLBM_EINVAL, "NULL cotangent or gradient array");
+    const long long R0 = c->step - c->tape_origin;
+    if (nsteps < 0 || nsteps > R0)
+        return fail(HLBM_EINVAL, "nsteps must be in [0, %lld] (steps recorded on the tape)", R0);
+    const size_t n = c->p.N;
+    const double* gr = dJ_drho;
+    const double* gu = dJ_du;
+    double* gd = dJ_dd;
+    void* tmp = nullptr;
+    hipError_t e = hipSuccess;
+    if (!on_device) {
+        e = hipMalloc(&tmp, 5 * n * sizeof(double));
+        if (e != hipSuccess) return fail(HLBM_ENOMEM, "staging allocation: %s", hipGetErrorString(e));
+        double* t = static_cast<double*>(tmp);
+        e = hipMemcpyAsync(t, dJ_drho, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(t + n, dJ_du, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(t + 4 * n, dJ_dd, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        gr = t;
+        gu = t + n;
+        gd = t + 4 * n;
+    }
+    const int K = c->tape_every;
+    const int q = c->q, storage = c->cfg.storage, bc = c->bcmode;
+    // state with index r (relative to the tape origin) of the replayed segment
+    auto seg_state = [&](long long r) -> const void* {
+        const long long m = r / K, j = r - m * K;
+        if (j == 0) return c->tape_cps + (size_t)m * c->pop_bytes;
+        return c->tape_seg + (size_t)(j - 1) * c->pop_bytes;
+    };
+    int a = 0;
+    if (e == hipSuccess && nsteps > 0)
+        e = hlbm::launch_adjoint_seed(q, storage, bc, c->p, c->pop[c->cur], gr, gu, c->tape_lam[a], c->bx,
+                                      c->stream);
+    long long seg_loaded = -1;
+    for (long long t = R0; e == hipSuccess && t > R0 - nsteps; --t) {
+        const long long r = t - 1;  // the step t reads x_{t-1}
+        const long long m = r / K;
+        if (m != seg_loaded) {
+            // replay segment m from its checkpoint up to the last state needed
+            const long long jmax = (r - m * K);
+            for (long long j = 1; j <= jmax && e == hipSuccess; ++j)
+                e = hlbm::launch_sweep(q, storage, bc, c->p, seg_state(m * K + j - 1),
+                                       const_cast<void*>(seg_state(m * K + j)), c->dfield, c->bx, c->stream);
+            seg_loaded = m;
+        }
+        if (e == hipSuccess)
+            e = hlbm::launch_adjoint(q, storage, bc, c->p, c->tape_lam[a], c->tape_lam[a ^ 1], seg_state(r),
+                                     c->dfield, gd, c->bx, c->stream);
+        a ^= 1;
+    }
+    if (e == hipSuccess && tmp)
+        e = hipMemcpyAsync(dJ_dd, gd, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "adjoint");
+    return HLBM_OK;
 }
 
 int hlbm_sync(hlbm_ctx* c)
@@ -651,13 +887,11 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
     if (e == hipSuccess) e = hipMalloc(&c->item_totals_dev, sizeof(double) * 4 * (size_t)n_items);
     if (e == hipSuccess) e = hipMalloc(&c->bar_counter, sizeof(unsigned));
     if (e == hipSuccess) e = hipMalloc(&c->bar_err, sizeof(int));
-    if (e == hipSuccess) e = hipMalloc(&c->flags_dev, sizeof(int) * (size_t)((max_cells + 255) / 256));
     if (e == hipSuccess) e = hipMalloc(&c->flag_out, sizeof(int));
     if (e != hipSuccess) {
         hlbm_destroy(c);
         return fail(HLBM_ENOMEM, "device allocation for the batch failed: %s", hipGetErrorString(e));
     }
-    c->flags_blocks = (uint32_t)((max_cells + 255) / 256);
     e = hipMemcpy(c->items_dev, c->items.data(), sizeof(hlbm::BatchItem) * n_items, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(c->tile_item_dev, tile_item.data(), sizeof(uint32_t) * (size_t)ntiles, hipMemcpyHostToDevice);
@@ -740,8 +974,7 @@ int hlbm_batch_set_porosity(hlbm_ctx* c, int item, const void* d, int dtype, int
         src = tmp;
     }
     void* out = static_cast<char*>(c->dfield) + (size_t)it.base * c->delem;
-    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, out, (uint32_t)n, c->flags_dev,
-                                      c->flag_out, c->stream);
+    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, out, (uint32_t)n, c->flag_out, c->stream);
     int flag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, c->flag_out, sizeof(int), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

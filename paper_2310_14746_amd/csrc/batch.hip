@@ -6,9 +6,14 @@
 // Layout: the items' cells are packed one after another, x fastest inside an
 // item, and each population row spans all items: buf[i*Ntot + base_k + local].
 // The packed cells are cut into tiles of TILE consecutive cells that never
-// straddle two items (a tile's tail past the item's end is masked).  Block b
-// owns the contiguous tile range [b*T/G, (b+1)*T/G): neighbouring rows of one
-// item stay in the same block, hence in the same CU's L1 and XCD's L2.
+// straddle two items (a tile's tail past the item's end is masked).  Within a
+// step, block b takes tiles b, b + G, b + 2G, ... (G blocks): the blocks
+// resident at any moment work on one contiguous band of tiles, as the blocks of
+// a one-launch-per-step grid would, so the rows a pull reads from the
+// neighbouring y and z rows are still in L2 when the band reaches them.
+// (Giving each block one contiguous range of T/G tiles instead spreads the
+// resident blocks over the whole batch; their neighbour rows no longer fit in
+// L2 and the kernel ran at half the per-step kernel's rate.)
 //
 // The grid is sized to the number of blocks that can be resident at once.
 // The barrier waits with a bounded spin; if the bound is exceeded (a block was
@@ -27,17 +32,20 @@ __device__ __forceinline__ bool grid_barrier(unsigned* __restrict__ counter, uns
                                              int* __restrict__ err, unsigned spin_limit)
 {
     __shared__ int ok;
-    // Every wave releases its own stores at device scope (waits for them and
-    // writes back its L2) before the block barrier; a workgroup barrier alone
-    // does not wait for other waves' stores, and the step's results must be
-    // visible to blocks on every XCD.
-    __threadfence();
+    // Release: every wave makes its own stores visible at device scope (waits
+    // for them and writes back its XCD's L2) before the block barrier; a
+    // workgroup barrier alone does not wait for other waves' stores, and the
+    // step's results must be visible to blocks on every XCD.  Release only: an
+    // acquire here would invalidate the L2 under blocks still computing.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
         atomicAdd(counter, 1u);
         int good = 1;
         unsigned spins = 0;
-        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        // Relaxed polling (device-coherent loads, no cache invalidation per
+        // poll); the acquire follows once, below.
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                 good = 0;
                 break;
@@ -49,10 +57,15 @@ __device__ __forceinline__ bool grid_barrier(unsigned* __restrict__ counter, uns
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        __threadfence();
+        // acquire by the thread that observed the count ...
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         ok = good;
     }
     __syncthreads();
+    // ... and by every wave after the block barrier: drop stale copies of
+    // other blocks' results from this CU's and this XCD's caches before the
+    // next step reads them.
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return ok != 0;
 }
 
@@ -100,14 +113,11 @@ __global__ __launch_bounds__(TILE) void batch_persistent_kernel(
 {
     using R = typename S::R;
     const R rho0 = R(rho0_d), scale = R(scale_d), inv_scale = R(1.0 / scale_d);
-    const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-    const uint32_t t_begin = blockIdx.x * per;
-    const uint32_t t_end = min(ntiles, t_begin + per);
     for (int s = 0; s < nsteps; ++s) {
         const bool from_b = ((s + start_in_b) & 1) != 0;
         const typename S::T* __restrict__ src = from_b ? buf_b : buf_a;
         typename S::T* __restrict__ dst = from_b ? buf_a : buf_b;
-        for (uint32_t t = t_begin; t < t_end; ++t) {
+        for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
             const BatchItem it = items[tile_item[t]];
             const uint32_t l = (t - it.tile0) * TILE + threadIdx.x;
             if (l < it.cells) batch_cell<S>(src, dst, dfield, Ntot, it, l, rho0, scale, inv_scale);

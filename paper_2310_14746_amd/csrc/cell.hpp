@@ -121,24 +121,26 @@ __device__ __forceinline__ void collide(R (&g)[L::Q], R d, R F0, R F1, R F2, R r
 }
 
 // Moments only (no collision), same definitions as in collide().
+// The sums run in FP64 and the results are rounded to R once, exactly as the
+// collision forms them, so reported moments equal the collision's own.
 template <class L, class R>
 __device__ __forceinline__ void moments_of(const R (&g)[L::Q], R F0, R F1, R F2, R rho0, R& drho,
                                            R& ux, R& uy, R& uz)
 {
-    R s = R(0), jx = R(0), jy = R(0), jz = R(0);
+    double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        s += g[i];
-        if (L::cx[i]) jx += L::cx[i] > 0 ? g[i] : -g[i];
-        if (L::cy[i]) jy += L::cy[i] > 0 ? g[i] : -g[i];
-        if (L::cz[i]) jz += L::cz[i] > 0 ? g[i] : -g[i];
+        const double gi = (double)g[i];
+        s += gi;
+        if (L::cx[i]) jx += L::cx[i] > 0 ? gi : -gi;
+        if (L::cy[i]) jy += L::cy[i] > 0 ? gi : -gi;
+        if (L::cz[i]) jz += L::cz[i] > 0 ? gi : -gi;
     }
-    const R rho = rho0 + s;
-    const R inv_rho = R(1) / rho;
-    drho = s;
-    ux = (jx + R(0.5) * F0) * inv_rho;
-    uy = (jy + R(0.5) * F1) * inv_rho;
-    uz = (jz + R(0.5) * F2) * inv_rho;
+    const double inv_rho = 1.0 / ((double)rho0 + s);
+    drho = R(s);
+    ux = R((jx + 0.5 * (double)F0) * inv_rho);
+    uy = R((jy + 0.5 * (double)F1) * inv_rho);
+    uz = R((jz + 0.5 * (double)F2) * inv_rho);
 }
 
 // ---------------------------------------------------------------------------

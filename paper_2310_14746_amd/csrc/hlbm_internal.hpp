@@ -34,14 +34,31 @@ struct Launch {
 Launch cell_launch(const Params& p, int bx);
 
 // Kernel launchers (sweep.hip).  All return the launch status.
+// One sweep.  With diag_partials != NULL the diagnostic variant also writes
+// FP64 block partials of the totals (one 4-double record per block).
 hipError_t launch_sweep(int q, int storage, int bcmode, const Params& p, const void* src,
-                        void* dst, const void* dfield, int bx, hipStream_t s);
+                        void* dst, const void* dfield, int bx, hipStream_t s,
+                        double* diag_partials = nullptr);
 hipError_t launch_moments(int q, int storage, int bcmode, const Params& p, const void* src,
                           void* drho, void* u, int out_f64, double* partials, int bx,
                           hipStream_t s);
-hipError_t launch_reduce4(const double* partials, uint32_t nblocks, double* out, hipStream_t s);
+// Reverse sweep (adjoint.hip): seed from the moments' cotangents, then one
+// launch per reverse step.  Adjoint populations are FP64 rows of N values.
+hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, const void* src,
+                               const double* drho_bar, const double* u_bar, double* lam, int bx,
+                               hipStream_t s);
+hipError_t launch_adjoint(int q, int storage, int bcmode, const Params& p, const double* lam_in,
+                          double* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
+                          hipStream_t s);
+// Fixed-order two-pass sum of `nblocks` partials of 4 doubles into out[4];
+// `stage` holds 4*REDUCE_STAGE doubles.
+constexpr uint32_t REDUCE_STAGE = 256;
+hipError_t launch_reduce4(const double* partials, uint32_t nblocks, double* stage, double* out,
+                          hipStream_t s);
+// Convert and validate the porosity; *flag (device) ends nonzero if any value
+// is NaN or outside [0, 1].
 hipError_t launch_porosity_convert(int in_dtype, const void* in, int storage, void* out,
-                                   uint32_t n, int* block_flags, int* flag_out, hipStream_t s);
+                                   uint32_t n, int* flag, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Batched periodic boxes

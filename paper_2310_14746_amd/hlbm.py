@@ -108,6 +108,12 @@ def load() -> ctypes.CDLL:
         "hlbm_batch_set_mode": ([vp, i], i),
         "hlbm_batch_set_porosity": ([vp, i, vp, i, i], i),
         "hlbm_batch_moments": ([vp, i, vp, vp, i, P(ctypes.c_double)], i),
+        "hlbm_set_diagnostics": ([vp, i, i], i),
+        "hlbm_read_diagnostics": ([vp, P(ctypes.c_double), i, P(ctypes.c_int), P(ctypes.c_longlong)], i),
+        "hlbm_set_tape": ([vp, i, i], i),
+        "hlbm_tape_info": ([vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_longlong),
+                            P(ctypes.c_size_t)], i),
+        "hlbm_adjoint_step": ([vp, i, vp, vp, vp, i], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -294,6 +300,55 @@ class HLBM:
             raise ValueError("state size mismatch")
         _check(load().hlbm_set_state(self.ctx, buf.contiguous().data_ptr(), 1 if buf.is_cuda else 0,
                                      int(step)))
+
+    # -- in-sweep diagnostics ------------------------------------------------
+    def set_diagnostics(self, every: int, capacity: int = 1024):
+        """Record FP64 totals inside the sweep at time levels n % every == 0."""
+        _check(load().hlbm_set_diagnostics(self.ctx, int(every), int(capacity)))
+
+    def read_diagnostics(self, max_records: int = 1 << 20):
+        """(steps[k], totals[k, 4], dropped) of the records since the last read."""
+        cap = max(1, int(max_records))
+        buf = (ctypes.c_double * (5 * cap))()
+        n, dropped = ctypes.c_int(), ctypes.c_longlong()
+        _check(load().hlbm_read_diagnostics(self.ctx, buf, cap, ctypes.byref(n), ctypes.byref(dropped)))
+        arr = np.frombuffer(buf, dtype=np.float64)[:5 * n.value].reshape(n.value, 5).copy()
+        return arr[:, 0].astype(np.int64), arr[:, 1:], dropped.value
+
+    # -- adjoint -----------------------------------------------------------
+    def set_tape(self, every: int, max_steps: int):
+        """Record checkpoints every `every` steps for up to `max_steps` steps from now."""
+        _check(load().hlbm_set_tape(self.ctx, int(every), int(max_steps)))
+
+    def tape_info(self) -> dict:
+        e, m, r, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong(), ctypes.c_size_t()
+        _check(load().hlbm_tape_info(self.ctx, ctypes.byref(e), ctypes.byref(m), ctypes.byref(r),
+                                     ctypes.byref(b)))
+        return {"every": e.value, "max_steps": m.value, "recorded": r.value,
+                "device_bytes": b.value}
+
+    def adjoint(self, nsteps: int, drho_bar, u_bar, d_bar=None):
+        """Reverse sweep over the last `nsteps` recorded steps.
+
+        drho_bar (N values) and u_bar (3*N values) are the cotangents of the
+        current moments (shapes as returned by :meth:`moments`); returns d_bar
+        (FP64 device tensor shaped (nz, ny, nx)) with dJ/dd through those
+        steps added to `d_bar` if given (else to zeros).
+        """
+        t = self.torch
+        nx, ny, nz = self.shape
+        gr = t.as_tensor(drho_bar, dtype=t.float64, device=self.device).contiguous()
+        gu = t.as_tensor(u_bar, dtype=t.float64, device=self.device).contiguous()
+        if gr.numel() != self.N or gu.numel() != 3 * self.N:
+            raise ValueError("cotangents need N and 3*N values")
+        if d_bar is None:
+            d_bar = t.zeros((nz, ny, nx), dtype=t.float64, device=self.device)
+        elif not (d_bar.dtype == t.float64 and d_bar.is_cuda and d_bar.is_contiguous()
+                  and d_bar.numel() == self.N):
+            raise ValueError("d_bar must be a contiguous FP64 device tensor of N values")
+        _check(load().hlbm_adjoint_step(self.ctx, int(nsteps), gr.data_ptr(), gu.data_ptr(),
+                                        d_bar.data_ptr(), 1))
+        return d_bar
 
     def state_f64(self, store_scale: Optional[float] = None) -> np.ndarray:
         """Current post-collision populations as float64 g[i, cell] (library order)."""

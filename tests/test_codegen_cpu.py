@@ -22,7 +22,7 @@ from paper_2310_14746_amd import build as hbuild
 def asm():
     funcs = {}
     with tempfile.TemporaryDirectory() as tmp:
-        for src in ("sweep.hip", "batch.hip"):
+        for src in ("sweep.hip", "batch.hip", "adjoint.hip"):
             out = os.path.join(tmp, src + ".s")
             cmd = [hbuild.hipcc(), *[f for f in hbuild.HIPCC_FLAGS if f != "-fPIC"],
                    "--cuda-device-only", "-S", os.path.join(hbuild.CSRC, src), "-o", out]
@@ -46,9 +46,19 @@ def test_sweep_kernels_are_straight_line(asm):
         assert branches <= 1, (name, branches)
 
 
+def test_adjoint_kernels_are_straight_line(asm):
+    kern = {**_kernels(asm, "_ZN4hlbm14adjoint_kernel"), **_kernels(asm, "_ZN4hlbm19adjoint_seed_kernel")}
+    assert len(kern) == 32
+    for name, body in kern.items():
+        branches = len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
+        assert branches <= 1, (name, branches)
+
+
 def test_no_private_memory_in_sweep_and_moments(asm):
     for name, body in {**_kernels(asm, "_ZN4hlbm12sweep_kernel"),
                        **_kernels(asm, "_ZN4hlbm14moments_kernel"),
+                       **_kernels(asm, "_ZN4hlbm14adjoint_kernel"),
+                       **_kernels(asm, "_ZN4hlbm19adjoint_seed_kernel"),
                        **_kernels(asm, "_ZN4hlbm23batch_persistent_kernel"),
                        **_kernels(asm, "_ZN4hlbm17batch_step_kernel")}.items():
         assert not re.search(r"^\s+(scratch_|buffer_store|buffer_load)", body, flags=re.M), name
@@ -83,3 +93,20 @@ def test_no_undefined_sgpr_copied_to_vgpr(asm):
         undef = set(re.findall(r"implicit-def: \$sgpr(\d+)_sgpr(\d+)", body))
         for a, b in undef:
             assert not re.search(r"v_mov_b64_e32 v\[\d+:\d+\], s\[%s:%s\]" % (a, b), body), name
+
+
+def test_barrier_polling_keeps_caches(asm):
+    """The grid barrier polls with coherent loads and no cache invalidation;
+    invalidating the L2 on every poll would evict the data of blocks still
+    computing (acquire happens once, after the count is reached)."""
+    for name, body in _kernels(asm, "_ZN4hlbm23batch_persistent_kernel").items():
+        lines = [l.strip() for l in body.splitlines()]
+        add = next(i for i, l in enumerate(lines) if l.startswith("global_atomic_add"))
+        sleep = next(i for i, l in enumerate(lines) if l.startswith("s_sleep"))
+        assert add < sleep, name
+        window = lines[add:sleep + 20]
+        assert not any(l.startswith("buffer_inv") for l in window), name
+        # polling loads are device-coherent
+        assert any(re.match(r"global_load_dword v\d+, v\d+, s\[\d+:\d+\] sc1", l) for l in window), name
+        # and an acquire (invalidate) follows the barrier somewhere in the kernel
+        assert any(l.startswith("buffer_inv sc1") for l in lines), name
