@@ -23,6 +23,9 @@ from .oracle import (  # noqa: F401
     stream_adjoint,
     moments_adjoint,
     gradient,
+    collide_cell_tensor,
+    collide_tensor,
+    run_tensor,
     PERIODIC,
     WALL,
     INLET_U,

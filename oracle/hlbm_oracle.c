@@ -388,6 +388,109 @@ int oracle_observe(const oracle_cfg *cfg, const double *g, double *drho, double 
     return 0;
 }
 
+/* ======================================================================== */
+/* Anisotropic porosity control (the tensor-permeability extension the     */
+/* paper names as future work; Sec. 3.2 fixes the scalar case by assuming   */
+/* isotropy).  The drag (1/tau)(1 - varpi) rho u becomes (1/tau) rho D u    */
+/* with D = nu tau K^{-1} a symmetric 3x3 matrix per cell, i.e. the         */
+/* equilibrium velocity is u_eq = (I - D) u.  D is passed as 6 rows         */
+/* D6[k*N + cell], k = xx, yy, zz, xy, xz, yz.  Everything else is the     */
+/* scalar collision above.                                                 */
+/* ======================================================================== */
+static void tensor_of(const double *D6, long N, long cell, double Dm[3][3])
+{
+    Dm[0][0] = D6[0 * N + cell];
+    Dm[1][1] = D6[1 * N + cell];
+    Dm[2][2] = D6[2 * N + cell];
+    Dm[0][1] = Dm[1][0] = D6[3 * N + cell];
+    Dm[0][2] = Dm[2][0] = D6[4 * N + cell];
+    Dm[1][2] = Dm[2][1] = D6[5 * N + cell];
+}
+
+static void collide_cell_tensor(const lattice_t *L, const oracle_cfg *cfg, const double Dm[3][3],
+                                const double *gpre, double *gpost)
+{
+    const double *F = cfg->force;
+    double drho = 0.0, j[3] = { 0.0, 0.0, 0.0 };
+    for (int i = 0; i < L->q; ++i) {
+        drho += gpre[i];
+        for (int a = 0; a < 3; ++a) j[a] += L->c[i][a] * gpre[i];
+    }
+    double rho = cfg->rho0 + drho;
+    double u[3], ueq[3];
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * F[a]) / rho;
+    for (int a = 0; a < 3; ++a) {
+        double Du = 0.0;
+        for (int b = 0; b < 3; ++b) Du += Dm[a][b] * u[b];
+        ueq[a] = u[a] - Du;
+    }
+    double geq[19];
+    equilibrium(L, cfg->rho0, rho, ueq, geq);
+    double pref = 1.0 - 0.5 / cfg->tau;
+    for (int i = 0; i < L->q; ++i) {
+        double cu = 0.0, cF = 0.0, uF = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            cu += L->c[i][a] * u[a];
+            cF += L->c[i][a] * F[a];
+            uF += u[a] * F[a];
+        }
+        double S = pref * L->w[i] * (3.0 * (cF - uF) + 9.0 * cu * cF);
+        gpost[i] = gpre[i] - (gpre[i] - geq[i]) / cfg->tau + S;
+    }
+}
+
+int oracle_collide_cell_tensor(const oracle_cfg *cfg, const double *D6cell, const double *gpre,
+                               double *gpost)
+{
+    lattice_t L;
+    if (build_lattice(cfg->q, &L)) return -1;
+    double Dm[3][3];
+    tensor_of(D6cell, 1, 0, Dm);
+    collide_cell_tensor(&L, cfg, Dm, gpre, gpost);
+    return 0;
+}
+
+int oracle_collide_tensor(const oracle_cfg *cfg, const double *D6, const double *pre, double *post,
+                          int nthreads)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    const int ny = cfg->ny, nz = cfg->nz, nx = cfg->nx, q = cfg->q;
+#pragma omp parallel for collapse(2) num_threads(nthreads) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long cell = cell_index(cfg, x, y, z);
+                double gin[19], gout[19], Dm[3][3];
+                if (is_solid(cfg, x, y, z)) {
+                    for (int i = 0; i < q; ++i) post[i * N + cell] = 0.0;
+                    continue;
+                }
+                for (int i = 0; i < q; ++i) gin[i] = pre[i * N + cell];
+                tensor_of(D6, N, cell, Dm);
+                collide_cell_tensor(&L, cfg, Dm, gin, gout);
+                for (int i = 0; i < q; ++i) post[i * N + cell] = gout[i];
+            }
+    return 0;
+}
+
+int oracle_run_tensor(const oracle_cfg *cfg, const double *D6, int nsteps, double *g, int nthreads)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L)) return -1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    double *pre = (double *)malloc(sizeof(double) * (size_t)L.q * (size_t)N);
+    if (!pre) return -2;
+    for (int t = 0; t < nsteps; ++t) {
+        oracle_stream(cfg, g, pre, nthreads);
+        oracle_collide_tensor(cfg, D6, pre, g, nthreads);
+    }
+    free(pre);
+    return 0;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

@@ -235,6 +235,52 @@ def _adj_load():
     return lib
 
 
+def _tensor_load():
+    lib = _load()
+    if not getattr(lib, "_tensor_ready", False):
+        P = ctypes.POINTER
+        D = P(ctypes.c_double)
+        C = P(_Cfg)
+        lib.oracle_collide_cell_tensor.argtypes = [C, D, D, D]
+        lib.oracle_collide_tensor.argtypes = [C, D, D, D, ctypes.c_int]
+        lib.oracle_run_tensor.argtypes = [C, D, ctypes.c_int, D, ctypes.c_int]
+        lib._tensor_ready = True
+    return lib
+
+
+def _tensor_field(cfg: OracleConfig, D6):
+    return np.ascontiguousarray(np.asarray(D6, dtype=np.float64).reshape(6, cfg.ncells))
+
+
+def collide_cell_tensor(cfg: OracleConfig, D6, gpre) -> np.ndarray:
+    """One cell with u_eq = (I - D) u; D6 = (xx, yy, zz, xy, xz, yz)."""
+    dd = np.ascontiguousarray(np.asarray(D6, dtype=np.float64).reshape(6))
+    gin = np.ascontiguousarray(np.asarray(gpre, dtype=np.float64))
+    gout = np.zeros(cfg.q, dtype=np.float64)
+    s = cfg.c_struct()
+    _check(_tensor_load().oracle_collide_cell_tensor(ctypes.byref(s), _dp(dd), _dp(gin), _dp(gout)),
+           "collide_cell_tensor")
+    return gout
+
+
+def collide_tensor(cfg: OracleConfig, D6, pre, nthreads: int = 1) -> np.ndarray:
+    pre = _state(cfg, pre)
+    post = np.zeros_like(pre)
+    s = cfg.c_struct()
+    _check(_tensor_load().oracle_collide_tensor(ctypes.byref(s), _dp(_tensor_field(cfg, D6)), _dp(pre),
+                                                _dp(post), nthreads), "collide_tensor")
+    return post
+
+
+def run_tensor(cfg: OracleConfig, D6, nsteps: int, g=None, nthreads: int = 1) -> np.ndarray:
+    """Advance with the tensor porosity control D6[6, N] (rows xx, yy, zz, xy, xz, yz)."""
+    g = _state(cfg, g)
+    s = cfg.c_struct()
+    _check(_tensor_load().oracle_run_tensor(ctypes.byref(s), _dp(_tensor_field(cfg, D6)), int(nsteps),
+                                            _dp(g), nthreads), "run_tensor")
+    return g
+
+
 def collide_adjoint(cfg: OracleConfig, d, pre, post_bar, nthreads: int = 1):
     """(pre_bar, d_bar) of one collision pass."""
     pre = _state(cfg, pre)

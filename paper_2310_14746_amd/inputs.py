@@ -151,3 +151,39 @@ def round_to(d: np.ndarray, dtype: str) -> np.ndarray:
     if dtype == "f16":
         return np.asarray(d, dtype=np.float16).astype(np.float64)
     raise ValueError(dtype)
+
+
+# ---------------------------------------------------------------------------
+# Tensor (anisotropic) porosity controls D = nu tau K^{-1}, symmetric 3x3 per
+# cell with eigenvalues in [0, 1], returned as 6 rows (xx, yy, zz, xy, xz, yz).
+# ---------------------------------------------------------------------------
+TENSOR_ROWS = ("xx", "yy", "zz", "xy", "xz", "yz")
+
+
+def tensor_rows(M: np.ndarray) -> np.ndarray:
+    """(..., 3, 3) symmetric matrices -> (6, ...) rows xx, yy, zz, xy, xz, yz."""
+    return np.stack([M[..., 0, 0], M[..., 1, 1], M[..., 2, 2], M[..., 0, 1], M[..., 0, 2],
+                     M[..., 1, 2]])
+
+
+def random_tensor_field(shape_zyx, seed: int = 0, sigma: float = 1.0, half: int = 3) -> np.ndarray:
+    """D = G G^T / (1 + |G|_F^2) with G a 3x3 of smoothed noise in [-1, 1]
+    per cell: symmetric positive semidefinite, eigenvalues in [0, 1)."""
+    rng = np.random.default_rng(seed)
+    G = np.empty(tuple(shape_zyx) + (3, 3))
+    for a in range(3):
+        for b in range(3):
+            G[..., a, b] = 2.0 * periodic_smooth(rng.random(shape_zyx), sigma, half) - 1.0
+    M = G @ np.swapaxes(G, -1, -2)
+    M /= (1.0 + (G * G).sum(axis=(-1, -2)))[..., None, None]
+    return tensor_rows(M).reshape(6, -1)
+
+
+def fiber_tensor_field(d: np.ndarray, axis=(2.0, 1.0, 1.0), aniso: float = 0.2) -> np.ndarray:
+    """D = d [aniso I + (1 - aniso) n n^T] for a scalar field d in [0, 1] and a
+    fixed unit fibre direction n: full drag d along n, aniso*d across it."""
+    n = np.asarray(axis, dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    T = aniso * np.eye(3) + (1.0 - aniso) * np.outer(n, n)
+    d = np.asarray(d, dtype=np.float64).ravel()
+    return tensor_rows(T)[:, None] * d[None, :]
