@@ -35,6 +35,7 @@ TAU = 0.6
 FORCE = (1e-6, 0.0, 0.0)
 SCALE_16 = 2.0 ** 24
 ALG_BYTES = {"f32": 19 * 4 * 2 + 4, "f16s": 19 * 2 * 2 + 2, "bf16s": 19 * 2 * 2 + 2}
+TENSOR_BYTES = 19 * 4 * 2 + 6 * 4
 COUNTERS = os.path.join(ROOT, "profiles", "sweep_d3q19_f32_512_counters.json")
 # sources the FP32 sweep kernel is compiled from (counters are valid for them only)
 SWEEP_SRCS = [os.path.join(ROOT, "paper_2310_14746_amd", "csrc", f)
@@ -55,13 +56,18 @@ def rel_l2_drho(dr, dr_ref, u_ref):
     return float(np.linalg.norm(dr - dr_ref) / max(np.linalg.norm(dr_ref), floor))
 
 
-def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0):
+def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar"):
     import torch
     reps = N_EDGE // 32
     dt = np.float32 if storage == "f32" else np.float16
-    d = np.tile(d_tile.astype(dt), (reps, reps, reps))
+    if porosity == "tensor":   # d_tile: (6, 32^3) rows of D
+        d = np.stack([np.tile(r.reshape(32, 32, 32).astype(dt), (reps, reps, reps)).ravel()
+                      for r in d_tile])
+    else:
+        d = np.tile(d_tile.astype(dt), (reps, reps, reps))
     sim = hlbm.HLBM(hlbm.D3Q19, storage, (N_EDGE,) * 3, tau=TAU, force=FORCE,
-                    store_scale=SCALE_16 if storage != "f32" else 1.0, block_x=block_x)
+                    store_scale=SCALE_16 if storage != "f32" else 1.0, block_x=block_x,
+                    porosity=porosity)
     try:
         sim.set_porosity(d)
         del d
@@ -257,7 +263,7 @@ def time_batched(hlbm, steps=2000, seed=0):
     return out
 
 
-ADJ_BYTES = 19 * 8 * 2 + 19 * 4 + 4 + 16  # adjoint kernel, FP32 forward: lam in/out, x, d, dJ/dd r+w
+ADJ_BYTES = 19 * 4 * 2 + 19 * 4 + 4 + 16  # adjoint kernel, FP32 form: lam in/out, x, d, dJ/dd r+w
 
 
 def time_gradient(hlbm, steps=500, every=50, seed=0):
@@ -307,6 +313,30 @@ def time_gradient(hlbm, steps=500, every=50, seed=0):
             "tape_MiB": round(tape / 2 ** 20, 1)}
 
 
+def time_tensor(hlbm, steps, warmup, block_x):
+    """Anisotropic control at 512^3, FP32: the same sphere array with a fibre
+    tensor D = d [0.2 I + 0.8 n n^T], n = (2, 1, 1)/sqrt(6); 19*4*2 + 6*4 = 176
+    algorithmic bytes per cell.  Checked against the oracle's 32^3 tile."""
+    import oracle
+    from paper_2310_14746_amd import inputs
+    tile = inputs.round_to(inputs.fiber_tensor_field(inputs.sphere_array_tile()), "f32")
+    ms, dr, u, tot, teq = time_form(hlbm, "f32", tile, steps, warmup, block_x=block_x, porosity="tensor")
+    cfg = oracle.OracleConfig(q=19, nx=32, ny=32, nz=32, tau=TAU, force=FORCE)
+    nt = max(1, min(16, os.cpu_count() or 1))
+    g = oracle.run_tensor(cfg, tile, steps + warmup, nthreads=nt)
+    dr_o, u_o = oracle.observe(cfg, g, nthreads=nt)
+    n_cells = N_EDGE ** 3
+    return {"workload": "D3Q19 512^3, sphere array with fibre tensor D = d (0.2 I + 0.8 n n^T), "
+                        "n = (2,1,1)/sqrt(6), FP32",
+            "mlups": round(n_cells * steps / (ms * 1e-3) / 1e6, 1),
+            "ms_per_step": round(ms / steps, 4),
+            "alg_bytes_per_cell": TENSOR_BYTES,
+            "alg_GBs": round(TENSOR_BYTES * n_cells * steps / (ms * 1e-3) / 1e9, 1),
+            "tiles_identical": teq,
+            "rel_l2_u_vs_fp64": float("%.3e" % rel_l2(u, u_o)),
+            "rel_l2_drho_vs_fp64": float("%.3e" % rel_l2_drho(dr, dr_o, u_o))}
+
+
 def cpu_baseline(steps_total):
     """Oracle on a 64^3 crop (2^3 obstacle cells; exact by periodicity) -> MLUPS."""
     import oracle
@@ -351,6 +381,7 @@ def main():
     ap.add_argument("--no-copy-reference", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gradient", action="store_true")
+    ap.add_argument("--no-tensor", action="store_true")
     ap.add_argument("--block-x", type=int, default=-1,
                     help="threads per block along x (-1: tuned value, 0: library default)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -388,6 +419,8 @@ def main():
     copy_ref = None if args.no_copy_reference else copy_reference()
     batched = None if args.no_batched else time_batched(hlbm)
     gradient = None if args.no_gradient else time_gradient(hlbm)
+    tensor = None if args.no_tensor else time_tensor(
+        hlbm, args.steps, args.warmup, args.block_x if args.block_x >= 0 else tune.lookup(hlbm.D3Q19, "f32", (N_EDGE,) * 3))
 
     cpu, refs = None, {}
     if not args.no_cpu_baseline:
@@ -436,6 +469,7 @@ def main():
         "forms": {},
         "batched": batched,
         "gradient": gradient,
+        "tensor_control": tensor,
     }
     for f in forms:
         r = results[f]

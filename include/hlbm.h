@@ -81,6 +81,13 @@ enum { HLBM_PERIODIC = 0, HLBM_WALL = 1, HLBM_INLET_U = 2, HLBM_OUTLET_RHO = 3 }
 /* Element types of caller arrays. */
 enum { HLBM_DT_F64 = 0, HLBM_DT_F32 = 1, HLBM_DT_F16 = 2 };
 
+/* Porosity control kinds.  HLBM_POROSITY_SCALAR: one value d = 1 - varpi per
+ * cell, u_eq = (1 - d) u (isotropic permeability, Sec. 3.2).
+ * HLBM_POROSITY_TENSOR (D3Q19): a symmetric 3x3 matrix D = nu tau K^{-1} per
+ * cell for a tensor permeability K, u_eq = (I - D) u -- the anisotropic
+ * extension the paper leaves to future work; D = d I is the scalar case. */
+enum { HLBM_POROSITY_SCALAR = 0, HLBM_POROSITY_TENSOR = 1 };
+
 typedef struct {
     int lattice;         /* HLBM_D2Q9 or HLBM_D3Q19 */
     int storage;         /* HLBM_F64, HLBM_F32, HLBM_F16S, HLBM_BF16S */
@@ -97,6 +104,7 @@ typedef struct {
     int external_memory; /* 1: caller binds population/porosity memory */
     int block_x;         /* threads per block along x (multiple of 64, <= 1024); 0 = auto */
     void *hip_stream;    /* hipStream_t for all work of this context, NULL = default */
+    int porosity_kind;   /* HLBM_POROSITY_SCALAR (default) or HLBM_POROSITY_TENSOR */
 } hlbm_config;
 
 /* Library ABI version (HLBM_ABI_VERSION). */
@@ -115,7 +123,8 @@ int hlbm_config_default(hlbm_config *cfg);
  * hlbm_get_state/hlbm_set_state follow this order. */
 int hlbm_lattice_info(int lattice, int *c, double *w);
 
-/* Bytes of one population buffer and of the porosity field for *cfg. */
+/* Bytes of one population buffer and of the porosity field for *cfg (six
+ * rows for a tensor control). */
 int hlbm_required_bytes(const hlbm_config *cfg, size_t *pop_bytes, size_t *porosity_bytes);
 
 /* Validate *cfg and create a context.  Unless cfg->external_memory is set the
@@ -141,7 +150,11 @@ int hlbm_destroy(hlbm_ctx *ctx);
  * N = nx*ny*nz values, x fastest, of type `dtype` (HLBM_DT_*), on the device
  * if on_device else on the host.  Values are rounded to nearest even into the
  * storage's porosity type (f64, f32, or f16 for the 16-bit forms).  Any NaN or
- * value outside [0, 1] -> EINVAL and the field is left unset.  Synchronous. */
+ * value outside [0, 1] -> EINVAL and the field is left unset.  Synchronous.
+ * With HLBM_POROSITY_TENSOR, d holds 6 rows of N values, D[r*N + cell] for
+ * r = xx, yy, zz, xy, xz, yz; D must have eigenvalues in [0, 1] (D and I - D
+ * positive semidefinite, checked through their principal minors with a
+ * rounding allowance of 1e-12), else EINVAL. */
 int hlbm_set_porosity(hlbm_ctx *ctx, const void *d, int dtype, int on_device);
 
 /* Enqueue `nsteps` >= 0 fused stream-collide sweeps.  ESTATE if the porosity
@@ -214,7 +227,8 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * J observes the moments (drho, u) of the current time level (definitions as
  * for hlbm_moments).  Given dJ/d(drho) and dJ/du at the current time level,
  * hlbm_adjoint_step applies the transposed Jacobians of the last `nsteps`
- * steps in reverse order, carrying FP64 adjoint populations, and adds
+ * steps in reverse order, carrying adjoint populations (stored in FP64 for
+ * HLBM_F64, in FP32 for the other forms; all arithmetic in FP64), and adds
  *   sum over those steps of (dJ/dx_t) . dC(y_t, d)/dd
  * to dJ_dd: the derivative of J with respect to d through those steps (the
  * state before them held fixed).  Explicit dependences of J on d are the
@@ -227,14 +241,14 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * state whenever the state or the porosity changes otherwise (hlbm_set_state,
  * hlbm_reset, hlbm_set_porosity, hlbm_bind_buffers).
  *
- * Single contexts only (a batch returns EUNSUPPORTED).  Requires
- * nx*ny*nz*8 < 4 GiB.
+ * Single contexts only (a batch returns EUNSUPPORTED).
  * ------------------------------------------------------------------------ */
 
 /* Allocate a tape for up to `max_steps` forward steps with a checkpoint every
  * `every` >= 1 steps, and start recording at the current state.  Device memory:
  * (max_steps/every + 1) checkpoints and every-1 replay states, each one
- * population buffer, plus two FP64 adjoint buffers of Q*N doubles.  every = 0
+ * population buffer, plus two adjoint buffers of Q*N values (8 bytes each for
+ * HLBM_F64, else 4).  every = 0
  * frees the tape.  hlbm_step returns EINVAL (and does nothing) if it would
  * take the recorded steps past max_steps.  Waits for the stream. */
 int hlbm_set_tape(hlbm_ctx *ctx, int every, int max_steps);

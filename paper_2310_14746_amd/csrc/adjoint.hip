@@ -28,13 +28,20 @@
 //     (mass kept, momentum (1 - omega) j + omega rho u_eq + (1 - 1/(2 tau)) F),
 //     so x_t itself is never read.
 //
-// Layout: adjoint populations are FP64 rows lam[k*N + cell] (the forward
-// state's layout); dJ/dd is one FP64 value per cell, accumulated.  Blocks
+// Layout: adjoint populations are rows lam[k*N + cell] (the forward state's
+// layout), FP64 for the FP64 form and FP32 for the others; all adjoint
+// arithmetic is FP64 and dJ/dd is one FP64 value per cell, accumulated.  Blocks
 // hold at most 256 threads (the FP64 adjoint needs more registers than a
 // 1024-thread block leaves per thread); the launchers clamp the block width.
+#include <type_traits>
+
 #include "cell.hpp"
 
 namespace hlbm {
+
+// Element type of the adjoint populations for storage policy S.
+template <class S>
+using LamT = typename std::conditional<std::is_same<S, StoreF64>::value, double, float>::type;
 
 // FP64 moments of the pre-collision populations gathered at one cell.
 struct Moms {
@@ -84,7 +91,7 @@ template <class L, class S, int BC>
 __global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* __restrict__ src,
                                                             const double* __restrict__ drho_bar,
                                                             const double* __restrict__ u_bar,
-                                                            double* __restrict__ lam, Params p)
+                                                            LamT<S>* __restrict__ lam, Params p)
 {
     const uint32_t N = p.N;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -106,7 +113,7 @@ __global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* 
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         const double v = base + double(L::cx[k]) * bx + double(L::cy[k]) * by + double(L::cz[k]) * bz;
-        st(lam + (size_t)k * N, cell, sel(solid, 0.0, v));
+        st(lam + (size_t)k * N, cell, LamT<S>(sel(solid, 0.0, v)));
     }
 }
 
@@ -114,8 +121,8 @@ __global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* 
 // S^T: adjoint of the post-collision populations of this cell from the
 // adjoint of the next step's pre-collision populations.
 // ---------------------------------------------------------------------------
-template <class L>
-__device__ __forceinline__ void stream_adjoint_periodic(const double* __restrict__ lam, uint32_t N,
+template <class L, class LT>
+__device__ __forceinline__ void stream_adjoint_periodic(const LT* __restrict__ lam, uint32_t N,
                                                         const Params& p, uint32_t x, uint32_t y,
                                                         uint32_t z, double (&pb)[L::Q])
 {
@@ -127,15 +134,15 @@ __device__ __forceinline__ void stream_adjoint_periodic(const double* __restrict
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         const uint32_t off = xs[L::cx[k] + 1] + nx * (ys[L::cy[k] + 1] + ny * zs[L::cz[k] + 1]);
-        pb[k] = ld(lam + (size_t)k * N, off);
+        pb[k] = (double)ld(lam + (size_t)k * N, off);
     }
 }
 
 // Walls and open faces.  `rho_b`, (ubx, uby, ubz) are this cell's
 // post-collision density and velocity j_b/rho_b at the forward step whose
 // open-face equilibria are being differentiated.
-template <class L>
-__device__ __forceinline__ void stream_adjoint_general(const double* __restrict__ lam, uint32_t N,
+template <class L, class LT>
+__device__ __forceinline__ void stream_adjoint_general(const LT* __restrict__ lam, uint32_t N,
                                                        const Params& p, int x, int y, int z,
                                                        double rho_b, double ubx, double uby,
                                                        double ubz, double (&pb)[L::Q])
@@ -162,7 +169,7 @@ __device__ __forceinline__ void stream_adjoint_general(const double* __restrict_
         const uint32_t noff = (uint32_t)sx + (uint32_t)b.nx * ((uint32_t)sy + (uint32_t)b.ny * (uint32_t)sz);
         const uint32_t row = sel(own, (uint32_t)opposite(k), (uint32_t)k);
         const uint32_t off = sel(own, cell, noff);
-        const double v = ld(lam + (size_t)row * N, off);
+        const double v = (double)ld(lam + (size_t)row * N, off);
         const bool open = outside & !wall;
         pb[k] = sel(open, 0.0, v);
         // open face: v is the adjoint of this cell's pre-collision population
@@ -264,8 +271,8 @@ __device__ __forceinline__ double collide_adjoint(const Moms& m, double d, const
 // forward state x_{t-1} in `xprev`; dbar += this step's dJ/dd.
 // ---------------------------------------------------------------------------
 template <class L, class S, int BC>
-__global__ __launch_bounds__(256) void adjoint_kernel(const double* __restrict__ lam_in,
-                                                       double* __restrict__ lam_out,
+__global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict__ lam_in,
+                                                       LamT<S>* __restrict__ lam_out,
                                                        const typename S::T* __restrict__ xprev,
                                                        const typename S::D* __restrict__ dfield,
                                                        double* __restrict__ dbar, Params p)
@@ -280,7 +287,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const double* __restrict__
     double pb[L::Q];
     bool solid = false;
     if (BC == BC_PERIODIC) {
-        stream_adjoint_periodic<L>(lam_in, N, p, x, y, z, pb);
+        stream_adjoint_periodic<L, LamT<S>>(lam_in, N, p, x, y, z, pb);
     } else {
         // post-collision moments of this cell at step t (balance laws)
         const double rho = p.rho0 + m.s, inv_rho = 1.0 / rho;
@@ -288,13 +295,13 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const double* __restrict__
         const double jbx = (1.0 - om) * m.jx + om * sh * (m.jx + 0.5 * p.F[0]) + p.pref * p.F[0];
         const double jby = (1.0 - om) * m.jy + om * sh * (m.jy + 0.5 * p.F[1]) + p.pref * p.F[1];
         const double jbz = (1.0 - om) * m.jz + om * sh * (m.jz + 0.5 * p.F[2]) + p.pref * p.F[2];
-        stream_adjoint_general<L>(lam_in, N, p, (int)x, (int)y, (int)z, rho, jbx * inv_rho,
+        stream_adjoint_general<L, LamT<S>>(lam_in, N, p, (int)x, (int)y, (int)z, rho, jbx * inv_rho,
                                   jby * inv_rho, jbz * inv_rho, pb);
         solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
     }
     const double dd = collide_adjoint<L>(m, d, p, pb);
 #pragma unroll
-    for (int k = 0; k < L::Q; ++k) st(lam_out + (size_t)k * N, cell, sel(solid, 0.0, pb[k]));
+    for (int k = 0; k < L::Q; ++k) st(lam_out + (size_t)k * N, cell, LamT<S>(sel(solid, 0.0, pb[k])));
     const double acc = ld(dbar, cell);
     st(dbar, cell, acc + sel(solid, 0.0, dd));
 }
@@ -304,39 +311,39 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const double* __restrict__
 // ---------------------------------------------------------------------------
 template <class L, class S>
 static hipError_t seed_dispatch_bc(int bcmode, const Params& p, const void* src, const double* drho_bar,
-                                   const double* u_bar, double* lam, int bx, hipStream_t s)
+                                   const double* u_bar, void* lam, int bx, hipStream_t s)
 {
     const Launch l = cell_launch(p, bx < 256 ? bx : 256);
     auto* a = static_cast<const typename S::T*>(src);
     if (bcmode == BC_PERIODIC)
         hipLaunchKernelGGL((adjoint_seed_kernel<L, S, BC_PERIODIC>), l.grid, l.block, 0, s, a, drho_bar,
-                           u_bar, lam, p);
+                           u_bar, static_cast<LamT<S>*>(lam), p);
     else
         hipLaunchKernelGGL((adjoint_seed_kernel<L, S, BC_GENERAL>), l.grid, l.block, 0, s, a, drho_bar,
-                           u_bar, lam, p);
+                           u_bar, static_cast<LamT<S>*>(lam), p);
     return hipGetLastError();
 }
 
 template <class L, class S>
-static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const double* lam_in, double* lam_out,
+static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* lam_in, void* lam_out,
                                       const void* xprev, const void* dfield, double* dbar, int bx,
                                       hipStream_t s)
 {
     const Launch l = cell_launch(p, bx < 256 ? bx : 256);
     auto* a = static_cast<const typename S::T*>(xprev);
     auto* d = static_cast<const typename S::D*>(dfield);
+    auto* li = static_cast<const LamT<S>*>(lam_in);
+    auto* lo = static_cast<LamT<S>*>(lam_out);
     if (bcmode == BC_PERIODIC)
-        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC>), l.grid, l.block, 0, s, lam_in, lam_out, a,
-                           d, dbar, p);
+        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC>), l.grid, l.block, 0, s, li, lo, a, d, dbar, p);
     else
-        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL>), l.grid, l.block, 0, s, lam_in, lam_out, a,
-                           d, dbar, p);
+        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL>), l.grid, l.block, 0, s, li, lo, a, d, dbar, p);
     return hipGetLastError();
 }
 
 template <class L>
 static hipError_t seed_dispatch_store(int storage, int bcmode, const Params& p, const void* src,
-                                      const double* drho_bar, const double* u_bar, double* lam, int bx,
+                                      const double* drho_bar, const double* u_bar, void* lam, int bx,
                                       hipStream_t s)
 {
     switch (storage) {
@@ -349,8 +356,8 @@ static hipError_t seed_dispatch_store(int storage, int bcmode, const Params& p, 
 }
 
 template <class L>
-static hipError_t adjoint_dispatch_store(int storage, int bcmode, const Params& p, const double* lam_in,
-                                         double* lam_out, const void* xprev, const void* dfield,
+static hipError_t adjoint_dispatch_store(int storage, int bcmode, const Params& p, const void* lam_in,
+                                         void* lam_out, const void* xprev, const void* dfield,
                                          double* dbar, int bx, hipStream_t s)
 {
     switch (storage) {
@@ -367,7 +374,7 @@ static hipError_t adjoint_dispatch_store(int storage, int bcmode, const Params& 
 }
 
 hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, const void* src,
-                               const double* drho_bar, const double* u_bar, double* lam, int bx,
+                               const double* drho_bar, const double* u_bar, void* lam, int bx,
                                hipStream_t s)
 {
     if (q == 9) return seed_dispatch_store<D2Q9>(storage, bcmode, p, src, drho_bar, u_bar, lam, bx, s);
@@ -375,8 +382,8 @@ hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_adjoint(int q, int storage, int bcmode, const Params& p, const double* lam_in,
-                          double* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
+hipError_t launch_adjoint(int q, int storage, int bcmode, const Params& p, const void* lam_in,
+                          void* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
                           hipStream_t s)
 {
     if (q == 9) return adjoint_dispatch_store<D2Q9>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);

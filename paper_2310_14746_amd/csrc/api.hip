@@ -50,7 +50,7 @@ struct hlbm_ctx {
     uint32_t* tile_item_dev;
     double* tile_partials;
     double* item_totals_dev;
-    unsigned* bar_counter;
+    unsigned long long* bar_sync;  // barrier arrivals and work counter
     int* bar_err;
     hlbm::BatchLaunch bl;
     hipGraphExec_t gexec[2];
@@ -64,7 +64,7 @@ struct hlbm_ctx {
     int tape_ncp;
     char* tape_cps;
     char* tape_seg;
-    double* tape_lam[2];
+    char* tape_lam[2];
     // in-sweep diagnostics (hlbm_set_diagnostics): FP64 totals of the time
     // levels n with n % diag_every == 0, appended to a device log
     int diag_every;
@@ -123,6 +123,8 @@ size_t porosity_elem_bytes(int storage)
     }
 }
 
+int porosity_rows(const hlbm_config* c) { return c->porosity_kind == HLBM_POROSITY_TENSOR ? 6 : 1; }
+
 int validate_config(const hlbm_config* c)
 {
     if (!c) return fail(HLBM_EINVAL, "config is NULL");
@@ -158,6 +160,10 @@ int validate_config(const hlbm_config* c)
         return fail(HLBM_EINVAL, "store_scale must be a positive power of two");
     if (c->block_x != 0 && (c->block_x < 64 || c->block_x > 1024 || c->block_x % 64))
         return fail(HLBM_EINVAL, "block_x must be 0 or a multiple of 64 in [64, 1024]");
+    if (c->porosity_kind != HLBM_POROSITY_SCALAR && c->porosity_kind != HLBM_POROSITY_TENSOR)
+        return fail(HLBM_EINVAL, "unknown porosity_kind %d", c->porosity_kind);
+    if (c->porosity_kind == HLBM_POROSITY_TENSOR && c->lattice != HLBM_D3Q19)
+        return fail(HLBM_EUNSUPPORTED, "a tensor porosity control needs D3Q19");
     return HLBM_OK;
 }
 
@@ -340,7 +346,7 @@ int hlbm_required_bytes(const hlbm_config* cfg, size_t* pop_bytes, size_t* poros
     if (rc) return rc;
     const size_t n = (size_t)cfg->nx * cfg->ny * cfg->nz;
     if (pop_bytes) *pop_bytes = n * (size_t)cfg->lattice * elem_bytes(cfg->storage);
-    if (porosity_bytes) *porosity_bytes = n * porosity_elem_bytes(cfg->storage);
+    if (porosity_bytes) *porosity_bytes = n * porosity_elem_bytes(cfg->storage) * porosity_rows(cfg);
     return HLBM_OK;
 }
 
@@ -368,7 +374,7 @@ int hlbm_create(const hlbm_config* cfg, hlbm_ctx** out)
     if (c->own_mem) {
         hipError_t e = hipMalloc(&c->pop[0], c->pop_bytes);
         if (e == hipSuccess) e = hipMalloc(&c->pop[1], c->pop_bytes);
-        if (e == hipSuccess) e = hipMalloc(&c->dfield, (size_t)c->p.N * c->delem);
+        if (e == hipSuccess) e = hipMalloc(&c->dfield, (size_t)c->p.N * c->delem * porosity_rows(cfg));
         if (e != hipSuccess) {
             hlbm_destroy(c);
             return fail(HLBM_ENOMEM, "device allocation of %zu bytes per buffer failed: %s",
@@ -439,7 +445,7 @@ int hlbm_destroy(hlbm_ctx* c)
     if (c->tile_item_dev) (void)hipFree(c->tile_item_dev);
     if (c->tile_partials) (void)hipFree(c->tile_partials);
     if (c->item_totals_dev) (void)hipFree(c->item_totals_dev);
-    if (c->bar_counter) (void)hipFree(c->bar_counter);
+    if (c->bar_sync) (void)hipFree(c->bar_sync);
     if (c->bar_err) (void)hipFree(c->bar_err);
     delete c;
     return rc;
@@ -455,20 +461,22 @@ int hlbm_set_porosity(hlbm_ctx* c, const void* d, int dtype, int on_device)
     if (dtype < HLBM_DT_F64 || dtype > HLBM_DT_F16) return fail(HLBM_EINVAL, "unknown dtype %d", dtype);
     const size_t in_elem = dtype == HLBM_DT_F64 ? 8 : (dtype == HLBM_DT_F32 ? 4 : 2);
     const size_t n = c->p.N;
+    const size_t rows = porosity_rows(&c->cfg);
     const void* src = d;
     void* tmp = nullptr;
     hipError_t e;
     if (!on_device) {
-        e = hipMalloc(&tmp, n * in_elem);
+        e = hipMalloc(&tmp, rows * n * in_elem);
         if (e != hipSuccess) return fail(HLBM_ENOMEM, "staging allocation: %s", hipGetErrorString(e));
-        e = hipMemcpyAsync(tmp, d, n * in_elem, hipMemcpyHostToDevice, c->stream);
+        e = hipMemcpyAsync(tmp, d, rows * n * in_elem, hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) {
             (void)hipFree(tmp);
             return hip_fail(e, "porosity upload");
         }
         src = tmp;
     }
-    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, c->dfield, (uint32_t)n, c->flag_out,
+    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, c->cfg.porosity_kind, c->dfield, (uint32_t)n,
+                                      c->flag_out,
                                       c->stream);
     int flag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, c->flag_out, sizeof(int), hipMemcpyDeviceToHost, c->stream);
@@ -477,7 +485,8 @@ int hlbm_set_porosity(hlbm_ctx* c, const void* d, int dtype, int on_device)
     if (e != hipSuccess) return hip_fail(e, "porosity conversion");
     if (flag) {
         c->porosity_set = false;
-        return fail(HLBM_EINVAL, "porosity values must be finite and in [0, 1]");
+        return fail(HLBM_EINVAL, rows == 1 ? "porosity values must be finite and in [0, 1]"
+                                           : "porosity tensors must be finite with eigenvalues in [0, 1]");
     }
     c->porosity_set = true;
     return tape_restart(c);
@@ -507,7 +516,8 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
         const bool diag = c->diag_every && c->step % c->diag_every == 0;
         const bool record = diag && c->diag_count < c->diag_cap;
         if (diag && !record) c->diag_dropped += 1;
-        e = hlbm::launch_sweep(c->q, c->cfg.storage, c->bcmode, c->p, c->pop[c->cur], c->pop[c->cur ^ 1],
+        e = hlbm::launch_sweep(c->q, c->cfg.storage, c->bcmode, c->cfg.porosity_kind, c->p, c->pop[c->cur],
+                               c->pop[c->cur ^ 1],
                                c->dfield, c->bx, c->stream, record ? c->partials : nullptr);
         if (e == hipSuccess && record)
             e = hlbm::launch_reduce4(c->partials, hlbm::cell_launch(c->p, c->bx).nblocks, c->reduce_stage,
@@ -687,16 +697,19 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (c->batch) return fail(HLBM_EUNSUPPORTED, "a batch has no adjoint");
+    if (c->cfg.porosity_kind != HLBM_POROSITY_SCALAR)
+        return fail(HLBM_EUNSUPPORTED, "the adjoint differentiates a scalar porosity control");
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (every < 0 || max_steps < 0) return fail(HLBM_EINVAL, "every and max_steps must be >= 0");
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "set_tape: outstanding work failed");
     tape_free(c);
     if (every == 0) return HLBM_OK;
-    if ((unsigned long long)c->p.N * sizeof(double) >= (1ull << 32))
-        return fail(HLBM_EUNSUPPORTED, "the adjoint needs nx*ny*nz*8 bytes < 4 GiB per population row");
+    const size_t lam_elem = hlbm::adjoint_elem_bytes(c->cfg.storage);
+    if ((unsigned long long)c->p.N * lam_elem >= (1ull << 32))
+        return fail(HLBM_EUNSUPPORTED, "an adjoint population row (nx*ny*nz elements) must be < 4 GiB");
     const int ncp = max_steps / every + 1;
-    const size_t lam_bytes = (size_t)c->p.N * (size_t)c->q * sizeof(double);
+    const size_t lam_bytes = (size_t)c->p.N * (size_t)c->q * lam_elem;
     e = hipMalloc(&c->tape_cps, (size_t)ncp * c->pop_bytes);
     if (e == hipSuccess && every > 1) e = hipMalloc(&c->tape_seg, (size_t)(every - 1) * c->pop_bytes);
     if (e == hipSuccess) e = hipMalloc(&c->tape_lam[0], lam_bytes);
@@ -723,7 +736,7 @@ int hlbm_tape_info(const hlbm_ctx* c, int* every, int* max_steps, long long* rec
         size_t b = 0;
         if (c->tape_every)
             b = (size_t)(c->tape_ncp + c->tape_every - 1) * c->pop_bytes +
-                2 * (size_t)c->p.N * (size_t)c->q * sizeof(double);
+                2 * (size_t)c->p.N * (size_t)c->q * hlbm::adjoint_elem_bytes(c->cfg.storage);
         *device_bytes = b;
     }
     return HLBM_OK;
@@ -778,7 +791,7 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
             // replay segment m from its checkpoint up to the last state needed
             const long long jmax = (r - m * K);
             for (long long j = 1; j <= jmax && e == hipSuccess; ++j)
-                e = hlbm::launch_sweep(q, storage, bc, c->p, seg_state(m * K + j - 1),
+                e = hlbm::launch_sweep(q, storage, bc, hlbm::PK_SCALAR, c->p, seg_state(m * K + j - 1),
                                        const_cast<void*>(seg_state(m * K + j)), c->dfield, c->bx, c->stream);
             seg_loaded = m;
         }
@@ -818,6 +831,8 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
         int rc = validate_config(it);
         if (rc) return fail(rc, "item %d: %s", k, hlbm_last_error());
         if (it->lattice != HLBM_D3Q19) return fail(HLBM_EUNSUPPORTED, "item %d: batches use D3Q19", k);
+        if (it->porosity_kind != HLBM_POROSITY_SCALAR)
+            return fail(HLBM_EUNSUPPORTED, "item %d: batch items take a scalar porosity control", k);
         if (it->storage != storage) return fail(HLBM_EINVAL, "item %d: all items share one storage", k);
         for (int a = 0; a < 3; ++a)
             if (it->bc_lo[a] != HLBM_PERIODIC || it->bc_hi[a] != HLBM_PERIODIC)
@@ -885,7 +900,7 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
     if (e == hipSuccess) e = hipMalloc(&c->tile_item_dev, sizeof(uint32_t) * (size_t)ntiles);
     if (e == hipSuccess) e = hipMalloc(&c->tile_partials, sizeof(double) * 4 * (size_t)ntiles);
     if (e == hipSuccess) e = hipMalloc(&c->item_totals_dev, sizeof(double) * 4 * (size_t)n_items);
-    if (e == hipSuccess) e = hipMalloc(&c->bar_counter, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMalloc(&c->bar_sync, 2 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(&c->bar_err, sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&c->flag_out, sizeof(int));
     if (e != hipSuccess) {
@@ -915,7 +930,7 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
     c->bl.Ntot = (uint32_t)ntot;
     c->bl.rho0 = c->p.rho0;
     c->bl.scale = c->p.scale;
-    c->bl.counter = c->bar_counter;
+    c->bl.sync = c->bar_sync;
     c->bl.err = c->bar_err;
     c->bl.spin_limit = 1u << 20;
     c->bl.grid = (int)grid;
@@ -974,7 +989,8 @@ int hlbm_batch_set_porosity(hlbm_ctx* c, int item, const void* d, int dtype, int
         src = tmp;
     }
     void* out = static_cast<char*>(c->dfield) + (size_t)it.base * c->delem;
-    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, out, (uint32_t)n, c->flag_out, c->stream);
+    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, hlbm::PK_SCALAR, out, (uint32_t)n, c->flag_out,
+                                      c->stream);
     int flag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, c->flag_out, sizeof(int), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

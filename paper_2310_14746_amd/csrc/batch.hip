@@ -6,15 +6,19 @@
 // Layout: the items' cells are packed one after another, x fastest inside an
 // item, and each population row spans all items: buf[i*Ntot + base_k + local].
 // The packed cells are cut into tiles of TILE consecutive cells that never
-// straddle two items (a tile's tail past the item's end is masked).  Within a
-// step, block b takes tiles b, b + G, b + 2G, ... (G blocks): the blocks
-// resident at any moment work on one contiguous band of tiles, as the blocks of
-// a one-launch-per-step grid would, so the rows a pull reads from the
-// neighbouring y and z rows are still in L2 when the band reaches them.
-// (Giving each block one contiguous range of T/G tiles instead spreads the
-// resident blocks over the whole batch; their neighbour rows no longer fit in
-// L2 and the kernel ran at half the per-step kernel's rate.)
+// straddle two items (a tile's tail past the item's end is masked).
 //
+// Work distribution of the persistent kernel: blocks take chunks of CHUNK
+// consecutive tiles from one device-wide counter, in order, so the blocks
+// resident at any moment work on one contiguous band of tiles (the rows a pull
+// reads from the neighbouring y and z rows are still in L2 when the band
+// reaches them) and a block that finishes early takes more (no static
+// imbalance at the step's end).  Chunk k belongs to step k / nch (nch chunks
+// per step); a block that draws a chunk of a later step keeps it and works on
+// it in that step, after the grid barrier.  Each block draws its next chunk
+// while it works on the current one.  (Measured on the 256-cell workload:
+// 2 tiles per draw beat 1, 4, 8 and 16, and drawing per block beat drawing
+// per wavefront, whose four times as many draws contend on the counter.)
 // The grid is sized to the number of blocks that can be resident at once.
 // The barrier waits with a bounded spin; if the bound is exceeded (a block was
 // never scheduled) or another block reported an error, every block leaves the
@@ -28,24 +32,30 @@ namespace hlbm {
 // (checked on the host for every item).
 __device__ __forceinline__ uint32_t div_magic(uint32_t l, uint32_t magic) { return __umulhi(l, magic); }
 
-__device__ __forceinline__ bool grid_barrier(unsigned* __restrict__ counter, unsigned target,
-                                             int* __restrict__ err, unsigned spin_limit)
+__device__ __forceinline__ bool grid_barrier(unsigned long long* __restrict__ arrivals,
+                                             unsigned long long target, int* __restrict__ err,
+                                             unsigned spin_limit)
 {
     __shared__ int ok;
-    // Release: every wave makes its own stores visible at device scope (waits
-    // for them and writes back its XCD's L2) before the block barrier; a
-    // workgroup barrier alone does not wait for other waves' stores, and the
-    // step's results must be visible to blocks on every XCD.  Release only: an
-    // acquire here would invalidate the L2 under blocks still computing.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Release.  Each wave waits until its own stores have completed (reached
+    // L2: the vector L1 is write-through), the block barrier orders that
+    // before thread 0, and thread 0 releases them at device scope -- one
+    // write-back of this XCD's L2 per block, not per wave -- before it signals
+    // arrival, so the step's results are visible to blocks on every XCD.
+    // Release only: an acquire here would invalidate the L2 under blocks still
+    // computing.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        atomicAdd(counter, 1u);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // the write-back must have completed before the arrival is counted
+        __builtin_amdgcn_s_waitcnt(0);
+        atomicAdd(arrivals, 1ull);
         int good = 1;
         unsigned spins = 0;
         // Relaxed polling (device-coherent loads, no cache invalidation per
         // poll); the acquire follows once, below.
-        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(arrivals, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                 good = 0;
                 break;
@@ -69,10 +79,11 @@ __device__ __forceinline__ bool grid_barrier(unsigned* __restrict__ counter, uns
     return ok != 0;
 }
 
-__global__ void batch_reset_kernel(unsigned* counter, int* err)
+__global__ void batch_reset_kernel(unsigned long long* sync, int* err)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *counter = 0u;
+        sync[0] = 0ull;
+        sync[1] = 0ull;
         *err = 0;
     }
 }
@@ -97,10 +108,10 @@ __device__ __forceinline__ void batch_cell(const typename S::T* __restrict__ src
     const uint32_t cell = it.base + l;
     const R d = S::load_d(ld(dfield, cell));
     R drho, ux, uy, uz;
-    collide<L, R>(g, d, R(it.F[0]), R(it.F[1]), R(it.F[2]), rho0, R(it.omega), R(it.pref), drho, ux,
+    collide<L, R>(g, ScalarShift<R>{d}, R(it.F[0]), R(it.F[1]), R(it.F[2]), rho0, R(it.omega), R(it.pref), drho, ux,
                   uy, uz);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) st(dst + (size_t)i * Ntot, cell, S::store(g[i], scale));
+    for (int i = 0; i < L::Q; ++i) st_stream(dst + (size_t)i * Ntot, cell, S::store(g[i], scale));
 }
 
 template <class S>
@@ -108,21 +119,40 @@ __global__ __launch_bounds__(TILE) void batch_persistent_kernel(
     typename S::T* __restrict__ buf_a, typename S::T* __restrict__ buf_b,
     const typename S::D* __restrict__ dfield, const BatchItem* __restrict__ items,
     const uint32_t* __restrict__ tile_item, uint32_t ntiles, uint32_t Ntot, int nsteps,
-    int start_in_b, double rho0_d, double scale_d, unsigned* __restrict__ counter,
+    int start_in_b, double rho0_d, double scale_d, unsigned long long* __restrict__ sync,
     int* __restrict__ err, unsigned spin_limit)
 {
     using R = typename S::R;
     const R rho0 = R(rho0_d), scale = R(scale_d), inv_scale = R(1.0 / scale_d);
+    const unsigned long long nch = (ntiles + CHUNK - 1) / CHUNK;  // chunks per step
+    __shared__ unsigned long long next;
+    if (threadIdx.x == 0) next = atomicAdd(&sync[1], 1ull);
+    __syncthreads();
+    unsigned long long cur = next;
     for (int s = 0; s < nsteps; ++s) {
         const bool from_b = ((s + start_in_b) & 1) != 0;
         const typename S::T* __restrict__ src = from_b ? buf_b : buf_a;
         typename S::T* __restrict__ dst = from_b ? buf_a : buf_b;
-        for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-            const BatchItem it = items[tile_item[t]];
-            const uint32_t l = (t - it.tile0) * TILE + threadIdx.x;
-            if (l < it.cells) batch_cell<S>(src, dst, dfield, Ntot, it, l, rho0, scale, inv_scale);
+        const unsigned long long first = (unsigned long long)s * nch;
+        while (cur < first + nch) {
+            // draw the following chunk now; its number is needed only after
+            // this chunk is done
+            unsigned long long drawn = 0ull;
+            if (threadIdx.x == 0) drawn = atomicAdd(&sync[1], 1ull);
+            const uint32_t t0 = (uint32_t)(cur - first) * CHUNK;
+            const uint32_t t1 = min(ntiles, t0 + CHUNK);
+            for (uint32_t t = t0; t < t1; ++t) {
+                const BatchItem it = items[tile_item[t]];
+                const uint32_t l = (t - it.tile0) * TILE + threadIdx.x;
+                if (l < it.cells) batch_cell<S>(src, dst, dfield, Ntot, it, l, rho0, scale, inv_scale);
+            }
+            __syncthreads();  // every thread has read `next` for this chunk
+            if (threadIdx.x == 0) next = drawn;
+            __syncthreads();
+            cur = next;
         }
-        if (s + 1 < nsteps && !grid_barrier(counter, (unsigned)(s + 1) * gridDim.x, err, spin_limit))
+        if (s + 1 < nsteps &&
+            !grid_barrier(&sync[0], (unsigned long long)(s + 1) * gridDim.x, err, spin_limit))
             return;
     }
 }
@@ -208,11 +238,11 @@ template <class S>
 static hipError_t persistent_dispatch(const BatchLaunch& b, void* buf_a, void* buf_b, const void* dfield,
                                       int nsteps, int start_in_b, hipStream_t s)
 {
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b.counter, b.err);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b.sync, b.err);
     hipLaunchKernelGGL((batch_persistent_kernel<S>), dim3(b.grid), dim3(TILE), 0, s,
                        static_cast<typename S::T*>(buf_a), static_cast<typename S::T*>(buf_b),
                        static_cast<const typename S::D*>(dfield), b.items, b.tile_item, b.ntiles,
-                       b.Ntot, nsteps, start_in_b, b.rho0, b.scale, b.counter, b.err, b.spin_limit);
+                       b.Ntot, nsteps, start_in_b, b.rho0, b.scale, b.sync, b.err, b.spin_limit);
     return hipGetLastError();
 }
 
@@ -289,9 +319,9 @@ static hipError_t graph_dispatch(const BatchLaunch& b, void* buf_a, void* buf_b,
     hipGraph_t g = nullptr;
     hipError_t e = hipGraphCreate(&g, 0);
     if (e != hipSuccess) return e;
-    unsigned* counter = b.counter;
+    unsigned long long* sync = b.sync;
     int* err = b.err;
-    void* reset_args[] = {&counter, &err};
+    void* reset_args[] = {&sync, &err};
     hipKernelNodeParams rp = {};
     rp.func = reinterpret_cast<void*>(batch_reset_kernel);
     rp.gridDim = dim3(1);
@@ -310,7 +340,7 @@ static hipError_t graph_dispatch(const BatchLaunch& b, void* buf_a, void* buf_b,
     double rho0 = b.rho0, scale = b.scale;
     unsigned spin = b.spin_limit;
     void* run_args[] = {&pa, &pb, &pd, &items, &tile_item, &ntiles, &Ntot, &nsteps,
-                        &start_in_b, &rho0, &scale, &counter, &err, &spin};
+                        &start_in_b, &rho0, &scale, &sync, &err, &spin};
     hipKernelNodeParams kp = {};
     kp.func = reinterpret_cast<void*>(batch_persistent_kernel<S>);
     kp.gridDim = dim3(b.grid);

@@ -30,9 +30,62 @@ __device__ __forceinline__ void st(T* __restrict__ base, uint32_t idx, T v)
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)) = v;
 }
 
+// Store of a new population: nothing reads it again within the step, so it
+// is written with the non-temporal hint (streamed past the caches).
+template <class T>
+__device__ __forceinline__ void st_stream(T* __restrict__ base, uint32_t idx, T v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)));
+}
+
+// Porosity shift policies: the equilibrium velocity u_eq from u.
+//   ScalarShift : u_eq = (1 - d) u                     (Sec. 3.2, varpi = 1 - d)
+//   TensorShift : u_eq = (I - D) u, D = nu tau K^{-1}  (tensor permeability K;
+//                 the isotropic case of Sec. 3.2 is D = d I)
+// eq() works in R, eq_d() in FP64 (for the exact post-collision momentum).
+template <class R>
+struct ScalarShift {
+    R d;
+    __device__ __forceinline__ void eq(R ux, R uy, R uz, R& ex, R& ey, R& ez) const
+    {
+        const R sh = R(1) - d;
+        ex = sh * ux;
+        ey = sh * uy;
+        ez = sh * uz;
+    }
+    __device__ __forceinline__ void eq_d(double ux, double uy, double uz, double& ex, double& ey,
+                                         double& ez) const
+    {
+        const double sh = 1.0 - (double)d;
+        ex = sh * ux;
+        ey = sh * uy;
+        ez = sh * uz;
+    }
+};
+
+template <class R>
+struct TensorShift {
+    R xx, yy, zz, xy, xz, yz;
+    __device__ __forceinline__ void eq(R ux, R uy, R uz, R& ex, R& ey, R& ez) const
+    {
+        ex = ux - (xx * ux + xy * uy + xz * uz);
+        ey = uy - (xy * ux + yy * uy + yz * uz);
+        ez = uz - (xz * ux + yz * uy + zz * uz);
+    }
+    __device__ __forceinline__ void eq_d(double ux, double uy, double uz, double& ex, double& ey,
+                                         double& ez) const
+    {
+        const double dxx = xx, dyy = yy, dzz = zz, dxy = xy, dxz = xz, dyz = yz;
+        ex = ux - (dxx * ux + dxy * uy + dxz * uz);
+        ey = uy - (dxy * ux + dyy * uy + dyz * uz);
+        ez = uz - (dxz * ux + dyz * uy + dzz * uz);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Collision of one fluid cell in the arithmetic type R (Sec. 3.2: BGK toward
-// the homogenized Maxwellian; the velocity argument is (1 - d) u).
+// the homogenized Maxwellian; the velocity argument is (1 - d) u, or (I - D) u
+// for a tensor control, see the shift policies below).
 //   rho = rho0 + sum g, j = sum c g, u = (j + F/2)/rho, u_eq = (1 - d) u
 //   g_i <- g_i - omega (g_i - g^eq_i(rho, u_eq)) + S_i
 //   g^eq_i = w_i [ drho + rho (3 c.u_eq + 9/2 (c.u_eq)^2 - 3/2 u_eq.u_eq) ]
@@ -53,9 +106,9 @@ __device__ __forceinline__ void st(T* __restrict__ base, uint32_t idx, T v)
 //     arithmetic this correction is zero.
 // Returns drho and u (the reported moments) through the reference arguments.
 // ---------------------------------------------------------------------------
-template <class L, class R>
-__device__ __forceinline__ void collide(R (&g)[L::Q], R d, R F0, R F1, R F2, R rho0, R omega,
-                                        R pref, R& drho_out, R& ux_out, R& uy_out, R& uz_out)
+template <class L, class R, class Shift>
+__device__ __forceinline__ void collide(R (&g)[L::Q], const Shift& shift, R F0, R F1, R F2, R rho0,
+                                        R omega, R pref, R& drho_out, R& ux_out, R& uy_out, R& uz_out)
 {
     double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
@@ -73,8 +126,8 @@ __device__ __forceinline__ void collide(R (&g)[L::Q], R d, R F0, R F1, R F2, R r
     const double uzd = (jz + 0.5 * (double)F2) * inv_rho_d;
     const R drho = R(s), rho = R(rho_d);
     const R ux = R(uxd), uy = R(uyd), uz = R(uzd);
-    const R sh = R(1) - d;
-    const R ex = sh * ux, ey = sh * uy, ez = sh * uz;
+    R ex, ey, ez;
+    shift.eq(ux, uy, uz, ex, ey, ez);
     const R uu = ex * ex + ey * ey + ez * ez;
     const R uF = ux * F0 + uy * F1 + uz * F2;
     const R base = drho - R(1.5) * rho * uu;  // common part of every g^eq_i / w_i
@@ -96,10 +149,12 @@ __device__ __forceinline__ void collide(R (&g)[L::Q], R d, R F0, R F1, R F2, R r
         if (L::cz[i]) pz += L::cz[i] > 0 ? gi : -gi;
     }
     // exact post-collision moments from the pre-collision ones (FP64)
-    const double om = (double)omega, sh_d = 1.0 - (double)d, pr = (double)pref;
-    const double tx = (1.0 - om) * jx + om * rho_d * sh_d * uxd + pr * (double)F0;
-    const double ty = (1.0 - om) * jy + om * rho_d * sh_d * uyd + pr * (double)F1;
-    const double tz = (1.0 - om) * jz + om * rho_d * sh_d * uzd + pr * (double)F2;
+    const double om = (double)omega, pr = (double)pref;
+    double exd, eyd, ezd;
+    shift.eq_d(uxd, uyd, uzd, exd, eyd, ezd);
+    const double tx = (1.0 - om) * jx + om * rho_d * exd + pr * (double)F0;
+    const double ty = (1.0 - om) * jy + om * rho_d * eyd + pr * (double)F1;
+    const double tz = (1.0 - om) * jz + om * rho_d * ezd + pr * (double)F2;
     constexpr int xp = axis_velocity<L>(0, 1), xm = axis_velocity<L>(0, -1);
     constexpr int yp = axis_velocity<L>(1, 1), ym = axis_velocity<L>(1, -1);
     const R hx = R(0.5 * (tx - px)), hy = R(0.5 * (ty - py));

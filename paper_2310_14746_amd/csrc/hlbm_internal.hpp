@@ -24,6 +24,8 @@ struct Params {
 };
 
 enum BcMode { BC_PERIODIC = 0, BC_GENERAL = 1 };
+// Porosity control kinds: one value d per cell, or a symmetric 3x3 D (6 rows).
+enum PorosityKind { PK_SCALAR = 0, PK_TENSOR = 1 };
 
 // Launch geometry shared by every per-cell kernel: blocks of `bx` threads
 // along x, grid (ceil(nx/bx), ny, nz).
@@ -31,24 +33,26 @@ struct Launch {
     dim3 grid, block;
     uint32_t nblocks;
 };
-Launch cell_launch(const Params& p, int bx);
+Launch cell_launch(const Params& p, int bx, int cells_per_thread = 1);
 
 // Kernel launchers (sweep.hip).  All return the launch status.
 // One sweep.  With diag_partials != NULL the diagnostic variant also writes
 // FP64 block partials of the totals (one 4-double record per block).
-hipError_t launch_sweep(int q, int storage, int bcmode, const Params& p, const void* src,
+hipError_t launch_sweep(int q, int storage, int bcmode, int pk, const Params& p, const void* src,
                         void* dst, const void* dfield, int bx, hipStream_t s,
                         double* diag_partials = nullptr);
 hipError_t launch_moments(int q, int storage, int bcmode, const Params& p, const void* src,
                           void* drho, void* u, int out_f64, double* partials, int bx,
                           hipStream_t s);
 // Reverse sweep (adjoint.hip): seed from the moments' cotangents, then one
-// launch per reverse step.  Adjoint populations are FP64 rows of N values.
+// launch per reverse step.  Adjoint populations are rows of N values of
+// adjoint_elem_bytes(storage) bytes (FP64 for the FP64 form, FP32 otherwise).
+inline size_t adjoint_elem_bytes(int storage) { return storage == 0 ? 8 : 4; }
 hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, const void* src,
-                               const double* drho_bar, const double* u_bar, double* lam, int bx,
+                               const double* drho_bar, const double* u_bar, void* lam, int bx,
                                hipStream_t s);
-hipError_t launch_adjoint(int q, int storage, int bcmode, const Params& p, const double* lam_in,
-                          double* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
+hipError_t launch_adjoint(int q, int storage, int bcmode, const Params& p, const void* lam_in,
+                          void* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
                           hipStream_t s);
 // Fixed-order two-pass sum of `nblocks` partials of 4 doubles into out[4];
 // `stage` holds 4*REDUCE_STAGE doubles.
@@ -57,13 +61,14 @@ hipError_t launch_reduce4(const double* partials, uint32_t nblocks, double* stag
                           hipStream_t s);
 // Convert and validate the porosity; *flag (device) ends nonzero if any value
 // is NaN or outside [0, 1].
-hipError_t launch_porosity_convert(int in_dtype, const void* in, int storage, void* out,
+hipError_t launch_porosity_convert(int in_dtype, const void* in, int storage, int pk, void* out,
                                    uint32_t n, int* flag, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Batched periodic boxes
 // ---------------------------------------------------------------------------
-constexpr int TILE = 256;  // cells per tile (one block of the batched kernels)
+constexpr int TILE = 256;         // cells per tile (one block of the batched kernels)
+constexpr uint32_t CHUNK = 2;     // tiles per draw of a block of the persistent kernel
 
 // One item of a batch, as read by the kernels.
 struct BatchItem {
@@ -82,7 +87,7 @@ struct BatchLaunch {
     const uint32_t* tile_item;  // device, ntiles
     uint32_t n_items, ntiles, Ntot;
     double rho0, scale;
-    unsigned* counter;          // device barrier counter
+    unsigned long long* sync;   // device: [0] barrier arrivals, [1] work chunks taken
     int* err;                   // device error flag
     unsigned spin_limit;
     int grid;                   // resident blocks of the persistent kernel

@@ -20,7 +20,7 @@ namespace hlbm {
 // store into the other buffer.  Returns the pre-collision moments (time level
 // of `src`) and whether the cell is solid.
 // ---------------------------------------------------------------------------
-template <class L, class S, int BC>
+template <class L, class S, int BC, int PK>
 __device__ __forceinline__ bool sweep_cell(const typename S::T* __restrict__ src,
                                            typename S::T* __restrict__ dst,
                                            const typename S::D* __restrict__ dfield, const Params& p,
@@ -42,17 +42,28 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* __restrict__ src
                               R(p.outlet_rho)};
         gather_general<L, S>(src, N, b, of, (int)x, (int)y, (int)z, inv_scale, g);
     }
-    const R d = S::load_d(ld(dfield, cell));
-    collide<L, R>(g, d, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+    if (PK == PK_SCALAR) {
+        const ScalarShift<R> sh{S::load_d(ld(dfield, cell))};
+        collide<L, R>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+    } else {
+        // six rows xx, yy, zz, xy, xz, yz of the symmetric control D
+        const TensorShift<R> sh{S::load_d(ld(dfield, cell)),
+                                S::load_d(ld(dfield + (size_t)N, cell)),
+                                S::load_d(ld(dfield + 2 * (size_t)N, cell)),
+                                S::load_d(ld(dfield + 3 * (size_t)N, cell)),
+                                S::load_d(ld(dfield + 4 * (size_t)N, cell)),
+                                S::load_d(ld(dfield + 5 * (size_t)N, cell))};
+        collide<L, R>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+    }
     // solid cells (wall layers) hold zeros; selected, not branched
     bool solid = false;
     if (BC != BC_PERIODIC) solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) st(dst + (size_t)i * N, cell, S::store(sel(solid, R(0), g[i]), scale));
+    for (int i = 0; i < L::Q; ++i) st_stream(dst + (size_t)i * N, cell, S::store(sel(solid, R(0), g[i]), scale));
     return solid;
 }
 
-template <class L, class S, int BC>
+template <class L, class S, int BC, int PK>
 __global__ __launch_bounds__(1024) void sweep_kernel(const typename S::T* __restrict__ src,
                                                       typename S::T* __restrict__ dst,
                                                       const typename S::D* __restrict__ dfield,
@@ -62,14 +73,14 @@ __global__ __launch_bounds__(1024) void sweep_kernel(const typename S::T* __rest
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)p.nx) return;
     R drho, ux, uy, uz;
-    (void)sweep_cell<L, S, BC>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
+    (void)sweep_cell<L, S, BC, PK>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
 }
 
 // The same step on a diagnostic step: the sweep also reduces the moments it
 // has formed (time level of `src`, fluid cells) to FP64 block partials
 // [sum drho, sum rho u_x, sum rho u_y, sum rho u_z], with the same block
 // geometry and arithmetic as the moments kernel's totals.
-template <class L, class S, int BC>
+template <class L, class S, int BC, int PK>
 __global__ __launch_bounds__(1024) void sweep_diag_kernel(const typename S::T* __restrict__ src,
                                                            typename S::T* __restrict__ dst,
                                                            const typename S::D* __restrict__ dfield,
@@ -81,7 +92,7 @@ __global__ __launch_bounds__(1024) void sweep_diag_kernel(const typename S::T* _
     if (x < (uint32_t)p.nx) {
         R drho, ux, uy, uz;
         const bool solid =
-            sweep_cell<L, S, BC>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
+            sweep_cell<L, S, BC, PK>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
         const double rho = p.rho0 + (double)drho;
         m0 = sel(solid, 0.0, (double)drho);
         m1 = sel(solid, 0.0, rho * (double)ux);
@@ -90,6 +101,112 @@ __global__ __launch_bounds__(1024) void sweep_diag_kernel(const typename S::T* _
     }
     const uint32_t bk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     block_sum4(m0, m1, m2, m3, partials + 4 * (size_t)bk);
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit storage, periodic box: two neighbouring cells of an x-row per
+// thread.  A 16-bit row element is too narrow to keep the memory system busy
+// one lane at a time; a pair is one 32-bit access per population.  The pair
+// pulled for c_x = +1 starts one element to the left of the thread's own pair
+// and the pair for c_x = -1 one to the right (2-byte aligned 32-bit loads);
+// at the two ends of a row the pair wraps around, and the lane there patches
+// the wrapped element with one more 16-bit load.  Each cell goes through the
+// same collision as in sweep_kernel, so results are bit for bit those of the
+// one-cell kernel.  Requires nx even and >= 4.
+// ---------------------------------------------------------------------------
+template <class S>
+__device__ __forceinline__ uint32_t ld_pair(const typename S::T* __restrict__ row, uint32_t x)
+{
+    uint32_t w;
+    __builtin_memcpy(&w, reinterpret_cast<const char*>(row) + x * (uint32_t)sizeof(typename S::T), 4);
+    return w;
+}
+
+template <class S>
+__device__ __forceinline__ typename S::R unpack(uint32_t bits16, typename S::R inv_scale)
+{
+    const uint16_t h = static_cast<uint16_t>(bits16);
+    typename S::T v;
+    __builtin_memcpy(&v, &h, 2);
+    return S::load(v, inv_scale);
+}
+
+template <class S>
+__device__ __forceinline__ uint32_t pack(typename S::R lo, typename S::R hi, typename S::R scale)
+{
+    const typename S::T a = S::store(lo, scale), b = S::store(hi, scale);
+    uint16_t ua, ub;
+    __builtin_memcpy(&ua, &a, 2);
+    __builtin_memcpy(&ub, &b, 2);
+    return (uint32_t)ua | ((uint32_t)ub << 16);
+}
+
+template <class S>
+__global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* __restrict__ src,
+                                                           typename S::T* __restrict__ dst,
+                                                           const typename S::D* __restrict__ dfield,
+                                                           Params p)
+{
+    using L = D3Q19;
+    using R = typename S::R;
+    using T = typename S::T;
+    const uint32_t x0 = 2u * (blockIdx.x * blockDim.x + threadIdx.x);
+    const uint32_t nx = p.nx, ny = p.ny, nz = p.nz, N = p.N;
+    if (x0 >= nx) return;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    const R inv_scale = R(p.inv_scale), scale = R(p.scale);
+    const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
+    const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};
+    const bool first = x0 == 0, last = x0 + 2 == nx;
+    R lo[L::Q], hi[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const T* row = src + (size_t)i * N + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+        // start of the pulled pair: x0 - c_x, kept inside the row at the ends
+        uint32_t xs = x0;
+        if (L::cx[i] > 0) xs = sel(first, x0, x0 - 1);
+        if (L::cx[i] < 0) xs = sel(last, x0, x0 + 1);
+        const uint32_t w = ld_pair<S>(row, xs);
+        lo[i] = unpack<S>(w & 0xffffu, inv_scale);
+        hi[i] = unpack<S>(w >> 16, inv_scale);
+    }
+    if (first) {  // c_x = +1 pulls (nx - 1, 0): the loaded pair was (0, 1)
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            if (L::cx[i] <= 0) continue;
+            const T* row = src + (size_t)i * N + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+            hi[i] = lo[i];
+            lo[i] = S::load(ld(row, nx - 1), inv_scale);
+        }
+    }
+    if (last) {  // c_x = -1 pulls (nx - 1, 0): the loaded pair was (nx - 2, nx - 1)
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            if (L::cx[i] >= 0) continue;
+            const T* row = src + (size_t)i * N + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+            lo[i] = hi[i];
+            hi[i] = S::load(ld(row, 0u), inv_scale);
+        }
+    }
+    const uint32_t cell = x0 + nx * (y + ny * z);
+    const R F0 = R(p.F[0]), F1 = R(p.F[1]), F2 = R(p.F[2]);
+    const R rho0 = R(p.rho0), omega = R(p.omega), pref = R(p.pref);
+    R drho, ux, uy, uz;
+    // the two cells' controls as one 32-bit load (16-bit porosity elements)
+    static_assert(sizeof(typename S::D) == 2, "pair kernel expects 16-bit porosity elements");
+    uint32_t dw;
+    __builtin_memcpy(&dw, reinterpret_cast<const char*>(dfield) + cell * 2u, 4);
+    typename S::D d_lo, d_hi;
+    const uint16_t dl = (uint16_t)(dw & 0xffffu), dh = (uint16_t)(dw >> 16);
+    __builtin_memcpy(&d_lo, &dl, 2);
+    __builtin_memcpy(&d_hi, &dh, 2);
+    collide<L, R>(lo, ScalarShift<R>{S::load_d(d_lo)}, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+    collide<L, R>(hi, ScalarShift<R>{S::load_d(d_hi)}, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        uint32_t* out = reinterpret_cast<uint32_t*>(dst + (size_t)i * N);
+        st_stream(out, cell / 2u, pack<S>(lo[i], hi[i], scale));
+    }
 }
 
 // Moments at the current time level (gather + moments, no collision).
@@ -180,19 +297,54 @@ __global__ __launch_bounds__(256) void porosity_kernel(const I* __restrict__ in,
     if (threadIdx.x == 0 && any) atomicOr(flag, 1);
 }
 
+// Tensor control: six input rows (xx, yy, zz, xy, xz, yz) of N values; D must
+// be symmetric with eigenvalues in [0, 1] (both D and I - D positive
+// semidefinite: all principal minors >= 0, to a rounding allowance of 1e-12).
+__device__ __forceinline__ bool psd3(double a, double b, double c, double ab, double ac, double bc)
+{
+    const double tol = -1e-12;
+    const double m2ab = a * b - ab * ab, m2ac = a * c - ac * ac, m2bc = b * c - bc * bc;
+    const double det = a * m2bc - ab * (ab * c - bc * ac) + ac * (ab * bc - b * ac);
+    return (a >= tol) & (b >= tol) & (c >= tol) & (m2ab >= tol) & (m2ac >= tol) & (m2bc >= tol) &
+           (det >= tol);
+}
+
+template <class I, class O>
+__global__ __launch_bounds__(256) void tensor_porosity_kernel(const I* __restrict__ in,
+                                                              O* __restrict__ out, uint32_t n,
+                                                              int* __restrict__ flag)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    int bad = 0;
+    if (k < n) {
+        double v[6];
+        for (int r = 0; r < 6; ++r) {
+            v[r] = (double)in[(size_t)r * n + k];
+            bad |= !(v[r] == v[r]) | !(v[r] - v[r] == 0.0);  // NaN or infinite
+            out[(size_t)r * n + k] = O(in[(size_t)r * n + k]);
+        }
+        const bool ok = psd3(v[0], v[1], v[2], v[3], v[4], v[5]) &&
+                        psd3(1.0 - v[0], 1.0 - v[1], 1.0 - v[2], -v[3], -v[4], -v[5]);
+        bad |= !ok;
+    }
+    const int any = __syncthreads_or(bad);
+    if (threadIdx.x == 0 && any) atomicOr(flag, 1);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-Launch cell_launch(const Params& p, int bx)
+Launch cell_launch(const Params& p, int bx, int cells_per_thread)
 {
     Launch l;
+    const int tx = (p.nx + cells_per_thread - 1) / cells_per_thread;  // threads per x-row
     l.block = dim3(bx, 1, 1);
-    l.grid = dim3((p.nx + bx - 1) / bx, p.ny, p.nz);
+    l.grid = dim3((tx + bx - 1) / bx, p.ny, p.nz);
     l.nblocks = l.grid.x * l.grid.y * l.grid.z;
     return l;
 }
 
-template <class L, class S>
+template <class L, class S, int PK>
 static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src, void* dst,
                                     const void* dfield, int bx, hipStream_t s, double* diag)
 {
@@ -202,36 +354,47 @@ static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src
     auto* d = static_cast<const typename S::D*>(dfield);
     if (diag) {
         if (bcmode == BC_PERIODIC)
-            hipLaunchKernelGGL((sweep_diag_kernel<L, S, BC_PERIODIC>), l.grid, l.block, 0, s, a, b, d, diag, p);
+            hipLaunchKernelGGL((sweep_diag_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, a, b, d, diag, p);
         else
-            hipLaunchKernelGGL((sweep_diag_kernel<L, S, BC_GENERAL>), l.grid, l.block, 0, s, a, b, d, diag, p);
+            hipLaunchKernelGGL((sweep_diag_kernel<L, S, BC_GENERAL, PK>), l.grid, l.block, 0, s, a, b, d, diag, p);
     } else if (bcmode == BC_PERIODIC) {
-        hipLaunchKernelGGL((sweep_kernel<L, S, BC_PERIODIC>), l.grid, l.block, 0, s, a, b, d, p);
+        if constexpr (sizeof(typename S::T) == 2 && L::Q == 19 && PK == PK_SCALAR) {
+            if (p.nx % 2 == 0 && p.nx >= 4) {
+                const Launch lp = cell_launch(p, bx, 2);
+                hipLaunchKernelGGL((sweep_pair_kernel<S>), lp.grid, lp.block, 0, s, a, b, d, p);
+                return hipGetLastError();
+            }
+        }
+        hipLaunchKernelGGL((sweep_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, a, b, d, p);
     } else {
-        hipLaunchKernelGGL((sweep_kernel<L, S, BC_GENERAL>), l.grid, l.block, 0, s, a, b, d, p);
+        hipLaunchKernelGGL((sweep_kernel<L, S, BC_GENERAL, PK>), l.grid, l.block, 0, s, a, b, d, p);
     }
     return hipGetLastError();
 }
 
-template <class L>
+template <class L, int PK>
 static hipError_t sweep_dispatch_store(int storage, int bcmode, const Params& p, const void* src,
                                        void* dst, const void* dfield, int bx, hipStream_t s,
                                        double* diag)
 {
     switch (storage) {
-    case StoreF64::code: return sweep_dispatch_bc<L, StoreF64>(bcmode, p, src, dst, dfield, bx, s, diag);
-    case StoreF32::code: return sweep_dispatch_bc<L, StoreF32>(bcmode, p, src, dst, dfield, bx, s, diag);
-    case StoreF16S::code: return sweep_dispatch_bc<L, StoreF16S>(bcmode, p, src, dst, dfield, bx, s, diag);
-    case StoreBF16S::code: return sweep_dispatch_bc<L, StoreBF16S>(bcmode, p, src, dst, dfield, bx, s, diag);
+    case StoreF64::code: return sweep_dispatch_bc<L, StoreF64, PK>(bcmode, p, src, dst, dfield, bx, s, diag);
+    case StoreF32::code: return sweep_dispatch_bc<L, StoreF32, PK>(bcmode, p, src, dst, dfield, bx, s, diag);
+    case StoreF16S::code: return sweep_dispatch_bc<L, StoreF16S, PK>(bcmode, p, src, dst, dfield, bx, s, diag);
+    case StoreBF16S::code: return sweep_dispatch_bc<L, StoreBF16S, PK>(bcmode, p, src, dst, dfield, bx, s, diag);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep(int q, int storage, int bcmode, const Params& p, const void* src, void* dst,
-                        const void* dfield, int bx, hipStream_t s, double* diag_partials)
+hipError_t launch_sweep(int q, int storage, int bcmode, int pk, const Params& p, const void* src,
+                        void* dst, const void* dfield, int bx, hipStream_t s, double* diag_partials)
 {
-    if (q == 9) return sweep_dispatch_store<D2Q9>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials);
-    if (q == 19) return sweep_dispatch_store<D3Q19>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials);
+    if (q == 9 && pk == PK_SCALAR)
+        return sweep_dispatch_store<D2Q9, PK_SCALAR>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials);
+    if (q == 19 && pk == PK_SCALAR)
+        return sweep_dispatch_store<D3Q19, PK_SCALAR>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials);
+    if (q == 19 && pk == PK_TENSOR)
+        return sweep_dispatch_store<D3Q19, PK_TENSOR>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials);
     return hipErrorInvalidValue;
 }
 
@@ -321,11 +484,34 @@ static hipError_t porosity_dispatch_out(const void* in, int storage, void* out, 
     return hipGetLastError();
 }
 
-hipError_t launch_porosity_convert(int in_dtype, const void* in, int storage, void* out, uint32_t n,
-                                   int* flag, hipStream_t s)
+template <class I>
+static hipError_t tensor_dispatch_out(const void* in, int storage, void* out, uint32_t n, int* flag,
+                                      hipStream_t s)
+{
+    const uint32_t nb = (n + 255) / 256;
+    auto* src = static_cast<const I*>(in);
+    if (storage == StoreF64::code)
+        hipLaunchKernelGGL((tensor_porosity_kernel<I, double>), dim3(nb), dim3(256), 0, s, src,
+                           static_cast<double*>(out), n, flag);
+    else if (storage == StoreF32::code)
+        hipLaunchKernelGGL((tensor_porosity_kernel<I, float>), dim3(nb), dim3(256), 0, s, src,
+                           static_cast<float*>(out), n, flag);
+    else
+        hipLaunchKernelGGL((tensor_porosity_kernel<I, _Float16>), dim3(nb), dim3(256), 0, s, src,
+                           static_cast<_Float16*>(out), n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_porosity_convert(int in_dtype, const void* in, int storage, int pk, void* out,
+                                   uint32_t n, int* flag, hipStream_t s)
 {
     hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
     if (e != hipSuccess) return e;
+    if (pk == PK_TENSOR) {
+        if (in_dtype == 0) return tensor_dispatch_out<double>(in, storage, out, n, flag, s);
+        if (in_dtype == 1) return tensor_dispatch_out<float>(in, storage, out, n, flag, s);
+        return tensor_dispatch_out<_Float16>(in, storage, out, n, flag, s);
+    }
     if (in_dtype == 0) return porosity_dispatch_out<double>(in, storage, out, n, flag, s);
     if (in_dtype == 1) return porosity_dispatch_out<float>(in, storage, out, n, flag, s);
     return porosity_dispatch_out<_Float16>(in, storage, out, n, flag, s);

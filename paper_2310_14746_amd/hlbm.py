@@ -26,6 +26,8 @@ D2Q9, D3Q19 = 9, 19
 F64, F32, F16S, BF16S = 0, 1, 2, 3
 AB = 0
 PERIODIC, WALL, INLET_U, OUTLET_RHO = 0, 1, 2, 3
+POROSITY_SCALAR, POROSITY_TENSOR = 0, 1
+POROSITY_KINDS = {"scalar": POROSITY_SCALAR, "tensor": POROSITY_TENSOR}
 DT_F64, DT_F32, DT_F16 = 0, 1, 2
 
 STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S}
@@ -56,6 +58,7 @@ class Config(ctypes.Structure):
         ("external_memory", ctypes.c_int),
         ("block_x", ctypes.c_int),
         ("hip_stream", ctypes.c_void_p),
+        ("porosity_kind", ctypes.c_int),
     ]
 
 
@@ -140,7 +143,8 @@ def lattice_info(q: int):
 def make_config(lattice: int = D3Q19, storage="f32", shape=(32, 32, 32), tau: float = 0.6,
                 force=(0.0, 0.0, 0.0), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), inlet_u=(0.0, 0.0, 0.0),
                 outlet_rho: float = 1.0, rho0: float = 1.0, store_scale: float = 1.0,
-                block_x: int = 0, external_memory: int = 0, stream: Optional[int] = None) -> Config:
+                block_x: int = 0, external_memory: int = 0, stream: Optional[int] = None,
+                porosity: str = "scalar") -> Config:
     cfg = Config()
     _check(load().hlbm_config_default(ctypes.byref(cfg)))
     cfg.lattice = int(lattice)
@@ -159,6 +163,7 @@ def make_config(lattice: int = D3Q19, storage="f32", shape=(32, 32, 32), tau: fl
     cfg.block_x = int(block_x)
     cfg.external_memory = int(external_memory)
     cfg.hip_stream = stream
+    cfg.porosity_kind = POROSITY_KINDS[porosity]
     return cfg
 
 
@@ -172,7 +177,7 @@ class HLBM:
     def __init__(self, lattice: int = D3Q19, storage="f32", shape=(32, 32, 32), tau=0.6,
                  force=(0.0, 0.0, 0.0), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0),
                  inlet_u=(0.0, 0.0, 0.0), outlet_rho=1.0, rho0=1.0, store_scale=1.0,
-                 block_x=0, device="cuda:0"):
+                 block_x=0, device="cuda:0", porosity="scalar"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -180,8 +185,9 @@ class HLBM:
         lib = load()
         self.cfg = make_config(lattice, storage, shape, tau, force, bc_lo, bc_hi, inlet_u,
                                outlet_rho, rho0, store_scale, block_x, external_memory=1,
-                               stream=self.stream.cuda_stream)
+                               stream=self.stream.cuda_stream, porosity=porosity)
         self.q = self.cfg.lattice
+        self.porosity_rows = 6 if porosity == "tensor" else 1
         self.storage = self.cfg.storage
         self.shape = (self.cfg.nx, self.cfg.ny, self.cfg.nz)
         self.N = self.cfg.nx * self.cfg.ny * self.cfg.nz
@@ -219,13 +225,15 @@ class HLBM:
 
     # -- porosity ----------------------------------------------------------
     def set_porosity(self, d):
-        """d = 1 - varpi per cell: numpy array (host) or torch tensor (host or device)."""
+        """d = 1 - varpi per cell (or, for porosity="tensor", rows xx, yy, zz, xy,
+        xz, yz of D, shape (6, N)): numpy array (host) or torch tensor (host or
+        device)."""
         t = self.torch
         if isinstance(d, t.Tensor):
             dd = d.contiguous()
             dtype = {t.float64: DT_F64, t.float32: DT_F32, t.float16: DT_F16}[dd.dtype]
-            if dd.numel() != self.N:
-                raise ValueError("porosity needs nx*ny*nz values")
+            if dd.numel() != self.N * self.porosity_rows:
+                raise ValueError(f"porosity needs {self.porosity_rows} x nx*ny*nz values")
             on_dev = 1 if dd.is_cuda else 0
             if on_dev:
                 _check(load().hlbm_set_porosity(self.ctx, dd.data_ptr(), dtype, 1))
@@ -234,8 +242,8 @@ class HLBM:
                 _check(load().hlbm_set_porosity(self.ctx, arr.ctypes.data, dtype, 0))
             return
         arr = np.ascontiguousarray(d)
-        if arr.size != self.N:
-            raise ValueError("porosity needs nx*ny*nz values")
+        if arr.size != self.N * self.porosity_rows:
+            raise ValueError(f"porosity needs {self.porosity_rows} x nx*ny*nz values")
         dtype = {np.dtype(np.float64): DT_F64, np.dtype(np.float32): DT_F32,
                  np.dtype(np.float16): DT_F16}[arr.dtype]
         _check(load().hlbm_set_porosity(self.ctx, arr.ctypes.data, dtype, 0))

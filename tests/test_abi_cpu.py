@@ -61,6 +61,11 @@ def test_required_bytes():
     assert rc == 0 and pb == 19 * 2 * 64 * 32 * 16 and db == 2 * 64 * 32 * 16
     rc, pb, db = _rb(hlbm.make_config(9, "f64", (128, 64, 1), bc_lo=(0, 1, 0), bc_hi=(0, 1, 0)))
     assert rc == 0 and pb == 9 * 8 * 128 * 64 and db == 8 * 128 * 64
+    # a tensor control holds six rows
+    rc, pb, db = _rb(hlbm.make_config(19, "f32", (32, 16, 8), porosity="tensor"))
+    assert rc == 0 and pb == 19 * 4 * 32 * 16 * 8 and db == 6 * 4 * 32 * 16 * 8
+    rc, pb, db = _rb(hlbm.make_config(19, "bf16s", (32, 16, 8), porosity="tensor", store_scale=2.0 ** 20))
+    assert rc == 0 and db == 6 * 2 * 32 * 16 * 8
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -79,6 +84,7 @@ def test_required_bytes():
     (dict(shape=(8, 70000, 4)), hlbm.EUNSUPPORTED),
     (dict(lattice=9, shape=(8, 8, 2)), hlbm.EINVAL),
     (dict(bc_lo=(1, 0, 0), bc_hi=(1, 0, 0), shape=(2, 8, 8)), hlbm.EINVAL),
+    (dict(lattice=9, shape=(8, 8, 1), porosity="tensor"), hlbm.EUNSUPPORTED),
 ])
 def test_config_validation(kw, code):
     args = dict(lattice=19, storage="f32", shape=(16, 16, 16))
@@ -86,6 +92,13 @@ def test_config_validation(kw, code):
     rc, _, _ = _rb(hlbm.make_config(**args))
     assert rc == code
     assert hlbm.load().hlbm_last_error().decode()
+
+
+def test_unknown_porosity_kind():
+    cfg = hlbm.make_config(19, "f32", (16, 16, 16))
+    cfg.porosity_kind = 7
+    rc, _, _ = _rb(cfg)
+    assert rc == hlbm.EINVAL and "porosity_kind" in hlbm.load().hlbm_last_error().decode()
 
 
 def test_null_arguments(lib):

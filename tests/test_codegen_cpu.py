@@ -40,7 +40,7 @@ def _kernels(funcs, prefix):
 
 def test_sweep_kernels_are_straight_line(asm):
     sweeps = _kernels(asm, "_ZN4hlbm12sweep_kernel")
-    assert len(sweeps) == 16
+    assert len(sweeps) == 24  # 16 scalar-control kernels + 8 tensor-control (D3Q19)
     for name, body in sweeps.items():
         branches = len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
         assert branches <= 1, (name, branches)
@@ -58,27 +58,37 @@ def test_no_private_memory_in_sweep_and_moments(asm):
     for name, body in {**_kernels(asm, "_ZN4hlbm12sweep_kernel"),
                        **_kernels(asm, "_ZN4hlbm14moments_kernel"),
                        **_kernels(asm, "_ZN4hlbm14adjoint_kernel"),
+                       **_kernels(asm, "_ZN4hlbm17sweep_pair_kernel"),
                        **_kernels(asm, "_ZN4hlbm19adjoint_seed_kernel"),
                        **_kernels(asm, "_ZN4hlbm23batch_persistent_kernel"),
                        **_kernels(asm, "_ZN4hlbm17batch_step_kernel")}.items():
         assert not re.search(r"^\s+(scratch_|buffer_store|buffer_load)", body, flags=re.M), name
 
 
+def _arrival_atomic(lines):
+    """Index of the grid barrier's arrival atomic: the last atomic add before
+    the polling loop (the one with s_sleep)."""
+    sleep = next(i for i, l in enumerate(lines) if l.startswith("s_sleep"))
+    return max(i for i in range(sleep) if lines[i].startswith("global_atomic_add"))
+
+
 def test_persistent_barrier_releases_every_wave(asm):
-    """Each wave writes back (device-scope release) before the block barrier
-    that precedes the arrival count, so stores of every wave are visible to
-    blocks on other XCDs after the grid barrier."""
+    """Every wave waits for its stores (vmcnt(0)) before the block barrier that
+    precedes the arrival count, and the L2 is written back (device-scope
+    release) between that barrier and the arrival atomic, so the stores of
+    every wave are visible to blocks on other XCDs after the grid barrier."""
     kern = _kernels(asm, "_ZN4hlbm23batch_persistent_kernel")
     assert len(kern) == 4
     for name, body in kern.items():
         lines = [l.strip() for l in body.splitlines()]
-        idx = [i for i, l in enumerate(lines) if l.startswith("global_atomic_add")]
-        assert idx, name
-        # the block barrier before the arrival atomic is preceded by wbl2 + vmcnt(0)
-        bar = max(i for i in range(idx[0]) if lines[i].startswith("s_barrier"))
-        window = lines[max(0, bar - 6):bar]
-        assert any(l.startswith("buffer_wbl2") for l in window), name
-        assert any(l.startswith("s_waitcnt vmcnt(0)") for l in window), name
+        arrive = _arrival_atomic(lines)
+        bar = max(i for i in range(arrive) if lines[i].startswith("s_barrier"))
+        before = lines[max(0, bar - 4):bar]
+        assert any(l.startswith("s_waitcnt vmcnt(0)") for l in before), name
+        between = lines[bar:arrive]
+        wb = [i for i, l in enumerate(between) if l.startswith("buffer_wbl2 sc1")]
+        assert wb, name
+        assert any(l.startswith("s_waitcnt vmcnt(0)") for l in between[wb[0]:]), name
 
 
 def test_no_scalar_cache_writes(asm):
@@ -101,7 +111,7 @@ def test_barrier_polling_keeps_caches(asm):
     computing (acquire happens once, after the count is reached)."""
     for name, body in _kernels(asm, "_ZN4hlbm23batch_persistent_kernel").items():
         lines = [l.strip() for l in body.splitlines()]
-        add = next(i for i, l in enumerate(lines) if l.startswith("global_atomic_add"))
+        add = _arrival_atomic(lines)
         sleep = next(i for i, l in enumerate(lines) if l.startswith("s_sleep"))
         assert add < sleep, name
         window = lines[add:sleep + 20]
