@@ -56,16 +56,16 @@ def rel_l2_drho(dr, dr_ref, u_ref):
     return float(np.linalg.norm(dr - dr_ref) / max(np.linalg.norm(dr_ref), floor))
 
 
-def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar"):
+def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar", edge=N_EDGE):
     import torch
-    reps = N_EDGE // 32
+    reps = edge // 32
     dt = np.float32 if storage == "f32" else np.float16
     if porosity == "tensor":   # d_tile: (6, 32^3) rows of D
         d = np.stack([np.tile(r.reshape(32, 32, 32).astype(dt), (reps, reps, reps)).ravel()
                       for r in d_tile])
     else:
         d = np.tile(d_tile.astype(dt), (reps, reps, reps))
-    sim = hlbm.HLBM(hlbm.D3Q19, storage, (N_EDGE,) * 3, tau=TAU, force=FORCE,
+    sim = hlbm.HLBM(hlbm.D3Q19, storage, (edge,) * 3, tau=TAU, force=FORCE,
                     store_scale=SCALE_16 if storage != "f32" else 1.0, block_x=block_x,
                     porosity=porosity)
     try:
@@ -88,7 +88,7 @@ def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar"
         dr_t = drho[:32, :32, :32].cpu().numpy().ravel()
         u_t = u[:, :32, :32, :32].cpu().numpy().reshape(3, -1)
         # every 32^3 tile identical (exact periodicity of the workload)
-        r = N_EDGE // 32
+        r = edge // 32
         v = drho.reshape(r, 32, r, 32, r, 32)
         tiles_equal = bool((v == v[:1, :, :1, :, :1, :]).all().item())
         del drho, u, v
@@ -337,6 +337,21 @@ def time_tensor(hlbm, steps, warmup, block_x):
             "rel_l2_drho_vs_fp64": float("%.3e" % rel_l2_drho(dr, dr_o, u_o))}
 
 
+def time_c1(hlbm, block_x):
+    """The same FP32 sweep on the 256^3 box (8^3 sphere cells), 1000 steps."""
+    from paper_2310_14746_amd import inputs
+    steps = 1000
+    tile = inputs.round_to(inputs.sphere_array_tile(), "f32")
+    ms, _, _, _, teq = time_form(hlbm, "f32", tile, steps, 20, block_x=block_x, edge=256)
+    n_cells = 256 ** 3
+    return {"workload": "D3Q19 256^3 periodic, 8^3 sphere array, tau=0.6, F=1e-6 x, FP32, 1000 steps",
+            "mlups": round(n_cells * steps / (ms * 1e-3) / 1e6, 1),
+            "ms_per_step": round(ms / steps, 4),
+            "alg_GBs": round(156 * n_cells * steps / (ms * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(156 * n_cells * steps / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "tiles_identical": teq}
+
+
 def cpu_baseline(steps_total):
     """Oracle on a 64^3 crop (2^3 obstacle cells; exact by periodicity) -> MLUPS."""
     import oracle
@@ -382,6 +397,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gradient", action="store_true")
     ap.add_argument("--no-tensor", action="store_true")
+    ap.add_argument("--no-c1", action="store_true")
     ap.add_argument("--block-x", type=int, default=-1,
                     help="threads per block along x (-1: tuned value, 0: library default)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -419,6 +435,7 @@ def main():
     copy_ref = None if args.no_copy_reference else copy_reference()
     batched = None if args.no_batched else time_batched(hlbm)
     gradient = None if args.no_gradient else time_gradient(hlbm)
+    c1 = None if args.no_c1 else time_c1(hlbm, tune.lookup(hlbm.D3Q19, "f32", (256,) * 3))
     tensor = None if args.no_tensor else time_tensor(
         hlbm, args.steps, args.warmup, args.block_x if args.block_x >= 0 else tune.lookup(hlbm.D3Q19, "f32", (N_EDGE,) * 3))
 
@@ -470,6 +487,7 @@ def main():
         "batched": batched,
         "gradient": gradient,
         "tensor_control": tensor,
+        "c1_256": c1,
     }
     for f in forms:
         r = results[f]

@@ -108,7 +108,7 @@ __device__ __forceinline__ void batch_cell(const typename S::T* __restrict__ src
     const uint32_t cell = it.base + l;
     const R d = S::load_d(ld(dfield, cell));
     R drho, ux, uy, uz;
-    collide<L, R>(g, ScalarShift<R>{d}, R(it.F[0]), R(it.F[1]), R(it.F[2]), rho0, R(it.omega), R(it.pref), drho, ux,
+    collide<L, R, ScalarShift<R>, S::exact_moments>(g, ScalarShift<R>{d}, R(it.F[0]), R(it.F[1]), R(it.F[2]), rho0, R(it.omega), R(it.pref), drho, ux,
                   uy, uz);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) st_stream(dst + (size_t)i * Ntot, cell, S::store(g[i], scale));
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(TILE) void batch_moments_kernel(
         R g[L::Q];
         gather_periodic<L, S>(src, Ntot, it.base, it.nx, it.ny, it.nz, x, y, z, R(1.0 / scale_d), g);
         R drho, ux, uy, uz;
-        moments_of<L, R>(g, R(it.F[0]), R(it.F[1]), R(it.F[2]), R(rho0_d), drho, ux, uy, uz);
+        moments_of<L, R, S::exact_moments>(g, R(it.F[0]), R(it.F[1]), R(it.F[2]), R(rho0_d), drho, ux, uy, uz);
         const double rho = rho0_d + (double)drho;
         m0 = (double)drho;
         m1 = rho * (double)ux;

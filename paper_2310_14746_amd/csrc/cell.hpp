@@ -106,10 +106,59 @@ struct TensorShift {
 //     arithmetic this correction is zero.
 // Returns drho and u (the reported moments) through the reference arguments.
 // ---------------------------------------------------------------------------
+// The same collision with the moment sums in R and no correction, for the
+// 16-bit storage forms: their stored values carry ~2^-11 relative rounding, far
+// above anything the FP64 sums would remove, and at half the bytes per cell the
+// FP64 work would become the sweep's bottleneck.
 template <class L, class R, class Shift>
+__device__ __forceinline__ void collide_plain(R (&g)[L::Q], const Shift& shift, R F0, R F1, R F2,
+                                              R rho0, R omega, R pref, R& drho_out, R& ux_out,
+                                              R& uy_out, R& uz_out)
+{
+    R s = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        s += g[i];
+        if (L::cx[i]) jx += L::cx[i] > 0 ? g[i] : -g[i];
+        if (L::cy[i]) jy += L::cy[i] > 0 ? g[i] : -g[i];
+        if (L::cz[i]) jz += L::cz[i] > 0 ? g[i] : -g[i];
+    }
+    const R rho = rho0 + s;
+    const R inv_rho = R(1) / rho;
+    const R ux = (jx + R(0.5) * F0) * inv_rho;
+    const R uy = (jy + R(0.5) * F1) * inv_rho;
+    const R uz = (jz + R(0.5) * F2) * inv_rho;
+    R ex, ey, ez;
+    shift.eq(ux, uy, uz, ex, ey, ez);
+    const R uu = ex * ex + ey * ey + ez * ez;
+    const R uF = ux * F0 + uy * F1 + uz * F2;
+    const R base = s - R(1.5) * rho * uu;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const R cx = R(L::cx[i]), cy = R(L::cy[i]), cz = R(L::cz[i]);
+        const R w = R(L::w[i]);
+        const R ce = cx * ex + cy * ey + cz * ez;
+        const R cu = cx * ux + cy * uy + cz * uz;
+        const R cF = cx * F0 + cy * F1 + cz * F2;
+        const R geq = w * (base + rho * (R(3) * ce + R(4.5) * ce * ce));
+        const R S = pref * w * (R(3) * (cF - uF) + R(9) * cu * cF);
+        g[i] = g[i] + (S - omega * (g[i] - geq));
+    }
+    drho_out = s;
+    ux_out = ux;
+    uy_out = uy;
+    uz_out = uz;
+}
+
+template <class L, class R, class Shift, bool Exact = true>
 __device__ __forceinline__ void collide(R (&g)[L::Q], const Shift& shift, R F0, R F1, R F2, R rho0,
                                         R omega, R pref, R& drho_out, R& ux_out, R& uy_out, R& uz_out)
 {
+    if constexpr (!Exact) {
+        collide_plain<L, R, Shift>(g, shift, F0, F1, F2, rho0, omega, pref, drho_out, ux_out, uy_out,
+                                   uz_out);
+        return;
+    }
     double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
@@ -176,12 +225,28 @@ __device__ __forceinline__ void collide(R (&g)[L::Q], const Shift& shift, R F0, 
 }
 
 // Moments only (no collision), same definitions as in collide().
-// The sums run in FP64 and the results are rounded to R once, exactly as the
-// collision forms them, so reported moments equal the collision's own.
-template <class L, class R>
+// The sums run as the collision's do (FP64, rounded to R once; or in R for
+// the 16-bit forms), so reported moments equal the collision's own.
+template <class L, class R, bool Exact = true>
 __device__ __forceinline__ void moments_of(const R (&g)[L::Q], R F0, R F1, R F2, R rho0, R& drho,
                                            R& ux, R& uy, R& uz)
 {
+    if constexpr (!Exact) {
+        R s = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            s += g[i];
+            if (L::cx[i]) jx += L::cx[i] > 0 ? g[i] : -g[i];
+            if (L::cy[i]) jy += L::cy[i] > 0 ? g[i] : -g[i];
+            if (L::cz[i]) jz += L::cz[i] > 0 ? g[i] : -g[i];
+        }
+        const R inv_rho = R(1) / (rho0 + s);
+        drho = s;
+        ux = (jx + R(0.5) * F0) * inv_rho;
+        uy = (jy + R(0.5) * F1) * inv_rho;
+        uz = (jz + R(0.5) * F2) * inv_rho;
+        return;
+    }
     double s = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {

@@ -19,6 +19,7 @@ struct StoreF64 {
     using R = double;  // arithmetic type
     using D = double;  // porosity element
     static constexpr int code = 0;
+    static constexpr bool exact_moments = true;  // FP64 moment sums + balance-law correction
     __device__ static inline R load(T v, R) { return v; }
     __device__ static inline T store(R v, R) { return v; }
     __device__ static inline R load_d(D v) { return v; }
@@ -29,6 +30,7 @@ struct StoreF32 {
     using R = float;
     using D = float;
     static constexpr int code = 1;
+    static constexpr bool exact_moments = true;
     __device__ static inline R load(T v, R) { return v; }
     __device__ static inline T store(R v, R) { return v; }
     __device__ static inline R load_d(D v) { return v; }
@@ -39,6 +41,7 @@ struct StoreF16S {
     using R = float;
     using D = _Float16;
     static constexpr int code = 2;
+    static constexpr bool exact_moments = false;  // moment sums in f32
     __device__ static inline R load(T v, R inv_scale) { return static_cast<float>(v) * inv_scale; }
     // f32 -> f16 conversion rounds to nearest even in the default mode.
     __device__ static inline T store(R v, R scale) { return static_cast<_Float16>(v * scale); }
@@ -53,6 +56,7 @@ struct StoreBF16S {
     using R = float;
     using D = _Float16;
     static constexpr int code = 3;
+    static constexpr bool exact_moments = false;
     __device__ static inline R load(T v, R inv_scale)
     {
         return __uint_as_float(static_cast<uint32_t>(v) << 16) * inv_scale;

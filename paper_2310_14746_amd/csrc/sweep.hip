@@ -44,7 +44,7 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* __restrict__ src
     }
     if (PK == PK_SCALAR) {
         const ScalarShift<R> sh{S::load_d(ld(dfield, cell))};
-        collide<L, R>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+        collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
     } else {
         // six rows xx, yy, zz, xy, xz, yz of the symmetric control D
         const TensorShift<R> sh{S::load_d(ld(dfield, cell)),
@@ -53,7 +53,7 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* __restrict__ src
                                 S::load_d(ld(dfield + 3 * (size_t)N, cell)),
                                 S::load_d(ld(dfield + 4 * (size_t)N, cell)),
                                 S::load_d(ld(dfield + 5 * (size_t)N, cell))};
-        collide<L, R>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+        collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
     }
     // solid cells (wall layers) hold zeros; selected, not branched
     bool solid = false;
@@ -200,8 +200,10 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
     const uint16_t dl = (uint16_t)(dw & 0xffffu), dh = (uint16_t)(dw >> 16);
     __builtin_memcpy(&d_lo, &dl, 2);
     __builtin_memcpy(&d_hi, &dh, 2);
-    collide<L, R>(lo, ScalarShift<R>{S::load_d(d_lo)}, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
-    collide<L, R>(hi, ScalarShift<R>{S::load_d(d_hi)}, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+    collide<L, R, ScalarShift<R>, S::exact_moments>(lo, ScalarShift<R>{S::load_d(d_lo)}, F0, F1, F2, rho0, omega,
+                                                    pref, drho, ux, uy, uz);
+    collide<L, R, ScalarShift<R>, S::exact_moments>(hi, ScalarShift<R>{S::load_d(d_hi)}, F0, F1, F2, rho0, omega,
+                                                    pref, drho, ux, uy, uz);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         uint32_t* out = reinterpret_cast<uint32_t*>(dst + (size_t)i * N);
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(1024) void moments_kernel(const typename S::T* __re
             gather_general<L, S>(src, N, b, of, (int)x, (int)y, (int)z, inv_scale, g);
         }
         R drho, ux, uy, uz;
-        moments_of<L, R>(g, F0, F1, F2, rho0, drho, ux, uy, uz);
+        moments_of<L, R, S::exact_moments>(g, F0, F1, F2, rho0, drho, ux, uy, uz);
         drho = sel(fluid, drho, R(0));
         ux = sel(fluid, ux, R(0));
         uy = sel(fluid, uy, R(0));
