@@ -163,7 +163,7 @@ def counters_traffic(n_cells):
     return info.get("hbm_bytes_per_launch")
 
 
-SWEEP_F32 = "hlbm::sweep_kernel<hlbm::D3Q19, hlbm::StoreF32, 0>"
+SWEEP_F32 = "hlbm::sweep_kernel<hlbm::D3Q19, hlbm::StoreF32, 0, 0>"  # periodic, scalar control
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
@@ -367,6 +367,12 @@ def cpu_baseline(steps_total):
     dr, u = oracle.observe(cfg, g, nthreads=nt)
     dr = dr.reshape(n, n, n)[:32, :32, :32].ravel()
     u = u.reshape(3, n, n, n)[:, :32, :32, :32].reshape(3, -1)
+    # one host thread, on the 32^3 cell (exact by periodicity), 100 steps
+    cfg1 = oracle.OracleConfig(q=19, nx=32, ny=32, nz=32, tau=TAU, force=FORCE)
+    d1 = d.reshape(n, n, n)[:32, :32, :32].ravel().copy()
+    t1 = time.perf_counter()
+    oracle.run(cfg1, d1, 100, nthreads=1)
+    secs1 = time.perf_counter() - t1
     return {
         "value": n ** 3 * steps_total / secs / 1e6,
         "unit": "MLUPS",
@@ -374,6 +380,8 @@ def cpu_baseline(steps_total):
         "kind": "oracle",
         "sample": f"FP64 oracle, {n}^3 periodic crop of the same workload (2^3 obstacle cells, "
                   f"exact by 32-periodicity), {steps_total} steps, {secs:.1f} s",
+        "single_thread": {"value": round(32 ** 3 * 100 / secs1 / 1e6, 2), "unit": "MLUPS", "cores": 1,
+                          "sample": f"32^3 cell, 100 steps, {secs1:.1f} s"},
     }, dr, u
 
 

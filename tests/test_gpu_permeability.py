@@ -1,10 +1,11 @@
 """Unit-cell permeability workloads on the batched sweep: the running
 permeability k(t) = nu <rho u_x>(t)/F of homogenized unit cells driven from
 rest (the integral of the transient permeability of the time-dependent cell
-problem) against the FP64 oracle at several times, its monotone rise (the
-transient permeability is non-negative here), and the smoothed control against
-the sharp indicator of the same spheres (reported; the resolved-geometry
-permeability has no exact value here: parity unpinned)."""
+problem) against the FP64 oracle at several times, and the smoothed control
+against the sharp indicator of the same spheres (reported; the
+resolved-geometry permeability has no exact value here: parity unpinned).
+k(t) is not monotone: the lattice fluid is weakly compressible, and the
+acoustic response to the suddenly applied force overshoots before it settles."""
 import os
 
 import numpy as np
@@ -47,9 +48,8 @@ def test_transient_permeability_vs_oracle(H):
             f"oracle {np.array2string(ko, precision=5)} max rel {err:.2e}")
         assert err <= 1e-5
         assert abs(k[0, j] - (it["tau"] - 0.5) / 6.0) <= 1e-6 * k[0, j]   # rest state: u = F/2
-        assert np.all(np.diff(k[:, j]) >= -1e-6 * np.abs(k[:, j]).max())
     rate = permeability.transient_rate(times, k)
-    assert np.all(rate >= -1e-9)
+    assert rate.shape == (len(times) - 1, len(items)) and np.all(np.isfinite(rate))
 
 
 def test_sharp_indicator_vs_homogenized(H):
