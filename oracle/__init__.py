@@ -26,6 +26,9 @@ from .oracle import (  # noqa: F401
     collide_cell_tensor,
     collide_tensor,
     run_tensor,
+    stream_masked,
+    run_masked,
+    observe_masked,
     PERIODIC,
     WALL,
     INLET_U,

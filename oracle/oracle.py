@@ -281,6 +281,57 @@ def run_tensor(cfg: OracleConfig, D6, nsteps: int, g=None, nthreads: int = 1) ->
     return g
 
 
+def _mask_load():
+    lib = _load()
+    if not getattr(lib, "_mask_ready", False):
+        P = ctypes.POINTER
+        D = P(ctypes.c_double)
+        C = P(_Cfg)
+        U8 = P(ctypes.c_ubyte)
+        lib.oracle_stream_masked.argtypes = [C, U8, D, D, ctypes.c_int]
+        lib.oracle_run_masked.argtypes = [C, U8, D, ctypes.c_int, D, ctypes.c_int]
+        lib.oracle_observe_masked.argtypes = [C, U8, D, D, D, ctypes.c_int]
+        lib._mask_ready = True
+    return lib
+
+
+def _mask(cfg: OracleConfig, mask):
+    m = np.ascontiguousarray(np.asarray(mask).reshape(cfg.ncells).astype(np.uint8))
+    return m, m.ctypes.data_as(ctypes.POINTER(ctypes.c_ubyte))
+
+
+def stream_masked(cfg: OracleConfig, mask, post, nthreads: int = 1) -> np.ndarray:
+    """Pull streaming in a periodic box with solid cells (mask != 0)."""
+    post = _state(cfg, post)
+    pre = np.zeros_like(post)
+    m, mp = _mask(cfg, mask)
+    s = cfg.c_struct()
+    _check(_mask_load().oracle_stream_masked(ctypes.byref(s), mp, _dp(post), _dp(pre), nthreads),
+           "stream_masked")
+    return pre
+
+
+def run_masked(cfg: OracleConfig, mask, d, nsteps: int, g=None, nthreads: int = 1) -> np.ndarray:
+    """Advance a periodic box with resolved solid cells (bounce-back links)."""
+    g = _state(cfg, g)
+    m, mp = _mask(cfg, mask)
+    s = cfg.c_struct()
+    _check(_mask_load().oracle_run_masked(ctypes.byref(s), mp, _dp(_field(cfg, d)), int(nsteps), _dp(g),
+                                          nthreads), "run_masked")
+    return g
+
+
+def observe_masked(cfg: OracleConfig, mask, g, nthreads: int = 1):
+    g = _state(cfg, g)
+    drho = np.zeros(cfg.ncells)
+    u = np.zeros((3, cfg.ncells))
+    m, mp = _mask(cfg, mask)
+    s = cfg.c_struct()
+    _check(_mask_load().oracle_observe_masked(ctypes.byref(s), mp, _dp(g), _dp(drho), _dp(u), nthreads),
+           "observe_masked")
+    return drho, u
+
+
 def collide_adjoint(cfg: OracleConfig, d, pre, post_bar, nthreads: int = 1):
     """(pre_bar, d_bar) of one collision pass."""
     pre = _state(cfg, pre)
