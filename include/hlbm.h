@@ -197,6 +197,19 @@ int hlbm_reset(hlbm_ctx *ctx);
  * batch, if a grid barrier of the persistent kernel timed out). */
 int hlbm_sync(hlbm_ctx *ctx);
 
+/* Resolved obstacles in a fully periodic box (the geometry of the periodic
+ * unit-cell Stokes problem the homogenized control stands in for, Sec. 2.2):
+ * mask[cell] != 0 marks a solid cell (N bytes, x fastest; device memory if
+ * on_device, else host).  No-slip u = 0 on the obstacle surface (Sec. 2.4,
+ * eq:targetEBTL) by halfway bounce-back at every fluid-solid link: a
+ * population whose pull source is solid is the cell's own opposite one.
+ * Solid cells hold zeros and report zero moments; the porosity control still
+ * applies in fluid cells.  mask = NULL removes the obstacles.  The link mask
+ * (4 bytes per cell) is built on the device.  EUNSUPPORTED unless every face
+ * is periodic, or for a batch; ESTATE while an adjoint tape is set.
+ * Synchronous. */
+int hlbm_set_solid_mask(hlbm_ctx *ctx, const unsigned char *mask, int on_device);
+
 /* Diagnostics taken inside the sweep.  With every > 0, each hlbm_step sweep
  * that starts from a time level n with n % every == 0 also reduces the moments
  * it forms (those of time level n, as hlbm_moments would report them) to FP64

@@ -73,6 +73,8 @@ struct hlbm_ctx {
     long long diag_dropped;
     double* diag_log;
     std::vector<long long> diag_steps;
+    // resolved solid cells (hlbm_set_solid_mask): per-cell link mask
+    uint32_t* linkmask;
 };
 
 namespace {
@@ -438,6 +440,7 @@ int hlbm_destroy(hlbm_ctx* c)
     if (c->reduce_stage) (void)hipFree(c->reduce_stage);
     if (c->flag_out) (void)hipFree(c->flag_out);
     if (c->diag_log) (void)hipFree(c->diag_log);
+    if (c->linkmask) (void)hipFree(c->linkmask);
     for (int k = 0; k < 2; ++k)
         if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
     tape_free(c);
@@ -692,6 +695,48 @@ int hlbm_read_diagnostics(hlbm_ctx* c, double* out, int max_records, int* count,
     return HLBM_OK;
 }
 
+int hlbm_set_solid_mask(hlbm_ctx* c, const unsigned char* mask, int on_device)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->batch) return fail(HLBM_EUNSUPPORTED, "batch items take no solid mask");
+    if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
+    for (int a = 0; a < 3; ++a)
+        if (c->cfg.bc_lo[a] != HLBM_PERIODIC)
+            return fail(HLBM_EUNSUPPORTED, "a solid mask needs periodic faces on every axis");
+    if (c->tape_every) return fail(HLBM_ESTATE, "free the adjoint tape first (hlbm_set_tape(ctx, 0, 0))");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "set_solid_mask: outstanding work failed");
+    if (!mask) {
+        c->bcmode = hlbm::BC_PERIODIC;
+        c->p.linkmask = nullptr;
+        return HLBM_OK;
+    }
+    const size_t n = c->p.N;
+    if (!c->linkmask) {
+        e = hipMalloc(&c->linkmask, n * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            c->linkmask = nullptr;
+            return fail(HLBM_ENOMEM, "link mask allocation: %s", hipGetErrorString(e));
+        }
+    }
+    const unsigned char* src = mask;
+    void* tmp = nullptr;
+    if (!on_device) {
+        e = hipMalloc(&tmp, n);
+        if (e != hipSuccess) return fail(HLBM_ENOMEM, "staging allocation: %s", hipGetErrorString(e));
+        e = hipMemcpyAsync(tmp, mask, n, hipMemcpyHostToDevice, c->stream);
+        src = static_cast<const unsigned char*>(tmp);
+    }
+    if (e == hipSuccess) e = hlbm::launch_linkmask(c->q, c->p, src, c->linkmask, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "solid mask");
+    c->bcmode = hlbm::BC_MASKED;
+    c->p.linkmask = c->linkmask;
+    return HLBM_OK;
+}
+
 int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
 {
     int rc = check_ctx(c);
@@ -699,6 +744,8 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
     if (c->batch) return fail(HLBM_EUNSUPPORTED, "a batch has no adjoint");
     if (c->cfg.porosity_kind != HLBM_POROSITY_SCALAR)
         return fail(HLBM_EUNSUPPORTED, "the adjoint differentiates a scalar porosity control");
+    if (c->bcmode == hlbm::BC_MASKED)
+        return fail(HLBM_EUNSUPPORTED, "the adjoint does not cover resolved solid cells");
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (every < 0 || max_steps < 0) return fail(HLBM_EINVAL, "every and max_steps must be >= 0");
     hipError_t e = hipStreamSynchronize(c->stream);

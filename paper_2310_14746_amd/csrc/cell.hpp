@@ -410,6 +410,36 @@ __device__ __forceinline__ void gather_general(const typename S::T* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Pull gather in a periodic box with resolved solid cells: where the source of
+// direction i is solid, halfway bounce-back g*_i(x) = g_opp(i)(x) (the link
+// mask, precomputed per cell, says which sources are solid).  Straight-line:
+// the load address switches to this cell's opposite population.  Returns
+// whether the cell itself is solid.
+// ---------------------------------------------------------------------------
+template <class L, class S>
+__device__ __forceinline__ bool gather_masked(const typename S::T* __restrict__ src, uint32_t N,
+                                              const uint32_t* __restrict__ linkmask, uint32_t nx,
+                                              uint32_t ny, uint32_t nz, uint32_t x, uint32_t y,
+                                              uint32_t z, typename S::R inv_scale,
+                                              typename S::R (&g)[L::Q])
+{
+    const uint32_t cell = x + nx * (y + ny * z);
+    const uint32_t lm = ld(linkmask, cell);
+    const uint32_t xs[3] = {x + 1 == nx ? 0u : x + 1, x, x == 0 ? nx - 1 : x - 1};
+    const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
+    const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const bool back = ((lm >> i) & 1u) != 0u;
+        const uint32_t noff = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+        const uint32_t row = sel(back, (uint32_t)opposite(i), (uint32_t)i);
+        const uint32_t off = sel(back, cell, noff);
+        g[i] = S::load(ld(src + (size_t)row * N, off), inv_scale);
+    }
+    return (lm & LINK_SOLID_SELF) != 0u;
+}
+
+// ---------------------------------------------------------------------------
 // FP64 block reduction of 4 values (wavefront shuffle, then across waves in
 // LDS).  Thread 0 writes the block's partials.  Fixed order -> deterministic.
 // ---------------------------------------------------------------------------

@@ -21,9 +21,13 @@ struct Params {
     int bc_hi[3];
     double inlet_u[3];
     double outlet_rho;
+    const uint32_t* linkmask;  // BC_MASKED: per cell, bit i = source of direction i is solid,
+                               // bit 31 = the cell itself is solid (else unused)
 };
 
-enum BcMode { BC_PERIODIC = 0, BC_GENERAL = 1 };
+// BC_MASKED: periodic box with resolved solid cells (bounce-back links).
+enum BcMode { BC_PERIODIC = 0, BC_GENERAL = 1, BC_MASKED = 2 };
+constexpr uint32_t LINK_SOLID_SELF = 1u << 31;
 // Porosity control kinds: one value d per cell, or a symmetric 3x3 D (6 rows).
 enum PorosityKind { PK_SCALAR = 0, PK_TENSOR = 1 };
 
@@ -57,6 +61,9 @@ hipError_t launch_adjoint(int q, int storage, int bcmode, const Params& p, const
 // Fixed-order two-pass sum of `nblocks` partials of 4 doubles into out[4];
 // `stage` holds 4*REDUCE_STAGE doubles.
 constexpr uint32_t REDUCE_STAGE = 256;
+// Link mask of a solid mask (uint8 per cell, nonzero = solid), periodic box.
+hipError_t launch_linkmask(int q, const Params& p, const unsigned char* mask, uint32_t* linkmask,
+                           hipStream_t s);
 hipError_t launch_reduce4(const double* partials, uint32_t nblocks, double* stage, double* out,
                           hipStream_t s);
 // Convert and validate the porosity; *flag (device) ends nonzero if any value

@@ -34,13 +34,17 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* __restrict__ src
     const R F0 = R(p.F[0]), F1 = R(p.F[1]), F2 = R(p.F[2]);
     const R rho0 = R(p.rho0), omega = R(p.omega), pref = R(p.pref);
     R g[L::Q];
+    bool solid = false;
     if (BC == BC_PERIODIC) {
         gather_periodic<L, S>(src, N, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+    } else if (BC == BC_MASKED) {
+        solid = gather_masked<L, S>(src, N, p.linkmask, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
     } else {
         const Box b = box_of(p);
         const OpenFaces<R> of{rho0, R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
                               R(p.outlet_rho)};
         gather_general<L, S>(src, N, b, of, (int)x, (int)y, (int)z, inv_scale, g);
+        solid = in_wall_layer(b, (int)x, (int)y, (int)z);
     }
     if (PK == PK_SCALAR) {
         const ScalarShift<R> sh{S::load_d(ld(dfield, cell))};
@@ -55,9 +59,7 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* __restrict__ src
                                 S::load_d(ld(dfield + 5 * (size_t)N, cell))};
         collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
     }
-    // solid cells (wall layers) hold zeros; selected, not branched
-    bool solid = false;
-    if (BC != BC_PERIODIC) solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
+    // solid cells (wall layers, masked cells) hold zeros; selected, not branched
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) st_stream(dst + (size_t)i * N, cell, S::store(sel(solid, R(0), g[i]), scale));
     return solid;
@@ -232,6 +234,8 @@ __global__ __launch_bounds__(1024) void moments_kernel(const typename S::T* __re
         bool fluid = true;
         if (BC == BC_PERIODIC) {
             gather_periodic<L, S>(src, N, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+        } else if (BC == BC_MASKED) {
+            fluid = !gather_masked<L, S>(src, N, p.linkmask, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
         } else {
             const Box b = box_of(p);
             fluid = !in_wall_layer(b, (int)x, (int)y, (int)z);
@@ -333,6 +337,29 @@ __global__ __launch_bounds__(256) void tensor_porosity_kernel(const I* __restric
     if (threadIdx.x == 0 && any) atomicOr(flag, 1);
 }
 
+// Link mask of a solid mask in a periodic box: bit i set where the pull
+// source x - c_i of direction i is solid, bit 31 where x itself is.
+template <class L>
+__global__ __launch_bounds__(256) void linkmask_kernel(const unsigned char* __restrict__ mask,
+                                                       uint32_t* __restrict__ linkmask, uint32_t nx,
+                                                       uint32_t ny, uint32_t nz)
+{
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    const uint32_t cell = x + nx * (y + ny * z);
+    const uint32_t xs[3] = {x + 1 == nx ? 0u : x + 1, x, x == 0 ? nx - 1 : x - 1};
+    const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
+    const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};
+    uint32_t lm = mask[cell] ? LINK_SOLID_SELF : 0u;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const uint32_t src = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+        lm |= (mask[src] ? 1u : 0u) << i;
+    }
+    linkmask[cell] = lm;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -357,8 +384,12 @@ static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src
     if (diag) {
         if (bcmode == BC_PERIODIC)
             hipLaunchKernelGGL((sweep_diag_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, a, b, d, diag, p);
+        else if (bcmode == BC_MASKED)
+            hipLaunchKernelGGL((sweep_diag_kernel<L, S, BC_MASKED, PK>), l.grid, l.block, 0, s, a, b, d, diag, p);
         else
             hipLaunchKernelGGL((sweep_diag_kernel<L, S, BC_GENERAL, PK>), l.grid, l.block, 0, s, a, b, d, diag, p);
+    } else if (bcmode == BC_MASKED) {
+        hipLaunchKernelGGL((sweep_kernel<L, S, BC_MASKED, PK>), l.grid, l.block, 0, s, a, b, d, p);
     } else if (bcmode == BC_PERIODIC) {
         if constexpr (sizeof(typename S::T) == 2 && L::Q == 19 && PK == PK_SCALAR) {
             if (p.nx % 2 == 0 && p.nx >= 4) {
@@ -409,6 +440,9 @@ static hipError_t moments_dispatch_bc(int bcmode, const Params& p, const void* s
     if (bcmode == BC_PERIODIC)
         hipLaunchKernelGGL((moments_kernel<L, S, BC_PERIODIC, O>), l.grid, l.block, 0, s, a,
                            static_cast<O*>(drho), static_cast<O*>(u), partials, p);
+    else if (bcmode == BC_MASKED)
+        hipLaunchKernelGGL((moments_kernel<L, S, BC_MASKED, O>), l.grid, l.block, 0, s, a,
+                           static_cast<O*>(drho), static_cast<O*>(u), partials, p);
     else
         hipLaunchKernelGGL((moments_kernel<L, S, BC_GENERAL, O>), l.grid, l.block, 0, s, a,
                            static_cast<O*>(drho), static_cast<O*>(u), partials, p);
@@ -450,6 +484,19 @@ hipError_t launch_moments(int q, int storage, int bcmode, const Params& p, const
     if (q == 19)
         return moments_dispatch_store<D3Q19>(storage, out_f64, bcmode, p, src, drho, u, partials, bx, s);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_linkmask(int q, const Params& p, const unsigned char* mask, uint32_t* linkmask,
+                           hipStream_t s)
+{
+    const Launch l = cell_launch(p, 256);
+    if (q == 9)
+        hipLaunchKernelGGL(linkmask_kernel<D2Q9>, l.grid, l.block, 0, s, mask, linkmask, (uint32_t)p.nx,
+                           (uint32_t)p.ny, (uint32_t)p.nz);
+    else
+        hipLaunchKernelGGL(linkmask_kernel<D3Q19>, l.grid, l.block, 0, s, mask, linkmask, (uint32_t)p.nx,
+                           (uint32_t)p.ny, (uint32_t)p.nz);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce4(const double* partials, uint32_t nblocks, double* stage, double* out,

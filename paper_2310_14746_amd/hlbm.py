@@ -111,6 +111,7 @@ def load() -> ctypes.CDLL:
         "hlbm_batch_set_mode": ([vp, i], i),
         "hlbm_batch_set_porosity": ([vp, i, vp, i, i], i),
         "hlbm_batch_moments": ([vp, i, vp, vp, i, P(ctypes.c_double)], i),
+        "hlbm_set_solid_mask": ([vp, vp, i], i),
         "hlbm_set_diagnostics": ([vp, i, i], i),
         "hlbm_read_diagnostics": ([vp, P(ctypes.c_double), i, P(ctypes.c_int), P(ctypes.c_longlong)], i),
         "hlbm_set_tape": ([vp, i, i], i),
@@ -308,6 +309,24 @@ class HLBM:
             raise ValueError("state size mismatch")
         _check(load().hlbm_set_state(self.ctx, buf.contiguous().data_ptr(), 1 if buf.is_cuda else 0,
                                      int(step)))
+
+    # -- resolved obstacles ------------------------------------------------
+    def set_solid_mask(self, mask):
+        """Solid cells (nonzero) of a periodic box, shape (nz, ny, nx) or N; None removes them."""
+        if mask is None:
+            _check(load().hlbm_set_solid_mask(self.ctx, None, 0))
+            return
+        t = self.torch
+        if isinstance(mask, t.Tensor):
+            m = mask.reshape(-1).to(t.uint8).contiguous()
+            if m.numel() != self.N:
+                raise ValueError("mask needs nx*ny*nz values")
+            _check(load().hlbm_set_solid_mask(self.ctx, m.data_ptr(), 1 if m.is_cuda else 0))
+            return
+        m = np.ascontiguousarray(np.asarray(mask).reshape(-1) != 0, dtype=np.uint8)
+        if m.size != self.N:
+            raise ValueError("mask needs nx*ny*nz values")
+        _check(load().hlbm_set_solid_mask(self.ctx, m.ctypes.data, 0))
 
     # -- in-sweep diagnostics ------------------------------------------------
     def set_diagnostics(self, every: int, capacity: int = 1024):

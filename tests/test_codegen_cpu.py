@@ -40,7 +40,8 @@ def _kernels(funcs, prefix):
 
 def test_sweep_kernels_are_straight_line(asm):
     sweeps = _kernels(asm, "_ZN4hlbm12sweep_kernel")
-    assert len(sweeps) == 24  # 16 scalar-control kernels + 8 tensor-control (D3Q19)
+    # (2 lattices x 4 storages scalar + 4 storages tensor) x 3 boundary modes
+    assert len(sweeps) == 36
     for name, body in sweeps.items():
         branches = len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
         assert branches <= 1, (name, branches)
