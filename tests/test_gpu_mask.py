@@ -117,3 +117,35 @@ def test_resolved_vs_homogenized_unit_cells(H):
         say(f"cell {j}: E={e} phi={phi:.2f} tau={tau}: k resolved {k_r:.4g}, homogenized {k_s[j]:.4g} "
             f"({100 * (k_s[j] / k_r - 1):+.1f}%), sharp control {k_i[j]:.4g} ({100 * (k_i[j] / k_r - 1):+.1f}%)")
         assert k_r > 0 and np.isfinite(k_r)
+
+
+def test_mask_api_rules(H):
+    """Host-side rules of hlbm_set_solid_mask (no kernel runs on bad input)."""
+    n = 8 ** 3
+    walls = H.HLBM(19, "f32", (8, 8, 8), bc_lo=(0, 1, 0), bc_hi=(0, 1, 0))
+    try:
+        with pytest.raises(H.HLBMError, match="periodic"):
+            walls.set_solid_mask(np.zeros(n, dtype=np.uint8))
+    finally:
+        walls.close()
+    sim = H.HLBM(19, "f64", (8, 8, 8), force=(1e-5, 0, 0))
+    try:
+        sim.set_porosity(np.zeros(n))
+        with pytest.raises(ValueError):
+            sim.set_solid_mask(np.zeros(n - 1, dtype=np.uint8))
+        sim.set_tape(2, 10)
+        with pytest.raises(H.HLBMError, match="tape"):
+            sim.set_solid_mask(np.zeros(n, dtype=np.uint8))
+        sim.set_tape(0, 0)
+        mask = np.zeros(n, dtype=np.uint8)
+        mask[100] = 1
+        sim.set_solid_mask(mask)
+        with pytest.raises(H.HLBMError, match="solid"):
+            sim.set_tape(2, 10)
+        sim.step(3)
+        drho, u = sim.moments("f64")
+        assert float(u.reshape(3, -1)[:, 100].abs().max()) == 0.0
+        sim.set_solid_mask(None)            # obstacles removed: the adjoint is available again
+        sim.set_tape(2, 10)
+    finally:
+        sim.close()
