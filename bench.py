@@ -337,6 +337,43 @@ def time_tensor(hlbm, steps, warmup, block_x):
             "rel_l2_drho_vs_fp64": float("%.3e" % rel_l2_drho(dr, dr_o, u_o))}
 
 
+def time_adjoint_large(hlbm, edge=256, steps=40, every=10):
+    """Reverse sweep on a large periodic box (the sphere array, FP32 forward,
+    FP32 adjoint populations, FP64 gradient): time of hlbm_adjoint_step over
+    `steps` steps, which also replays the forward inside each checkpoint
+    segment.  Shows the adjoint kernel away from the small-domain limits of the
+    128x64x64 workload."""
+    import torch
+    from paper_2310_14746_amd import inputs
+    tile = inputs.round_to(inputs.sphere_array_tile(), "f32").astype(np.float32)
+    reps = edge // 32
+    sim = hlbm.HLBM(hlbm.D3Q19, "f32", (edge,) * 3, tau=TAU, force=FORCE)
+    try:
+        sim.set_porosity(np.tile(tile, (reps, reps, reps)))
+        sim.set_tape(every, steps)
+        sim.step(steps)
+        n = edge ** 3
+        g_r = torch.zeros(n, dtype=torch.float64, device=sim.device)
+        g_u = torch.zeros(3 * n, dtype=torch.float64, device=sim.device)
+        g_u[:n] = 1.0 / n                               # J = mean u_x
+        sim.adjoint(steps, g_r, g_u)                    # warm-up
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.adjoint(steps, g_r, g_u)
+        e1.record(sim.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+    finally:
+        sim.close()
+    replays = steps - (steps + every - 1) // every
+    moved = edge ** 3 * (steps * ADJ_BYTES + replays * 156)
+    return {"workload": f"D3Q19 {edge}^3 periodic sphere array, {steps} reverse steps, checkpoint every {every}",
+            "ms": round(ms, 2), "ms_per_reverse_step": round(ms / steps, 4),
+            "alg_GBs": round(moved / (ms * 1e-3) / 1e9, 1), "replay_steps": replays}
+
+
 def time_c1(hlbm, block_x):
     """The same FP32 sweep on the 256^3 box (8^3 sphere cells), 1000 steps."""
     from paper_2310_14746_amd import inputs
@@ -443,6 +480,8 @@ def main():
     copy_ref = None if args.no_copy_reference else copy_reference()
     batched = None if args.no_batched else time_batched(hlbm)
     gradient = None if args.no_gradient else time_gradient(hlbm)
+    if gradient is not None:
+        gradient["large_periodic"] = time_adjoint_large(hlbm)
     c1 = None if args.no_c1 else time_c1(hlbm, tune.lookup(hlbm.D3Q19, "f32", (256,) * 3))
     tensor = None if args.no_tensor else time_tensor(
         hlbm, args.steps, args.warmup, args.block_x if args.block_x >= 0 else tune.lookup(hlbm.D3Q19, "f32", (N_EDGE,) * 3))

@@ -294,3 +294,42 @@ def test_pair_kernel_bitwise_equals_one_cell_kernel(H, storage, shape):
         finally:
             sim.close()
     assert np.array_equal(states[0], states[1])
+
+
+@pytest.mark.parametrize("storage,shape", [("f32", (1024, 1024, 1023)), ("f16s", (2048, 1024, 1023))])
+def test_maximum_size(H, storage, shape):
+    """The largest boxes the 32-bit row offsets allow (one population row just
+    under 4 GiB).  The control varies only along z, so every x-y plane is
+    uniform and the flow equals the oracle's 1 x 1 x nz column; checked on the
+    last planes, where the byte offsets are largest."""
+    import torch
+    nx, ny, nz = shape
+    steps = 12
+    say(f"maximum size {storage} {shape}: {nx * ny * nz} cells, {steps} steps")
+    dz = 0.5 + 0.4 * np.sin(2 * np.pi * np.arange(nz) / nz)
+    dz = inputs.round_to(dz, "f32" if storage == "f32" else "f16")
+    F = (2e-5, -1e-5, 0.0)
+    sim = H.HLBM(19, storage, shape, tau=0.7, force=F, store_scale=2.0 ** 20)
+    try:
+        dt = torch.float32 if storage == "f32" else torch.float16
+        d = torch.tensor(dz, dtype=dt, device="cuda").repeat_interleave(nx * ny)
+        sim.set_porosity(d)
+        del d
+        sim.step(steps)
+        drho, u = sim.moments("f32")
+        last = u[:, nz - 3:, :, :]                       # the last three planes
+        ux = last[0].double()
+        spread = float((ux - ux[:, :1, :1]).abs().max())  # planes uniform
+        u_last = last[:, :, 0, 0].double().cpu().numpy()  # (3, 3)
+        del drho, u, last
+    finally:
+        sim.close()
+        torch.cuda.empty_cache()
+    cfg = OracleConfig(q=19, nx=1, ny=1, nz=nz, tau=0.7, force=F)
+    g = oracle.run(cfg, dz, steps)
+    _, uo = oracle.observe(cfg, g)
+    uo_last = uo[:, nz - 3:]
+    err = np.abs(u_last - uo_last).max() / np.abs(uo_last).max()
+    say(f"last planes vs oracle column: max rel {err:.2e}, in-plane spread {spread:.2e}")
+    assert spread == 0.0
+    assert err <= (1e-5 if storage == "f32" else 2e-3)
