@@ -8,7 +8,8 @@ from rest.  A "step" is one fused pull-stream + collide sweep over all cells.
 The headline form stores populations in FP32 (FP32 arithmetic).  The FP16- and
 BF16-shifted storage forms (FP32 arithmetic) run on the same workload and are
 reported beside it with their speed-up and their relative L2 error against the
-FP64 oracle.  The error is exact to evaluate at full size: the workload is
+FP64 oracle.  Forms suffixed "-aa" run the in-place (AA) pattern: one population
+buffer instead of two, the same bytes per cell and bit-identical results.  The error is exact to evaluate at full size: the workload is
 32-periodic, so every 32^3 tile equals a 32^3 run of one obstacle cell, which
 the oracle computes (as part of the timed CPU-baseline sample).
 
@@ -43,6 +44,11 @@ SWEEP_SRCS = [os.path.join(ROOT, "paper_2310_14746_amd", "csrc", f)
 METRIC = "MLUPS and % HBM roofline, D3Q19 HLBM 512^3; FP16-storage vs FP32 at stated L2 error"
 
 
+def storage_of(form):
+    """Storage name of a bench form ("f32", "f16s-aa", ...)."""
+    return form.split("-")[0]
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -56,7 +62,8 @@ def rel_l2_drho(dr, dr_ref, u_ref):
     return float(np.linalg.norm(dr - dr_ref) / max(np.linalg.norm(dr_ref), floor))
 
 
-def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar", edge=N_EDGE):
+def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar", edge=N_EDGE,
+              pattern="ab"):
     import torch
     reps = edge // 32
     dt = np.float32 if storage == "f32" else np.float16
@@ -67,7 +74,7 @@ def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar"
         d = np.tile(d_tile.astype(dt), (reps, reps, reps))
     sim = hlbm.HLBM(hlbm.D3Q19, storage, (edge,) * 3, tau=TAU, force=FORCE,
                     store_scale=SCALE_16 if storage != "f32" else 1.0, block_x=block_x,
-                    porosity=porosity)
+                    porosity=porosity, pattern=pattern)
     try:
         sim.set_porosity(d)
         del d
@@ -436,7 +443,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--forms", default="f32,f16s,bf16s")
+    ap.add_argument("--forms", default="f32,f16s,bf16s,f32-aa,f16s-aa")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-reference", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -473,9 +480,10 @@ def main():
     results = {}
     from paper_2310_14746_amd import tune
     for f in forms:
-        tile = inputs.round_to(d_tile, "f32" if f == "f32" else "f16")
-        bx = args.block_x if args.block_x >= 0 else tune.lookup(hlbm.D3Q19, f, (N_EDGE,) * 3)
-        ms, dr, u, tot, teq = time_form(hlbm, f, tile, args.steps, args.warmup, block_x=bx)
+        st, pattern = storage_of(f), ("aa" if f.endswith("-aa") else "ab")
+        tile = inputs.round_to(d_tile, "f32" if st == "f32" else "f16")
+        bx = args.block_x if args.block_x >= 0 else tune.lookup(hlbm.D3Q19, st, (N_EDGE,) * 3)
+        ms, dr, u, tot, teq = time_form(hlbm, st, tile, args.steps, args.warmup, block_x=bx, pattern=pattern)
         results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq, block_x=bx)
     copy_ref = None if args.no_copy_reference else copy_reference()
     batched = None if args.no_batched else time_batched(hlbm)
@@ -490,10 +498,12 @@ def main():
     if not args.no_cpu_baseline:
         cpu, dr_o, u_o = cpu_baseline(args.steps + args.warmup)
         refs["f32"] = (dr_o, u_o)
-        if any(f != "f32" for f in forms):
+        if any(storage_of(f) != "f32" for f in forms):
             refs["f16"] = oracle_tile(inputs.round_to(d_tile, "f16"), args.steps + args.warmup)
 
     head = forms[0]
+    if head.endswith("-aa"):
+        raise SystemExit("the first form is the headline and must be a two-buffer form")
     ms_step = results[head]["ms"] / args.steps
     mlups = n_cells * args.steps / (results[head]["ms"] * 1e-3) / 1e6
     achieved = ALG_BYTES[head] * n_cells / (ms_step * 1e-3) / 1e9
@@ -541,13 +551,19 @@ def main():
         ent = {
             "mlups": round(n_cells * args.steps / (r["ms"] * 1e-3) / 1e6, 1),
             "ms_per_step": round(r["ms"] / args.steps, 4),
-            "alg_GBs": round(ALG_BYTES[f] * n_cells * args.steps / (r["ms"] * 1e-3) / 1e9, 1),
+            "alg_GBs": round(ALG_BYTES[storage_of(f)] * n_cells * args.steps / (r["ms"] * 1e-3) / 1e9, 1),
             "speedup_vs_" + head: round(results[head]["ms"] / r["ms"], 3),
             "tiles_identical": r["tiles_equal"],
             "block_x": r["block_x"],
             "mass_excess_total": float(r["tot"][0]),
         }
-        ref = refs.get("f32" if f == "f32" else "f16")
+        if f.endswith("-aa") and storage_of(f) in results:
+            twin = results[storage_of(f)]
+            ent["pattern"] = "in-place (AA), one population buffer"
+            ent["equals_two_buffer_bitwise"] = bool(np.array_equal(r["tot"], twin["tot"]) and
+                                                    np.array_equal(r["u"], twin["u"]) and
+                                                    np.array_equal(r["dr"], twin["dr"]))
+        ref = refs.get("f32" if storage_of(f) == "f32" else "f16")
         if ref is not None:
             ent["rel_l2_u_vs_fp64"] = float("%.3e" % rel_l2(r["u"], ref[1]))
             ent["rel_l2_drho_vs_fp64"] = float("%.3e" % rel_l2_drho(r["dr"], ref[0], ref[1]))

@@ -69,8 +69,17 @@ enum { HLBM_D2Q9 = 9, HLBM_D3Q19 = 19 };
  * two) with f32 arithmetic, round to nearest even on store. */
 enum { HLBM_F64 = 0, HLBM_F32 = 1, HLBM_F16S = 2, HLBM_BF16S = 3 };
 
-/* Buffer pattern: two population buffers swapped every step (AB). */
-enum { HLBM_AB = 0 };
+/* Buffer pattern.  HLBM_AB: two population buffers swapped every step.
+ * HLBM_AA: one buffer updated in place (the AA pattern), half the population
+ * memory, fully periodic boxes only.  Its steps alternate between two forms:
+ * one reads the cell's own slots and writes post-collision population i to
+ * the cell's slot opp(i); the other reads population i from slot opp(i) of
+ * x - c_i and writes post-collision population i to slot i of x + c_i.  Every
+ * slot is read and written by one cell per step, and each cell does the
+ * arithmetic of the AB sweep, so both patterns give the same results bit for
+ * bit.  hlbm_get_state / hlbm_set_state use the AB layout for both.  HLBM_AA
+ * takes block_x <= 256 (EUNSUPPORTED otherwise). */
+enum { HLBM_AB = 0, HLBM_AA = 1 };
 
 /* Face kinds, per axis and side.  HLBM_PERIODIC must be used on both sides of
  * an axis or on neither.  HLBM_WALL makes the first (lo) or last (hi) layer of
@@ -139,6 +148,7 @@ int hlbm_create(const hlbm_config *cfg, hlbm_ctx **out);
  * least 256-byte aligned.  The memory must outlive the context.  Resets the
  * state to rest and the step counter to 0; the porosity must be set again. */
 int hlbm_bind_buffers(hlbm_ctx *ctx, void *pop_a, void *pop_b, void *porosity);
+/* (HLBM_AA: one population buffer; pop_b must be NULL, else EINVAL.) */
 
 /* Wait for outstanding work, free library-owned memory, destroy the context.
  * NULL is accepted.  Returns EDEVICE if outstanding work had failed (the
@@ -184,6 +194,11 @@ int hlbm_state_bytes(const hlbm_ctx *ctx, size_t *bytes);
  * population order, g[i*N + cell]) to `dst` (device if on_device) and the step
  * counter to *step (may be NULL).  Waits for the stream. */
 int hlbm_get_state(hlbm_ctx *ctx, void *dst, int on_device, long long *step);
+/* (HLBM_AA: the state is converted to the AB layout by a copy kernel; a device
+ * dst must not overlap the population buffer, else EINVAL; a host dst may take
+ * a temporary device buffer of one population buffer's size.  hlbm_set_state
+ * copies row i of the snapshot into row opp(i); a device src must not overlap
+ * the population buffer either.) */
 
 /* Replace the current state by a snapshot taken with hlbm_get_state and set
  * the step counter.  Resuming from a snapshot reproduces the original run
@@ -206,7 +221,8 @@ int hlbm_sync(hlbm_ctx *ctx);
  * Solid cells hold zeros and report zero moments; the porosity control still
  * applies in fluid cells.  mask = NULL removes the obstacles.  The link mask
  * (4 bytes per cell) is built on the device.  EUNSUPPORTED unless every face
- * is periodic, or for a batch; ESTATE while an adjoint tape is set.
+ * is periodic, for HLBM_AA or for a batch; ESTATE while an adjoint tape is
+ * set.
  * Synchronous. */
 int hlbm_set_solid_mask(hlbm_ctx *ctx, const unsigned char *mask, int on_device);
 
@@ -254,7 +270,7 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * state whenever the state or the porosity changes otherwise (hlbm_set_state,
  * hlbm_reset, hlbm_set_porosity, hlbm_bind_buffers).
  *
- * Single contexts only (a batch returns EUNSUPPORTED).
+ * Single HLBM_AB contexts only (a batch or HLBM_AA returns EUNSUPPORTED).
  * ------------------------------------------------------------------------ */
 
 /* Allocate a tape for up to `max_steps` forward steps with a checkpoint every

@@ -33,6 +33,11 @@ struct hlbm_ctx {
     bool bound;
     bool porosity_set;
     int cur;           // buffer holding the current post-collision state
+    // in-place (AA) pattern: one buffer (pop[0]); aa_pulled is set when it
+    // holds the pulled populations of the next step in natural slots, clear
+    // when it holds the post-collision populations in opposite slots
+    bool aa;
+    bool aa_pulled;
     long long step;
     hipStream_t stream;
     double* partials;  // FP64 per-block partials for the totals
@@ -133,7 +138,8 @@ int validate_config(const hlbm_config* c)
     if (c->lattice != HLBM_D2Q9 && c->lattice != HLBM_D3Q19)
         return fail(HLBM_EINVAL, "lattice must be HLBM_D2Q9 or HLBM_D3Q19 (got %d)", c->lattice);
     if (elem_bytes(c->storage) == 0) return fail(HLBM_EINVAL, "unknown storage %d", c->storage);
-    if (c->pattern != HLBM_AB) return fail(HLBM_EUNSUPPORTED, "pattern %d not provided", c->pattern);
+    if (c->pattern != HLBM_AB && c->pattern != HLBM_AA)
+        return fail(HLBM_EINVAL, "pattern must be HLBM_AB or HLBM_AA (got %d)", c->pattern);
     if (c->nx < 1 || c->ny < 1 || c->nz < 1)
         return fail(HLBM_EINVAL, "dimensions must be >= 1 (got %d x %d x %d)", c->nx, c->ny, c->nz);
     if (c->lattice == HLBM_D2Q9 && c->nz != 1) return fail(HLBM_EINVAL, "D2Q9 needs nz = 1");
@@ -166,6 +172,12 @@ int validate_config(const hlbm_config* c)
         return fail(HLBM_EINVAL, "unknown porosity_kind %d", c->porosity_kind);
     if (c->porosity_kind == HLBM_POROSITY_TENSOR && c->lattice != HLBM_D3Q19)
         return fail(HLBM_EUNSUPPORTED, "a tensor porosity control needs D3Q19");
+    if (c->pattern == HLBM_AA) {
+        for (int a = 0; a < 3; ++a)
+            if (c->bc_lo[a] != HLBM_PERIODIC)
+                return fail(HLBM_EUNSUPPORTED, "the in-place pattern (HLBM_AA) needs periodic faces on every axis");
+        if (c->block_x > 256) return fail(HLBM_EUNSUPPORTED, "the in-place pattern (HLBM_AA) needs block_x <= 256");
+    }
     return HLBM_OK;
 }
 
@@ -218,12 +230,48 @@ int ensure_partials(hlbm_ctx* c, uint32_t nblocks)
 
 int zero_state(hlbm_ctx* c)
 {
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < (c->aa ? 1 : 2); ++k) {
         hipError_t e = hipMemsetAsync(c->pop[k], 0, c->pop_bytes, c->stream);
         if (e != hipSuccess) return hip_fail(e, "zeroing populations");
     }
     c->cur = 0;
+    c->aa_pulled = false;  // zeros are the post-collision state in any slot order
     c->step = 0;
+    return HLBM_OK;
+}
+
+// State of an in-place context in A/B layout (the post-collision populations
+// of the last step, population i of cell x at row i, element x).
+int aa_get_state(hlbm_ctx* c, void* dst, int on_device, long long* step)
+{
+    hipError_t e = hipSuccess;
+    const size_t row = (size_t)c->p.N * c->elem;
+    void* tmp = nullptr;
+    if (!c->aa_pulled && !on_device) {
+        // opposite slots: one row copy per population
+        for (int i = 0; i < c->q && e == hipSuccess; ++i)
+            e = hipMemcpyAsync(static_cast<char*>(dst) + (size_t)i * row,
+                               static_cast<const char*>(c->pop[0]) + (size_t)hlbm::opposite(i) * row, row,
+                               hipMemcpyDeviceToHost, c->stream);
+    } else {
+        void* out = dst;
+        if (!on_device) {
+            e = hipMalloc(&tmp, c->pop_bytes);
+            if (e != hipSuccess) return fail(HLBM_ENOMEM, "staging allocation: %s", hipGetErrorString(e));
+            out = tmp;
+        } else {
+            const char* a = static_cast<const char*>(dst);
+            const char* b = static_cast<const char*>(c->pop[0]);
+            if (a < b + c->pop_bytes && b < a + c->pop_bytes)
+                return fail(HLBM_EINVAL, "dst overlaps the population buffer");
+        }
+        e = hlbm::launch_aa_export(c->q, c->cfg.storage, c->p, c->pop[0], out, c->aa_pulled ? 0 : 1, c->stream);
+        if (e == hipSuccess && tmp) e = hipMemcpyAsync(dst, tmp, c->pop_bytes, hipMemcpyDeviceToHost, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "get_state");
+    if (step) *step = c->step;
     return HLBM_OK;
 }
 
@@ -363,6 +411,7 @@ int hlbm_create(const hlbm_config* cfg, hlbm_ctx** out)
     c->cfg = *cfg;
     fill_params(cfg, &c->p);
     c->q = cfg->lattice;
+    c->aa = cfg->pattern == HLBM_AA;
     bool general = false;
     for (int a = 0; a < 3; ++a)
         if (cfg->bc_lo[a] != HLBM_PERIODIC) general = true;
@@ -375,7 +424,7 @@ int hlbm_create(const hlbm_config* cfg, hlbm_ctx** out)
     c->own_mem = !cfg->external_memory;
     if (c->own_mem) {
         hipError_t e = hipMalloc(&c->pop[0], c->pop_bytes);
-        if (e == hipSuccess) e = hipMalloc(&c->pop[1], c->pop_bytes);
+        if (e == hipSuccess && !c->aa) e = hipMalloc(&c->pop[1], c->pop_bytes);
         if (e == hipSuccess) e = hipMalloc(&c->dfield, (size_t)c->p.N * c->delem * porosity_rows(cfg));
         if (e != hipSuccess) {
             hlbm_destroy(c);
@@ -410,7 +459,8 @@ int hlbm_bind_buffers(hlbm_ctx* c, void* pop_a, void* pop_b, void* porosity)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (c->own_mem) return fail(HLBM_ESTATE, "context owns its memory (external_memory = 0)");
-    if (!pop_a || !pop_b || !porosity) return fail(HLBM_EINVAL, "NULL buffer");
+    if (c->aa && pop_b) return fail(HLBM_EINVAL, "the in-place pattern takes one population buffer (pop_b = NULL)");
+    if (!pop_a || (!c->aa && !pop_b) || !porosity) return fail(HLBM_EINVAL, "NULL buffer");
     if (pop_a == pop_b) return fail(HLBM_EINVAL, "population buffers must differ");
     if (((uintptr_t)pop_a | (uintptr_t)pop_b | (uintptr_t)porosity) & 255u)
         return fail(HLBM_EINVAL, "buffers must be 256-byte aligned");
@@ -519,9 +569,13 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
         const bool diag = c->diag_every && c->step % c->diag_every == 0;
         const bool record = diag && c->diag_count < c->diag_cap;
         if (diag && !record) c->diag_dropped += 1;
-        e = hlbm::launch_sweep(c->q, c->cfg.storage, c->bcmode, c->cfg.porosity_kind, c->p, c->pop[c->cur],
-                               c->pop[c->cur ^ 1],
-                               c->dfield, c->bx, c->stream, record ? c->partials : nullptr);
+        if (c->aa)
+            e = hlbm::launch_sweep(c->q, c->cfg.storage, c->aa_pulled ? hlbm::BC_AA_EVEN : hlbm::BC_AA_ODD,
+                                   c->cfg.porosity_kind, c->p, c->pop[0], c->pop[0], c->dfield, c->bx, c->stream,
+                                   record ? c->partials : nullptr);
+        else
+            e = hlbm::launch_sweep(c->q, c->cfg.storage, c->bcmode, c->cfg.porosity_kind, c->p, c->pop[c->cur],
+                                   c->pop[c->cur ^ 1], c->dfield, c->bx, c->stream, record ? c->partials : nullptr);
         if (e == hipSuccess && record)
             e = hlbm::launch_reduce4(c->partials, hlbm::cell_launch(c->p, c->bx).nblocks, c->reduce_stage,
                                      c->diag_log + 4 * (size_t)c->diag_count, c->stream);
@@ -530,7 +584,10 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
             c->diag_steps.push_back(c->step);
             c->diag_count += 1;
         }
-        c->cur ^= 1;
+        if (c->aa)
+            c->aa_pulled = !c->aa_pulled;
+        else
+            c->cur ^= 1;
         c->step += 1;
     }
     return HLBM_OK;
@@ -574,7 +631,8 @@ int hlbm_moments(hlbm_ctx* c, void* drho, void* u, int dtype, int on_device, dou
         }
         partials = c->partials;
     }
-    e = hlbm::launch_moments(c->q, c->cfg.storage, c->bcmode, c->p, c->pop[c->cur], ddr, du,
+    const int mbc = !c->aa ? c->bcmode : (c->aa_pulled ? hlbm::BC_AA_EVEN : hlbm::BC_AA_ODD);
+    e = hlbm::launch_moments(c->q, c->cfg.storage, mbc, c->p, c->pop[c->cur], ddr, du,
                              dtype == HLBM_DT_F64, partials, c->bx, c->stream);
     if (e == hipSuccess && totals)
         e = hlbm::launch_reduce4(partials, l.nblocks, c->reduce_stage, c->totals_dev, c->stream);
@@ -608,6 +666,7 @@ int hlbm_get_state(hlbm_ctx* c, void* dst, int on_device, long long* step)
     if (rc) return rc;
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (!dst) return fail(HLBM_EINVAL, "dst is NULL");
+    if (c->aa) return aa_get_state(c, dst, on_device, step);
     hipError_t e = hipMemcpyAsync(dst, c->pop[c->cur], c->pop_bytes,
                                   on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -623,8 +682,26 @@ int hlbm_set_state(hlbm_ctx* c, const void* src, int on_device, long long step)
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (!src) return fail(HLBM_EINVAL, "src is NULL");
     if (step < 0) return fail(HLBM_EINVAL, "step must be >= 0");
-    hipError_t e = hipMemcpyAsync(c->pop[c->cur], src, c->pop_bytes,
-                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+    hipError_t e = hipSuccess;
+    if (c->aa) {
+        if (on_device) {
+            const char* a = static_cast<const char*>(src);
+            const char* b = static_cast<const char*>(c->pop[0]);
+            if (a < b + c->pop_bytes && b < a + c->pop_bytes)
+                return fail(HLBM_EINVAL, "src overlaps the population buffer");
+        }
+        // row i of the A/B-layout state into slot row opp(i): ready for the
+        // shifted step
+        const size_t row = (size_t)c->p.N * c->elem;
+        for (int i = 0; i < c->q && e == hipSuccess; ++i)
+            e = hipMemcpyAsync(static_cast<char*>(c->pop[0]) + (size_t)hlbm::opposite(i) * row,
+                               static_cast<const char*>(src) + (size_t)i * row, row,
+                               on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+        c->aa_pulled = false;
+    } else {
+        e = hipMemcpyAsync(c->pop[c->cur], src, c->pop_bytes,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "set_state");
     c->step = step;
@@ -704,6 +781,7 @@ int hlbm_set_solid_mask(hlbm_ctx* c, const unsigned char* mask, int on_device)
     for (int a = 0; a < 3; ++a)
         if (c->cfg.bc_lo[a] != HLBM_PERIODIC)
             return fail(HLBM_EUNSUPPORTED, "a solid mask needs periodic faces on every axis");
+    if (c->aa) return fail(HLBM_EUNSUPPORTED, "a solid mask needs the two-buffer pattern (HLBM_AB)");
     if (c->tape_every) return fail(HLBM_ESTATE, "free the adjoint tape first (hlbm_set_tape(ctx, 0, 0))");
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "set_solid_mask: outstanding work failed");
@@ -746,6 +824,7 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
         return fail(HLBM_EUNSUPPORTED, "the adjoint differentiates a scalar porosity control");
     if (c->bcmode == hlbm::BC_MASKED)
         return fail(HLBM_EUNSUPPORTED, "the adjoint does not cover resolved solid cells");
+    if (c->aa) return fail(HLBM_EUNSUPPORTED, "the adjoint tape needs the two-buffer pattern (HLBM_AB)");
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (every < 0 || max_steps < 0) return fail(HLBM_EINVAL, "every and max_steps must be >= 0");
     hipError_t e = hipStreamSynchronize(c->stream);
@@ -881,6 +960,7 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
         if (it->porosity_kind != HLBM_POROSITY_SCALAR)
             return fail(HLBM_EUNSUPPORTED, "item %d: batch items take a scalar porosity control", k);
         if (it->storage != storage) return fail(HLBM_EINVAL, "item %d: all items share one storage", k);
+        if (it->pattern != HLBM_AB) return fail(HLBM_EUNSUPPORTED, "item %d: batch items use HLBM_AB", k);
         for (int a = 0; a < 3; ++a)
             if (it->bc_lo[a] != HLBM_PERIODIC || it->bc_hi[a] != HLBM_PERIODIC)
                 return fail(HLBM_EUNSUPPORTED, "item %d: batch items are fully periodic", k);

@@ -284,6 +284,32 @@ __device__ __forceinline__ void gather_periodic(const typename S::T* __restrict_
     }
 }
 
+// AA pattern, even step: the cell's own slots hold its pulled populations.
+template <class L, class S>
+__device__ __forceinline__ void gather_aa_even(const typename S::T* src, uint32_t N, uint32_t cell,
+                                               typename S::R inv_scale, typename S::R (&g)[L::Q])
+{
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) g[i] = S::load(ld(src + (size_t)i * N, cell), inv_scale);
+}
+
+// AA pattern, odd step: population i arrives from slot opp(i) of x - c_i
+// (where the even step left the post-collision population i), with wrap.
+template <class L, class S>
+__device__ __forceinline__ void gather_aa_odd(const typename S::T* src, uint32_t N, uint32_t nx, uint32_t ny,
+                                              uint32_t nz, uint32_t x, uint32_t y, uint32_t z,
+                                              typename S::R inv_scale, typename S::R (&g)[L::Q])
+{
+    const uint32_t xs[3] = {x + 1 == nx ? 0u : x + 1, x, x == 0 ? nx - 1 : x - 1};
+    const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
+    const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const uint32_t off = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+        g[i] = S::load(ld(src + (size_t)opposite(i) * N, off), inv_scale);
+    }
+}
+
 // Select between two values.  Arguments are taken by value so the choice is a
 // select of register values: a conditional over two lvalues would select
 // between their addresses, which keeps the operands in private memory.

@@ -26,7 +26,14 @@ struct Params {
 };
 
 // BC_MASKED: periodic box with resolved solid cells (bounce-back links).
-enum BcMode { BC_PERIODIC = 0, BC_GENERAL = 1, BC_MASKED = 2 };
+// BC_AA_EVEN / BC_AA_ODD: the two steps of the in-place (AA) pattern in a
+// periodic box.  Even step: the cell reads its own slots, which hold its
+// pulled pre-collision populations, and writes post-collision population i to
+// its own slot opp(i).  Odd step: it reads population i from slot opp(i) of
+// x - c_i and writes post-collision population i to slot i of x + c_i.  Each
+// slot is read and written by one thread per step, so one buffer suffices,
+// and the arithmetic is that of the A/B pull bit for bit.
+enum BcMode { BC_PERIODIC = 0, BC_GENERAL = 1, BC_MASKED = 2, BC_AA_EVEN = 3, BC_AA_ODD = 4 };
 constexpr uint32_t LINK_SOLID_SELF = 1u << 31;
 // Porosity control kinds: one value d per cell, or a symmetric 3x3 D (6 rows).
 enum PorosityKind { PK_SCALAR = 0, PK_TENSOR = 1 };
@@ -64,6 +71,12 @@ constexpr uint32_t REDUCE_STAGE = 256;
 // Link mask of a solid mask (uint8 per cell, nonzero = solid), periodic box.
 hipError_t launch_linkmask(int q, const Params& p, const unsigned char* mask, uint32_t* linkmask,
                            hipStream_t s);
+// AA-pattern state export (periodic box): the post-collision populations in
+// A/B layout from the AA buffer (odd_ready: the buffer holds them in opposite
+// slots; else it holds the pulled populations in natural slots).  out must not
+// overlap buf.
+hipError_t launch_aa_export(int q, int storage, const Params& p, const void* buf, void* out, int odd_ready,
+                            hipStream_t s);
 hipError_t launch_reduce4(const double* partials, uint32_t nblocks, double* stage, double* out,
                           hipStream_t s);
 // Convert and validate the porosity; *flag (device) ends nonzero if any value

@@ -20,9 +20,10 @@ namespace hlbm {
 // store into the other buffer.  Returns the pre-collision moments (time level
 // of `src`) and whether the cell is solid.
 // ---------------------------------------------------------------------------
+// src and dst are one buffer in the AA modes, so they carry no restrict here
+// (the A/B kernels' own arguments do).
 template <class L, class S, int BC, int PK>
-__device__ __forceinline__ bool sweep_cell(const typename S::T* __restrict__ src,
-                                           typename S::T* __restrict__ dst,
+__device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S::T* dst,
                                            const typename S::D* __restrict__ dfield, const Params& p,
                                            uint32_t x, uint32_t y, uint32_t z, typename S::R& drho,
                                            typename S::R& ux, typename S::R& uy, typename S::R& uz)
@@ -37,6 +38,10 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* __restrict__ src
     bool solid = false;
     if (BC == BC_PERIODIC) {
         gather_periodic<L, S>(src, N, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+    } else if (BC == BC_AA_EVEN) {
+        gather_aa_even<L, S>(src, N, cell, inv_scale, g);
+    } else if (BC == BC_AA_ODD) {
+        gather_aa_odd<L, S>(src, N, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
     } else if (BC == BC_MASKED) {
         solid = gather_masked<L, S>(src, N, p.linkmask, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
     } else {
@@ -59,9 +64,27 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* __restrict__ src
                                 S::load_d(ld(dfield + 5 * (size_t)N, cell))};
         collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
     }
-    // solid cells (wall layers, masked cells) hold zeros; selected, not branched
+    if (BC == BC_AA_EVEN) {
+        // post-collision population i into this cell's slot opp(i)
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) st_stream(dst + (size_t)i * N, cell, S::store(sel(solid, R(0), g[i]), scale));
+        for (int i = 0; i < L::Q; ++i) st_stream(dst + (size_t)opposite(i) * N, cell, S::store(g[i], scale));
+    } else if (BC == BC_AA_ODD) {
+        // post-collision population i into slot i of x + c_i
+        const uint32_t nx = p.nx, ny = p.ny, nz = p.nz;
+        const uint32_t xs[3] = {x == 0 ? nx - 1 : x - 1, x, x + 1 == nx ? 0u : x + 1};
+        const uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y + 1 == ny ? 0u : y + 1};
+        const uint32_t zs[3] = {z == 0 ? nz - 1 : z - 1, z, z + 1 == nz ? 0u : z + 1};
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const uint32_t off = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+            st_stream(dst + (size_t)i * N, off, S::store(g[i], scale));
+        }
+    } else {
+        // solid cells (wall layers, masked cells) hold zeros; selected, not branched
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i)
+            st_stream(dst + (size_t)i * N, cell, S::store(sel(solid, R(0), g[i]), scale));
+    }
     return solid;
 }
 
@@ -76,6 +99,22 @@ __global__ __launch_bounds__(1024) void sweep_kernel(const typename S::T* __rest
     if (x >= (uint32_t)p.nx) return;
     R drho, ux, uy, uz;
     (void)sweep_cell<L, S, BC, PK>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
+}
+
+// In-place (AA) step: one buffer, even or odd mode.  Blocks of at most 256
+// threads: the shifted form keeps 19 store addresses live beside the 19
+// values, which in FP64 needs more than the 128 VGPRs a 1024-thread block
+// leaves per lane.
+template <class L, class S, int BC, int PK>
+__global__ __launch_bounds__(256) void sweep_aa_kernel(typename S::T* buf,
+                                                         const typename S::D* __restrict__ dfield,
+                                                         Params p)
+{
+    using R = typename S::R;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (uint32_t)p.nx) return;
+    R drho, ux, uy, uz;
+    (void)sweep_cell<L, S, BC, PK>(buf, buf, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
 }
 
 // The same step on a diagnostic step: the sweep also reduces the moments it
@@ -100,6 +139,27 @@ __global__ __launch_bounds__(1024) void sweep_diag_kernel(const typename S::T* _
         m1 = sel(solid, 0.0, rho * (double)ux);
         m2 = sel(solid, 0.0, rho * (double)uy);
         m3 = sel(solid, 0.0, rho * (double)uz);
+    }
+    const uint32_t bk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum4(m0, m1, m2, m3, partials + 4 * (size_t)bk);
+}
+
+template <class L, class S, int BC, int PK>
+__global__ __launch_bounds__(256) void sweep_aa_diag_kernel(typename S::T* buf,
+                                                              const typename S::D* __restrict__ dfield,
+                                                              double* __restrict__ partials, Params p)
+{
+    using R = typename S::R;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    if (x < (uint32_t)p.nx) {
+        R drho, ux, uy, uz;
+        (void)sweep_cell<L, S, BC, PK>(buf, buf, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
+        const double rho = p.rho0 + (double)drho;
+        m0 = (double)drho;
+        m1 = rho * (double)ux;
+        m2 = rho * (double)uy;
+        m3 = rho * (double)uz;
     }
     const uint32_t bk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     block_sum4(m0, m1, m2, m3, partials + 4 * (size_t)bk);
@@ -234,6 +294,10 @@ __global__ __launch_bounds__(1024) void moments_kernel(const typename S::T* __re
         bool fluid = true;
         if (BC == BC_PERIODIC) {
             gather_periodic<L, S>(src, N, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+        } else if (BC == BC_AA_EVEN) {
+            gather_aa_even<L, S>(src, N, cell, inv_scale, g);
+        } else if (BC == BC_AA_ODD) {
+            gather_aa_odd<L, S>(src, N, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
         } else if (BC == BC_MASKED) {
             fluid = !gather_masked<L, S>(src, N, p.linkmask, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
         } else {
@@ -337,6 +401,29 @@ __global__ __launch_bounds__(256) void tensor_porosity_kernel(const I* __restric
     if (threadIdx.x == 0 && any) atomicOr(flag, 1);
 }
 
+// AA-pattern state in A/B layout: out[i][x] = post-collision population i of
+// cell x.  With odd_ready the buffer holds it in slot opp(i) of x; otherwise
+// the buffer holds the pulled populations, and population i of x sits in slot
+// i of x + c_i (periodic wrap).  Raw element copies.
+template <class L, class E, bool OddReady>
+__global__ __launch_bounds__(256) void aa_export_kernel(const E* __restrict__ buf, E* __restrict__ out,
+                                                        uint32_t nx, uint32_t ny, uint32_t nz)
+{
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    const uint32_t N = nx * ny * nz;
+    const uint32_t cell = x + nx * (y + ny * z);
+    const uint32_t xs[3] = {x == 0 ? nx - 1 : x - 1, x, x + 1 == nx ? 0u : x + 1};
+    const uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y + 1 == ny ? 0u : y + 1};
+    const uint32_t zs[3] = {z == 0 ? nz - 1 : z - 1, z, z + 1 == nz ? 0u : z + 1};
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const uint32_t fwd = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+        out[(size_t)i * N + cell] = OddReady ? buf[(size_t)opposite(i) * N + cell] : buf[(size_t)i * N + fwd];
+    }
+}
+
 // Link mask of a solid mask in a periodic box: bit i set where the pull
 // source x - c_i of direction i is solid, bit 31 where x itself is.
 template <class L>
@@ -381,6 +468,21 @@ static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src
     auto* a = static_cast<const typename S::T*>(src);
     auto* b = static_cast<typename S::T*>(dst);
     auto* d = static_cast<const typename S::D*>(dfield);
+    if (bcmode == BC_AA_EVEN || bcmode == BC_AA_ODD) {
+        // one buffer: src and dst are the same address
+        if (src != dst || bx > 256) return hipErrorInvalidValue;
+        if (diag) {
+            if (bcmode == BC_AA_EVEN)
+                hipLaunchKernelGGL((sweep_aa_diag_kernel<L, S, BC_AA_EVEN, PK>), l.grid, l.block, 0, s, b, d, diag, p);
+            else
+                hipLaunchKernelGGL((sweep_aa_diag_kernel<L, S, BC_AA_ODD, PK>), l.grid, l.block, 0, s, b, d, diag, p);
+        } else if (bcmode == BC_AA_EVEN) {
+            hipLaunchKernelGGL((sweep_aa_kernel<L, S, BC_AA_EVEN, PK>), l.grid, l.block, 0, s, b, d, p);
+        } else {
+            hipLaunchKernelGGL((sweep_aa_kernel<L, S, BC_AA_ODD, PK>), l.grid, l.block, 0, s, b, d, p);
+        }
+        return hipGetLastError();
+    }
     if (diag) {
         if (bcmode == BC_PERIODIC)
             hipLaunchKernelGGL((sweep_diag_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, a, b, d, diag, p);
@@ -440,6 +542,12 @@ static hipError_t moments_dispatch_bc(int bcmode, const Params& p, const void* s
     if (bcmode == BC_PERIODIC)
         hipLaunchKernelGGL((moments_kernel<L, S, BC_PERIODIC, O>), l.grid, l.block, 0, s, a,
                            static_cast<O*>(drho), static_cast<O*>(u), partials, p);
+    else if (bcmode == BC_AA_EVEN)
+        hipLaunchKernelGGL((moments_kernel<L, S, BC_AA_EVEN, O>), l.grid, l.block, 0, s, a,
+                           static_cast<O*>(drho), static_cast<O*>(u), partials, p);
+    else if (bcmode == BC_AA_ODD)
+        hipLaunchKernelGGL((moments_kernel<L, S, BC_AA_ODD, O>), l.grid, l.block, 0, s, a,
+                           static_cast<O*>(drho), static_cast<O*>(u), partials, p);
     else if (bcmode == BC_MASKED)
         hipLaunchKernelGGL((moments_kernel<L, S, BC_MASKED, O>), l.grid, l.block, 0, s, a,
                            static_cast<O*>(drho), static_cast<O*>(u), partials, p);
@@ -483,6 +591,40 @@ hipError_t launch_moments(int q, int storage, int bcmode, const Params& p, const
         return moments_dispatch_store<D2Q9>(storage, out_f64, bcmode, p, src, drho, u, partials, bx, s);
     if (q == 19)
         return moments_dispatch_store<D3Q19>(storage, out_f64, bcmode, p, src, drho, u, partials, bx, s);
+    return hipErrorInvalidValue;
+}
+
+template <class L, class E>
+static hipError_t aa_export_as(const Params& p, const void* buf, void* out, int odd_ready, hipStream_t s)
+{
+    const Launch l = cell_launch(p, 256);
+    auto* a = static_cast<const E*>(buf);
+    auto* b = static_cast<E*>(out);
+    if (odd_ready)
+        hipLaunchKernelGGL((aa_export_kernel<L, E, true>), l.grid, l.block, 0, s, a, b, (uint32_t)p.nx,
+                           (uint32_t)p.ny, (uint32_t)p.nz);
+    else
+        hipLaunchKernelGGL((aa_export_kernel<L, E, false>), l.grid, l.block, 0, s, a, b, (uint32_t)p.nx,
+                           (uint32_t)p.ny, (uint32_t)p.nz);
+    return hipGetLastError();
+}
+
+template <class L>
+static hipError_t aa_export_elem(int storage, const Params& p, const void* buf, void* out, int odd_ready,
+                                 hipStream_t s)
+{
+    if (storage == StoreF64::code) return aa_export_as<L, uint64_t>(p, buf, out, odd_ready, s);
+    if (storage == StoreF32::code) return aa_export_as<L, uint32_t>(p, buf, out, odd_ready, s);
+    if (storage == StoreF16S::code || storage == StoreBF16S::code)
+        return aa_export_as<L, uint16_t>(p, buf, out, odd_ready, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_aa_export(int q, int storage, const Params& p, const void* buf, void* out, int odd_ready,
+                            hipStream_t s)
+{
+    if (q == 9) return aa_export_elem<D2Q9>(storage, p, buf, out, odd_ready, s);
+    if (q == 19) return aa_export_elem<D3Q19>(storage, p, buf, out, odd_ready, s);
     return hipErrorInvalidValue;
 }
 

@@ -24,7 +24,8 @@ BATCH_GRAPH, BATCH_PERSISTENT, BATCH_PER_STEP = 0, 1, 2
 BATCH_MODES = {"graph": BATCH_GRAPH, "persistent": BATCH_PERSISTENT, "per_step": BATCH_PER_STEP}
 D2Q9, D3Q19 = 9, 19
 F64, F32, F16S, BF16S = 0, 1, 2, 3
-AB = 0
+AB, AA = 0, 1
+PATTERNS = {"ab": AB, "aa": AA}
 PERIODIC, WALL, INLET_U, OUTLET_RHO = 0, 1, 2, 3
 POROSITY_SCALAR, POROSITY_TENSOR = 0, 1
 POROSITY_KINDS = {"scalar": POROSITY_SCALAR, "tensor": POROSITY_TENSOR}
@@ -145,12 +146,12 @@ def make_config(lattice: int = D3Q19, storage="f32", shape=(32, 32, 32), tau: fl
                 force=(0.0, 0.0, 0.0), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), inlet_u=(0.0, 0.0, 0.0),
                 outlet_rho: float = 1.0, rho0: float = 1.0, store_scale: float = 1.0,
                 block_x: int = 0, external_memory: int = 0, stream: Optional[int] = None,
-                porosity: str = "scalar") -> Config:
+                porosity: str = "scalar", pattern: str = "ab") -> Config:
     cfg = Config()
     _check(load().hlbm_config_default(ctypes.byref(cfg)))
     cfg.lattice = int(lattice)
     cfg.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
-    cfg.pattern = AB
+    cfg.pattern = PATTERNS[pattern]
     nx, ny, nz = (tuple(shape) + (1,))[:3] if len(shape) == 2 else tuple(shape)
     cfg.nx, cfg.ny, cfg.nz = int(nx), int(ny), int(nz)
     cfg.tau = float(tau)
@@ -172,13 +173,14 @@ class HLBM:
     """One lattice (context).  Device memory comes from torch tensors.
 
     ``shape`` is (nx, ny, nz); fields returned by :meth:`moments` have shape
-    (nz, ny, nx) for drho and (3, nz, ny, nx) for u.
+    (nz, ny, nx) for drho and (3, nz, ny, nx) for u.  ``pattern`` "ab" keeps two
+    population buffers; "aa" updates one in place (fully periodic boxes only).
     """
 
     def __init__(self, lattice: int = D3Q19, storage="f32", shape=(32, 32, 32), tau=0.6,
                  force=(0.0, 0.0, 0.0), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0),
                  inlet_u=(0.0, 0.0, 0.0), outlet_rho=1.0, rho0=1.0, store_scale=1.0,
-                 block_x=0, device="cuda:0", porosity="scalar"):
+                 block_x=0, device="cuda:0", porosity="scalar", pattern="ab"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -186,7 +188,8 @@ class HLBM:
         lib = load()
         self.cfg = make_config(lattice, storage, shape, tau, force, bc_lo, bc_hi, inlet_u,
                                outlet_rho, rho0, store_scale, block_x, external_memory=1,
-                               stream=self.stream.cuda_stream, porosity=porosity)
+                               stream=self.stream.cuda_stream, porosity=porosity, pattern=pattern)
+        self.pattern = pattern
         self.q = self.cfg.lattice
         self.porosity_rows = 6 if porosity == "tensor" else 1
         self.storage = self.cfg.storage
@@ -197,12 +200,15 @@ class HLBM:
         self.pop_bytes = pb.value
         with torch.cuda.device(self.device):
             self._pop_a = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
-            self._pop_b = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
+            # the in-place pattern keeps one population buffer
+            self._pop_b = (None if pattern == "aa"
+                           else torch.empty(pb.value, dtype=torch.uint8, device=self.device))
             self._dfield = torch.empty(max(db.value, 1), dtype=torch.uint8, device=self.device)
         ctx = ctypes.c_void_p()
         _check(lib.hlbm_create(ctypes.byref(self.cfg), ctypes.byref(ctx)))
         self.ctx = ctx
-        _check(lib.hlbm_bind_buffers(self.ctx, self._pop_a.data_ptr(), self._pop_b.data_ptr(),
+        _check(lib.hlbm_bind_buffers(self.ctx, self._pop_a.data_ptr(),
+                                     None if self._pop_b is None else self._pop_b.data_ptr(),
                                      self._dfield.data_ptr()))
 
     # -- lifecycle ---------------------------------------------------------

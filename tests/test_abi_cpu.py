@@ -85,6 +85,9 @@ def test_required_bytes():
     (dict(lattice=9, shape=(8, 8, 2)), hlbm.EINVAL),
     (dict(bc_lo=(1, 0, 0), bc_hi=(1, 0, 0), shape=(2, 8, 8)), hlbm.EINVAL),
     (dict(lattice=9, shape=(8, 8, 1), porosity="tensor"), hlbm.EUNSUPPORTED),
+    (dict(pattern="aa", bc_lo=(0, 1, 0), bc_hi=(0, 1, 0)), hlbm.EUNSUPPORTED),
+    (dict(pattern="aa", bc_lo=(2, 0, 0), bc_hi=(3, 0, 0)), hlbm.EUNSUPPORTED),
+    (dict(pattern="aa", block_x=512), hlbm.EUNSUPPORTED),
 ])
 def test_config_validation(kw, code):
     args = dict(lattice=19, storage="f32", shape=(16, 16, 16))
@@ -99,6 +102,19 @@ def test_unknown_porosity_kind():
     cfg.porosity_kind = 7
     rc, _, _ = _rb(cfg)
     assert rc == hlbm.EINVAL and "porosity_kind" in hlbm.load().hlbm_last_error().decode()
+
+
+def test_pattern_field():
+    # the in-place pattern is accepted for periodic boxes and needs the same
+    # bytes per population buffer (it keeps one buffer instead of two)
+    rc, pb, db = _rb(hlbm.make_config(19, "f32", (64, 32, 16), pattern="aa"))
+    assert rc == 0 and pb == 19 * 4 * 64 * 32 * 16
+    rc, _, _ = _rb(hlbm.make_config(9, "f16s", (64, 32, 1), pattern="aa", porosity="scalar"))
+    assert rc == 0
+    cfg = hlbm.make_config(19, "f32", (16, 16, 16))
+    cfg.pattern = 2
+    rc, _, _ = _rb(cfg)
+    assert rc == hlbm.EINVAL and "pattern" in hlbm.load().hlbm_last_error().decode()
 
 
 def test_null_arguments(lib):
@@ -125,6 +141,7 @@ def _batch_rc(items):
     (dict(shape=(2000, 8, 8)), hlbm.EINVAL),
     (dict(shape=(1000, 1000, 8)), hlbm.EUNSUPPORTED),   # multiply-high quotient bound
     (dict(tau=0.4), hlbm.EINVAL),
+    (dict(pattern="aa"), hlbm.EUNSUPPORTED),
 ])
 def test_batch_validation(change, code):
     base = dict(lattice=19, storage="f32", shape=(32, 32, 32), tau=0.7)

@@ -47,6 +47,17 @@ def test_sweep_kernels_are_straight_line(asm):
         assert branches <= 1, (name, branches)
 
 
+def test_in_place_kernels_are_straight_line(asm):
+    aa = _kernels(asm, "_ZN4hlbm15sweep_aa_kernel")
+    # (2 lattices x 4 storages scalar + 4 storages tensor) x 2 step forms
+    assert len(aa) == 24
+    exports = _kernels(asm, "_ZN4hlbm16aa_export_kernel")
+    assert len(exports) == 12
+    for name, body in {**aa, **exports}.items():
+        branches = len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
+        assert branches <= 1, (name, branches)
+
+
 def test_adjoint_kernels_are_straight_line(asm):
     kern = {**_kernels(asm, "_ZN4hlbm14adjoint_kernel"), **_kernels(asm, "_ZN4hlbm19adjoint_seed_kernel")}
     assert len(kern) == 32
@@ -60,6 +71,8 @@ def test_no_private_memory_in_sweep_and_moments(asm):
                        **_kernels(asm, "_ZN4hlbm14moments_kernel"),
                        **_kernels(asm, "_ZN4hlbm14adjoint_kernel"),
                        **_kernels(asm, "_ZN4hlbm17sweep_pair_kernel"),
+                       **_kernels(asm, "_ZN4hlbm15sweep_aa_kernel"),
+                       **_kernels(asm, "_ZN4hlbm20sweep_aa_diag_kernel"),
                        **_kernels(asm, "_ZN4hlbm19adjoint_seed_kernel"),
                        **_kernels(asm, "_ZN4hlbm23batch_persistent_kernel"),
                        **_kernels(asm, "_ZN4hlbm17batch_step_kernel")}.items():
