@@ -235,10 +235,14 @@ def time_batched(hlbm, steps=2000, seed=0):
     items = [dict(shape=(e, e, e), tau=t, force=(1e-6, 0, 0)) for e, _, t in spec]
     log("batched: building 256 unit-cell fields")
     fields = {}
+    from paper_2310_14746_amd import tune
+    sched = tune.lookup_batch(items, "f32") or {}
     out = {"workload": "256 periodic D3Q19 unit cells, edges {32,48,64,80,96}, phi U[0.1,0.9], "
                        f"tau U[0.55,1.0], F=1e-6, FP32, seed {seed}", "steps": steps}
     for mode in ("graph", "per_step"):
-        b = hlbm.HLBMBatch(items, "f32", mode=mode)
+        b = hlbm.HLBMBatch(items, "f32", mode=mode, **sched)
+        out["schedule"] = b.schedule()
+        out["schedule"]["tuned"] = bool(sched)
         try:
             for k, (e, phi, _) in enumerate(spec):
                 if (e, phi) not in fields:
@@ -482,7 +486,7 @@ def main():
     for f in forms:
         st, pattern = storage_of(f), ("aa" if f.endswith("-aa") else "ab")
         tile = inputs.round_to(d_tile, "f32" if st == "f32" else "f16")
-        bx = args.block_x if args.block_x >= 0 else tune.lookup(hlbm.D3Q19, st, (N_EDGE,) * 3)
+        bx = args.block_x if args.block_x >= 0 else tune.lookup(hlbm.D3Q19, st, (N_EDGE,) * 3, pattern)
         ms, dr, u, tot, teq = time_form(hlbm, st, tile, args.steps, args.warmup, block_x=bx, pattern=pattern)
         results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq, block_x=bx)
     copy_ref = None if args.no_copy_reference else copy_reference()

@@ -314,7 +314,13 @@ int hlbm_adjoint_step(hlbm_ctx *ctx, int nsteps, const double *dJ_drho, const do
  *                         steps with a grid-wide barrier between them;
  *   HLBM_BATCH_PERSISTENT the same persistent kernel launched directly;
  *   HLBM_BATCH_PER_STEP   one kernel launch per step.
- * The persistent kernel is sized to the blocks that fit on the GPU at once.
+ * Schedule: the packed cells are cut into tiles of `tile` cells that never
+ * straddle two items; a tile is one block of `tile` threads in every mode.
+ * The persistent kernel keeps blocks_per_cu blocks resident on each CU (at
+ * most what fits at once) and blocks draw `chunk` tiles at a time from a
+ * device-wide counter.  The state does not depend on the schedule (bit for
+ * bit); hlbm_batch_moments' totals sum per-tile partials, so their rounding
+ * follows the tile size.
  * Its barrier waits with a bounded spin; if the bound is hit, every block
  * leaves and the next syncing call returns HLBM_EDEVICE.
  * hlbm_get_state / hlbm_set_state / hlbm_reset / hlbm_get_step work on the
@@ -327,8 +333,12 @@ enum { HLBM_BATCH_GRAPH = 0, HLBM_BATCH_PERSISTENT = 1, HLBM_BATCH_PER_STEP = 2 
  * (each in [2, 1024], with nx*ny*nz*max(nx, ny) < 2^32), tau and force; all
  * items must use HLBM_D3Q19, the same storage, HLBM_AB and periodic faces on
  * every axis.  rho0, store_scale, block_x and hip_stream are taken from
- * items[0]; external_memory must be 0 (the library allocates).  The packed
- * cell count times the element size must stay below 4 GiB.  State at rest. */
+ * items[0]; items[0].block_x is the tile (0 = 256 cells; else a multiple of 64
+ * up to 512, EINVAL above).  external_memory must be 0 (the library allocates).  The packed
+ * cell count times the element size must stay below 4 GiB.  State at rest.
+ * EUNSUPPORTED if no block of `tile` threads of the batched kernel fits on a
+ * CU.  The schedule starts at blocks_per_cu = max(1, 512 / tile) (capped at
+ * what fits) and chunk = 2. */
 int hlbm_create_batch(const hlbm_config *items, int n_items, hlbm_ctx **out);
 
 /* Number of items and total packed cells of a batch (EINVAL if not a batch). */
@@ -336,6 +346,16 @@ int hlbm_batch_info(const hlbm_ctx *ctx, int *n_items, size_t *total_cells);
 
 /* Select how hlbm_step advances a batch (HLBM_BATCH_*). */
 int hlbm_batch_set_mode(hlbm_ctx *ctx, int mode);
+
+/* Schedule of the persistent kernel: resident blocks per CU, in
+ * [1, max_blocks_per_cu] (0 = the default), and tiles per draw, in [1, 64]
+ * (0 = 2).  EINVAL outside those ranges.  Waits for the stream. */
+int hlbm_batch_set_schedule(hlbm_ctx *ctx, int blocks_per_cu, int chunk);
+
+/* The batch's tile, resident blocks per CU, the most blocks that fit per CU,
+ * and chunk.  Any output may be NULL.  EINVAL if not a batch. */
+int hlbm_batch_get_schedule(const hlbm_ctx *ctx, int *tile, int *blocks_per_cu, int *max_blocks_per_cu,
+                            int *chunk);
 
 /* Porosity control d = 1 - varpi of one item (nx*ny*nz values, x fastest),
  * same rules as hlbm_set_porosity.  Every item must be set before stepping. */

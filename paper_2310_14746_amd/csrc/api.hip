@@ -60,6 +60,9 @@ struct hlbm_ctx {
     hlbm::BatchLaunch bl;
     hipGraphExec_t gexec[2];
     int gsteps[2];
+    int cus;             // compute units of the device
+    int batch_bpc;       // resident blocks per CU of the persistent kernel
+    int max_blocks_per_cu;  // resident blocks of the persistent kernel that fit
     // adjoint tape (hlbm_set_tape): checkpoints of the state every `every`
     // steps since step `tape_origin`, a replay segment and two FP64 adjoint
     // population buffers
@@ -298,6 +301,28 @@ int tape_restart(hlbm_ctx* c)
                                   c->stream);
     if (e != hipSuccess) return hip_fail(e, "tape checkpoint");
     return HLBM_OK;
+}
+
+// Resident grid and chunk of the persistent kernel (0 = default); drops the
+// cached graphs, which hold the old launch shape.
+void set_batch_schedule(hlbm_ctx* c, int blocks_per_cu, int chunk)
+{
+    if (blocks_per_cu == 0) {
+        blocks_per_cu = hlbm::BATCH_THREADS_PER_CU_DEFAULT / (int)c->bl.tile;
+        if (blocks_per_cu < 1) blocks_per_cu = 1;
+        if (blocks_per_cu > c->max_blocks_per_cu) blocks_per_cu = c->max_blocks_per_cu;
+    }
+    long long grid = (long long)blocks_per_cu * c->cus;
+    if (grid > (long long)c->bl.ntiles) grid = (long long)c->bl.ntiles;
+    if (grid < 1) grid = 1;
+    c->bl.grid = (int)grid;
+    c->bl.chunk = (uint32_t)(chunk ? chunk : hlbm::CHUNK_DEFAULT);
+    c->batch_bpc = blocks_per_cu;
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        c->gexec[k] = nullptr;
+        c->gsteps[k] = -1;
+    }
 }
 
 int batch_check_barrier(hlbm_ctx* c)
@@ -951,6 +976,9 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
     if (!items) return fail(HLBM_EINVAL, "items is NULL");
     if (n_items < 1 || n_items > 65536) return fail(HLBM_EINVAL, "n_items must be in [1, 65536]");
     const int storage = items[0].storage;
+    // items[0].block_x is the tile: cells per tile = threads per block
+    const int tile = items[0].block_x ? items[0].block_x : hlbm::TILE_DEFAULT;
+    if (tile > hlbm::TILE_MAX) return fail(HLBM_EINVAL, "a batch tile (items[0].block_x) must be <= %d", hlbm::TILE_MAX);
     unsigned long long ntot = 0, ntiles = 0, max_cells = 0;
     for (int k = 0; k < n_items; ++k) {
         const hlbm_config* it = &items[k];
@@ -971,7 +999,7 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
         if (cells * mxy >= (1ull << 32))
             return fail(HLBM_EUNSUPPORTED, "item %d: nx*ny*nz*max(nx,ny) must be < 2^32", k);
         ntot += cells;
-        ntiles += (cells + hlbm::TILE - 1) / hlbm::TILE;
+        ntiles += (cells + tile - 1) / tile;
         if (cells > max_cells) max_cells = cells;
     }
     if (items[0].external_memory) return fail(HLBM_EUNSUPPORTED, "a batch allocates its own memory");
@@ -1015,7 +1043,7 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
         b.omega = 1.0 / it->tau;
         b.pref = 1.0 - 0.5 / it->tau;
         for (int a = 0; a < 3; ++a) b.F[a] = it->force[a];
-        const uint32_t nt = (b.cells + hlbm::TILE - 1) / hlbm::TILE;
+        const uint32_t nt = (b.cells + tile - 1) / tile;
         for (uint32_t j = 0; j < nt; ++j) tile_item[tile0 + j] = (uint32_t)k;
         base += b.cells;
         tile0 += nt;
@@ -1039,7 +1067,7 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
         e = hipMemcpy(c->tile_item_dev, tile_item.data(), sizeof(uint32_t) * (size_t)ntiles, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(c->bar_err, 0, sizeof(int));
     int per_cu = 0, cus = 0;
-    if (e == hipSuccess) e = hlbm::batch_occupancy(storage, &per_cu);
+    if (e == hipSuccess) e = hlbm::batch_occupancy(storage, tile, &per_cu);
     int dev = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1047,9 +1075,12 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
         hlbm_destroy(c);
         return hip_fail(e, "batch set-up");
     }
-    long long grid = (long long)per_cu * cus;
-    if (grid > (long long)ntiles) grid = (long long)ntiles;
-    if (grid < 1) grid = 1;
+    if (per_cu < 1) {
+        hlbm_destroy(c);
+        return fail(HLBM_EUNSUPPORTED, "no block of %d threads of the batched kernel fits on a CU", tile);
+    }
+    c->cus = cus;
+    c->max_blocks_per_cu = per_cu;
     c->bl.items = c->items_dev;
     c->bl.tile_item = c->tile_item_dev;
     c->bl.n_items = (uint32_t)n_items;
@@ -1060,7 +1091,8 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
     c->bl.sync = c->bar_sync;
     c->bl.err = c->bar_err;
     c->bl.spin_limit = 1u << 20;
-    c->bl.grid = (int)grid;
+    c->bl.tile = (uint32_t)tile;
+    set_batch_schedule(c, 0, 0);
     c->bound = true;
     int rc = zero_state(c);
     if (rc) {
@@ -1088,6 +1120,33 @@ int hlbm_batch_set_mode(hlbm_ctx* c, int mode)
     if (!c->batch) return fail(HLBM_EINVAL, "not a batch context");
     if (mode < HLBM_BATCH_GRAPH || mode > HLBM_BATCH_PER_STEP) return fail(HLBM_EINVAL, "unknown batch mode %d", mode);
     c->batch_mode = mode;
+    return HLBM_OK;
+}
+
+int hlbm_batch_set_schedule(hlbm_ctx* c, int blocks_per_cu, int chunk)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!c->batch) return fail(HLBM_EINVAL, "not a batch context");
+    if (blocks_per_cu < 0 || blocks_per_cu > c->max_blocks_per_cu)
+        return fail(HLBM_EINVAL, "blocks_per_cu must be in [0, %d] for tiles of %u cells", c->max_blocks_per_cu,
+                    c->bl.tile);
+    if (chunk < 0 || chunk > hlbm::CHUNK_MAX) return fail(HLBM_EINVAL, "chunk must be in [0, %d]", hlbm::CHUNK_MAX);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch_set_schedule: outstanding work failed");
+    set_batch_schedule(c, blocks_per_cu, chunk);
+    return HLBM_OK;
+}
+
+int hlbm_batch_get_schedule(const hlbm_ctx* c, int* tile, int* blocks_per_cu, int* max_blocks_per_cu, int* chunk)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!c->batch) return fail(HLBM_EINVAL, "not a batch context");
+    if (tile) *tile = (int)c->bl.tile;
+    if (blocks_per_cu) *blocks_per_cu = c->batch_bpc;
+    if (max_blocks_per_cu) *max_blocks_per_cu = c->max_blocks_per_cu;
+    if (chunk) *chunk = (int)c->bl.chunk;
     return HLBM_OK;
 }
 

@@ -5,10 +5,11 @@
 //
 // Layout: the items' cells are packed one after another, x fastest inside an
 // item, and each population row spans all items: buf[i*Ntot + base_k + local].
-// The packed cells are cut into tiles of TILE consecutive cells that never
+// The packed cells are cut into tiles of `tile` consecutive cells (one block
+// of `tile` threads; the block size of every batched launch) that never
 // straddle two items (a tile's tail past the item's end is masked).
 //
-// Work distribution of the persistent kernel: blocks take chunks of CHUNK
+// Work distribution of the persistent kernel: blocks take chunks of `chunk`
 // consecutive tiles from one device-wide counter, in order, so the blocks
 // resident at any moment work on one contiguous band of tiles (the rows a pull
 // reads from the neighbouring y and z rows are still in L2 when the band
@@ -16,10 +17,14 @@
 // imbalance at the step's end).  Chunk k belongs to step k / nch (nch chunks
 // per step); a block that draws a chunk of a later step keeps it and works on
 // it in that step, after the grid barrier.  Each block draws its next chunk
-// while it works on the current one.  (Measured on the 256-cell workload:
-// 2 tiles per draw beat 1, 4, 8 and 16, and drawing per block beat drawing
-// per wavefront, whose four times as many draws contend on the counter.)
-// The grid is sized to the number of blocks that can be resident at once.
+// while it works on the current one.  (Drawing per block beat drawing per
+// wavefront, whose four times as many draws contend on the counter.)  The
+// grid is `blocks_per_cu` resident blocks per CU, at most what fits.  Every
+// block takes part in every grid barrier, and each participant costs a cache
+// write-back and invalidation, so fewer, busier blocks win: on the 256-cell
+// workload 2 blocks of 256 threads per CU ran 10% faster than the 5 that fit.
+// Tile size, blocks per CU and chunk are chosen by the autotuner; results do
+// not depend on them.
 // The barrier waits with a bounded spin; if the bound is exceeded (a block was
 // never scheduled) or another block reported an error, every block leaves the
 // kernel at its next barrier and the host sees the error flag, so the kernel
@@ -115,16 +120,17 @@ __device__ __forceinline__ void batch_cell(const typename S::T* __restrict__ src
 }
 
 template <class S>
-__global__ __launch_bounds__(TILE) void batch_persistent_kernel(
+__global__ __launch_bounds__(TILE_MAX) void batch_persistent_kernel(
     typename S::T* __restrict__ buf_a, typename S::T* __restrict__ buf_b,
     const typename S::D* __restrict__ dfield, const BatchItem* __restrict__ items,
-    const uint32_t* __restrict__ tile_item, uint32_t ntiles, uint32_t Ntot, int nsteps,
+    const uint32_t* __restrict__ tile_item, uint32_t ntiles, uint32_t chunk, uint32_t Ntot, int nsteps,
     int start_in_b, double rho0_d, double scale_d, unsigned long long* __restrict__ sync,
     int* __restrict__ err, unsigned spin_limit)
 {
     using R = typename S::R;
     const R rho0 = R(rho0_d), scale = R(scale_d), inv_scale = R(1.0 / scale_d);
-    const unsigned long long nch = (ntiles + CHUNK - 1) / CHUNK;  // chunks per step
+    const uint32_t tile = blockDim.x;
+    const unsigned long long nch = (ntiles + chunk - 1) / chunk;  // chunks per step
     __shared__ unsigned long long next;
     if (threadIdx.x == 0) next = atomicAdd(&sync[1], 1ull);
     __syncthreads();
@@ -139,11 +145,11 @@ __global__ __launch_bounds__(TILE) void batch_persistent_kernel(
             // this chunk is done
             unsigned long long drawn = 0ull;
             if (threadIdx.x == 0) drawn = atomicAdd(&sync[1], 1ull);
-            const uint32_t t0 = (uint32_t)(cur - first) * CHUNK;
-            const uint32_t t1 = min(ntiles, t0 + CHUNK);
+            const uint32_t t0 = (uint32_t)(cur - first) * chunk;
+            const uint32_t t1 = min(ntiles, t0 + chunk);
             for (uint32_t t = t0; t < t1; ++t) {
                 const BatchItem it = items[tile_item[t]];
-                const uint32_t l = (t - it.tile0) * TILE + threadIdx.x;
+                const uint32_t l = (t - it.tile0) * tile + threadIdx.x;
                 if (l < it.cells) batch_cell<S>(src, dst, dfield, Ntot, it, l, rho0, scale, inv_scale);
             }
             __syncthreads();  // every thread has read `next` for this chunk
@@ -160,7 +166,7 @@ __global__ __launch_bounds__(TILE) void batch_persistent_kernel(
 // One launch per step over all tiles (no barrier); used for the non-persistent
 // form and as the reference the persistent form must match bit for bit.
 template <class S>
-__global__ __launch_bounds__(TILE) void batch_step_kernel(
+__global__ __launch_bounds__(TILE_MAX) void batch_step_kernel(
     const typename S::T* __restrict__ src, typename S::T* __restrict__ dst,
     const typename S::D* __restrict__ dfield, const BatchItem* __restrict__ items,
     const uint32_t* __restrict__ tile_item, uint32_t Ntot, double rho0_d, double scale_d)
@@ -168,7 +174,7 @@ __global__ __launch_bounds__(TILE) void batch_step_kernel(
     using R = typename S::R;
     const uint32_t t = blockIdx.x;
     const BatchItem it = items[tile_item[t]];
-    const uint32_t l = (t - it.tile0) * TILE + threadIdx.x;
+    const uint32_t l = (t - it.tile0) * blockDim.x + threadIdx.x;
     if (l < it.cells)
         batch_cell<S>(src, dst, dfield, Ntot, it, l, R(rho0_d), R(scale_d), R(1.0 / scale_d));
 }
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(TILE) void batch_step_kernel(
 // Moments of every item at the current time level: one block per tile writes
 // FP64 partials (sum drho, sum rho u); optionally the fields of one item.
 template <class S>
-__global__ __launch_bounds__(TILE) void batch_moments_kernel(
+__global__ __launch_bounds__(TILE_MAX) void batch_moments_kernel(
     const typename S::T* __restrict__ src, const BatchItem* __restrict__ items,
     const uint32_t* __restrict__ tile_item, uint32_t Ntot, double rho0_d, double scale_d,
     double* __restrict__ partials, int sel_item, double* __restrict__ drho_out,
@@ -187,7 +193,7 @@ __global__ __launch_bounds__(TILE) void batch_moments_kernel(
     const uint32_t t = blockIdx.x;
     const uint32_t k = tile_item[t];
     const BatchItem it = items[k];
-    const uint32_t l = (t - it.tile0) * TILE + threadIdx.x;
+    const uint32_t l = (t - it.tile0) * blockDim.x + threadIdx.x;
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
     if (l < it.cells) {
         const uint32_t q = div_magic(l, it.mx);
@@ -216,10 +222,10 @@ __global__ __launch_bounds__(TILE) void batch_moments_kernel(
 // Per-item totals: block k sums the partials of item k's tiles in order.
 __global__ __launch_bounds__(256) void batch_item_reduce_kernel(const double* __restrict__ partials,
                                                                 const BatchItem* __restrict__ items,
-                                                                double* __restrict__ totals)
+                                                                uint32_t tile, double* __restrict__ totals)
 {
     const BatchItem it = items[blockIdx.x];
-    const uint32_t nt = (it.cells + TILE - 1) / TILE;
+    const uint32_t nt = (it.cells + tile - 1) / tile;
     double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
     for (uint32_t j = threadIdx.x; j < nt; j += blockDim.x) {
         const double* p = partials + 4 * (size_t)(it.tile0 + j);
@@ -239,9 +245,9 @@ static hipError_t persistent_dispatch(const BatchLaunch& b, void* buf_a, void* b
                                       int nsteps, int start_in_b, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b.sync, b.err);
-    hipLaunchKernelGGL((batch_persistent_kernel<S>), dim3(b.grid), dim3(TILE), 0, s,
+    hipLaunchKernelGGL((batch_persistent_kernel<S>), dim3(b.grid), dim3(b.tile), 0, s,
                        static_cast<typename S::T*>(buf_a), static_cast<typename S::T*>(buf_b),
-                       static_cast<const typename S::D*>(dfield), b.items, b.tile_item, b.ntiles,
+                       static_cast<const typename S::D*>(dfield), b.items, b.tile_item, b.ntiles, b.chunk,
                        b.Ntot, nsteps, start_in_b, b.rho0, b.scale, b.sync, b.err, b.spin_limit);
     return hipGetLastError();
 }
@@ -262,7 +268,7 @@ template <class S>
 static hipError_t step_dispatch(const BatchLaunch& b, const void* src, void* dst, const void* dfield,
                                 hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_step_kernel<S>), dim3(b.ntiles), dim3(TILE), 0, s,
+    hipLaunchKernelGGL((batch_step_kernel<S>), dim3(b.ntiles), dim3(b.tile), 0, s,
                        static_cast<const typename S::T*>(src), static_cast<typename S::T*>(dst),
                        static_cast<const typename S::D*>(dfield), b.items, b.tile_item, b.Ntot,
                        b.rho0, b.scale);
@@ -286,13 +292,13 @@ static hipError_t moments_dispatch(const BatchLaunch& b, const void* src, double
                                    int sel_item, double* drho, double* u, double* totals,
                                    hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_moments_kernel<S>), dim3(b.ntiles), dim3(TILE), 0, s,
+    hipLaunchKernelGGL((batch_moments_kernel<S>), dim3(b.ntiles), dim3(b.tile), 0, s,
                        static_cast<const typename S::T*>(src), b.items, b.tile_item, b.Ntot, b.rho0,
                        b.scale, partials, sel_item, drho, u);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(batch_item_reduce_kernel, dim3(b.n_items), dim3(256), 0, s, partials, b.items,
-                       totals);
+                       b.tile, totals);
     return hipGetLastError();
 }
 
@@ -336,15 +342,15 @@ static hipError_t graph_dispatch(const BatchLaunch& b, void* buf_a, void* buf_b,
     auto* pd = static_cast<const typename S::D*>(dfield);
     const BatchItem* items = b.items;
     const uint32_t* tile_item = b.tile_item;
-    uint32_t ntiles = b.ntiles, Ntot = b.Ntot;
+    uint32_t ntiles = b.ntiles, chunk = b.chunk, Ntot = b.Ntot;
     double rho0 = b.rho0, scale = b.scale;
     unsigned spin = b.spin_limit;
-    void* run_args[] = {&pa, &pb, &pd, &items, &tile_item, &ntiles, &Ntot, &nsteps,
+    void* run_args[] = {&pa, &pb, &pd, &items, &tile_item, &ntiles, &chunk, &Ntot, &nsteps,
                         &start_in_b, &rho0, &scale, &sync, &err, &spin};
     hipKernelNodeParams kp = {};
     kp.func = reinterpret_cast<void*>(batch_persistent_kernel<S>);
     kp.gridDim = dim3(b.grid);
-    kp.blockDim = dim3(TILE);
+    kp.blockDim = dim3(b.tile);
     kp.sharedMemBytes = 0;
     kp.kernelParams = run_args;
     kp.extra = nullptr;
@@ -366,17 +372,17 @@ hipError_t build_batch_graph(int storage, const BatchLaunch& b, void* buf_a, voi
     }
 }
 
-hipError_t batch_occupancy(int storage, int* blocks_per_cu)
+hipError_t batch_occupancy(int storage, int tile, int* blocks_per_cu)
 {
     switch (storage) {
     case StoreF32::code:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF32>, TILE, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF32>, tile, 0);
     case StoreF16S::code:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF16S>, TILE, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF16S>, tile, 0);
     case StoreBF16S::code:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreBF16S>, TILE, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreBF16S>, tile, 0);
     case StoreF64::code:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF64>, TILE, 0);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF64>, tile, 0);
     default: return hipErrorInvalidValue;
     }
 }

@@ -87,8 +87,17 @@ hipError_t launch_porosity_convert(int in_dtype, const void* in, int storage, in
 // ---------------------------------------------------------------------------
 // Batched periodic boxes
 // ---------------------------------------------------------------------------
-constexpr int TILE = 256;         // cells per tile (one block of the batched kernels)
-constexpr uint32_t CHUNK = 2;     // tiles per draw of a block of the persistent kernel
+// Schedule of the batched kernels: a tile is `tile` consecutive cells of one
+// item and one block of `tile` threads; the persistent kernel keeps
+// `blocks_per_cu` blocks resident per CU and draws `chunk` tiles at a time.
+constexpr int TILE_DEFAULT = 256;
+constexpr int TILE_MAX = 512;   // FP64 needs more than the 128 VGPRs a 1024-thread block leaves
+constexpr int CHUNK_DEFAULT = 2;
+constexpr int CHUNK_MAX = 64;
+// default resident threads per CU of the persistent kernel (blocks_per_cu =
+// this / tile, at least 1): a few waves per SIMD, so that the grid barrier
+// has few participants
+constexpr int BATCH_THREADS_PER_CU_DEFAULT = 512;
 
 // One item of a batch, as read by the kernels.
 struct BatchItem {
@@ -111,6 +120,8 @@ struct BatchLaunch {
     int* err;                   // device error flag
     unsigned spin_limit;
     int grid;                   // resident blocks of the persistent kernel
+    uint32_t tile;              // cells per tile = threads per block
+    uint32_t chunk;             // tiles per draw of the persistent kernel
 };
 
 hipError_t launch_batch_persistent(int storage, const BatchLaunch& b, void* buf_a, void* buf_b,
@@ -119,7 +130,7 @@ hipError_t launch_batch_step(int storage, const BatchLaunch& b, const void* src,
                              const void* dfield, hipStream_t s);
 hipError_t launch_batch_moments(int storage, const BatchLaunch& b, const void* src, double* partials,
                                 int sel_item, double* drho, double* u, double* totals, hipStream_t s);
-hipError_t batch_occupancy(int storage, int* blocks_per_cu);
+hipError_t batch_occupancy(int storage, int tile, int* blocks_per_cu);
 hipError_t build_batch_graph(int storage, const BatchLaunch& b, void* buf_a, void* buf_b,
                              const void* dfield, int nsteps, int start_in_b, hipGraphExec_t* out);
 

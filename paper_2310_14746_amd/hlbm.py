@@ -110,6 +110,8 @@ def load() -> ctypes.CDLL:
         "hlbm_create_batch": ([P(Config), i, P(vp)], i),
         "hlbm_batch_info": ([vp, P(ctypes.c_int), P(ctypes.c_size_t)], i),
         "hlbm_batch_set_mode": ([vp, i], i),
+        "hlbm_batch_set_schedule": ([vp, i, i], i),
+        "hlbm_batch_get_schedule": ([vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int)], i),
         "hlbm_batch_set_porosity": ([vp, i, vp, i, i], i),
         "hlbm_batch_moments": ([vp, i, vp, vp, i, P(ctypes.c_double)], i),
         "hlbm_set_solid_mask": ([vp, vp, i], i),
@@ -423,11 +425,13 @@ class HLBMBatch:
 
     ``items`` is a sequence of dicts with keys ``shape`` (nx, ny, nz), ``tau``
     and ``force``.  The library owns the packed device memory; torch supplies
-    the stream.
+    the stream.  ``tile`` (cells per tile = threads per block, 0 = 256),
+    ``blocks_per_cu`` and ``chunk`` (0 = defaults) set the persistent kernel's
+    schedule; results do not depend on it.
     """
 
     def __init__(self, items, storage="f32", store_scale=1.0, rho0=1.0, mode="graph",
-                 device="cuda:0"):
+                 device="cuda:0", tile=0, blocks_per_cu=0, chunk=0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -437,7 +441,8 @@ class HLBMBatch:
         arr = (Config * n)()
         for k, it in enumerate(items):
             c = make_config(D3Q19, storage, it["shape"], it["tau"], it.get("force", (0, 0, 0)),
-                            rho0=rho0, store_scale=store_scale, stream=self.stream.cuda_stream)
+                            rho0=rho0, store_scale=store_scale, stream=self.stream.cuda_stream,
+                            block_x=tile if k == 0 else 0)
             arr[k] = c
         self.items = [dict(shape=tuple(int(v) for v in it["shape"]), tau=float(it["tau"]),
                            force=tuple(float(v) for v in it.get("force", (0, 0, 0))))
@@ -447,6 +452,8 @@ class HLBMBatch:
         self.ctx = ctx
         self.n_items = n
         self.set_mode(mode)
+        if blocks_per_cu or chunk:
+            self.set_schedule(blocks_per_cu, chunk)
 
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
@@ -474,6 +481,16 @@ class HLBMBatch:
     def set_mode(self, mode):
         _check(load().hlbm_batch_set_mode(self.ctx, BATCH_MODES[mode] if isinstance(mode, str)
                                           else int(mode)))
+
+    def set_schedule(self, blocks_per_cu: int = 0, chunk: int = 0):
+        """Resident blocks per CU and tiles per draw of the persistent kernel (0 = default)."""
+        _check(load().hlbm_batch_set_schedule(self.ctx, int(blocks_per_cu), int(chunk)))
+
+    def schedule(self) -> dict:
+        t, b, m, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(load().hlbm_batch_get_schedule(self.ctx, ctypes.byref(t), ctypes.byref(b), ctypes.byref(m),
+                                              ctypes.byref(c)))
+        return {"tile": t.value, "blocks_per_cu": b.value, "max_blocks_per_cu": m.value, "chunk": c.value}
 
     def set_porosity(self, item: int, d):
         nx, ny, nz = self.items[item]["shape"]

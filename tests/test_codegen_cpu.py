@@ -128,7 +128,7 @@ def test_barrier_polling_keeps_caches(asm):
         add = _arrival_atomic(lines)
         sleep = next(i for i, l in enumerate(lines) if l.startswith("s_sleep"))
         assert add < sleep, name
-        window = lines[add:sleep + 20]
+        window = lines[add:sleep + 40]
         assert not any(l.startswith("buffer_inv") for l in window), name
         # polling loads are device-coherent
         assert any(re.match(r"global_load_dword v\d+, v\d+, s\[\d+:\d+\] sc1", l) for l in window), name

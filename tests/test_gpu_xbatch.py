@@ -1,7 +1,8 @@
 """GPU tests of batched periodic boxes (persistent kernel with grid barrier,
 graph launch, per-step launches).  Collected after the other GPU tests.
 
-* every mode gives the same bits;
+* every mode gives the same bits, under every schedule (tile size, resident
+  blocks per CU, tiles per draw);
 * an item evolves bit for bit as a single context of the same configuration;
 * an item matches the FP64 oracle to the FP32 bar;
 * the full workload (256 homogenized unit cells, edges 32..96, 2000 steps)
@@ -52,8 +53,8 @@ def _fields(items, seed=0):
     return out
 
 
-def _run_batch(H, items, fields, steps, mode):
-    b = H.HLBMBatch(items, "f32", mode=mode)
+def _run_batch(H, items, fields, steps, mode, **sched):
+    b = H.HLBMBatch(items, "f32", mode=mode, **sched)
     try:
         for k, d in enumerate(fields):
             b.set_porosity(k, d)
@@ -104,6 +105,61 @@ def test_modes_bitwise_and_items_match_single_contexts(H):
         _, (dr, u), tot_s = _run_single(H, it, fields[k], steps)
         assert np.array_equal(ref[1][k][0], dr) and np.array_equal(ref[1][k][1], u), k
         assert np.allclose(ref[2][k], tot_s, rtol=1e-12, atol=1e-18), k
+
+
+@pytest.mark.parametrize("tile,bpc,chunk", [(64, 0, 1), (128, 1, 3), (256, 0, 0), (256, -1, 2),
+                                            (320, 1, 1), (512, 1, 1), (512, 0, 7)])
+def test_schedules_bitwise(H, tile, bpc, chunk):
+    """Every tile size, resident-block count and chunk gives the state of the
+    default per-step run bit for bit (ragged last tiles included); bpc -1 = all
+    that fit."""
+    fields = _fields(ITEMS, 11)
+    steps = 23
+    ref, _, ref_tot = _run_batch(H, ITEMS, fields, steps, "per_step")
+    for mode in ("graph", "persistent", "per_step"):
+        b = H.HLBMBatch(ITEMS, "f32", mode=mode, tile=tile)
+        try:
+            sc = b.schedule()
+            b.set_schedule(sc["max_blocks_per_cu"] if bpc < 0 else bpc, chunk)
+            sc = b.schedule()
+            say(f"schedule {sc}, mode {mode}")
+            assert sc["tile"] == tile and 1 <= sc["blocks_per_cu"] <= sc["max_blocks_per_cu"]
+            assert sc["chunk"] == (chunk or 2)
+            for k, d in enumerate(fields):
+                b.set_porosity(k, d)
+            b.step(steps)
+            b.sync()
+            st = b.get_state()[0].cpu().numpy()
+            tot = b.totals()
+        finally:
+            b.close()
+        assert np.array_equal(st, ref), (mode, sc)
+        # totals sum per-tile partials: the same values, grouped by the tile size
+        if tile == 256:
+            assert np.array_equal(tot, ref_tot), (mode, sc)
+        else:
+            assert np.allclose(tot[:, 1:], ref_tot[:, 1:], rtol=1e-12, atol=0), (mode, sc)
+            assert np.allclose(tot[:, 0], ref_tot[:, 0], rtol=0, atol=1e-14), (mode, sc)
+
+
+def test_schedule_rules(H):
+    with pytest.raises(H.HLBMError):
+        H.HLBMBatch(ITEMS, "f32", tile=1024)
+    with pytest.raises(H.HLBMError):
+        H.HLBMBatch(ITEMS, "f32", tile=100)
+    b = H.HLBMBatch(ITEMS, "f32", tile=512)
+    try:
+        sc = b.schedule()
+        assert sc == {"tile": 512, "blocks_per_cu": 1, "max_blocks_per_cu": sc["max_blocks_per_cu"], "chunk": 2}
+        with pytest.raises(H.HLBMError):
+            b.set_schedule(sc["max_blocks_per_cu"] + 1, 0)
+        with pytest.raises(H.HLBMError):
+            b.set_schedule(0, 65)
+        with pytest.raises(H.HLBMError):
+            b.set_schedule(-1, 0)
+        assert b.schedule() == sc                        # rejected calls change nothing
+    finally:
+        b.close()
 
 
 def test_graph_relaunch_and_odd_even_steps(H):
