@@ -271,16 +271,12 @@ __device__ __forceinline__ double collide_adjoint(const Moms& m, double d, const
 // forward state x_{t-1} in `xprev`; dbar += this step's dJ/dd.
 // ---------------------------------------------------------------------------
 template <class L, class S, int BC>
-__global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict__ lam_in,
-                                                       LamT<S>* __restrict__ lam_out,
-                                                       const typename S::T* __restrict__ xprev,
-                                                       const typename S::D* __restrict__ dfield,
-                                                       double* __restrict__ dbar, Params p)
+__device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in, LamT<S>* __restrict__ lam_out,
+                                             const typename S::T* __restrict__ xprev,
+                                             const typename S::D* __restrict__ dfield, double* __restrict__ dbar,
+                                             const Params& p, uint32_t x, uint32_t y, uint32_t z)
 {
     const uint32_t N = p.N;
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= (uint32_t)p.nx) return;
-    const uint32_t y = blockIdx.y, z = blockIdx.z;
     const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
     const Moms m = forward_moments<L, S, BC>(xprev, p, x, y, z);
     const double d = (double)S::load_d(ld(dfield, cell));
@@ -304,6 +300,46 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict_
     for (int k = 0; k < L::Q; ++k) st(lam_out + (size_t)k * N, cell, LamT<S>(sel(solid, 0.0, pb[k])));
     const double acc = ld(dbar, cell);
     st(dbar, cell, acc + sel(solid, 0.0, dd));
+}
+
+template <class L, class S, int BC>
+__global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict__ lam_in,
+                                                       LamT<S>* __restrict__ lam_out,
+                                                       const typename S::T* __restrict__ xprev,
+                                                       const typename S::D* __restrict__ dfield,
+                                                       double* __restrict__ dbar, Params p)
+{
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (uint32_t)p.nx) return;
+    adjoint_cell<L, S, BC>(lam_in, lam_out, xprev, dfield, dbar, p, x, blockIdx.y, blockIdx.z);
+}
+
+// Interior and shell of a box with walls or open faces (see Split), in one
+// launch: in the interior the periodic forms of the gather and of its
+// transpose load what the general rule would; the shell takes the general
+// rule.  The choice is uniform per block.
+template <class L, class S>
+__global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __restrict__ lam_in,
+                                                             LamT<S>* __restrict__ lam_out,
+                                                             const typename S::T* __restrict__ xprev,
+                                                             const typename S::D* __restrict__ dfield,
+                                                             double* __restrict__ dbar, Params p, Split sp)
+{
+    const uint32_t b = blockIdx.x;
+    if (b < sp.blocks_in) {
+        const uint32_t row = b / sp.gx, bxi = b - row * sp.gx;
+        const uint32_t iy = sp.hi[1] - sp.lo[1];
+        const uint32_t zz = row / iy, yy = row - zz * iy;
+        const uint32_t x = sp.lo[0] + bxi * blockDim.x + threadIdx.x;
+        if (x >= sp.hi[0]) return;
+        adjoint_cell<L, S, BC_PERIODIC>(lam_in, lam_out, xprev, dfield, dbar, p, x, sp.lo[1] + yy, sp.lo[2] + zz);
+    } else {
+        const uint32_t k = (b - sp.blocks_in) * blockDim.x + threadIdx.x;
+        if (k >= sp.n_shell) return;
+        uint32_t x, y, z;
+        shell_cell(sp, (uint32_t)p.nx, (uint32_t)p.ny, k, x, y, z);
+        adjoint_cell<L, S, BC_GENERAL>(lam_in, lam_out, xprev, dfield, dbar, p, x, y, z);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -334,10 +370,17 @@ static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* l
     auto* d = static_cast<const typename S::D*>(dfield);
     auto* li = static_cast<const LamT<S>*>(lam_in);
     auto* lo = static_cast<LamT<S>*>(lam_out);
-    if (bcmode == BC_PERIODIC)
+    if (bcmode == BC_PERIODIC) {
         hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC>), l.grid, l.block, 0, s, li, lo, a, d, dbar, p);
-    else
+        return hipGetLastError();
+    }
+    const Split sp = split_of(p, (int)l.block.x);
+    if (!sp.interior()) {
         hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL>), l.grid, l.block, 0, s, li, lo, a, d, dbar, p);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((adjoint_split_kernel<L, S>), dim3(sp.blocks_in + sp.blocks_shell), l.block, 0, s, li, lo, a,
+                       d, dbar, p, sp);
     return hipGetLastError();
 }
 

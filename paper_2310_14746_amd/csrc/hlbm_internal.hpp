@@ -38,6 +38,54 @@ constexpr uint32_t LINK_SOLID_SELF = 1u << 31;
 // Porosity control kinds: one value d per cell, or a symmetric 3x3 D (6 rows).
 enum PorosityKind { PK_SCALAR = 0, PK_TENSOR = 1 };
 
+// Boxes with walls or open faces.  The cells at least two layers away from
+// every non-periodic face (the "interior") pull only from in-box fluid cells,
+// so the periodic gather and its transpose load exactly what the general rule
+// would; the adjoint sweep runs them there and the general rule, whose
+// open-face terms are costly in FP64, on the rest (the "shell").  Interior range per axis: [lo, hi), the whole axis when periodic,
+// else [2, n - 2) (possibly empty).  rows_out counts the rows (y, z) outside
+// the interior rows; n_shell = rows_out * nx + interior rows * (nx - (hi[0] -
+// lo[0])).  One launch of blocks of bx threads covers both: gx blocks per
+// interior row, blocks_in interior blocks, then blocks_shell shell blocks.
+struct Split {
+    uint32_t lo[3], hi[3];
+    uint32_t rows_out, n_shell;
+    uint32_t gx, blocks_in, blocks_shell;
+    bool interior() const { return hi[0] > lo[0] && hi[1] > lo[1] && hi[2] > lo[2]; }
+};
+Split split_of(const Params& p, int bx);
+
+// Coordinates of shell cell k < n_shell: first every cell of the rows outside
+// the interior rows (z below the interior; then interior z with y outside
+// the interior; then z above), x fastest; then, row by row, the cells of the
+// interior rows outside the interior x-range.  Written with selects (the
+// discarded candidates may wrap; they are never used as addresses).
+__host__ __device__ inline void shell_cell(const Split& s, uint32_t nx, uint32_t ny, uint32_t k, uint32_t& x,
+                                           uint32_t& y, uint32_t& z)
+{
+    const uint32_t ix = s.hi[0] - s.lo[0], iy = s.hi[1] - s.lo[1], iz = s.hi[2] - s.lo[2];
+    const uint32_t full = s.rows_out * nx;
+    // rows outside the interior rows
+    const uint32_t r = k / nx, xa = k - r * nx;
+    const uint32_t below = s.lo[2] * ny, mid = iz * (ny - iy);
+    const uint32_t wy = ny - iy > 0u ? ny - iy : 1u;
+    const uint32_t z1 = r / ny, y1 = r - z1 * ny;
+    const uint32_t q2 = r - below, zz2 = q2 / wy, yy2 = q2 - zz2 * wy;
+    const uint32_t y2 = yy2 < s.lo[1] ? yy2 : s.hi[1] + (yy2 - s.lo[1]), z2 = s.lo[2] + zz2;
+    const uint32_t q3 = r - below - mid, zz3 = q3 / ny, y3 = q3 - zz3 * ny, z3 = s.hi[2] + zz3;
+    const uint32_t ya = r < below ? y1 : (r < below + mid ? y2 : y3);
+    const uint32_t za = r < below ? z1 : (r < below + mid ? z2 : z3);
+    // interior rows, x outside the interior range
+    const uint32_t wx = nx - ix > 0u ? nx - ix : 1u, wiy = iy > 0u ? iy : 1u;
+    const uint32_t q4 = k - full, r4 = q4 / wx, j4 = q4 - r4 * wx;
+    const uint32_t xb = j4 < s.lo[0] ? j4 : s.hi[0] + (j4 - s.lo[0]);
+    const uint32_t zz4 = r4 / wiy, yb = s.lo[1] + (r4 - zz4 * wiy), zb = s.lo[2] + zz4;
+    const bool a = k < full;
+    x = a ? xa : xb;
+    y = a ? ya : yb;
+    z = a ? za : zb;
+}
+
 // Launch geometry shared by every per-cell kernel: blocks of `bx` threads
 // along x, grid (ceil(nx/bx), ny, nz).
 struct Launch {

@@ -450,6 +450,28 @@ __global__ __launch_bounds__(256) void linkmask_kernel(const unsigned char* __re
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+Split split_of(const Params& p, int bx)
+{
+    Split s;
+    const uint32_t n[3] = {(uint32_t)p.nx, (uint32_t)p.ny, (uint32_t)p.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (p.bc_lo[a] == 0) {
+            s.lo[a] = 0;
+            s.hi[a] = n[a];
+        } else {
+            s.lo[a] = n[a] < 2u ? n[a] : 2u;
+            s.hi[a] = n[a] >= 2u + s.lo[a] ? n[a] - 2u : s.lo[a];
+        }
+    }
+    const uint32_t ix = s.hi[0] - s.lo[0], iy = s.hi[1] - s.lo[1], iz = s.hi[2] - s.lo[2];
+    s.rows_out = n[1] * n[2] - iy * iz;
+    s.n_shell = s.rows_out * n[0] + iy * iz * (n[0] - ix);
+    s.gx = (ix + (uint32_t)bx - 1) / (uint32_t)bx;
+    s.blocks_in = s.gx * iy * iz;
+    s.blocks_shell = (s.n_shell + (uint32_t)bx - 1) / (uint32_t)bx;
+    return s;
+}
+
 Launch cell_launch(const Params& p, int bx, int cells_per_thread)
 {
     Launch l;
@@ -502,6 +524,9 @@ static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src
         }
         hipLaunchKernelGGL((sweep_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, a, b, d, p);
     } else {
+        // (the interior/shell split that the adjoint uses does not pay here:
+        // the general gather costs the forward sweep little, and the shell's
+        // cells at the row ends load poorly coalesced)
         hipLaunchKernelGGL((sweep_kernel<L, S, BC_GENERAL, PK>), l.grid, l.block, 0, s, a, b, d, p);
     }
     return hipGetLastError();
