@@ -133,12 +133,12 @@ int hlbm_config_default(hlbm_config *cfg);
 int hlbm_lattice_info(int lattice, int *c, double *w);
 
 /* Bytes of one population buffer and of the porosity field for *cfg (six
- * rows for a tensor control). */
+ * rows for a tensor control).  HLBM_AB uses two such buffers, HLBM_AA one. */
 int hlbm_required_bytes(const hlbm_config *cfg, size_t *pop_bytes, size_t *porosity_bytes);
 
 /* Validate *cfg and create a context.  Unless cfg->external_memory is set the
- * library allocates both population buffers and the porosity field in device
- * memory.  The state starts at rest (g = 0: rho = rho0, u = 0 before the
+ * library allocates the population buffers (two for HLBM_AB, one for HLBM_AA)
+ * and the porosity field in device memory.  The state starts at rest (g = 0: rho = rho0, u = 0 before the
  * half-force shift), step counter 0.  EINVAL on a bad field, EUNSUPPORTED on an
  * unsupported combination, ENOMEM if allocation fails. */
 int hlbm_create(const hlbm_config *cfg, hlbm_ctx **out);
