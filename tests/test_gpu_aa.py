@@ -206,19 +206,27 @@ def test_aa_full_size_equals_ab(H, storage):
     del g
     d = (torch.rand(n ** 3, generator=gen, device="cuda") * 0.6).to(
         torch.float32 if storage == "f32" else torch.float16)
+    from paper_2310_14746_amd import tune
     kw = dict(tau=0.6, force=(1e-6, -2e-7, 0), store_scale=SCALE16)
-    sims = [H.HLBM(19, storage, (n, n, n), pattern=p, **kw) for p in ("ab", "aa")]
+    # each pattern at the block width bench.py times it with
+    sims = [H.HLBM(19, storage, (n, n, n), pattern=p, block_x=tune.lookup(19, storage, (n, n, n), p), **kw)
+            for p in ("ab", "aa")]
     try:
         for s in sims:
             s.set_porosity(d)
             s.set_state(state, 0)
         del state
+        same_bx = sims[0].cfg.block_x == sims[1].cfg.block_x
         for k in (3, 1):
             tot = []
             for s in sims:
                 s.step(k)
                 tot.append(s.totals())
-            assert np.array_equal(tot[0], tot[1])
+            # the FP64 totals sum per-block partials: bitwise only at one block width
+            if same_bx:
+                assert np.array_equal(tot[0], tot[1])
+            else:
+                assert np.allclose(tot[0], tot[1], rtol=1e-10, atol=1e-8)
             a = sims[0].get_state()[0]
             b = sims[1].get_state()[0]
             assert torch.equal(a, b)

@@ -207,7 +207,10 @@ def test_unit_cell_workload_full_size(H):
     say("building 256 unit-cell fields")
     fields = [inputs.round_to(inputs.batch_item_field(e, phi), "f32").astype(np.float32).ravel()
               for e, phi, _ in spec]
-    b = H.HLBMBatch(items, "f32", mode="graph")
+    from paper_2310_14746_amd import tune
+    sched = tune.lookup_batch(items, "f32") or {}      # the schedule bench.py times
+    b = H.HLBMBatch(items, "f32", mode="graph", **sched)
+    say(f"schedule {b.schedule()}")
     try:
         for k, d in enumerate(fields):
             b.set_porosity(k, d)
