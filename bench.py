@@ -62,6 +62,9 @@ def rel_l2_drho(dr, dr_ref, u_ref):
     return float(np.linalg.norm(dr - dr_ref) / max(np.linalg.norm(dr_ref), floor))
 
 
+TIMING_PARTS = {}   # (storage, pattern, porosity, edge) -> ms per step in five parts of the timed region
+
+
 def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar", edge=N_EDGE,
               pattern="ab"):
     import torch
@@ -82,15 +85,21 @@ def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar"
         sim.step(warmup)
         sim.sync()
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(sim.stream)
-        sim.step(steps)
-        e1.record(sim.stream)
-        e1.synchronize()
+        # one timed region of `steps` sweeps; events recorded between five
+        # equal parts of it (no synchronization inside) give the spread
+        parts = [steps // 5 + (1 if k < steps % 5 else 0) for k in range(5)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev[0].record(sim.stream)
+        for k, n in enumerate(parts):
+            sim.step(n)
+            ev[k + 1].record(sim.stream)
+        ev[5].synchronize()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        log(f"{storage}: {steps} steps in {ms:.1f} ms")
+        ms = ev[0].elapsed_time(ev[5])
+        per_step = [ev[k].elapsed_time(ev[k + 1]) / n for k, n in enumerate(parts) if n]
+        log(f"{storage}: {steps} steps in {ms:.1f} ms; per step in five parts: "
+            + ", ".join(f"{v:.4f}" for v in per_step) + " ms")
+        TIMING_PARTS[(storage, pattern, porosity, edge)] = per_step
         drho, u, tot = sim.moments("f64", totals=True)
         dr_t = drho[:32, :32, :32].cpu().numpy().ravel()
         u_t = u[:, :32, :32, :32].cpu().numpy().reshape(3, -1)
@@ -581,6 +590,9 @@ def main():
             "speedup_vs_" + head: round(results[head]["ms"] / r["ms"], 3),
             "tiles_identical": r["tiles_equal"],
             "block_x": r["block_x"],
+            "ms_per_step_parts": [round(v, 4) for v in
+                                  TIMING_PARTS.get((storage_of(f), "aa" if f.endswith("-aa") else "ab", "scalar",
+                                                    N_EDGE), [])],
             "mass_excess_total": float(r["tot"][0]),
         }
         if f.endswith("-aa") and storage_of(f) in results:

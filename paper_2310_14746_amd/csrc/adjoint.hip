@@ -317,7 +317,9 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict_
 // Interior and shell of a box with walls or open faces (see Split), in one
 // launch: in the interior the periodic forms of the gather and of its
 // transpose load what the general rule would; the shell takes the general
-// rule.  The choice is uniform per block.
+// rule.  The choice is uniform per block.  The shell's blocks come first:
+// they are the slow ones, and blocks start in index order, so the interior
+// blocks fill in behind them instead of leaving them as the tail.
 template <class L, class S>
 __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __restrict__ lam_in,
                                                              LamT<S>* __restrict__ lam_out,
@@ -326,19 +328,20 @@ __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __res
                                                              double* __restrict__ dbar, Params p, Split sp)
 {
     const uint32_t b = blockIdx.x;
-    if (b < sp.blocks_in) {
-        const uint32_t row = b / sp.gx, bxi = b - row * sp.gx;
+    if (b < sp.blocks_shell) {
+        const uint32_t k = b * blockDim.x + threadIdx.x;
+        if (k >= sp.n_shell) return;
+        uint32_t x, y, z;
+        shell_cell(sp, (uint32_t)p.nx, (uint32_t)p.ny, k, x, y, z);
+        adjoint_cell<L, S, BC_GENERAL>(lam_in, lam_out, xprev, dfield, dbar, p, x, y, z);
+    } else {
+        const uint32_t bi = b - sp.blocks_shell;
+        const uint32_t row = bi / sp.gx, bxi = bi - row * sp.gx;
         const uint32_t iy = sp.hi[1] - sp.lo[1];
         const uint32_t zz = row / iy, yy = row - zz * iy;
         const uint32_t x = sp.lo[0] + bxi * blockDim.x + threadIdx.x;
         if (x >= sp.hi[0]) return;
         adjoint_cell<L, S, BC_PERIODIC>(lam_in, lam_out, xprev, dfield, dbar, p, x, sp.lo[1] + yy, sp.lo[2] + zz);
-    } else {
-        const uint32_t k = (b - sp.blocks_in) * blockDim.x + threadIdx.x;
-        if (k >= sp.n_shell) return;
-        uint32_t x, y, z;
-        shell_cell(sp, (uint32_t)p.nx, (uint32_t)p.ny, k, x, y, z);
-        adjoint_cell<L, S, BC_GENERAL>(lam_in, lam_out, xprev, dfield, dbar, p, x, y, z);
     }
 }
 

@@ -39,14 +39,16 @@ constexpr uint32_t LINK_SOLID_SELF = 1u << 31;
 enum PorosityKind { PK_SCALAR = 0, PK_TENSOR = 1 };
 
 // Boxes with walls or open faces.  The cells at least two layers away from
-// every non-periodic face (the "interior") pull only from in-box fluid cells,
-// so the periodic gather and its transpose load exactly what the general rule
-// would; the adjoint sweep runs them there and the general rule, whose
-// open-face terms are costly in FP64, on the rest (the "shell").  Interior range per axis: [lo, hi), the whole axis when periodic,
-// else [2, n - 2) (possibly empty).  rows_out counts the rows (y, z) outside
-// the interior rows; n_shell = rows_out * nx + interior rows * (nx - (hi[0] -
-// lo[0])).  One launch of blocks of bx threads covers both: gx blocks per
-// interior row, blocks_in interior blocks, then blocks_shell shell blocks.
+// every wall face and one layer away from every open face (the "interior")
+// pull only from in-box fluid cells, so the periodic gather and its transpose
+// load exactly what the general rule would.  The adjoint sweep runs them there
+// and the general rule, whose open-face terms are costly in FP64, on the rest
+// (the "shell").  Interior range per axis: [lo, hi), the whole axis when
+// periodic, else lo = 2 past a wall face or 1 past an open face, likewise hi
+// (possibly empty).  rows_out counts the rows (y, z) outside the interior
+// rows; n_shell = rows_out * nx + interior rows * (nx - (hi[0] - lo[0])).  One
+// launch of blocks of bx threads covers both: blocks_shell shell blocks, then
+// blocks_in interior blocks (gx per interior row).
 struct Split {
     uint32_t lo[3], hi[3];
     uint32_t rows_out, n_shell;

@@ -459,8 +459,11 @@ Split split_of(const Params& p, int bx)
             s.lo[a] = 0;
             s.hi[a] = n[a];
         } else {
-            s.lo[a] = n[a] < 2u ? n[a] : 2u;
-            s.hi[a] = n[a] >= 2u + s.lo[a] ? n[a] - 2u : s.lo[a];
+            // a wall face: its solid layer and the layer that bounces back
+            // against it; an open face: its own layer only
+            const uint32_t dlo = p.bc_lo[a] == 1 ? 2u : 1u, dhi = p.bc_hi[a] == 1 ? 2u : 1u;
+            s.lo[a] = n[a] < dlo ? n[a] : dlo;
+            s.hi[a] = n[a] >= dhi + s.lo[a] ? n[a] - dhi : s.lo[a];
         }
     }
     const uint32_t ix = s.hi[0] - s.lo[0], iy = s.hi[1] - s.lo[1], iz = s.hi[2] - s.lo[2];
