@@ -247,3 +247,45 @@ def test_unit_cell_workload_full_size(H):
     eu, er = rel_l2_u(u, u_o), rel_l2_drho(dr, dr_o, u_o)
     say(f"item {k32} (32^3) vs oracle after 2000 steps: u {eu:.2e} drho {er:.2e}")
     assert eu <= 1e-5 and er <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16s", "bf16s"])
+def test_storage_forms_match_single_contexts(H, storage):
+    """FP64 and 16-bit batches: every mode gives the bits of a single context
+    of the same storage (graph with the default schedule and with 64-cell
+    tiles, persistent, per step)."""
+    items = ITEMS[:3]
+    fields = _fields(items, 13)
+    steps = 17
+    scale = 2.0 ** 16 if storage != "f64" else 1.0
+    dt = np.float64 if storage == "f64" else np.float16
+    refs = []
+    for it, d in zip(items, fields):
+        sim = H.HLBM(19, storage, it["shape"], tau=it["tau"], force=it["force"], store_scale=scale)
+        try:
+            sim.set_porosity(d.astype(dt))
+            sim.step(steps)
+            refs.append(sim.get_state()[0].cpu().numpy())
+        finally:
+            sim.close()
+    for mode, tile in (("graph", 0), ("graph", 64), ("persistent", 0), ("per_step", 0)):
+        say(f"{storage} batch, mode {mode}, tile {tile or 'default'}")
+        b = H.HLBMBatch(items, storage, store_scale=scale, mode=mode, tile=tile)
+        try:
+            for k, d in enumerate(fields):
+                b.set_porosity(k, d.astype(dt))
+            b.step(steps)
+            b.sync()
+            st = b.get_state()[0].cpu().numpy()
+        finally:
+            b.close()
+        # the packed state: population row i spans all items, item k at its base
+        elem = 8 if storage == "f64" else 2
+        cells = [int(np.prod(it["shape"])) for it in items]
+        ntot = sum(cells)
+        packed = st.view(np.uint8).reshape(19, ntot * elem)
+        base = 0
+        for k, n in enumerate(cells):
+            single = refs[k].view(np.uint8).reshape(19, n * elem)
+            assert np.array_equal(packed[:, base * elem:(base + n) * elem], single), (mode, tile, k)
+            base += n
