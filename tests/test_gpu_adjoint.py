@@ -5,7 +5,8 @@ adjoint and against finite differences of the GPU's own FP64 forward.
   equals the oracle gradient (explicit 19x19 Jacobians, scatter transpose of
   streaming) to relative L2 1e-10, over periodic boxes, bounce-back walls and
   inlet/outlet faces, several checkpoint spacings and a single step.
-* FP32 storage (FP64 adjoint): relative L2 1e-3 against the oracle.
+* FP32 storage (FP64 adjoint): relative L2 1e-3 against the oracle; FP16S and
+  BF16S storage: 2e-3 and 1e-2 (measured 3.2e-4 and 2.3e-3; the forward's own storage error).
 * The differentiation workload at full size (128x64x64 channel, inlet
   u = 0.02, outlet rho = 1, walls in y and z, d ~ U[0,1), 500 steps, a
   checkpoint every 50) through ``torch.autograd``: the gradient of the channel
@@ -60,8 +61,8 @@ def _ids(c):
     return f"q{c[0]}-{c[1][0]}x{c[1][1]}x{c[1][2]}-lo{''.join(map(str, c[4]))}-T{c[7]}-K{c[8]}"
 
 
-def _gpu_gradient(H, storage, q, shape, tau, F, lo, hi, inu, steps, every, d, a, b):
-    sim = H.HLBM(q, storage, shape, tau=tau, force=F, bc_lo=lo, bc_hi=hi, inlet_u=inu)
+def _gpu_gradient(H, storage, q, shape, tau, F, lo, hi, inu, steps, every, d, a, b, store_scale=1.0):
+    sim = H.HLBM(q, storage, shape, tau=tau, force=F, bc_lo=lo, bc_hi=hi, inlet_u=inu, store_scale=store_scale)
     try:
         sim.set_porosity(d)
         sim.set_tape(every, steps)
@@ -105,6 +106,26 @@ def test_adjoint_f32_forward_matches_oracle(H):
     err = _rel(g, go)
     say(f"rel-L2 {err:.2e}")
     assert err <= 1e-3
+
+
+@pytest.mark.parametrize("storage,bar", [("f16s", 2e-3), ("bf16s", 1e-2)])
+def test_adjoint_16bit_forward_vs_oracle(H, storage, bar):
+    """16-bit stored forward (FP32 adjoint populations, FP64 adjoint
+    arithmetic): the gradient of the stored-precision forward map against the
+    oracle's FP64 gradient.  The storage rounding is not differentiated, so the
+    difference follows the forward's own error (reported against a bar)."""
+    q, shape, tau, F, lo, hi, inu, steps, every = CASES[4]
+    nx, ny, nz = shape
+    say(f"adjoint {storage} forward, 40x12x10 channel, 40 steps")
+    d = inputs.round_to(smooth_noise((nz, ny, nx), seed=3), "f16").ravel()
+    a, b = _cotangents(nx * ny * nz, q, seed=9)
+    g = _gpu_gradient(H, storage, q, shape, tau, F, lo, hi, inu, steps, 8, d.astype(np.float16), a, b,
+                      store_scale=2.0 ** 16)
+    cfg = OracleConfig(q=q, nx=nx, ny=ny, nz=nz, tau=tau, force=F, bc_lo=lo, bc_hi=hi, inlet_u=inu)
+    go = oracle.gradient(cfg, d, steps, a, b, every=8, nthreads=NT)
+    err = _rel(g, go)
+    say(f"rel-L2 {err:.2e}")
+    assert err <= bar
 
 
 def test_tape_rules(H):
