@@ -55,7 +55,30 @@ struct Split {
     uint32_t gx, blocks_in, blocks_shell;
     bool interior() const { return hi[0] > lo[0] && hi[1] > lo[1] && hi[2] > lo[2]; }
 };
-Split split_of(const Params& p, int bx);
+inline Split split_of(const Params& p, int bx)
+{
+    Split s;
+    const uint32_t n[3] = {(uint32_t)p.nx, (uint32_t)p.ny, (uint32_t)p.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (p.bc_lo[a] == 0) {
+            s.lo[a] = 0;
+            s.hi[a] = n[a];
+        } else {
+            // a wall face: its solid layer and the layer that bounces back
+            // against it; an open face: its own layer only
+            const uint32_t dlo = p.bc_lo[a] == 1 ? 2u : 1u, dhi = p.bc_hi[a] == 1 ? 2u : 1u;
+            s.lo[a] = n[a] < dlo ? n[a] : dlo;
+            s.hi[a] = n[a] >= dhi + s.lo[a] ? n[a] - dhi : s.lo[a];
+        }
+    }
+    const uint32_t ix = s.hi[0] - s.lo[0], iy = s.hi[1] - s.lo[1], iz = s.hi[2] - s.lo[2];
+    s.rows_out = n[1] * n[2] - iy * iz;
+    s.n_shell = s.rows_out * n[0] + iy * iz * (n[0] - ix);
+    s.gx = (ix + (uint32_t)bx - 1) / (uint32_t)bx;
+    s.blocks_in = s.gx * iy * iz;
+    s.blocks_shell = (s.n_shell + (uint32_t)bx - 1) / (uint32_t)bx;
+    return s;
+}
 
 // Coordinates of shell cell k < n_shell: first every cell of the rows outside
 // the interior rows (z below the interior; then interior z with y outside
