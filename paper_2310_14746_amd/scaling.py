@@ -103,6 +103,43 @@ def shear_wave_decay(hlbm, N: int, nu: float = 0.1, K: float = 0.05, t_end: floa
     return -math.log(a1 / a0) / t, shear_wave_rate_exact(nu, K), steps
 
 
+def darcy_pressure_exact(x: np.ndarray, g: float, a: float) -> np.ndarray:
+    """Steady 1-D flow through a periodic medium with 1/K(x) = (1 + a cos 2 pi x)/K0
+    under acceleration g: continuity makes u = U uniform, periodicity of p fixes
+    U = g K0 / nu, and the momentum balance dp/dx = g - nu U / K(x) gives
+    p(x) = -(g a / (2 pi)) sin(2 pi x) (zero mean)."""
+    return -(g * a / (2.0 * math.pi)) * np.sin(2.0 * math.pi * x)
+
+
+def darcy_pressure(hlbm, N: int, nu: float = 0.1, K0: float = 0.01, g: float = 1.0, a: float = 0.5,
+                   decay: float = 36.0, storage: str = "f64"):
+    """Pressure of Darcy flow through a medium whose permeability varies along
+    the flow (periodic in x, N cells per unit length; D2Q9 on N x 4).  The
+    lattice pressure is c_s^2 drho; under the diffusive scaling the physical
+    pressure is p = drho / (3 eps^2).  Returns (x, p, p_exact, U, U_exact,
+    steps)."""
+    eps = 1.0 / N
+    tau = 3.0 * nu + 0.5
+    x = (np.arange(N) + 0.5) / N
+    inv_k = (1.0 + a * np.cos(2.0 * math.pi * x)) / K0
+    d = nu * tau * eps * eps * inv_k                    # d = nu tau eps^2 / K(x)
+    rate = nu / K0 * (1.0 - a)                          # slowest Darcy relaxation per unit time
+    steps = int(math.ceil(decay / rate * N * N))
+    nx, ny = N, 4
+    sim = hlbm.HLBM(hlbm.D2Q9, storage, (nx, ny, 1), tau=tau, force=(g * eps ** 3, 0.0, 0.0))
+    try:
+        sim.set_porosity(np.ascontiguousarray(np.broadcast_to(d[None, :], (ny, nx)).ravel()))
+        sim.step(steps)
+        drho, u = sim.moments("f64")
+        drho = drho[0, 0, :].cpu().numpy()
+        ux = u[0, 0, 0, :].cpu().numpy()
+    finally:
+        sim.close()
+    p = drho / (3.0 * eps * eps)
+    U = float(((1.0 + drho) * ux).mean() / eps)          # mean mass flux, physical units
+    return x, p, darcy_pressure_exact(x, g, a), U, g * K0 / nu, steps
+
+
 def observed_order(errors, Ns) -> list:
     """log2 of successive error ratios for resolutions doubling."""
     return [math.log(errors[k] / errors[k + 1]) / math.log(Ns[k + 1] / Ns[k]) for k in range(len(Ns) - 1)]
