@@ -193,14 +193,13 @@ __device__ __forceinline__ typename S::R unpack(uint32_t bits16, typename S::R i
     return S::load(v, inv_scale);
 }
 
+// The 16 bits of a stored element, in the low half of a word.
 template <class S>
-__device__ __forceinline__ uint32_t pack(typename S::R lo, typename S::R hi, typename S::R scale)
+__device__ __forceinline__ uint32_t bits16(typename S::T v)
 {
-    const typename S::T a = S::store(lo, scale), b = S::store(hi, scale);
-    uint16_t ua, ub;
-    __builtin_memcpy(&ua, &a, 2);
-    __builtin_memcpy(&ub, &b, 2);
-    return (uint32_t)ua | ((uint32_t)ub << 16);
+    uint16_t u;
+    __builtin_memcpy(&u, &v, 2);
+    return (uint32_t)u;
 }
 
 template <class S>
@@ -220,7 +219,11 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
     const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
     const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};
     const bool first = x0 == 0, last = x0 + 2 == nx;
-    R lo[L::Q], hi[L::Q];
+    // Each population pair stays packed in one 32-bit word: the low cell is
+    // unpacked, collided and its result written back into the low half, then
+    // the same for the high cell.  Only one cell's 19 values are live as
+    // floats at a time.
+    uint32_t w[L::Q];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const T* row = src + (size_t)i * N + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
@@ -228,17 +231,14 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
         uint32_t xs = x0;
         if (L::cx[i] > 0) xs = sel(first, x0, x0 - 1);
         if (L::cx[i] < 0) xs = sel(last, x0, x0 + 1);
-        const uint32_t w = ld_pair<S>(row, xs);
-        lo[i] = unpack<S>(w & 0xffffu, inv_scale);
-        hi[i] = unpack<S>(w >> 16, inv_scale);
+        w[i] = ld_pair<S>(row, xs);
     }
     if (first) {  // c_x = +1 pulls (nx - 1, 0): the loaded pair was (0, 1)
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             if (L::cx[i] <= 0) continue;
             const T* row = src + (size_t)i * N + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
-            hi[i] = lo[i];
-            lo[i] = S::load(ld(row, nx - 1), inv_scale);
+            w[i] = bits16<S>(ld(row, nx - 1)) | (w[i] << 16);
         }
     }
     if (last) {  // c_x = -1 pulls (nx - 1, 0): the loaded pair was (nx - 2, nx - 1)
@@ -246,8 +246,7 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
         for (int i = 0; i < L::Q; ++i) {
             if (L::cx[i] >= 0) continue;
             const T* row = src + (size_t)i * N + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
-            lo[i] = hi[i];
-            hi[i] = S::load(ld(row, 0u), inv_scale);
+            w[i] = (w[i] >> 16) | (bits16<S>(ld(row, 0u)) << 16);
         }
     }
     const uint32_t cell = x0 + nx * (y + ny * z);
@@ -262,14 +261,21 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
     const uint16_t dl = (uint16_t)(dw & 0xffffu), dh = (uint16_t)(dw >> 16);
     __builtin_memcpy(&d_lo, &dl, 2);
     __builtin_memcpy(&d_hi, &dh, 2);
-    collide<L, R, ScalarShift<R>, S::exact_moments>(lo, ScalarShift<R>{S::load_d(d_lo)}, F0, F1, F2, rho0, omega,
+    R g[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) g[i] = unpack<S>(w[i] & 0xffffu, inv_scale);
+    collide<L, R, ScalarShift<R>, S::exact_moments>(g, ScalarShift<R>{S::load_d(d_lo)}, F0, F1, F2, rho0, omega,
                                                     pref, drho, ux, uy, uz);
-    collide<L, R, ScalarShift<R>, S::exact_moments>(hi, ScalarShift<R>{S::load_d(d_hi)}, F0, F1, F2, rho0, omega,
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) w[i] = (w[i] & 0xffff0000u) | bits16<S>(S::store(g[i], scale));
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) g[i] = unpack<S>(w[i] >> 16, inv_scale);
+    collide<L, R, ScalarShift<R>, S::exact_moments>(g, ScalarShift<R>{S::load_d(d_hi)}, F0, F1, F2, rho0, omega,
                                                     pref, drho, ux, uy, uz);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         uint32_t* out = reinterpret_cast<uint32_t*>(dst + (size_t)i * N);
-        st_stream(out, cell / 2u, pack<S>(lo[i], hi[i], scale));
+        st_stream(out, cell / 2u, (w[i] & 0xffffu) | (bits16<S>(S::store(g[i], scale)) << 16));
     }
 }
 
