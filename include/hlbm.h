@@ -100,7 +100,7 @@ enum { HLBM_POROSITY_SCALAR = 0, HLBM_POROSITY_TENSOR = 1 };
 typedef struct {
     int lattice;         /* HLBM_D2Q9 or HLBM_D3Q19 */
     int storage;         /* HLBM_F64, HLBM_F32, HLBM_F16S, HLBM_BF16S */
-    int pattern;         /* HLBM_AB */
+    int pattern;         /* HLBM_AB or HLBM_AA */
     int nx, ny, nz;      /* cells per axis; nz = 1 for D2Q9; nx*ny*nz < 2^32 */
     double tau;          /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3 */
     double force[3];     /* body-force density F (lattice units) */
@@ -111,7 +111,8 @@ typedef struct {
     double rho0;         /* reference density of the shifted populations (1) */
     double store_scale;  /* power of two s for F16S/BF16S; ignored otherwise */
     int external_memory; /* 1: caller binds population/porosity memory */
-    int block_x;         /* threads per block along x (multiple of 64, <= 1024); 0 = auto */
+    int block_x;         /* threads per block along x (multiple of 64, <= 1024; <= 256 for HLBM_AA;
+                            for a batch, items[0].block_x is the tile, <= 512); 0 = auto */
     void *hip_stream;    /* hipStream_t for all work of this context, NULL = default */
     int porosity_kind;   /* HLBM_POROSITY_SCALAR (default) or HLBM_POROSITY_TENSOR */
 } hlbm_config;
