@@ -353,6 +353,15 @@ int hlbm_batch_set_mode(hlbm_ctx *ctx, int mode);
  * (0 = 2).  EINVAL outside those ranges.  Waits for the stream. */
 int hlbm_batch_set_schedule(hlbm_ctx *ctx, int blocks_per_cu, int chunk);
 
+/* Bound on the wait of the persistent kernel's grid barrier, in polls of
+ * about 0.1 us each (default 2^20).  When a block's wait exceeds it, every
+ * block leaves the kernel at its next barrier (the kernel always ends) and the
+ * next syncing call (hlbm_sync, hlbm_batch_moments) returns HLBM_EDEVICE; the
+ * state is then undefined until hlbm_reset or hlbm_set_state.  0 makes any
+ * wait fail, which exercises that path.  EINVAL for polls < 0 or if not a
+ * batch.  Waits for the stream. */
+int hlbm_batch_set_barrier_limit(hlbm_ctx *ctx, int polls);
+
 /* The batch's tile, resident blocks per CU, the most blocks that fit per CU,
  * and chunk.  Any output may be NULL.  EINVAL if not a batch. */
 int hlbm_batch_get_schedule(const hlbm_ctx *ctx, int *tile, int *blocks_per_cu, int *max_blocks_per_cu,

@@ -18,6 +18,10 @@
 
 using hlbm::Params;
 
+// Polls of the persistent batch kernel's grid barrier before it gives up
+// (each poll sleeps about 0.1 us): far beyond any step of the workloads here.
+constexpr unsigned kBarrierPollsDefault = 1u << 20;
+
 struct hlbm_ctx {
     hlbm_config cfg;
     Params p;
@@ -1090,7 +1094,7 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
     c->bl.scale = c->p.scale;
     c->bl.sync = c->bar_sync;
     c->bl.err = c->bar_err;
-    c->bl.spin_limit = 1u << 20;
+    c->bl.spin_limit = kBarrierPollsDefault;
     c->bl.tile = (uint32_t)tile;
     set_batch_schedule(c, 0, 0);
     c->bound = true;
@@ -1135,6 +1139,23 @@ int hlbm_batch_set_schedule(hlbm_ctx* c, int blocks_per_cu, int chunk)
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "batch_set_schedule: outstanding work failed");
     set_batch_schedule(c, blocks_per_cu, chunk);
+    return HLBM_OK;
+}
+
+int hlbm_batch_set_barrier_limit(hlbm_ctx* c, int polls)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!c->batch) return fail(HLBM_EINVAL, "not a batch context");
+    if (polls < 0) return fail(HLBM_EINVAL, "polls must be >= 0");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch_set_barrier_limit: outstanding work failed");
+    c->bl.spin_limit = (unsigned)polls;
+    for (int k = 0; k < 2; ++k) {  // the graphs hold the old bound
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        c->gexec[k] = nullptr;
+        c->gsteps[k] = -1;
+    }
     return HLBM_OK;
 }
 

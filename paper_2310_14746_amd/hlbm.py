@@ -111,6 +111,7 @@ def load() -> ctypes.CDLL:
         "hlbm_batch_info": ([vp, P(ctypes.c_int), P(ctypes.c_size_t)], i),
         "hlbm_batch_set_mode": ([vp, i], i),
         "hlbm_batch_set_schedule": ([vp, i, i], i),
+        "hlbm_batch_set_barrier_limit": ([vp, i], i),
         "hlbm_batch_get_schedule": ([vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int)], i),
         "hlbm_batch_set_porosity": ([vp, i, vp, i, i], i),
         "hlbm_batch_moments": ([vp, i, vp, vp, i, P(ctypes.c_double)], i),
@@ -486,6 +487,10 @@ class HLBMBatch:
         """Resident blocks per CU and tiles per draw of the persistent kernel (0 = default)."""
         _check(load().hlbm_batch_set_schedule(self.ctx, int(blocks_per_cu), int(chunk)))
 
+    def set_barrier_limit(self, polls: int):
+        """Bound on the persistent kernel's barrier wait (polls of ~0.1 us)."""
+        _check(load().hlbm_batch_set_barrier_limit(self.ctx, int(polls)))
+
     def schedule(self) -> dict:
         t, b, m, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(load().hlbm_batch_get_schedule(self.ctx, ctypes.byref(t), ctypes.byref(b), ctypes.byref(m),
@@ -503,6 +508,10 @@ class HLBMBatch:
 
     def sync(self):
         _check(load().hlbm_sync(self.ctx))
+
+    def reset(self):
+        """Every item back to rest (g = 0) and step 0; the porosity is kept."""
+        _check(load().hlbm_reset(self.ctx))
 
     @property
     def step_count(self) -> int:

@@ -289,3 +289,31 @@ def test_storage_forms_match_single_contexts(H, storage):
             single = refs[k].view(np.uint8).reshape(19, n * elem)
             assert np.array_equal(packed[:, base * elem:(base + n) * elem], single), (mode, tile, k)
             base += n
+
+
+def test_barrier_bound_error_path(H):
+    """A barrier bound of 0 polls makes the persistent kernel's first grid
+    barrier fail: every block leaves, the call that syncs reports EDEVICE, and
+    after a reset the batch runs again and matches one launch per step."""
+    fields = _fields(ITEMS, 17)
+    ref, _, _ = _run_batch(H, ITEMS, fields, 9, "per_step")
+    for mode in ("persistent", "graph"):
+        say(f"barrier bound 0, mode {mode}")
+        b = H.HLBMBatch(ITEMS, "f32", mode=mode)
+        try:
+            for k, d in enumerate(fields):
+                b.set_porosity(k, d)
+            b.set_barrier_limit(0)
+            b.step(5)
+            with pytest.raises(H.HLBMError) as ei:
+                b.sync()
+            assert ei.value.code == H.EDEVICE and "barrier" in str(ei.value)
+            with pytest.raises(H.HLBMError):
+                b.set_barrier_limit(-1)
+            b.set_barrier_limit(1 << 20)
+            b.reset()
+            b.step(9)
+            b.sync()
+            assert np.array_equal(b.get_state()[0].cpu().numpy(), ref)
+        finally:
+            b.close()
