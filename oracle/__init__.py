@@ -26,6 +26,8 @@ from .oracle import (  # noqa: F401
     collide_cell_tensor,
     collide_tensor,
     run_tensor,
+    collide_adjoint_tensor,
+    gradient_tensor,
     stream_masked,
     run_masked,
     observe_masked,

@@ -705,6 +705,103 @@ int oracle_collide_adjoint(const oracle_cfg *cfg, const double *d, const double 
     return 0;
 }
 
+/* ======================================================================== */
+/* Adjoint with the tensor control: u_eq = (I - D) u, D symmetric, given as */
+/* its 6 rows (xx, yy, zz, xy, xz, yz).  The collision's Jacobian in the    */
+/* populations is the scalar one with (1 - d) replaced by (I - D); its      */
+/* Jacobian in the six components follows from d u_eq / d D_ab = -u_b e_a  */
+/* for a diagonal entry and -(u_b e_a + u_a e_b) for an off-diagonal one    */
+/* (which stands at (a, b) and (b, a)).                                      */
+/* ======================================================================== */
+static const int TENSOR_AXES[6][2] = { { 0, 0 }, { 1, 1 }, { 2, 2 }, { 0, 1 }, { 0, 2 }, { 1, 2 } };
+
+static void collide_cell_adjoint_tensor(const lattice_t *L, const oracle_cfg *cfg, const double Dm[3][3],
+                                        const double *pre, const double *post_bar, double *pre_bar,
+                                        double D_bar[6])
+{
+    const int q = L->q;
+    const double *F = cfg->force;
+    const double om = 1.0 / cfg->tau, pref = 1.0 - 0.5 / cfg->tau;
+    double s = 0.0, j[3] = { 0.0, 0.0, 0.0 };
+    for (int i = 0; i < q; ++i) {
+        s += pre[i];
+        for (int a = 0; a < 3; ++a) j[a] += L->c[i][a] * pre[i];
+    }
+    double rho = cfg->rho0 + s, u[3], v[3];
+    for (int a = 0; a < 3; ++a) u[a] = (j[a] + 0.5 * F[a]) / rho;
+    for (int a = 0; a < 3; ++a) {
+        v[a] = u[a];
+        for (int b = 0; b < 3; ++b) v[a] -= Dm[a][b] * u[b];
+    }
+    /* J[i][k] = d post_i / d pre_k, JD[i][r] = d post_i / d D_r */
+    double J[19][19], JD[19][6];
+    for (int i = 0; i < q; ++i) {
+        double dg_rho, dg_v[3];
+        equilibrium_derivs(L, rho, v, i, &dg_rho, dg_v);
+        double cF = L->c[i][0] * F[0] + L->c[i][1] * F[1] + L->c[i][2] * F[2];
+        double dS_u[3];
+        for (int a = 0; a < 3; ++a) dS_u[a] = pref * L->w[i] * (-3.0 * F[a] + 9.0 * L->c[i][a] * cF);
+        for (int k = 0; k < q; ++k) {
+            double du[3], dv[3];
+            for (int a = 0; a < 3; ++a) du[a] = (L->c[k][a] - u[a]) / rho;
+            for (int a = 0; a < 3; ++a) {
+                dv[a] = du[a];
+                for (int b = 0; b < 3; ++b) dv[a] -= Dm[a][b] * du[b];
+            }
+            double dgeq = dg_rho + dg_v[0] * dv[0] + dg_v[1] * dv[1] + dg_v[2] * dv[2];
+            double dS = dS_u[0] * du[0] + dS_u[1] * du[1] + dS_u[2] * du[2];
+            J[i][k] = (i == k ? 1.0 - om : 0.0) + om * dgeq + dS;
+        }
+        for (int r = 0; r < 6; ++r) {
+            const int a = TENSOR_AXES[r][0], b = TENSOR_AXES[r][1];
+            double dv[3] = { 0.0, 0.0, 0.0 };
+            dv[a] -= u[b];
+            if (a != b) dv[b] -= u[a];
+            JD[i][r] = om * (dg_v[0] * dv[0] + dg_v[1] * dv[1] + dg_v[2] * dv[2]);
+        }
+    }
+    for (int k = 0; k < q; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < q; ++i) acc += J[i][k] * post_bar[i];
+        pre_bar[k] = acc;
+    }
+    for (int r = 0; r < 6; ++r) {
+        double acc = 0.0;
+        for (int i = 0; i < q; ++i) acc += JD[i][r] * post_bar[i];
+        D_bar[r] += acc;
+    }
+}
+
+int oracle_collide_adjoint_tensor(const oracle_cfg *cfg, const double *D6, const double *pre,
+                                  const double *post_bar, double *pre_bar, double *D_bar, int nthreads)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L) || cfg->q != 19) return -1;
+    if (nthreads < 1) nthreads = 1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    const int ny = cfg->ny, nz = cfg->nz, nx = cfg->nx, q = cfg->q;
+#pragma omp parallel for collapse(2) num_threads(nthreads) schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long cell = cell_index(cfg, x, y, z);
+                if (is_solid(cfg, x, y, z)) {
+                    for (int i = 0; i < q; ++i) pre_bar[i * N + cell] = 0.0;
+                    continue;
+                }
+                double gin[19], pb[19], gb[19], Dm[3][3], db[6] = { 0, 0, 0, 0, 0, 0 };
+                for (int i = 0; i < q; ++i) {
+                    gin[i] = pre[i * N + cell];
+                    pb[i] = post_bar[i * N + cell];
+                }
+                tensor_of(D6, N, cell, Dm);
+                collide_cell_adjoint_tensor(&L, cfg, Dm, gin, pb, gb, db);
+                for (int i = 0; i < q; ++i) pre_bar[i * N + cell] = gb[i];
+                for (int r = 0; r < 6; ++r) D_bar[r * N + cell] += db[r];
+            }
+    return 0;
+}
+
 /* Transpose of pull streaming at post-collision state `post`, written as a
  * scatter: every pre-collision population sends its adjoint to whatever it
  * was read from.  post_bar is overwritten.  Single-threaded (scatter).     */
@@ -851,6 +948,54 @@ int oracle_gradient(const oracle_cfg *cfg, const double *d, int nsteps, int ever
             const double *xprev = seg + (size_t)(t - 1 - t0) * S;
             oracle_stream(cfg, xprev, pre, nthreads);
             oracle_collide_adjoint(cfg, d, pre, xbar, ybar, d_bar, nthreads);
+            oracle_stream_adjoint(cfg, xprev, ybar, xbar);
+        }
+    }
+    free(cps); free(seg); free(pre); free(xbar); free(ybar); free(x);
+    return 0;
+}
+
+/* Gradient with respect to the six rows of the tensor control D (D3Q19);
+ * otherwise as oracle_gradient.  D_bar[6N] is accumulated (+=).             */
+int oracle_gradient_tensor(const oracle_cfg *cfg, const double *D6, int nsteps, int every,
+                           const double *drho_bar, const double *u_bar, double *D_bar, int nthreads)
+{
+    lattice_t L;
+    if (check_cfg(cfg, &L) || cfg->q != 19) return -1;
+    if (nsteps < 0 || every < 1) return -1;
+    const long N = (long)cfg->nx * cfg->ny * cfg->nz;
+    const size_t S = (size_t)L.q * (size_t)N;
+    const int ncp = nsteps / every + 1;
+    double *cps = (double *)calloc((size_t)ncp * S, sizeof(double));
+    double *seg = (double *)malloc((size_t)(every + 1) * S * sizeof(double));
+    double *pre = (double *)malloc(S * sizeof(double));
+    double *xbar = (double *)malloc(S * sizeof(double));
+    double *ybar = (double *)malloc(S * sizeof(double));
+    double *x = (double *)calloc(S, sizeof(double));
+    if (!cps || !seg || !pre || !xbar || !ybar || !x) {
+        free(cps); free(seg); free(pre); free(xbar); free(ybar); free(x);
+        return -2;
+    }
+    for (int t = 0; t < nsteps; ++t) {
+        if (t % every == 0) memcpy(cps + (size_t)(t / every) * S, x, S * sizeof(double));
+        oracle_stream(cfg, x, pre, nthreads);
+        oracle_collide_tensor(cfg, D6, pre, x, nthreads);
+    }
+    oracle_stream(cfg, x, pre, nthreads);
+    oracle_moments_adjoint(cfg, pre, drho_bar, u_bar, ybar);
+    oracle_stream_adjoint(cfg, x, ybar, xbar);
+    for (int m = (nsteps - 1) / every; m >= 0 && nsteps > 0; --m) {
+        const int t0 = m * every;
+        const int t1 = (t0 + every < nsteps) ? t0 + every : nsteps;
+        memcpy(seg, cps + (size_t)m * S, S * sizeof(double));
+        for (int t = t0; t < t1; ++t) {
+            oracle_stream(cfg, seg + (size_t)(t - t0) * S, pre, nthreads);
+            oracle_collide_tensor(cfg, D6, pre, seg + (size_t)(t - t0 + 1) * S, nthreads);
+        }
+        for (int t = t1; t > t0; --t) {
+            const double *xprev = seg + (size_t)(t - 1 - t0) * S;
+            oracle_stream(cfg, xprev, pre, nthreads);
+            oracle_collide_adjoint_tensor(cfg, D6, pre, xbar, ybar, D_bar, nthreads);
             oracle_stream_adjoint(cfg, xprev, ybar, xbar);
         }
     }

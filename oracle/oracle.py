@@ -244,6 +244,8 @@ def _tensor_load():
         lib.oracle_collide_cell_tensor.argtypes = [C, D, D, D]
         lib.oracle_collide_tensor.argtypes = [C, D, D, D, ctypes.c_int]
         lib.oracle_run_tensor.argtypes = [C, D, ctypes.c_int, D, ctypes.c_int]
+        lib.oracle_collide_adjoint_tensor.argtypes = [C, D, D, D, D, D, ctypes.c_int]
+        lib.oracle_gradient_tensor.argtypes = [C, D, ctypes.c_int, ctypes.c_int, D, D, D, ctypes.c_int]
         lib._tensor_ready = True
     return lib
 
@@ -279,6 +281,34 @@ def run_tensor(cfg: OracleConfig, D6, nsteps: int, g=None, nthreads: int = 1) ->
     _check(_tensor_load().oracle_run_tensor(ctypes.byref(s), _dp(_tensor_field(cfg, D6)), int(nsteps),
                                             _dp(g), nthreads), "run_tensor")
     return g
+
+
+def collide_adjoint_tensor(cfg: OracleConfig, D6, pre, post_bar, nthreads: int = 1):
+    """(pre_bar, D_bar[6, N]) of one collision pass with the tensor control."""
+    pre = _state(cfg, pre)
+    pb = _state(cfg, post_bar)
+    out = np.zeros_like(pre)
+    Dbar = np.zeros((6, cfg.ncells))
+    s = cfg.c_struct()
+    _check(_tensor_load().oracle_collide_adjoint_tensor(ctypes.byref(s), _dp(_tensor_field(cfg, D6)), _dp(pre),
+                                                        _dp(pb), _dp(out), _dp(Dbar), nthreads),
+           "collide_adjoint_tensor")
+    return out, Dbar
+
+
+def gradient_tensor(cfg: OracleConfig, D6, nsteps: int, drho_bar, u_bar, every: int = 10,
+                    nthreads: int = 1) -> np.ndarray:
+    """d/dD6 (rows xx, yy, zz, xy, xz, yz) of <drho_bar, drho> + <u_bar, u> at the
+    moments after nsteps from rest; an off-diagonal row is one variable that
+    stands at two places of the symmetric matrix."""
+    db = np.ascontiguousarray(np.asarray(drho_bar, dtype=np.float64).reshape(cfg.ncells))
+    ub = np.ascontiguousarray(np.asarray(u_bar, dtype=np.float64).reshape(3, cfg.ncells))
+    out = np.zeros((6, cfg.ncells))
+    s = cfg.c_struct()
+    _check(_tensor_load().oracle_gradient_tensor(ctypes.byref(s), _dp(_tensor_field(cfg, D6)), int(nsteps),
+                                                 int(every), _dp(db), _dp(ub), _dp(out), nthreads),
+           "gradient_tensor")
+    return out
 
 
 def _mask_load():
