@@ -262,7 +262,11 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  *   sum over those steps of (dJ/dx_t) . dC(y_t, d)/dd
  * to dJ_dd: the derivative of J with respect to d through those steps (the
  * state before them held fixed).  Explicit dependences of J on d are the
- * caller's to add.
+ * caller's to add.  With HLBM_POROSITY_TENSOR the control is the six rows
+ * xx, yy, zz, xy, xz, yz of the symmetric D in u_eq = (I - D) u, and dJ_dd
+ * holds one row of N derivatives per control row; an off-diagonal row is one
+ * variable standing at (a, b) and (b, a), so its derivative counts both
+ * places.  At D = d I the three diagonal rows sum to the scalar dJ/dd.
  *
  * The forward states are recovered from a tape: with a tape set, hlbm_step
  * stores the state every `every` steps (checkpoints); the reverse sweep
@@ -291,7 +295,8 @@ int hlbm_tape_info(const hlbm_ctx *ctx, int *every, int *max_steps, long long *r
 /* Reverse sweep over the last nsteps recorded steps (0 <= nsteps <= recorded).
  * dJ_drho[N] and dJ_du[3][N] (x fastest, u component-major as in
  * hlbm_moments; entries of solid cells are ignored) are FP64 cotangents of the
- * moments at the current time level; dJ_dd[N] (FP64) is accumulated (+=).
+ * moments at the current time level; dJ_dd (FP64) is accumulated (+=): N
+ * values for a scalar control, 6 rows of N for a tensor one.
  * All three arrays are device memory if on_device, else host memory.  The
  * current state and the step counter are unchanged.  ESTATE without a tape;
  * EINVAL for nsteps outside the recorded range or a NULL array.  Waits for

@@ -18,6 +18,10 @@ from . import hlbm as _h
 class HLBMFunction(torch.autograd.Function):
     """(drho, u) = F(d) for one context ``sim`` (an :class:`hlbm.HLBM`).
 
+    d is the scalar control (nz, ny, nx), or for a tensor-control context the
+    six rows xx, yy, zz, xy, xz, yz of D, (6, nz, ny, nx); the gradient has d's
+    shape.
+
     forward(d, sim, nsteps, every): sets the porosity, resets ``sim`` to rest,
     records a tape with a checkpoint every ``every`` steps and runs ``nsteps``
     sweeps; returns FP64 device tensors drho (nz, ny, nx) and u (3, nz, ny, nx).

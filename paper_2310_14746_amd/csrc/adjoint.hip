@@ -1,5 +1,7 @@
 // Discrete adjoint of the sweep (reverse mode) for gradients of an objective
-// of the moments with respect to the porosity control d = 1 - varpi.
+// of the moments with respect to the porosity control: d = 1 - varpi
+// (Sec. 3.2), or the six rows xx, yy, zz, xy, xz, yz of a symmetric tensor D
+// (u_eq = (I - D) u; an off-diagonal row is one variable at two places).
 //
 // One forward step is y_t = S(x_{t-1}) (pull streaming) followed by
 // x_t = C(y_t, d) (the homogenized BGK collision of Sec. 3.2, cell-local), and
@@ -30,7 +32,8 @@
 //
 // Layout: adjoint populations are rows lam[k*N + cell] (the forward state's
 // layout), FP64 for the FP64 form and FP32 for the others; all adjoint
-// arithmetic is FP64 and dJ/dd is one FP64 value per cell, accumulated.  Blocks
+// arithmetic is FP64 and dJ/dd is one FP64 value per cell and control row,
+// accumulated.  Blocks
 // hold at most 256 threads (the FP64 adjoint needs more registers than a
 // 1024-thread block leaves per thread); the launchers clamp the block width.
 #include <type_traits>
@@ -203,20 +206,103 @@ __device__ __forceinline__ void stream_adjoint_general(const LT* __restrict__ la
 }
 
 // ---------------------------------------------------------------------------
-// C^T of one fluid cell.  In: the FP64 moments of y, d, and pb = adjoint of
-// the post-collision populations.  Out: pb overwritten with the adjoint of
-// the pre-collision populations; returns this step's dJ/dd contribution.
-//   u = (j + F/2)/rho, v = (1 - d) u
+// The control in the adjoint's FP64: u_eq = M u with M = (1 - d) I (scalar) or
+// M = I - D (tensor; symmetric, so M^T = M).
+//   om_m(om, a) = omega M a
+//   grad(om, Av, u, g): g_r = omega Av . (dM/dtheta_r) u, the cotangent of
+//   control row r, with dM/dd = -I for the scalar d, -e_a e_a^T for a
+//   diagonal row and -(e_a e_b^T + e_b e_a^T) for an off-diagonal row (a, b).
+// ---------------------------------------------------------------------------
+struct AdjScalar {
+    static constexpr int rows = 1;
+    double d;
+    template <class S>
+    __device__ __forceinline__ static AdjScalar load(const typename S::D* __restrict__ f, uint32_t, uint32_t cell)
+    {
+        return AdjScalar{(double)S::load_d(ld(f, cell))};
+    }
+    __device__ __forceinline__ void eq(double ux, double uy, double uz, double& vx, double& vy, double& vz) const
+    {
+        const double sh = 1.0 - d;
+        vx = sh * ux;
+        vy = sh * uy;
+        vz = sh * uz;
+    }
+    __device__ __forceinline__ void om_m(double om, double ax, double ay, double az, double& bx, double& by,
+                                         double& bz) const
+    {
+        const double s = om * (1.0 - d);
+        bx = s * ax;
+        by = s * ay;
+        bz = s * az;
+    }
+    __device__ __forceinline__ void grad(double om, double Avx, double Avy, double Avz, double ux, double uy,
+                                         double uz, double (&g)[1]) const
+    {
+        g[0] = -om * (Avx * ux + Avy * uy + Avz * uz);
+    }
+};
+
+struct AdjTensor {
+    static constexpr int rows = 6;
+    double xx, yy, zz, xy, xz, yz;
+    template <class S>
+    __device__ __forceinline__ static AdjTensor load(const typename S::D* __restrict__ f, uint32_t N,
+                                                     uint32_t cell)
+    {
+        return AdjTensor{(double)S::load_d(ld(f, cell)),
+                         (double)S::load_d(ld(f + (size_t)N, cell)),
+                         (double)S::load_d(ld(f + 2 * (size_t)N, cell)),
+                         (double)S::load_d(ld(f + 3 * (size_t)N, cell)),
+                         (double)S::load_d(ld(f + 4 * (size_t)N, cell)),
+                         (double)S::load_d(ld(f + 5 * (size_t)N, cell))};
+    }
+    __device__ __forceinline__ void eq(double ux, double uy, double uz, double& vx, double& vy, double& vz) const
+    {
+        vx = ux - (xx * ux + xy * uy + xz * uz);
+        vy = uy - (xy * ux + yy * uy + yz * uz);
+        vz = uz - (xz * ux + yz * uy + zz * uz);
+    }
+    __device__ __forceinline__ void om_m(double om, double ax, double ay, double az, double& bx, double& by,
+                                         double& bz) const
+    {
+        double mx, my, mz;
+        eq(ax, ay, az, mx, my, mz);
+        bx = om * mx;
+        by = om * my;
+        bz = om * mz;
+    }
+    __device__ __forceinline__ void grad(double om, double Avx, double Avy, double Avz, double ux, double uy,
+                                         double uz, double (&g)[6]) const
+    {
+        g[0] = -om * (Avx * ux);
+        g[1] = -om * (Avy * uy);
+        g[2] = -om * (Avz * uz);
+        g[3] = -om * (Avx * uy + Avy * ux);
+        g[4] = -om * (Avx * uz + Avz * ux);
+        g[5] = -om * (Avy * uz + Avz * uy);
+    }
+};
+
+template <int PK>
+using AdjShift = typename std::conditional<PK == PK_TENSOR, AdjTensor, AdjScalar>::type;
+
+// ---------------------------------------------------------------------------
+// C^T of one fluid cell.  In: the FP64 moments of y, the control, and pb =
+// adjoint of the post-collision populations.  Out: pb overwritten with the
+// adjoint of the pre-collision populations, and this step's cotangent of each
+// control row in g.
+//   u = (j + F/2)/rho, v = M u
 //   dA/drho = P0 (1 - 3/2 v.v) + 3 P1.v + 9/2 v.P2.v
 //   dA/dv   = rho (3 P1 + 9 P2 v - 3 P0 v)
 //   dB/du   = (1 - 1/(2 tau)) (9 P2 F - 3 P0 F)
-//   ubar    = omega (1 - d) dA/dv + dB/du
+//   ubar    = omega M^T dA/dv + dB/du
 //   pre_k   = (1 - omega) pb_k + omega dA/drho - ubar.u/rho + c_k.ubar/rho
-//   dJ/dd  += -omega dA/dv . u
+//   g_r     = omega dA/dv . (dM/dtheta_r) u
 // ---------------------------------------------------------------------------
-template <class L>
-__device__ __forceinline__ double collide_adjoint(const Moms& m, double d, const Params& p,
-                                                  double (&pb)[L::Q])
+template <class L, class Sh>
+__device__ __forceinline__ void collide_adjoint(const Moms& m, const Sh& sh, const Params& p,
+                                                double (&pb)[L::Q], double (&g)[Sh::rows])
 {
     const double om = p.omega, pref = p.pref;
     const double F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
@@ -224,8 +310,8 @@ __device__ __forceinline__ double collide_adjoint(const Moms& m, double d, const
     const double ux = (m.jx + 0.5 * F0) * inv_rho;
     const double uy = (m.jy + 0.5 * F1) * inv_rho;
     const double uz = (m.jz + 0.5 * F2) * inv_rho;
-    const double sh = 1.0 - d;
-    const double vx = sh * ux, vy = sh * uy, vz = sh * uz;
+    double vx, vy, vz;
+    sh.eq(ux, uy, uz, vx, vy, vz);
     double P0 = 0.0, Px = 0.0, Py = 0.0, Pz = 0.0;
     double Pxx = 0.0, Pyy = 0.0, Pzz = 0.0, Pxy = 0.0, Pxz = 0.0, Pyz = 0.0;
 #pragma unroll
@@ -254,23 +340,26 @@ __device__ __forceinline__ double collide_adjoint(const Moms& m, double d, const
     const double PFx = Pxx * F0 + Pxy * F1 + Pxz * F2;
     const double PFy = Pxy * F0 + Pyy * F1 + Pyz * F2;
     const double PFz = Pxz * F0 + Pyz * F1 + Pzz * F2;
-    const double ubx = om * sh * Avx + pref * (9.0 * PFx - 3.0 * F0 * P0);
-    const double uby = om * sh * Avy + pref * (9.0 * PFy - 3.0 * F1 * P0);
-    const double ubz = om * sh * Avz + pref * (9.0 * PFz - 3.0 * F2 * P0);
+    double mAx, mAy, mAz;
+    sh.om_m(om, Avx, Avy, Avz, mAx, mAy, mAz);
+    const double ubx = mAx + pref * (9.0 * PFx - 3.0 * F0 * P0);
+    const double uby = mAy + pref * (9.0 * PFy - 3.0 * F1 * P0);
+    const double ubz = mAz + pref * (9.0 * PFz - 3.0 * F2 * P0);
     const double rbar = om * A_rho - (ubx * ux + uby * uy + ubz * uz) * inv_rho;
     const double jbx = ubx * inv_rho, jby = uby * inv_rho, jbz = ubz * inv_rho;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k)
         pb[k] = (1.0 - om) * pb[k] + rbar + double(L::cx[k]) * jbx + double(L::cy[k]) * jby +
                 double(L::cz[k]) * jbz;
-    return -om * (Avx * ux + Avy * uy + Avz * uz);
+    sh.grad(om, Avx, Avy, Avz, ux, uy, uz, g);
 }
 
 // ---------------------------------------------------------------------------
 // One reverse step t: lam_out = lambda_t from lam_in = lambda_{t+1}, with the
-// forward state x_{t-1} in `xprev`; dbar += this step's dJ/dd.
+// forward state x_{t-1} in `xprev`; each control row of dbar += this step's
+// cotangent of that row.
 // ---------------------------------------------------------------------------
-template <class L, class S, int BC>
+template <class L, class S, int BC, int PK>
 __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in, LamT<S>* __restrict__ lam_out,
                                              const typename S::T* __restrict__ xprev,
                                              const typename S::D* __restrict__ dfield, double* __restrict__ dbar,
@@ -279,7 +368,8 @@ __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in,
     const uint32_t N = p.N;
     const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
     const Moms m = forward_moments<L, S, BC>(xprev, p, x, y, z);
-    const double d = (double)S::load_d(ld(dfield, cell));
+    using Sh = AdjShift<PK>;
+    const Sh sh = Sh::template load<S>(dfield, N, cell);
     double pb[L::Q];
     bool solid = false;
     if (BC == BC_PERIODIC) {
@@ -287,22 +377,28 @@ __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in,
     } else {
         // post-collision moments of this cell at step t (balance laws)
         const double rho = p.rho0 + m.s, inv_rho = 1.0 / rho;
-        const double om = p.omega, sh = 1.0 - d;
-        const double jbx = (1.0 - om) * m.jx + om * sh * (m.jx + 0.5 * p.F[0]) + p.pref * p.F[0];
-        const double jby = (1.0 - om) * m.jy + om * sh * (m.jy + 0.5 * p.F[1]) + p.pref * p.F[1];
-        const double jbz = (1.0 - om) * m.jz + om * sh * (m.jz + 0.5 * p.F[2]) + p.pref * p.F[2];
+        const double om = p.omega;
+        double rvx, rvy, rvz;  // omega rho u_eq = omega M (j + F/2)
+        sh.om_m(om, m.jx + 0.5 * p.F[0], m.jy + 0.5 * p.F[1], m.jz + 0.5 * p.F[2], rvx, rvy, rvz);
+        const double jbx = (1.0 - om) * m.jx + rvx + p.pref * p.F[0];
+        const double jby = (1.0 - om) * m.jy + rvy + p.pref * p.F[1];
+        const double jbz = (1.0 - om) * m.jz + rvz + p.pref * p.F[2];
         stream_adjoint_general<L, LamT<S>>(lam_in, N, p, (int)x, (int)y, (int)z, rho, jbx * inv_rho,
                                   jby * inv_rho, jbz * inv_rho, pb);
         solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
     }
-    const double dd = collide_adjoint<L>(m, d, p, pb);
+    double g[Sh::rows];
+    collide_adjoint<L>(m, sh, p, pb, g);
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) st(lam_out + (size_t)k * N, cell, LamT<S>(sel(solid, 0.0, pb[k])));
-    const double acc = ld(dbar, cell);
-    st(dbar, cell, acc + sel(solid, 0.0, dd));
+#pragma unroll
+    for (int r = 0; r < Sh::rows; ++r) {
+        const double acc = ld(dbar + (size_t)r * N, cell);
+        st(dbar + (size_t)r * N, cell, acc + sel(solid, 0.0, g[r]));
+    }
 }
 
-template <class L, class S, int BC>
+template <class L, class S, int BC, int PK>
 __global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict__ lam_in,
                                                        LamT<S>* __restrict__ lam_out,
                                                        const typename S::T* __restrict__ xprev,
@@ -311,7 +407,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict_
 {
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)p.nx) return;
-    adjoint_cell<L, S, BC>(lam_in, lam_out, xprev, dfield, dbar, p, x, blockIdx.y, blockIdx.z);
+    adjoint_cell<L, S, BC, PK>(lam_in, lam_out, xprev, dfield, dbar, p, x, blockIdx.y, blockIdx.z);
 }
 
 // Interior and shell of a box with walls or open faces (see Split), in one
@@ -320,7 +416,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict_
 // rule.  The choice is uniform per block.  The shell's blocks come first:
 // they are the slow ones, and blocks start in index order, so the interior
 // blocks fill in behind them instead of leaving them as the tail.
-template <class L, class S>
+template <class L, class S, int PK>
 __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __restrict__ lam_in,
                                                              LamT<S>* __restrict__ lam_out,
                                                              const typename S::T* __restrict__ xprev,
@@ -333,7 +429,7 @@ __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __res
         if (k >= sp.n_shell) return;
         uint32_t x, y, z;
         shell_cell(sp, (uint32_t)p.nx, (uint32_t)p.ny, k, x, y, z);
-        adjoint_cell<L, S, BC_GENERAL>(lam_in, lam_out, xprev, dfield, dbar, p, x, y, z);
+        adjoint_cell<L, S, BC_GENERAL, PK>(lam_in, lam_out, xprev, dfield, dbar, p, x, y, z);
     } else {
         const uint32_t bi = b - sp.blocks_shell;
         const uint32_t row = bi / sp.gx, bxi = bi - row * sp.gx;
@@ -341,7 +437,7 @@ __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __res
         const uint32_t zz = row / iy, yy = row - zz * iy;
         const uint32_t x = sp.lo[0] + bxi * blockDim.x + threadIdx.x;
         if (x >= sp.hi[0]) return;
-        adjoint_cell<L, S, BC_PERIODIC>(lam_in, lam_out, xprev, dfield, dbar, p, x, sp.lo[1] + yy, sp.lo[2] + zz);
+        adjoint_cell<L, S, BC_PERIODIC, PK>(lam_in, lam_out, xprev, dfield, dbar, p, x, sp.lo[1] + yy, sp.lo[2] + zz);
     }
 }
 
@@ -363,7 +459,7 @@ static hipError_t seed_dispatch_bc(int bcmode, const Params& p, const void* src,
     return hipGetLastError();
 }
 
-template <class L, class S>
+template <class L, class S, int PK>
 static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* lam_in, void* lam_out,
                                       const void* xprev, const void* dfield, double* dbar, int bx,
                                       hipStream_t s)
@@ -374,15 +470,15 @@ static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* l
     auto* li = static_cast<const LamT<S>*>(lam_in);
     auto* lo = static_cast<LamT<S>*>(lam_out);
     if (bcmode == BC_PERIODIC) {
-        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC>), l.grid, l.block, 0, s, li, lo, a, d, dbar, p);
+        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, li, lo, a, d, dbar, p);
         return hipGetLastError();
     }
     const Split sp = split_of(p, (int)l.block.x);
     if (!sp.interior()) {
-        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL>), l.grid, l.block, 0, s, li, lo, a, d, dbar, p);
+        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL, PK>), l.grid, l.block, 0, s, li, lo, a, d, dbar, p);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((adjoint_split_kernel<L, S>), dim3(sp.blocks_in + sp.blocks_shell), l.block, 0, s, li, lo, a,
+    hipLaunchKernelGGL((adjoint_split_kernel<L, S, PK>), dim3(sp.blocks_in + sp.blocks_shell), l.block, 0, s, li, lo, a,
                        d, dbar, p, sp);
     return hipGetLastError();
 }
@@ -401,20 +497,20 @@ static hipError_t seed_dispatch_store(int storage, int bcmode, const Params& p, 
     }
 }
 
-template <class L>
+template <class L, int PK>
 static hipError_t adjoint_dispatch_store(int storage, int bcmode, const Params& p, const void* lam_in,
                                          void* lam_out, const void* xprev, const void* dfield,
                                          double* dbar, int bx, hipStream_t s)
 {
     switch (storage) {
     case StoreF64::code:
-        return adjoint_dispatch_bc<L, StoreF64>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+        return adjoint_dispatch_bc<L, StoreF64, PK>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
     case StoreF32::code:
-        return adjoint_dispatch_bc<L, StoreF32>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+        return adjoint_dispatch_bc<L, StoreF32, PK>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
     case StoreF16S::code:
-        return adjoint_dispatch_bc<L, StoreF16S>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+        return adjoint_dispatch_bc<L, StoreF16S, PK>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
     case StoreBF16S::code:
-        return adjoint_dispatch_bc<L, StoreBF16S>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+        return adjoint_dispatch_bc<L, StoreBF16S, PK>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -428,13 +524,18 @@ hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_adjoint(int q, int storage, int bcmode, const Params& p, const void* lam_in,
+hipError_t launch_adjoint(int q, int storage, int bcmode, int pk, const Params& p, const void* lam_in,
                           void* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
                           hipStream_t s)
 {
-    if (q == 9) return adjoint_dispatch_store<D2Q9>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
-    if (q == 19)
-        return adjoint_dispatch_store<D3Q19>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+    if (q == 9 && pk == PK_SCALAR)
+        return adjoint_dispatch_store<D2Q9, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+    if (q == 19 && pk == PK_SCALAR)
+        return adjoint_dispatch_store<D3Q19, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx,
+                                                        s);
+    if (q == 19 && pk == PK_TENSOR)
+        return adjoint_dispatch_store<D3Q19, PK_TENSOR>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx,
+                                                        s);
     return hipErrorInvalidValue;
 }
 

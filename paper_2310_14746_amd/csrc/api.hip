@@ -849,8 +849,6 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (c->batch) return fail(HLBM_EUNSUPPORTED, "a batch has no adjoint");
-    if (c->cfg.porosity_kind != HLBM_POROSITY_SCALAR)
-        return fail(HLBM_EUNSUPPORTED, "the adjoint differentiates a scalar porosity control");
     if (c->bcmode == hlbm::BC_MASKED)
         return fail(HLBM_EUNSUPPORTED, "the adjoint does not cover resolved solid cells");
     if (c->aa) return fail(HLBM_EUNSUPPORTED, "the adjoint tape needs the two-buffer pattern (HLBM_AB)");
@@ -910,24 +908,26 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
     if (nsteps < 0 || nsteps > R0)
         return fail(HLBM_EINVAL, "nsteps must be in [0, %lld] (steps recorded on the tape)", R0);
     const size_t n = c->p.N;
+    const size_t rows = porosity_rows(&c->cfg);  // rows of the gradient: 1 scalar, 6 tensor
     const double* gr = dJ_drho;
     const double* gu = dJ_du;
     double* gd = dJ_dd;
     void* tmp = nullptr;
     hipError_t e = hipSuccess;
     if (!on_device) {
-        e = hipMalloc(&tmp, 5 * n * sizeof(double));
+        e = hipMalloc(&tmp, (4 + rows) * n * sizeof(double));
         if (e != hipSuccess) return fail(HLBM_ENOMEM, "staging allocation: %s", hipGetErrorString(e));
         double* t = static_cast<double*>(tmp);
         e = hipMemcpyAsync(t, dJ_drho, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(t + n, dJ_du, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(t + 4 * n, dJ_dd, n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(t + 4 * n, dJ_dd, rows * n * sizeof(double), hipMemcpyHostToDevice, c->stream);
         gr = t;
         gu = t + n;
         gd = t + 4 * n;
     }
     const int K = c->tape_every;
-    const int q = c->q, storage = c->cfg.storage, bc = c->bcmode;
+    const int q = c->q, storage = c->cfg.storage, bc = c->bcmode, pk = c->cfg.porosity_kind;
     // state with index r (relative to the tape origin) of the replayed segment
     auto seg_state = [&](long long r) -> const void* {
         const long long m = r / K, j = r - m * K;
@@ -946,17 +946,17 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
             // replay segment m from its checkpoint up to the last state needed
             const long long jmax = (r - m * K);
             for (long long j = 1; j <= jmax && e == hipSuccess; ++j)
-                e = hlbm::launch_sweep(q, storage, bc, hlbm::PK_SCALAR, c->p, seg_state(m * K + j - 1),
+                e = hlbm::launch_sweep(q, storage, bc, pk, c->p, seg_state(m * K + j - 1),
                                        const_cast<void*>(seg_state(m * K + j)), c->dfield, c->bx, c->stream);
             seg_loaded = m;
         }
         if (e == hipSuccess)
-            e = hlbm::launch_adjoint(q, storage, bc, c->p, c->tape_lam[a], c->tape_lam[a ^ 1], seg_state(r),
+            e = hlbm::launch_adjoint(q, storage, bc, pk, c->p, c->tape_lam[a], c->tape_lam[a ^ 1], seg_state(r),
                                      c->dfield, gd, c->bx, c->stream);
         a ^= 1;
     }
     if (e == hipSuccess && tmp)
-        e = hipMemcpyAsync(dJ_dd, gd, n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        e = hipMemcpyAsync(dJ_dd, gd, rows * n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (tmp) (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(e, "adjoint");

@@ -135,7 +135,8 @@ inline size_t adjoint_elem_bytes(int storage) { return storage == 0 ? 8 : 4; }
 hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, const void* src,
                                const double* drho_bar, const double* u_bar, void* lam, int bx,
                                hipStream_t s);
-hipError_t launch_adjoint(int q, int storage, int bcmode, const Params& p, const void* lam_in,
+// dbar holds one row of N values per row of the control (1 scalar, 6 tensor).
+hipError_t launch_adjoint(int q, int storage, int bcmode, int pk, const Params& p, const void* lam_in,
                           void* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
                           hipStream_t s);
 // Fixed-order two-pass sum of `nblocks` partials of 4 doubles into out[4];

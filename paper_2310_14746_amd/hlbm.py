@@ -368,20 +368,22 @@ class HLBM:
 
         drho_bar (N values) and u_bar (3*N values) are the cotangents of the
         current moments (shapes as returned by :meth:`moments`); returns d_bar
-        (FP64 device tensor shaped (nz, ny, nx)) with dJ/dd through those
+        (FP64 device tensor shaped (nz, ny, nx), or (6, nz, ny, nx) for a
+        tensor control: rows xx, yy, zz, xy, xz, yz) with dJ/dd through those
         steps added to `d_bar` if given (else to zeros).
         """
         t = self.torch
         nx, ny, nz = self.shape
+        rows = self.porosity_rows
         gr = t.as_tensor(drho_bar, dtype=t.float64, device=self.device).contiguous()
         gu = t.as_tensor(u_bar, dtype=t.float64, device=self.device).contiguous()
         if gr.numel() != self.N or gu.numel() != 3 * self.N:
             raise ValueError("cotangents need N and 3*N values")
         if d_bar is None:
-            d_bar = t.zeros((nz, ny, nx), dtype=t.float64, device=self.device)
+            d_bar = t.zeros(((rows,) if rows > 1 else ()) + (nz, ny, nx), dtype=t.float64, device=self.device)
         elif not (d_bar.dtype == t.float64 and d_bar.is_cuda and d_bar.is_contiguous()
-                  and d_bar.numel() == self.N):
-            raise ValueError("d_bar must be a contiguous FP64 device tensor of N values")
+                  and d_bar.numel() == rows * self.N):
+            raise ValueError(f"d_bar must be a contiguous FP64 device tensor of {rows}*N values")
         _check(load().hlbm_adjoint_step(self.ctx, int(nsteps), gr.data_ptr(), gu.data_ptr(),
                                         d_bar.data_ptr(), 1))
         return d_bar

@@ -60,7 +60,9 @@ def test_in_place_kernels_are_straight_line(asm):
 
 def test_adjoint_kernels_are_straight_line(asm):
     kern = {**_kernels(asm, "_ZN4hlbm14adjoint_kernel"), **_kernels(asm, "_ZN4hlbm19adjoint_seed_kernel")}
-    assert len(kern) == 32
+    # reverse step: (2 lattices x 4 storages scalar + 4 storages tensor) x 2 boundary modes;
+    # seed: 2 lattices x 4 storages x 2 boundary modes
+    assert len(kern) == 24 + 16
     for name, body in kern.items():
         branches = len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
         assert branches <= 1, (name, branches)
@@ -70,6 +72,7 @@ def test_no_private_memory_in_sweep_and_moments(asm):
     for name, body in {**_kernels(asm, "_ZN4hlbm12sweep_kernel"),
                        **_kernels(asm, "_ZN4hlbm14moments_kernel"),
                        **_kernels(asm, "_ZN4hlbm14adjoint_kernel"),
+                       **_kernels(asm, "_ZN4hlbm20adjoint_split_kernel"),
                        **_kernels(asm, "_ZN4hlbm17sweep_pair_kernel"),
                        **_kernels(asm, "_ZN4hlbm15sweep_aa_kernel"),
                        **_kernels(asm, "_ZN4hlbm20sweep_aa_diag_kernel"),

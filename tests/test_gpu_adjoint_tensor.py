@@ -1,0 +1,160 @@
+"""GPU discrete adjoint with the tensor control u_eq = (I - D) u, against the
+oracle's tensor adjoint (explicit 19x19 and 19x6 Jacobians).
+
+The gradient has six rows (xx, yy, zz, xy, xz, yz) of N values.
+
+* FP64 storage: relative L2 1e-10 per row over periodic boxes, walls, open
+  faces (the split launch with an interior), several checkpoint spacings and a
+  single step.
+* FP32 and FP16S storage (FP64 adjoint arithmetic): relative L2 1e-3 and 2e-3
+  over all six rows, the forward's own storage error.
+* At D = d I the diagonal rows of the GPU tensor gradient sum to the GPU scalar
+  gradient of the same run.
+* Through torch.autograd: the gradient of a linear functional of the moments
+  with respect to a (6, nz, ny, nx) control equals the oracle's.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleConfig
+from paper_2310_14746_amd import inputs
+from tests.test_gpu_parity import H, say, smooth_noise  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+NT = max(1, min(16, os.cpu_count() or 1))
+
+
+def _rel(x, y):
+    return float(np.linalg.norm(x - y) / np.linalg.norm(y))
+
+
+def _cotangents(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n), rng.standard_normal((3, n))
+
+
+def _control(shape, seed, dt="f64"):
+    nx, ny, nz = shape
+    # eigenvalues kept inside [0.01, 0.99], clear of the bounds after rounding
+    D6 = 0.98 * inputs.random_tensor_field((nz, ny, nx), seed=seed)
+    D6[:3] += 0.01
+    return inputs.round_to(D6, dt).reshape(6, -1)
+
+
+CASES = [
+    # shape, tau, force, bc_lo, bc_hi, inlet_u, steps, every
+    ((30, 9, 7), 0.7, (2e-5, -7e-6, 3e-6), (0, 0, 0), (0, 0, 0), (0, 0, 0), 25, 1),
+    ((13, 9, 8), 0.6, (1e-5, 0, 0), (0, 1, 1), (0, 1, 1), (0, 0, 0), 20, 6),
+    ((40, 12, 10), 0.6, (0, 0, 0), (2, 1, 1), (3, 1, 1), (0.02, 0, 0), 30, 50),
+    ((10, 10, 9), 0.8, (1e-5, 0, 0), (1, 2, 1), (1, 3, 1), (0, 0.01, 0), 24, 7),
+    ((16, 8, 8), 0.7, (1e-5, 2e-6, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0), 1, 3),
+]
+
+
+def _ids(c):
+    return f"{c[0][0]}x{c[0][1]}x{c[0][2]}-lo{''.join(map(str, c[3]))}-T{c[6]}-K{c[7]}"
+
+
+def _gpu_gradient(H, storage, shape, tau, F, lo, hi, inu, steps, every, D6, a, b, store_scale=1.0):
+    sim = H.HLBM(19, storage, shape, tau=tau, force=F, bc_lo=lo, bc_hi=hi, inlet_u=inu,
+                 porosity="tensor", store_scale=store_scale)
+    try:
+        sim.set_porosity(D6)
+        sim.set_tape(every, steps)
+        sim.step(steps)
+        st0, s0 = sim.get_state()
+        g = sim.adjoint(steps, a, b)
+        assert tuple(g.shape) == (6,) + tuple(reversed(shape))
+        st1, s1 = sim.get_state()
+        assert s0 == s1 == steps and bool((st0 == st1).all())
+        return g.cpu().numpy().reshape(6, -1)
+    finally:
+        sim.close()
+
+
+def _oracle(shape, tau, F, lo, hi, inu, steps, every, D6, a, b):
+    nx, ny, nz = shape
+    cfg = OracleConfig(q=19, nx=nx, ny=ny, nz=nz, tau=tau, force=F, bc_lo=lo, bc_hi=hi, inlet_u=inu)
+    return cfg, oracle.gradient_tensor(cfg, D6, steps, a, b, every=max(1, every), nthreads=NT)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_ids(c) for c in CASES])
+def test_tensor_adjoint_f64_matches_oracle(H, case):
+    shape, tau, F, lo, hi, inu, steps, every = case
+    say(f"tensor adjoint f64 {_ids(case)}")
+    D6 = _control(shape, seed=sum(shape))
+    a, b = _cotangents(int(np.prod(shape)), seed=steps)
+    g = _gpu_gradient(H, "f64", shape, tau, F, lo, hi, inu, steps, every, D6, a, b)
+    cfg, go = _oracle(shape, tau, F, lo, hi, inu, steps, every, D6, a, b)
+    # a row the oracle gives as exactly zero (u_z = 0 from rest with F_z = 0
+    # zeroes dJ/dD_zz after one step) must be exactly zero here too
+    errs = [_rel(g[r], go[r]) if np.any(go[r]) else float(np.abs(g[r]).max()) for r in range(6)]
+    say("rel-L2 per row " + " ".join(f"{e:.1e}" for e in errs))
+    assert all(e <= 1e-10 for e in errs)
+    assert all(np.any(go[r]) or not np.any(g[r]) for r in range(6))
+    assert (g[:, cfg.solid_mask().ravel()] == 0).all()
+
+
+@pytest.mark.parametrize("storage,dt,bar,scale", [("f32", "f32", 1e-3, 1.0), ("f16s", "f16", 2e-3, 2.0 ** 16)])
+def test_tensor_adjoint_stored_forward_vs_oracle(H, storage, dt, bar, scale):
+    shape, tau, F, lo, hi, inu, steps, every = CASES[2]
+    say(f"tensor adjoint {storage} forward, 40x12x10 channel, {steps} steps")
+    D6 = _control(shape, seed=3, dt=dt)
+    a, b = _cotangents(int(np.prod(shape)), seed=9)
+    npt = {"f32": np.float32, "f16": np.float16}[dt]
+    g = _gpu_gradient(H, storage, shape, tau, F, lo, hi, inu, steps, 8, D6.astype(npt), a, b, store_scale=scale)
+    _, go = _oracle(shape, tau, F, lo, hi, inu, steps, 8, D6, a, b)
+    err = _rel(g, go)
+    say(f"rel-L2 {err:.2e}")
+    assert err <= bar
+
+
+def test_isotropic_tensor_gradient_equals_scalar_on_gpu(H):
+    shape, tau, F, lo, hi, inu, steps, every = CASES[2]
+    nx, ny, nz = shape
+    say("tensor adjoint at D = d I vs scalar adjoint, f64")
+    d = smooth_noise((nz, ny, nx), seed=21).ravel()
+    D6 = np.zeros((6, d.size))
+    D6[:3] = d
+    a, b = _cotangents(d.size, seed=22)
+    gt = _gpu_gradient(H, "f64", shape, tau, F, lo, hi, inu, steps, 6, D6, a, b)
+    sim = H.HLBM(19, "f64", shape, tau=tau, force=F, bc_lo=lo, bc_hi=hi, inlet_u=inu)
+    try:
+        sim.set_porosity(d)
+        sim.set_tape(6, steps)
+        sim.step(steps)
+        gs = sim.adjoint(steps, a, b).cpu().numpy().ravel()
+    finally:
+        sim.close()
+    err = _rel(gt[:3].sum(axis=0), gs)
+    say(f"rel-L2 {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_tensor_autograd_vs_oracle(H):
+    import torch
+    from paper_2310_14746_amd.autograd import moments_of_porosity
+    shape, tau, F, lo, hi, inu, steps, every = CASES[3]
+    nx, ny, nz = shape
+    say(f"tensor control through torch.autograd {shape}, {steps} steps")
+    D6 = _control(shape, seed=31)
+    a, b = _cotangents(nx * ny * nz, seed=32)
+    sim = H.HLBM(19, "f64", shape, tau=tau, force=F, bc_lo=lo, bc_hi=hi, inlet_u=inu, porosity="tensor")
+    try:
+        Dt = torch.tensor(D6.reshape(6, nz, ny, nx), dtype=torch.float64, device=sim.device, requires_grad=True)
+        drho, u = moments_of_porosity(Dt, sim, steps, every)
+        at = torch.as_tensor(a.reshape(nz, ny, nx), device=sim.device)
+        bt = torch.as_tensor(b.reshape(3, nz, ny, nx), device=sim.device)
+        J = (at * drho).sum() + (bt * u).sum()
+        J.backward()
+        g = Dt.grad.detach().cpu().numpy().reshape(6, -1)
+    finally:
+        sim.close()
+    _, go = _oracle(shape, tau, F, lo, hi, inu, steps, every, D6, a, b)
+    err = _rel(g, go)
+    say(f"rel-L2 {err:.2e}")
+    assert err <= 1e-10
