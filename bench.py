@@ -308,6 +308,7 @@ def time_batched(hlbm, steps=2000, seed=0):
 
 
 ADJ_BYTES = 19 * 4 * 2 + 19 * 4 + 4 + 16  # adjoint kernel, FP32 form: lam in/out, x, d, dJ/dd r+w
+ADJT_BYTES = 19 * 4 * 2 + 19 * 4 + 6 * 4 + 6 * 16  # tensor control: six rows of D and of dJ/dD
 
 
 def time_gradient(hlbm, steps=500, every=50, seed=0):
@@ -381,19 +382,26 @@ def time_tensor(hlbm, steps, warmup, block_x):
             "rel_l2_drho_vs_fp64": float("%.3e" % rel_l2_drho(dr, dr_o, u_o))}
 
 
-def time_adjoint_large(hlbm, edge=256, steps=40, every=10):
+def time_adjoint_large(hlbm, edge=256, steps=40, every=10, porosity="scalar"):
     """Reverse sweep on a large periodic box (the sphere array, FP32 forward,
     FP32 adjoint populations, FP64 gradient): time of hlbm_adjoint_step over
     `steps` steps, which also replays the forward inside each checkpoint
     segment.  Shows the adjoint kernel away from the small-domain limits of the
-    128x64x64 workload."""
+    128x64x64 workload.  porosity="tensor": the fibre tensor of the same array
+    (six gradient rows)."""
     import torch
     from paper_2310_14746_amd import inputs
-    tile = inputs.round_to(inputs.sphere_array_tile(), "f32").astype(np.float32)
     reps = edge // 32
-    sim = hlbm.HLBM(hlbm.D3Q19, "f32", (edge,) * 3, tau=TAU, force=FORCE)
+    tensor = porosity == "tensor"
+    if tensor:
+        tile = inputs.fiber_tensor_field(inputs.sphere_array_tile()).reshape(6, 32, 32, 32)
+        field = np.tile(tile, (1, reps, reps, reps))
+    else:
+        field = np.tile(inputs.sphere_array_tile(), (reps, reps, reps))
+    field = inputs.round_to(field, "f32").astype(np.float32)
+    sim = hlbm.HLBM(hlbm.D3Q19, "f32", (edge,) * 3, tau=TAU, force=FORCE, porosity=porosity)
     try:
-        sim.set_porosity(np.tile(tile, (reps, reps, reps)))
+        sim.set_porosity(field)
         sim.set_tape(every, steps)
         sim.step(steps)
         n = edge ** 3
@@ -412,8 +420,10 @@ def time_adjoint_large(hlbm, edge=256, steps=40, every=10):
     finally:
         sim.close()
     replays = steps - (steps + every - 1) // every
-    moved = edge ** 3 * (steps * ADJ_BYTES + replays * 156)
-    return {"workload": f"D3Q19 {edge}^3 periodic sphere array, {steps} reverse steps, checkpoint every {every}",
+    adj, fwd = (ADJT_BYTES, TENSOR_BYTES) if tensor else (ADJ_BYTES, 156)
+    moved = edge ** 3 * (steps * adj + replays * fwd)
+    what = "periodic sphere array with the fibre tensor" if tensor else "periodic sphere array"
+    return {"workload": f"D3Q19 {edge}^3 {what}, {steps} reverse steps, checkpoint every {every}",
             "ms": round(ms, 2), "ms_per_reverse_step": round(ms / steps, 4),
             "alg_GBs": round(moved / (ms * 1e-3) / 1e9, 1), "replay_steps": replays}
 
@@ -527,6 +537,7 @@ def main():
     gradient = None if args.no_gradient else time_gradient(hlbm)
     if gradient is not None:
         gradient["large_periodic"] = time_adjoint_large(hlbm)
+        gradient["large_periodic_tensor"] = time_adjoint_large(hlbm, porosity="tensor")
     c1 = None if args.no_c1 else time_c1(hlbm, tune.lookup(hlbm.D3Q19, "f32", (256,) * 3))
     tensor = None if args.no_tensor else time_tensor(
         hlbm, args.steps, args.warmup, args.block_x if args.block_x >= 0 else tune.lookup(hlbm.D3Q19, "f32", (N_EDGE,) * 3))
