@@ -106,10 +106,11 @@ __global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* 
     const double ux = (m.jx + 0.5 * p.F[0]) * inv_rho;
     const double uy = (m.jy + 0.5 * p.F[1]) * inv_rho;
     const double uz = (m.jz + 0.5 * p.F[2]) * inv_rho;
-    const double rb = ld(drho_bar, cell);
-    const double bx = ld(u_bar, cell) * inv_rho;
-    const double by = ld(u_bar + N, cell) * inv_rho;
-    const double bz = ld(u_bar + 2 * (size_t)N, cell) * inv_rho;
+    // FP64 rows of N values can pass 4 GiB: 64-bit indexing
+    const double rb = drho_bar[cell];
+    const double bx = u_bar[cell] * inv_rho;
+    const double by = u_bar[(size_t)N + cell] * inv_rho;
+    const double bz = u_bar[2 * (size_t)N + cell] * inv_rho;
     const double base = rb - (bx * ux + by * uy + bz * uz);
     bool solid = false;
     if (BC != BC_PERIODIC) solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
@@ -393,8 +394,9 @@ __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in,
     for (int k = 0; k < L::Q; ++k) st(lam_out + (size_t)k * N, cell, LamT<S>(sel(solid, 0.0, pb[k])));
 #pragma unroll
     for (int r = 0; r < Sh::rows; ++r) {
-        const double acc = ld(dbar + (size_t)r * N, cell);
-        st(dbar + (size_t)r * N, cell, acc + sel(solid, 0.0, g[r]));
+        // FP64 gradient rows can pass 4 GiB: 64-bit indexing
+        double* const at = dbar + (size_t)r * N + cell;
+        *at = *at + sel(solid, 0.0, g[r]);
     }
 }
 

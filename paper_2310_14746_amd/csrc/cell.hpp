@@ -15,9 +15,13 @@
 namespace hlbm {
 
 // Element `idx` of a population row addressed by a 32-bit byte offset from a
-// uniform base.  The host guarantees N * sizeof(T) < 2^32, so the offset cannot
-// wrap; this lets every access use the scalar-base + 32-bit vector-offset
-// form of global loads and stores.
+// uniform base.  The host guarantees N * sizeof(T) < 2^32 for the rows these
+// helpers index: populations in their storage type, porosity rows (never wider
+// than the storage element) and adjoint population rows.  The offset cannot
+// wrap, and every access can use the scalar-base + 32-bit vector-offset form
+// of global loads and stores.  Per-cell arrays that may be wider (the link
+// mask under 16-bit storage, the adjoint's FP64 cotangents and gradient, FP64
+// moments) are indexed with ordinary 64-bit pointer arithmetic instead.
 template <class T>
 __device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t idx)
 {
@@ -450,7 +454,7 @@ __device__ __forceinline__ bool gather_masked(const typename S::T* __restrict__ 
                                               typename S::R (&g)[L::Q])
 {
     const uint32_t cell = x + nx * (y + ny * z);
-    const uint32_t lm = ld(linkmask, cell);
+    const uint32_t lm = linkmask[cell];  // 4 B per cell: may pass 4 GiB under 16-bit storage
     const uint32_t xs[3] = {x + 1 == nx ? 0u : x + 1, x, x == 0 ? nx - 1 : x - 1};
     const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
     const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};

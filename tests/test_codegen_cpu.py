@@ -17,6 +17,8 @@ import pytest
 
 from paper_2310_14746_amd import build as hbuild
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
 
 @pytest.fixture(scope="module")
 def asm():
@@ -137,3 +139,24 @@ def test_barrier_polling_keeps_caches(asm):
         assert any(re.match(r"global_load_dword v\d+, v\d+, s\[\d+:\d+\] sc1", l) for l in window), name
         # and an acquire (invalidate) follows the barrier somewhere in the kernel
         assert any(l.startswith("buffer_inv sc1") for l in lines), name
+
+
+def test_32bit_offset_helpers_only_index_bounded_rows():
+    """ld/st/st_stream form a 32-bit byte offset, which is exact only for rows
+    the host bounds below 4 GiB: populations, porosity rows and adjoint
+    population rows.  Wider per-cell arrays (FP64 cotangents and gradients,
+    the link mask, moments outputs) must use 64-bit indexing, so every call
+    of the helpers names one of the bounded arrays."""
+    import glob
+    bounded = {"src", "dst", "dfield", "f", "lam", "lam_in", "lam_out", "row", "out"}
+    seen = set()
+    for path in glob.glob(os.path.join(ROOT, "paper_2310_14746_amd", "csrc", "*.hip")) + \
+            glob.glob(os.path.join(ROOT, "paper_2310_14746_amd", "csrc", "*.hpp")):
+        text = open(path).read()
+        for m in re.finditer(r"\b(ld|st|st_stream)\(\s*([A-Za-z_]\w*)", text):
+            name = m.group(2)
+            if name in ("const", "T"):          # the helpers' own definitions
+                continue
+            seen.add(name)
+            assert name in bounded, (os.path.basename(path), m.group(0))
+    assert {"src", "dst", "dfield", "lam"} <= seen
