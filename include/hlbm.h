@@ -193,7 +193,8 @@ int hlbm_state_bytes(const hlbm_ctx *ctx, size_t *bytes);
 
 /* Copy the current post-collision populations (storage element type, library
  * population order, g[i*N + cell]) to `dst` (device if on_device) and the step
- * counter to *step (may be NULL).  Waits for the stream. */
+ * counter to *step (may be NULL).  A device dst must not overlap the buffer
+ * that holds the current state, else EINVAL.  Waits for the stream. */
 int hlbm_get_state(hlbm_ctx *ctx, void *dst, int on_device, long long *step);
 /* (HLBM_AA: the state is converted to the AB layout by a copy kernel; a device
  * dst must not overlap the population buffer, else EINVAL; a host dst may take
@@ -203,7 +204,8 @@ int hlbm_get_state(hlbm_ctx *ctx, void *dst, int on_device, long long *step);
 
 /* Replace the current state by a snapshot taken with hlbm_get_state and set
  * the step counter.  Resuming from a snapshot reproduces the original run
- * bit for bit.  Waits for the stream. */
+ * bit for bit.  A device src must not overlap the buffer that holds the
+ * current state, else EINVAL.  Waits for the stream. */
 int hlbm_set_state(hlbm_ctx *ctx, const void *src, int on_device, long long step);
 
 /* Reset to rest (g = 0) and step 0; the porosity field is kept. */

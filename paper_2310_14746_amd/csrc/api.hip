@@ -115,6 +115,14 @@ bool is_pow2(double s)
     return m == 0.5;
 }
 
+// True when the byte ranges [a, a + n) and [b, b + n) share a byte.
+bool overlaps(const void* a, const void* b, size_t n)
+{
+    const char* x = static_cast<const char*>(a);
+    const char* y = static_cast<const char*>(b);
+    return x < y + n && y < x + n;
+}
+
 size_t elem_bytes(int storage)
 {
     switch (storage) {
@@ -266,11 +274,8 @@ int aa_get_state(hlbm_ctx* c, void* dst, int on_device, long long* step)
             e = hipMalloc(&tmp, c->pop_bytes);
             if (e != hipSuccess) return fail(HLBM_ENOMEM, "staging allocation: %s", hipGetErrorString(e));
             out = tmp;
-        } else {
-            const char* a = static_cast<const char*>(dst);
-            const char* b = static_cast<const char*>(c->pop[0]);
-            if (a < b + c->pop_bytes && b < a + c->pop_bytes)
-                return fail(HLBM_EINVAL, "dst overlaps the population buffer");
+        } else if (overlaps(dst, c->pop[0], c->pop_bytes)) {
+            return fail(HLBM_EINVAL, "dst overlaps the population buffer");
         }
         e = hlbm::launch_aa_export(c->q, c->cfg.storage, c->p, c->pop[0], out, c->aa_pulled ? 0 : 1, c->stream);
         if (e == hipSuccess && tmp) e = hipMemcpyAsync(dst, tmp, c->pop_bytes, hipMemcpyDeviceToHost, c->stream);
@@ -696,6 +701,8 @@ int hlbm_get_state(hlbm_ctx* c, void* dst, int on_device, long long* step)
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (!dst) return fail(HLBM_EINVAL, "dst is NULL");
     if (c->aa) return aa_get_state(c, dst, on_device, step);
+    if (on_device && overlaps(dst, c->pop[c->cur], c->pop_bytes))
+        return fail(HLBM_EINVAL, "dst overlaps the current population buffer");
     hipError_t e = hipMemcpyAsync(dst, c->pop[c->cur], c->pop_bytes,
                                   on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -713,12 +720,8 @@ int hlbm_set_state(hlbm_ctx* c, const void* src, int on_device, long long step)
     if (step < 0) return fail(HLBM_EINVAL, "step must be >= 0");
     hipError_t e = hipSuccess;
     if (c->aa) {
-        if (on_device) {
-            const char* a = static_cast<const char*>(src);
-            const char* b = static_cast<const char*>(c->pop[0]);
-            if (a < b + c->pop_bytes && b < a + c->pop_bytes)
-                return fail(HLBM_EINVAL, "src overlaps the population buffer");
-        }
+        if (on_device && overlaps(src, c->pop[0], c->pop_bytes))
+            return fail(HLBM_EINVAL, "src overlaps the population buffer");
         // row i of the A/B-layout state into slot row opp(i): ready for the
         // shifted step
         const size_t row = (size_t)c->p.N * c->elem;
@@ -728,6 +731,8 @@ int hlbm_set_state(hlbm_ctx* c, const void* src, int on_device, long long step)
                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
         c->aa_pulled = false;
     } else {
+        if (on_device && overlaps(src, c->pop[c->cur], c->pop_bytes))
+            return fail(HLBM_EINVAL, "src overlaps the current population buffer");
         e = hipMemcpyAsync(c->pop[c->cur], src, c->pop_bytes,
                            on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
     }

@@ -271,6 +271,16 @@ def test_state_roundtrip_bitwise(H):
         assert sim.step_count == 50
         b = sim.state_f64()
         assert np.array_equal(a, b)
+        # a device snapshot must not overlap the buffer holding the current
+        # state (host-side check; nothing is copied)
+        # (20 steps since the reset: buffer A holds the state)
+        lib = H.load()
+        for off in (0, 64):
+            ptr = sim._pop_a.data_ptr() + off
+            assert lib.hlbm_get_state(sim.ctx, ptr, 1, None) == H.EINVAL
+            assert lib.hlbm_set_state(sim.ctx, ptr, 1, 50) == H.EINVAL
+        assert sim.step_count == 50
+        assert np.array_equal(sim.state_f64(), b)
     finally:
         sim.close()
 
