@@ -71,14 +71,19 @@ enum { HLBM_F64 = 0, HLBM_F32 = 1, HLBM_F16S = 2, HLBM_BF16S = 3 };
 
 /* Buffer pattern.  HLBM_AB: two population buffers swapped every step.
  * HLBM_AA: one buffer updated in place (the AA pattern), half the population
- * memory, fully periodic boxes only.  Its steps alternate between two forms:
- * one reads the cell's own slots and writes post-collision population i to
- * the cell's slot opp(i); the other reads population i from slot opp(i) of
- * x - c_i and writes post-collision population i to slot i of x + c_i.  Every
- * slot is read and written by one cell per step, and each cell does the
- * arithmetic of the AB sweep, so both patterns give the same results bit for
- * bit.  hlbm_get_state / hlbm_set_state use the AB layout for both.  HLBM_AA
- * takes block_x <= 256 (EUNSUPPORTED otherwise). */
+ * memory.  Its steps alternate between two forms: one reads the cell's own
+ * slots and writes post-collision population i to the cell's slot opp(i); the
+ * other reads population i from slot opp(i) of x - c_i and writes
+ * post-collision population i to slot i of x + c_i.  With wall faces the
+ * second form reads a population whose source is solid from the cell's own
+ * slot i and writes one whose target is solid to its own slot opp(i)
+ * (halfway bounce-back).  Every slot is read and written by one cell per step,
+ * and each cell does the arithmetic of the AB sweep, so both patterns give the
+ * same results bit for bit.  hlbm_get_state / hlbm_set_state use the AB
+ * layout for both.  HLBM_AA takes periodic and wall faces only: an open face
+ * needs the cell's own post-collision state, whose slots its neighbours write
+ * in the same step (EUNSUPPORTED).  It takes block_x <= 256 (EUNSUPPORTED
+ * otherwise). */
 enum { HLBM_AB = 0, HLBM_AA = 1 };
 
 /* Face kinds, per axis and side.  HLBM_PERIODIC must be used on both sides of
@@ -134,7 +139,12 @@ int hlbm_config_default(hlbm_config *cfg);
 int hlbm_lattice_info(int lattice, int *c, double *w);
 
 /* Bytes of one population buffer and of the porosity field for *cfg (six
- * rows for a tensor control).  HLBM_AB uses two such buffers, HLBM_AA one. */
+ * rows for a tensor control).  HLBM_AB uses two such buffers, HLBM_AA one.
+ * A population buffer holds Q rows; each row stores the N = nx*ny*nz cells
+ * followed by 8448 bytes of padding, which offsets consecutive rows by
+ * 8.25 KiB modulo any power of two, so the 19 read and 19 write streams of a
+ * sweep fall on different HBM channels even when N * element size is a large
+ * power of two.  The porosity rows and state snapshots are dense. */
 int hlbm_required_bytes(const hlbm_config *cfg, size_t *pop_bytes, size_t *porosity_bytes);
 
 /* Validate *cfg and create a context.  Unless cfg->external_memory is set the
@@ -188,7 +198,8 @@ int hlbm_get_step(const hlbm_ctx *ctx, long long *step);
  * a total is not finite. */
 int hlbm_moments(hlbm_ctx *ctx, void *drho, void *u, int dtype, int on_device, double *totals);
 
-/* Size in bytes of a raw state snapshot (one population buffer). */
+/* Size in bytes of a raw state snapshot: Q dense rows of N stored values
+ * (smaller than a population buffer, whose rows are padded). */
 int hlbm_state_bytes(const hlbm_ctx *ctx, size_t *bytes);
 
 /* Copy the current post-collision populations (storage element type, library

@@ -76,12 +76,12 @@ __device__ __forceinline__ Moms forward_moments(const typename S::T* __restrict_
     const R inv_scale = R(p.inv_scale);
     R g[L::Q];
     if (BC == BC_PERIODIC) {
-        gather_periodic<L, S>(src, p.N, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+        gather_periodic<L, S>(src, p.P, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
     } else {
         const Box b = box_of(p);
         const OpenFaces<R> of{R(p.rho0), R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
                               R(p.outlet_rho)};
-        gather_general<L, S>(src, p.N, b, of, (int)x, (int)y, (int)z, inv_scale, g);
+        gather_general<L, S>(src, p.P, b, of, (int)x, (int)y, (int)z, inv_scale, g);
     }
     return moments_f64<L, R>(g);
 }

@@ -30,7 +30,8 @@ struct hlbm_ctx {
     int bx;
     size_t elem;       // bytes per stored population value
     size_t delem;      // bytes per porosity value
-    size_t pop_bytes;  // one population buffer
+    size_t pop_bytes;  // one population buffer (q rows of p.P elements)
+    size_t state_bytes;  // one snapshot (q rows of p.N elements)
     void* pop[2];
     void* dfield;
     bool own_mem;
@@ -115,12 +116,20 @@ bool is_pow2(double s)
     return m == 0.5;
 }
 
-// True when the byte ranges [a, a + n) and [b, b + n) share a byte.
-bool overlaps(const void* a, const void* b, size_t n)
+// True when the byte ranges [a, a + na) and [b, b + nb) share a byte.
+bool overlaps(const void* a, size_t na, const void* b, size_t nb)
 {
     const char* x = static_cast<const char*>(a);
     const char* y = static_cast<const char*>(b);
-    return x < y + n && y < x + n;
+    return x < y + nb && y < x + na;
+}
+
+// Copy q rows of `row` bytes between buffers whose rows are dpitch / spitch
+// bytes apart (one 2D copy).
+hipError_t copy_rows(void* dst, size_t dpitch, const void* src, size_t spitch, size_t row, int q,
+                     hipMemcpyKind kind, hipStream_t s)
+{
+    return hipMemcpy2DAsync(dst, dpitch, src, spitch, row, (size_t)q, kind, s);
 }
 
 size_t elem_bytes(int storage)
@@ -188,9 +197,13 @@ int validate_config(const hlbm_config* c)
     if (c->porosity_kind == HLBM_POROSITY_TENSOR && c->lattice != HLBM_D3Q19)
         return fail(HLBM_EUNSUPPORTED, "a tensor porosity control needs D3Q19");
     if (c->pattern == HLBM_AA) {
+        // open faces need the cell's own post-collision state, whose slots the
+        // neighbours are writing during the shifted step
         for (int a = 0; a < 3; ++a)
-            if (c->bc_lo[a] != HLBM_PERIODIC)
-                return fail(HLBM_EUNSUPPORTED, "the in-place pattern (HLBM_AA) needs periodic faces on every axis");
+            if ((c->bc_lo[a] != HLBM_PERIODIC && c->bc_lo[a] != HLBM_WALL) ||
+                (c->bc_hi[a] != HLBM_PERIODIC && c->bc_hi[a] != HLBM_WALL))
+                return fail(HLBM_EUNSUPPORTED,
+                            "the in-place pattern (HLBM_AA) takes periodic and wall faces only (no open faces)");
         if (c->block_x > 256) return fail(HLBM_EUNSUPPORTED, "the in-place pattern (HLBM_AA) needs block_x <= 256");
     }
     return HLBM_OK;
@@ -203,6 +216,7 @@ void fill_params(const hlbm_config* c, Params* p)
     p->ny = c->ny;
     p->nz = c->nz;
     p->N = (uint32_t)((unsigned long long)c->nx * c->ny * c->nz);
+    p->P = hlbm::row_pitch(p->N, elem_bytes(c->storage));
     p->omega = 1.0 / c->tau;
     p->pref = 1.0 - 0.5 / c->tau;
     for (int a = 0; a < 3; ++a) {
@@ -223,6 +237,16 @@ int auto_block_x(int nx)
     int b = ((nx + 63) / 64) * 64;
     if (b > 256) b = 256;
     return b;
+}
+
+// Sweep / moments mode of an in-place context: the local step when the buffer
+// holds pulled populations, the shifted step otherwise; wall variants when a
+// face is a wall.
+int aa_mode(const hlbm_ctx* c)
+{
+    const bool walls = c->bcmode != hlbm::BC_PERIODIC;
+    if (c->aa_pulled) return walls ? hlbm::BC_AA_EVEN_W : hlbm::BC_AA_EVEN;
+    return walls ? hlbm::BC_AA_ODD_W : hlbm::BC_AA_ODD;
 }
 
 int check_ctx(const hlbm_ctx* c)
@@ -260,25 +284,25 @@ int zero_state(hlbm_ctx* c)
 int aa_get_state(hlbm_ctx* c, void* dst, int on_device, long long* step)
 {
     hipError_t e = hipSuccess;
-    const size_t row = (size_t)c->p.N * c->elem;
+    const size_t row = (size_t)c->p.N * c->elem, pitch = (size_t)c->p.P * c->elem;
     void* tmp = nullptr;
     if (!c->aa_pulled && !on_device) {
         // opposite slots: one row copy per population
         for (int i = 0; i < c->q && e == hipSuccess; ++i)
             e = hipMemcpyAsync(static_cast<char*>(dst) + (size_t)i * row,
-                               static_cast<const char*>(c->pop[0]) + (size_t)hlbm::opposite(i) * row, row,
+                               static_cast<const char*>(c->pop[0]) + (size_t)hlbm::opposite(i) * pitch, row,
                                hipMemcpyDeviceToHost, c->stream);
     } else {
         void* out = dst;
         if (!on_device) {
-            e = hipMalloc(&tmp, c->pop_bytes);
+            e = hipMalloc(&tmp, c->state_bytes);
             if (e != hipSuccess) return fail(HLBM_ENOMEM, "staging allocation: %s", hipGetErrorString(e));
             out = tmp;
-        } else if (overlaps(dst, c->pop[0], c->pop_bytes)) {
+        } else if (overlaps(dst, c->state_bytes, c->pop[0], c->pop_bytes)) {
             return fail(HLBM_EINVAL, "dst overlaps the population buffer");
         }
         e = hlbm::launch_aa_export(c->q, c->cfg.storage, c->p, c->pop[0], out, c->aa_pulled ? 0 : 1, c->stream);
-        if (e == hipSuccess && tmp) e = hipMemcpyAsync(dst, tmp, c->pop_bytes, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && tmp) e = hipMemcpyAsync(dst, tmp, c->state_bytes, hipMemcpyDeviceToHost, c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (tmp) (void)hipFree(tmp);
@@ -429,7 +453,8 @@ int hlbm_required_bytes(const hlbm_config* cfg, size_t* pop_bytes, size_t* poros
     int rc = validate_config(cfg);
     if (rc) return rc;
     const size_t n = (size_t)cfg->nx * cfg->ny * cfg->nz;
-    if (pop_bytes) *pop_bytes = n * (size_t)cfg->lattice * elem_bytes(cfg->storage);
+    const size_t pitch = hlbm::row_pitch((uint32_t)n, elem_bytes(cfg->storage));
+    if (pop_bytes) *pop_bytes = pitch * (size_t)cfg->lattice * elem_bytes(cfg->storage);
     if (porosity_bytes) *porosity_bytes = n * porosity_elem_bytes(cfg->storage) * porosity_rows(cfg);
     return HLBM_OK;
 }
@@ -453,7 +478,8 @@ int hlbm_create(const hlbm_config* cfg, hlbm_ctx** out)
     c->bx = cfg->block_x ? cfg->block_x : auto_block_x(cfg->nx);
     c->elem = elem_bytes(cfg->storage);
     c->delem = porosity_elem_bytes(cfg->storage);
-    c->pop_bytes = (size_t)c->p.N * (size_t)c->q * c->elem;
+    c->pop_bytes = (size_t)c->p.P * (size_t)c->q * c->elem;
+    c->state_bytes = (size_t)c->p.N * (size_t)c->q * c->elem;
     c->stream = static_cast<hipStream_t>(cfg->hip_stream);
     c->own_mem = !cfg->external_memory;
     if (c->own_mem) {
@@ -604,8 +630,7 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
         const bool record = diag && c->diag_count < c->diag_cap;
         if (diag && !record) c->diag_dropped += 1;
         if (c->aa)
-            e = hlbm::launch_sweep(c->q, c->cfg.storage, c->aa_pulled ? hlbm::BC_AA_EVEN : hlbm::BC_AA_ODD,
-                                   c->cfg.porosity_kind, c->p, c->pop[0], c->pop[0], c->dfield, c->bx, c->stream,
+            e = hlbm::launch_sweep(c->q, c->cfg.storage, aa_mode(c), c->cfg.porosity_kind, c->p, c->pop[0], c->pop[0], c->dfield, c->bx, c->stream,
                                    record ? c->partials : nullptr);
         else
             e = hlbm::launch_sweep(c->q, c->cfg.storage, c->bcmode, c->cfg.porosity_kind, c->p, c->pop[c->cur],
@@ -665,7 +690,7 @@ int hlbm_moments(hlbm_ctx* c, void* drho, void* u, int dtype, int on_device, dou
         }
         partials = c->partials;
     }
-    const int mbc = !c->aa ? c->bcmode : (c->aa_pulled ? hlbm::BC_AA_EVEN : hlbm::BC_AA_ODD);
+    const int mbc = c->aa ? aa_mode(c) : c->bcmode;
     e = hlbm::launch_moments(c->q, c->cfg.storage, mbc, c->p, c->pop[c->cur], ddr, du,
                              dtype == HLBM_DT_F64, partials, c->bx, c->stream);
     if (e == hipSuccess && totals)
@@ -690,7 +715,7 @@ int hlbm_state_bytes(const hlbm_ctx* c, size_t* bytes)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!bytes) return fail(HLBM_EINVAL, "bytes is NULL");
-    *bytes = c->pop_bytes;
+    *bytes = c->state_bytes;
     return HLBM_OK;
 }
 
@@ -701,10 +726,11 @@ int hlbm_get_state(hlbm_ctx* c, void* dst, int on_device, long long* step)
     if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
     if (!dst) return fail(HLBM_EINVAL, "dst is NULL");
     if (c->aa) return aa_get_state(c, dst, on_device, step);
-    if (on_device && overlaps(dst, c->pop[c->cur], c->pop_bytes))
+    if (on_device && overlaps(dst, c->state_bytes, c->pop[c->cur], c->pop_bytes))
         return fail(HLBM_EINVAL, "dst overlaps the current population buffer");
-    hipError_t e = hipMemcpyAsync(dst, c->pop[c->cur], c->pop_bytes,
-                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
+    const size_t row = (size_t)c->p.N * c->elem;
+    hipError_t e = copy_rows(dst, row, c->pop[c->cur], (size_t)c->p.P * c->elem, row, c->q,
+                             on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "get_state");
     if (step) *step = c->step;
@@ -720,21 +746,22 @@ int hlbm_set_state(hlbm_ctx* c, const void* src, int on_device, long long step)
     if (step < 0) return fail(HLBM_EINVAL, "step must be >= 0");
     hipError_t e = hipSuccess;
     if (c->aa) {
-        if (on_device && overlaps(src, c->pop[0], c->pop_bytes))
+        if (on_device && overlaps(src, c->state_bytes, c->pop[0], c->pop_bytes))
             return fail(HLBM_EINVAL, "src overlaps the population buffer");
         // row i of the A/B-layout state into slot row opp(i): ready for the
         // shifted step
-        const size_t row = (size_t)c->p.N * c->elem;
+        const size_t row = (size_t)c->p.N * c->elem, pitch = (size_t)c->p.P * c->elem;
         for (int i = 0; i < c->q && e == hipSuccess; ++i)
-            e = hipMemcpyAsync(static_cast<char*>(c->pop[0]) + (size_t)hlbm::opposite(i) * row,
+            e = hipMemcpyAsync(static_cast<char*>(c->pop[0]) + (size_t)hlbm::opposite(i) * pitch,
                                static_cast<const char*>(src) + (size_t)i * row, row,
                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
         c->aa_pulled = false;
     } else {
-        if (on_device && overlaps(src, c->pop[c->cur], c->pop_bytes))
+        if (on_device && overlaps(src, c->state_bytes, c->pop[c->cur], c->pop_bytes))
             return fail(HLBM_EINVAL, "src overlaps the current population buffer");
-        e = hipMemcpyAsync(c->pop[c->cur], src, c->pop_bytes,
-                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+        const size_t row = (size_t)c->p.N * c->elem;
+        e = copy_rows(c->pop[c->cur], (size_t)c->p.P * c->elem, src, row, row, c->q,
+                      on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "set_state");
@@ -1027,10 +1054,12 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
     c->p.ny = 1;
     c->p.nz = 1;
     c->p.N = (uint32_t)ntot;
+    c->p.P = (uint32_t)ntot;  // the packed items keep dense rows
     c->bx = 256;
     c->elem = elem_bytes(storage);
     c->delem = porosity_elem_bytes(storage);
     c->pop_bytes = (size_t)ntot * 19 * c->elem;
+    c->state_bytes = c->pop_bytes;
     c->stream = static_cast<hipStream_t>(items[0].hip_stream);
     c->own_mem = true;
     c->gsteps[0] = c->gsteps[1] = -1;

@@ -440,6 +440,55 @@ __device__ __forceinline__ void gather_general(const typename S::T* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// AA pattern with wall faces, odd step: population i from slot opp(i) of
+// x - c_i, or from this cell's own slot i where x - c_i is solid (halfway
+// bounce-back).  A fluid cell's sources stay inside the box (the wall layers
+// belong to it); for a solid cell, whose result the caller discards, a source
+// beyond the box also switches to the cell's own slot, so every address stays
+// in bounds.
+// ---------------------------------------------------------------------------
+template <class L, class S>
+__device__ __forceinline__ void gather_aa_odd_walls(const typename S::T* src, uint32_t N, const Box& b, int x,
+                                                    int y, int z, typename S::R inv_scale,
+                                                    typename S::R (&g)[L::Q])
+{
+    const uint32_t cell = (uint32_t)x + (uint32_t)b.nx * ((uint32_t)y + (uint32_t)b.ny * (uint32_t)z);
+    const bool px = b.lo0 == 0, py = b.lo1 == 0, pz = b.lo2 == 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int sx = wrap_source(x, L::cx[i], b.nx, px);
+        const int sy = wrap_source(y, L::cy[i], b.ny, py);
+        const int sz = wrap_source(z, L::cz[i], b.nz, pz);
+        const bool outside = (sx < 0) | (sx >= b.nx) | (sy < 0) | (sy >= b.ny) | (sz < 0) | (sz >= b.nz);
+        const bool own = in_wall_layer(b, sx, sy, sz) | outside;
+        const uint32_t noff = (uint32_t)sx + (uint32_t)b.nx * ((uint32_t)sy + (uint32_t)b.ny * (uint32_t)sz);
+        const uint32_t row = sel(own, (uint32_t)i, (uint32_t)opposite(i));
+        const uint32_t off = sel(own, cell, noff);
+        g[i] = S::load(ld(src + (size_t)row * N, off), inv_scale);
+    }
+}
+
+// Where the AA odd step with wall faces puts post-collision population i of
+// (x, y, z): slot i of x + c_i, or this cell's own slot opp(i) where x + c_i
+// is solid or beyond the box, or where the cell itself is solid: the row and
+// the cell offset within it.
+template <class L>
+__device__ __forceinline__ void aa_odd_target_walls(const Box& b, int x, int y, int z, bool self_solid, int i,
+                                                    uint32_t& row, uint32_t& off)
+{
+    const uint32_t cell = (uint32_t)x + (uint32_t)b.nx * ((uint32_t)y + (uint32_t)b.ny * (uint32_t)z);
+    const bool px = b.lo0 == 0, py = b.lo1 == 0, pz = b.lo2 == 0;
+    const int tx = wrap_source(x, -L::cx[i], b.nx, px);
+    const int ty = wrap_source(y, -L::cy[i], b.ny, py);
+    const int tz = wrap_source(z, -L::cz[i], b.nz, pz);
+    const bool outside = (tx < 0) | (tx >= b.nx) | (ty < 0) | (ty >= b.ny) | (tz < 0) | (tz >= b.nz);
+    const bool own = self_solid | in_wall_layer(b, tx, ty, tz) | outside;
+    const uint32_t toff = (uint32_t)tx + (uint32_t)b.nx * ((uint32_t)ty + (uint32_t)b.ny * (uint32_t)tz);
+    row = sel(own, (uint32_t)opposite(i), (uint32_t)i);
+    off = sel(own, cell, toff);
+}
+
+// ---------------------------------------------------------------------------
 // Pull gather in a periodic box with resolved solid cells: where the source of
 // direction i is solid, halfway bounce-back g*_i(x) = g_opp(i)(x) (the link
 // mask, precomputed per cell, says which sources are solid).  Straight-line:

@@ -11,6 +11,7 @@ namespace hlbm {
 struct Params {
     int nx, ny, nz;
     uint32_t N;          // cells = nx*ny*nz (< 2^32)
+    uint32_t P;          // elements from one population row to the next (>= N, see row_pitch)
     double omega;        // 1/tau
     double pref;         // 1 - 1/(2 tau), Guo source prefactor
     double F[3];         // body-force density
@@ -33,8 +34,36 @@ struct Params {
 // x - c_i and writes post-collision population i to slot i of x + c_i.  Each
 // slot is read and written by one thread per step, so one buffer suffices,
 // and the arithmetic is that of the A/B pull bit for bit.
-enum BcMode { BC_PERIODIC = 0, BC_GENERAL = 1, BC_MASKED = 2, BC_AA_EVEN = 3, BC_AA_ODD = 4 };
+// BC_AA_EVEN_W / BC_AA_ODD_W: the same steps with wall faces (periodic or
+// wall on every axis).  In the odd step a population whose source is solid is
+// read from the cell's own slot i (halfway bounce-back: the even step left
+// the cell's post-collision population opp(i) there), and a post-collision
+// population whose target is solid is written to the cell's own slot opp(i)
+// (where the even step expects the bounced population).  Those slots belong
+// to the solid neighbour, which touches only its own slots, so the pattern
+// stays free of races.  Solid cells store zeros, as in the A/B sweep.
+enum BcMode {
+    BC_PERIODIC = 0,
+    BC_GENERAL = 1,
+    BC_MASKED = 2,
+    BC_AA_EVEN = 3,
+    BC_AA_ODD = 4,
+    BC_AA_EVEN_W = 5,
+    BC_AA_ODD_W = 6
+};
 constexpr uint32_t LINK_SOLID_SELF = 1u << 31;
+
+// Population rows are ROW_PAD_BYTES longer than their N cells.  A box whose
+// row is a large power of two (512^3 FP32: 512 MiB) otherwise starts every
+// one of the 19 rows at the same offset modulo every power of two up to the
+// row size, so the 19 concurrent read streams of a wave and the 19 write
+// streams fall on the same few HBM channels at the same time.  Shifting row i
+// by i * 8.25 KiB spreads them; the pad was chosen by timing the 512^3 FP32
+// sweep over fresh allocations (8 KiB to 8.5 KiB pads: 3.51-3.57 ms per step
+// against 3.75 ms unpadded, means over 7 allocations each).  Snapshots
+// (hlbm_get_state / hlbm_set_state) keep the dense layout of N per row.
+constexpr size_t ROW_PAD_BYTES = 8448;
+inline uint32_t row_pitch(uint32_t n, size_t elem) { return n + (uint32_t)(ROW_PAD_BYTES / elem); }
 // Porosity control kinds: one value d per cell, or a symmetric 3x3 D (6 rows).
 enum PorosityKind { PK_SCALAR = 0, PK_TENSOR = 1 };
 

@@ -2,7 +2,8 @@
 // moments gather, FP64 reductions and porosity conversion, for gfx950.
 //
 // Memory layout: structure of arrays, population i of cell c at
-// buf[i*N + c], c = x + nx*(y + ny*z).  One thread owns one cell; a block
+// buf[i*P + c], c = x + nx*(y + ny*z), rows P >= N elements apart (the
+// pitch is padded past N; see row_pitch).  One thread owns one cell; a block
 // covers `bx` consecutive cells of one x-row, so every population row is read
 // by exactly one block and each load instruction of a wavefront is a
 // contiguous (possibly one-element shifted) 64-lane run.  The sweep reads each
@@ -29,7 +30,7 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
                                            typename S::R& ux, typename S::R& uy, typename S::R& uz)
 {
     using R = typename S::R;
-    const uint32_t N = p.N;
+    const uint32_t N = p.N, P = p.P;  // control rows hold N values; population rows are P apart
     const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
     const R inv_scale = R(p.inv_scale), scale = R(p.scale);
     const R F0 = R(p.F[0]), F1 = R(p.F[1]), F2 = R(p.F[2]);
@@ -37,18 +38,25 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
     R g[L::Q];
     bool solid = false;
     if (BC == BC_PERIODIC) {
-        gather_periodic<L, S>(src, N, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+        gather_periodic<L, S>(src, P, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
     } else if (BC == BC_AA_EVEN) {
-        gather_aa_even<L, S>(src, N, cell, inv_scale, g);
+        gather_aa_even<L, S>(src, P, cell, inv_scale, g);
     } else if (BC == BC_AA_ODD) {
-        gather_aa_odd<L, S>(src, N, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+        gather_aa_odd<L, S>(src, P, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+    } else if (BC == BC_AA_EVEN_W) {
+        gather_aa_even<L, S>(src, P, cell, inv_scale, g);
+        solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
+    } else if (BC == BC_AA_ODD_W) {
+        const Box b = box_of(p);
+        gather_aa_odd_walls<L, S>(src, P, b, (int)x, (int)y, (int)z, inv_scale, g);
+        solid = in_wall_layer(b, (int)x, (int)y, (int)z);
     } else if (BC == BC_MASKED) {
-        solid = gather_masked<L, S>(src, N, p.linkmask, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+        solid = gather_masked<L, S>(src, P, p.linkmask, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
     } else {
         const Box b = box_of(p);
         const OpenFaces<R> of{rho0, R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
                               R(p.outlet_rho)};
-        gather_general<L, S>(src, N, b, of, (int)x, (int)y, (int)z, inv_scale, g);
+        gather_general<L, S>(src, P, b, of, (int)x, (int)y, (int)z, inv_scale, g);
         solid = in_wall_layer(b, (int)x, (int)y, (int)z);
     }
     if (PK == PK_SCALAR) {
@@ -64,10 +72,23 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
                                 S::load_d(ld(dfield + 5 * (size_t)N, cell))};
         collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
     }
-    if (BC == BC_AA_EVEN) {
-        // post-collision population i into this cell's slot opp(i)
+    if (BC == BC_AA_EVEN || BC == BC_AA_EVEN_W) {
+        // post-collision population i into this cell's slot opp(i); a solid
+        // cell stores zeros there
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) st_stream(dst + (size_t)opposite(i) * N, cell, S::store(g[i], scale));
+        for (int i = 0; i < L::Q; ++i)
+            st_stream(dst + (size_t)opposite(i) * P, cell, S::store(sel(solid, R(0), g[i]), scale));
+    } else if (BC == BC_AA_ODD_W) {
+        // post-collision population i into slot i of x + c_i, or into this
+        // cell's own slot opp(i) where x + c_i is solid; a solid cell stores
+        // zeros into its own slots
+        const Box b = box_of(p);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            uint32_t row, off;
+            aa_odd_target_walls<L>(b, (int)x, (int)y, (int)z, solid, i, row, off);
+            st_stream(dst + (size_t)row * P, off, S::store(sel(solid, R(0), g[i]), scale));
+        }
     } else if (BC == BC_AA_ODD) {
         // post-collision population i into slot i of x + c_i
         const uint32_t nx = p.nx, ny = p.ny, nz = p.nz;
@@ -77,13 +98,13 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const uint32_t off = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
-            st_stream(dst + (size_t)i * N, off, S::store(g[i], scale));
+            st_stream(dst + (size_t)i * P, off, S::store(g[i], scale));
         }
     } else {
         // solid cells (wall layers, masked cells) hold zeros; selected, not branched
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
-            st_stream(dst + (size_t)i * N, cell, S::store(sel(solid, R(0), g[i]), scale));
+            st_stream(dst + (size_t)i * P, cell, S::store(sel(solid, R(0), g[i]), scale));
     }
     return solid;
 }
@@ -154,12 +175,13 @@ __global__ __launch_bounds__(256) void sweep_aa_diag_kernel(typename S::T* buf,
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
     if (x < (uint32_t)p.nx) {
         R drho, ux, uy, uz;
-        (void)sweep_cell<L, S, BC, PK>(buf, buf, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
+        const bool solid =
+            sweep_cell<L, S, BC, PK>(buf, buf, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
         const double rho = p.rho0 + (double)drho;
-        m0 = (double)drho;
-        m1 = rho * (double)ux;
-        m2 = rho * (double)uy;
-        m3 = rho * (double)uz;
+        m0 = sel(solid, 0.0, (double)drho);
+        m1 = sel(solid, 0.0, rho * (double)ux);
+        m2 = sel(solid, 0.0, rho * (double)uy);
+        m3 = sel(solid, 0.0, rho * (double)uz);
     }
     const uint32_t bk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     block_sum4(m0, m1, m2, m3, partials + 4 * (size_t)bk);
@@ -212,7 +234,7 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
     using R = typename S::R;
     using T = typename S::T;
     const uint32_t x0 = 2u * (blockIdx.x * blockDim.x + threadIdx.x);
-    const uint32_t nx = p.nx, ny = p.ny, nz = p.nz, N = p.N;
+    const uint32_t nx = p.nx, ny = p.ny, nz = p.nz, P = p.P;
     if (x0 >= nx) return;
     const uint32_t y = blockIdx.y, z = blockIdx.z;
     const R inv_scale = R(p.inv_scale), scale = R(p.scale);
@@ -226,7 +248,7 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
     uint32_t w[L::Q];
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const T* row = src + (size_t)i * N + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+        const T* row = src + (size_t)i * P + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
         // start of the pulled pair: x0 - c_x, kept inside the row at the ends
         uint32_t xs = x0;
         if (L::cx[i] > 0) xs = sel(first, x0, x0 - 1);
@@ -237,7 +259,7 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             if (L::cx[i] <= 0) continue;
-            const T* row = src + (size_t)i * N + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+            const T* row = src + (size_t)i * P + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
             w[i] = bits16<S>(ld(row, nx - 1)) | (w[i] << 16);
         }
     }
@@ -245,7 +267,7 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             if (L::cx[i] >= 0) continue;
-            const T* row = src + (size_t)i * N + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+            const T* row = src + (size_t)i * P + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
             w[i] = (w[i] >> 16) | (bits16<S>(ld(row, 0u)) << 16);
         }
     }
@@ -274,7 +296,7 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
                                                     pref, drho, ux, uy, uz);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        uint32_t* out = reinterpret_cast<uint32_t*>(dst + (size_t)i * N);
+        uint32_t* out = reinterpret_cast<uint32_t*>(dst + (size_t)i * P);
         st_stream(out, cell / 2u, (w[i] & 0xffffu) | (bits16<S>(S::store(g[i], scale)) << 16));
     }
 }
@@ -299,19 +321,26 @@ __global__ __launch_bounds__(1024) void moments_kernel(const typename S::T* __re
         R g[L::Q];
         bool fluid = true;
         if (BC == BC_PERIODIC) {
-            gather_periodic<L, S>(src, N, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+            gather_periodic<L, S>(src, p.P, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
         } else if (BC == BC_AA_EVEN) {
-            gather_aa_even<L, S>(src, N, cell, inv_scale, g);
+            gather_aa_even<L, S>(src, p.P, cell, inv_scale, g);
         } else if (BC == BC_AA_ODD) {
-            gather_aa_odd<L, S>(src, N, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+            gather_aa_odd<L, S>(src, p.P, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+        } else if (BC == BC_AA_EVEN_W) {
+            gather_aa_even<L, S>(src, p.P, cell, inv_scale, g);
+            fluid = !in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
+        } else if (BC == BC_AA_ODD_W) {
+            const Box b = box_of(p);
+            gather_aa_odd_walls<L, S>(src, p.P, b, (int)x, (int)y, (int)z, inv_scale, g);
+            fluid = !in_wall_layer(b, (int)x, (int)y, (int)z);
         } else if (BC == BC_MASKED) {
-            fluid = !gather_masked<L, S>(src, N, p.linkmask, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+            fluid = !gather_masked<L, S>(src, p.P, p.linkmask, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
         } else {
             const Box b = box_of(p);
             fluid = !in_wall_layer(b, (int)x, (int)y, (int)z);
             const OpenFaces<R> of{rho0, R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
                                   R(p.outlet_rho)};
-            gather_general<L, S>(src, N, b, of, (int)x, (int)y, (int)z, inv_scale, g);
+            gather_general<L, S>(src, p.P, b, of, (int)x, (int)y, (int)z, inv_scale, g);
         }
         R drho, ux, uy, uz;
         moments_of<L, R, S::exact_moments>(g, F0, F1, F2, rho0, drho, ux, uy, uz);
@@ -410,23 +439,36 @@ __global__ __launch_bounds__(256) void tensor_porosity_kernel(const I* __restric
 // AA-pattern state in A/B layout: out[i][x] = post-collision population i of
 // cell x.  With odd_ready the buffer holds it in slot opp(i) of x; otherwise
 // the buffer holds the pulled populations, and population i of x sits in slot
-// i of x + c_i (periodic wrap).  Raw element copies.
-template <class L, class E, bool OddReady>
-__global__ __launch_bounds__(256) void aa_export_kernel(const E* __restrict__ buf, E* __restrict__ out,
-                                                        uint32_t nx, uint32_t ny, uint32_t nz)
+// i of x + c_i (periodic wrap), or, with wall faces, in slot opp(i) of x where
+// x + c_i is solid or x itself is (whose slots hold zeros).  Raw element
+// copies; the buffer's rows are P elements apart, the output's N.
+template <class L, class E, bool OddReady, bool Walls>
+__global__ __launch_bounds__(256) void aa_export_kernel(const E* __restrict__ buf, E* __restrict__ out, Box b,
+                                                        uint32_t P)
 {
+    const uint32_t nx = b.nx, ny = b.ny, nz = b.nz;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= nx) return;
     const uint32_t y = blockIdx.y, z = blockIdx.z;
     const uint32_t N = nx * ny * nz;
     const uint32_t cell = x + nx * (y + ny * z);
+    if (!OddReady && Walls) {
+        const bool solid = in_wall_layer(b, (int)x, (int)y, (int)z);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            uint32_t row, off;
+            aa_odd_target_walls<L>(b, (int)x, (int)y, (int)z, solid, i, row, off);
+            out[(size_t)i * N + cell] = buf[(size_t)row * P + off];
+        }
+        return;
+    }
     const uint32_t xs[3] = {x == 0 ? nx - 1 : x - 1, x, x + 1 == nx ? 0u : x + 1};
     const uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y + 1 == ny ? 0u : y + 1};
     const uint32_t zs[3] = {z == 0 ? nz - 1 : z - 1, z, z + 1 == nz ? 0u : z + 1};
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const uint32_t fwd = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
-        out[(size_t)i * N + cell] = OddReady ? buf[(size_t)opposite(i) * N + cell] : buf[(size_t)i * N + fwd];
+        out[(size_t)i * N + cell] = OddReady ? buf[(size_t)opposite(i) * P + cell] : buf[(size_t)i * P + fwd];
     }
 }
 
@@ -474,18 +516,28 @@ static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src
     auto* a = static_cast<const typename S::T*>(src);
     auto* b = static_cast<typename S::T*>(dst);
     auto* d = static_cast<const typename S::D*>(dfield);
-    if (bcmode == BC_AA_EVEN || bcmode == BC_AA_ODD) {
+    if (bcmode == BC_AA_EVEN || bcmode == BC_AA_ODD || bcmode == BC_AA_EVEN_W || bcmode == BC_AA_ODD_W) {
         // one buffer: src and dst are the same address
         if (src != dst || bx > 256) return hipErrorInvalidValue;
         if (diag) {
             if (bcmode == BC_AA_EVEN)
                 hipLaunchKernelGGL((sweep_aa_diag_kernel<L, S, BC_AA_EVEN, PK>), l.grid, l.block, 0, s, b, d, diag, p);
-            else
+            else if (bcmode == BC_AA_ODD)
                 hipLaunchKernelGGL((sweep_aa_diag_kernel<L, S, BC_AA_ODD, PK>), l.grid, l.block, 0, s, b, d, diag, p);
+            else if (bcmode == BC_AA_EVEN_W)
+                hipLaunchKernelGGL((sweep_aa_diag_kernel<L, S, BC_AA_EVEN_W, PK>), l.grid, l.block, 0, s, b, d, diag,
+                                   p);
+            else
+                hipLaunchKernelGGL((sweep_aa_diag_kernel<L, S, BC_AA_ODD_W, PK>), l.grid, l.block, 0, s, b, d, diag,
+                                   p);
         } else if (bcmode == BC_AA_EVEN) {
             hipLaunchKernelGGL((sweep_aa_kernel<L, S, BC_AA_EVEN, PK>), l.grid, l.block, 0, s, b, d, p);
-        } else {
+        } else if (bcmode == BC_AA_ODD) {
             hipLaunchKernelGGL((sweep_aa_kernel<L, S, BC_AA_ODD, PK>), l.grid, l.block, 0, s, b, d, p);
+        } else if (bcmode == BC_AA_EVEN_W) {
+            hipLaunchKernelGGL((sweep_aa_kernel<L, S, BC_AA_EVEN_W, PK>), l.grid, l.block, 0, s, b, d, p);
+        } else {
+            hipLaunchKernelGGL((sweep_aa_kernel<L, S, BC_AA_ODD_W, PK>), l.grid, l.block, 0, s, b, d, p);
         }
         return hipGetLastError();
     }
@@ -557,6 +609,12 @@ static hipError_t moments_dispatch_bc(int bcmode, const Params& p, const void* s
     else if (bcmode == BC_AA_ODD)
         hipLaunchKernelGGL((moments_kernel<L, S, BC_AA_ODD, O>), l.grid, l.block, 0, s, a,
                            static_cast<O*>(drho), static_cast<O*>(u), partials, p);
+    else if (bcmode == BC_AA_EVEN_W)
+        hipLaunchKernelGGL((moments_kernel<L, S, BC_AA_EVEN_W, O>), l.grid, l.block, 0, s, a,
+                           static_cast<O*>(drho), static_cast<O*>(u), partials, p);
+    else if (bcmode == BC_AA_ODD_W)
+        hipLaunchKernelGGL((moments_kernel<L, S, BC_AA_ODD_W, O>), l.grid, l.block, 0, s, a,
+                           static_cast<O*>(drho), static_cast<O*>(u), partials, p);
     else if (bcmode == BC_MASKED)
         hipLaunchKernelGGL((moments_kernel<L, S, BC_MASKED, O>), l.grid, l.block, 0, s, a,
                            static_cast<O*>(drho), static_cast<O*>(u), partials, p);
@@ -609,12 +667,18 @@ static hipError_t aa_export_as(const Params& p, const void* buf, void* out, int 
     const Launch l = cell_launch(p, 256);
     auto* a = static_cast<const E*>(buf);
     auto* b = static_cast<E*>(out);
+    Box box;
+    box.nx = p.nx; box.ny = p.ny; box.nz = p.nz;
+    box.lo0 = p.bc_lo[0]; box.hi0 = p.bc_hi[0];
+    box.lo1 = p.bc_lo[1]; box.hi1 = p.bc_hi[1];
+    box.lo2 = p.bc_lo[2]; box.hi2 = p.bc_hi[2];
+    const bool walls = (p.bc_lo[0] | p.bc_lo[1] | p.bc_lo[2] | p.bc_hi[0] | p.bc_hi[1] | p.bc_hi[2]) != 0;
     if (odd_ready)
-        hipLaunchKernelGGL((aa_export_kernel<L, E, true>), l.grid, l.block, 0, s, a, b, (uint32_t)p.nx,
-                           (uint32_t)p.ny, (uint32_t)p.nz);
+        hipLaunchKernelGGL((aa_export_kernel<L, E, true, false>), l.grid, l.block, 0, s, a, b, box, p.P);
+    else if (walls)
+        hipLaunchKernelGGL((aa_export_kernel<L, E, false, true>), l.grid, l.block, 0, s, a, b, box, p.P);
     else
-        hipLaunchKernelGGL((aa_export_kernel<L, E, false>), l.grid, l.block, 0, s, a, b, (uint32_t)p.nx,
-                           (uint32_t)p.ny, (uint32_t)p.nz);
+        hipLaunchKernelGGL((aa_export_kernel<L, E, false, false>), l.grid, l.block, 0, s, a, b, box, p.P);
     return hipGetLastError();
 }
 

@@ -305,16 +305,24 @@ class HLBM:
         return np.array(tot)
 
     # -- state -------------------------------------------------------------
+    @property
+    def state_bytes(self) -> int:
+        """Bytes of one snapshot: q rows of N stored values (the population
+        buffers themselves pad their rows, see pop_bytes)."""
+        nb = ctypes.c_size_t()
+        _check(load().hlbm_state_bytes(self.ctx, ctypes.byref(nb)))
+        return nb.value
+
     def get_state(self):
         """(raw state bytes as a uint8 device tensor, step)."""
         t = self.torch
-        buf = t.empty(self.pop_bytes, dtype=t.uint8, device=self.device)
+        buf = t.empty(self.state_bytes, dtype=t.uint8, device=self.device)
         s = ctypes.c_longlong()
         _check(load().hlbm_get_state(self.ctx, buf.data_ptr(), 1, ctypes.byref(s)))
         return buf, s.value
 
     def set_state(self, buf, step: int):
-        if buf.numel() != self.pop_bytes:
+        if buf.numel() != self.state_bytes:
             raise ValueError("state size mismatch")
         _check(load().hlbm_set_state(self.ctx, buf.contiguous().data_ptr(), 1 if buf.is_cuda else 0,
                                      int(step)))

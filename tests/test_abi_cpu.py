@@ -54,16 +54,20 @@ def _rb(cfg):
     return hlbm.load().hlbm_required_bytes(ctypes.byref(cfg), ctypes.byref(pb), ctypes.byref(db)), pb.value, db.value
 
 
+ROW_PAD = 8448   # bytes each population row runs past its N cells
+
+
 def test_required_bytes():
+    # population buffers: q rows of N cells plus the row pad; control rows dense
     rc, pb, db = _rb(hlbm.make_config(19, "f32", (256, 256, 256)))
-    assert rc == 0 and pb == 19 * 4 * 256 ** 3 and db == 4 * 256 ** 3
+    assert rc == 0 and pb == 19 * (4 * 256 ** 3 + ROW_PAD) and db == 4 * 256 ** 3
     rc, pb, db = _rb(hlbm.make_config(19, "f16s", (64, 32, 16), store_scale=4096.0))
-    assert rc == 0 and pb == 19 * 2 * 64 * 32 * 16 and db == 2 * 64 * 32 * 16
+    assert rc == 0 and pb == 19 * (2 * 64 * 32 * 16 + ROW_PAD) and db == 2 * 64 * 32 * 16
     rc, pb, db = _rb(hlbm.make_config(9, "f64", (128, 64, 1), bc_lo=(0, 1, 0), bc_hi=(0, 1, 0)))
-    assert rc == 0 and pb == 9 * 8 * 128 * 64 and db == 8 * 128 * 64
+    assert rc == 0 and pb == 9 * (8 * 128 * 64 + ROW_PAD) and db == 8 * 128 * 64
     # a tensor control holds six rows
     rc, pb, db = _rb(hlbm.make_config(19, "f32", (32, 16, 8), porosity="tensor"))
-    assert rc == 0 and pb == 19 * 4 * 32 * 16 * 8 and db == 6 * 4 * 32 * 16 * 8
+    assert rc == 0 and pb == 19 * (4 * 32 * 16 * 8 + ROW_PAD) and db == 6 * 4 * 32 * 16 * 8
     rc, pb, db = _rb(hlbm.make_config(19, "bf16s", (32, 16, 8), porosity="tensor", store_scale=2.0 ** 20))
     assert rc == 0 and db == 6 * 2 * 32 * 16 * 8
 
@@ -85,8 +89,8 @@ def test_required_bytes():
     (dict(lattice=9, shape=(8, 8, 2)), hlbm.EINVAL),
     (dict(bc_lo=(1, 0, 0), bc_hi=(1, 0, 0), shape=(2, 8, 8)), hlbm.EINVAL),
     (dict(lattice=9, shape=(8, 8, 1), porosity="tensor"), hlbm.EUNSUPPORTED),
-    (dict(pattern="aa", bc_lo=(0, 1, 0), bc_hi=(0, 1, 0)), hlbm.EUNSUPPORTED),
     (dict(pattern="aa", bc_lo=(2, 0, 0), bc_hi=(3, 0, 0)), hlbm.EUNSUPPORTED),
+    (dict(pattern="aa", bc_lo=(1, 1, 0), bc_hi=(3, 1, 0)), hlbm.EUNSUPPORTED),
     (dict(pattern="aa", block_x=512), hlbm.EUNSUPPORTED),
 ])
 def test_config_validation(kw, code):
@@ -105,10 +109,13 @@ def test_unknown_porosity_kind():
 
 
 def test_pattern_field():
-    # the in-place pattern is accepted for periodic boxes and needs the same
-    # bytes per population buffer (it keeps one buffer instead of two)
+    # the in-place pattern is accepted for periodic boxes and wall faces and
+    # needs the same bytes per population buffer (it keeps one buffer instead
+    # of two); open faces are refused
     rc, pb, db = _rb(hlbm.make_config(19, "f32", (64, 32, 16), pattern="aa"))
-    assert rc == 0 and pb == 19 * 4 * 64 * 32 * 16
+    assert rc == 0 and pb == 19 * (4 * 64 * 32 * 16 + ROW_PAD)
+    rc, _, _ = _rb(hlbm.make_config(19, "f32", (64, 32, 16), pattern="aa", bc_lo=(0, 1, 1), bc_hi=(0, 1, 1)))
+    assert rc == 0
     rc, _, _ = _rb(hlbm.make_config(9, "f16s", (64, 32, 1), pattern="aa", porosity="scalar"))
     assert rc == 0
     cfg = hlbm.make_config(19, "f32", (16, 16, 16))

@@ -51,10 +51,11 @@ def test_sweep_kernels_are_straight_line(asm):
 
 def test_in_place_kernels_are_straight_line(asm):
     aa = _kernels(asm, "_ZN4hlbm15sweep_aa_kernel")
-    # (2 lattices x 4 storages scalar + 4 storages tensor) x 2 step forms
-    assert len(aa) == 24
+    # (2 lattices x 4 storages scalar + 4 storages tensor) x 2 step forms x (periodic, walls)
+    assert len(aa) == 48
     exports = _kernels(asm, "_ZN4hlbm16aa_export_kernel")
-    assert len(exports) == 12
+    # 2 lattices x 3 element sizes x (slots of the cell; pulled, periodic; pulled, walls)
+    assert len(exports) == 18
     for name, body in {**aa, **exports}.items():
         branches = len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
         assert branches <= 1, (name, branches)

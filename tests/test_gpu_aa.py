@@ -6,8 +6,9 @@ two-buffer pull sweep, so every observable must equal the two-buffer run bit
 for bit: the state (exported to the two-buffer layout), the moments, their
 FP64 totals and the in-sweep diagnostics, after odd and even step counts,
 for every storage form, both lattices and both control kinds, at ragged sizes
-and at the full 512^3 size.  One case is also checked directly against the
-oracle, and the host-side rules of the pattern are exercised.
+and at the full 512^3 size; with wall faces (halfway bounce-back) on any set
+of axes as well.  One case is also checked directly against the oracle, and
+the host-side rules of the pattern are exercised.
 """
 import ctypes
 import os
@@ -105,20 +106,94 @@ def test_aa_equals_ab_bitwise(H, q, storage, shape, porosity):
         aa.close()
 
 
-def test_aa_diagnostics_equal_ab(H):
-    say("AA vs AB in-sweep diagnostics")
-    ab, aa = _pair(H, 19, "f32", (70, 12, 10), diag=True, seed=5)
+WALL_CASES = [
+    # q, storage, shape, porosity, wall axes (bc_lo = bc_hi; 1 = wall, 0 = periodic)
+    (9, "f64", (24, 16, 1), "scalar", (0, 1, 0)),
+    (9, "f32", (17, 12, 1), "scalar", (1, 1, 0)),
+    (19, "f64", (13, 9, 8), "scalar", (0, 1, 1)),
+    (19, "f32", (70, 9, 7), "scalar", (1, 1, 1)),
+    (19, "f16s", (40, 6, 5), "scalar", (0, 0, 1)),
+    (19, "bf16s", (33, 5, 4), "scalar", (1, 0, 0)),
+    (19, "f32", (21, 8, 6), "tensor", (0, 1, 1)),
+    (19, "f64", (9, 8, 7), "tensor", (1, 0, 1)),
+    (19, "f32", (3, 3, 3), "scalar", (1, 1, 1)),
+]
+
+
+@pytest.mark.parametrize("q,storage,shape,porosity,walls", WALL_CASES,
+                         ids=[f"q{c[0]}-{c[1]}-{c[3]}-{c[2][0]}x{c[2][1]}x{c[2][2]}-w{''.join(map(str, c[4]))}"
+                              for c in WALL_CASES])
+def test_aa_walls_equal_ab_bitwise(H, q, storage, shape, porosity, walls):
+    say(f"AA vs AB with walls {walls} D{'3Q19' if q == 19 else '2Q9'} {storage} {porosity} {shape}")
+    ab, aa = _pair(H, q, storage, shape, porosity, seed=sum(shape) + 1, bc_lo=walls, bc_hi=walls)
     try:
-        ab.step(9)
-        aa.step(9)
-        sa, ta, da = ab.read_diagnostics()
-        sb, tb, db = aa.read_diagnostics()
-        assert np.array_equal(sa, sb) and da == db == 0
-        assert np.array_equal(ta, tb)
-        _assert_same(ab, aa)
+        for n in (1, 1, 1, 14, 7):
+            ab.step(n)
+            aa.step(n)
+            _assert_same(ab, aa)
     finally:
         ab.close()
         aa.close()
+
+
+def test_aa_walls_channel_c0(H):
+    """The D2Q9 wall channel (128 x 64, walls at y = 0 and 63, d = 0.5 on rows
+    16..47), 2000 steps in place: equal to the two-buffer run bit for bit."""
+    nx, ny = 128, 64
+    say("AA vs AB, D2Q9 wall channel 128x64, 2000 steps")
+    d = np.zeros((ny, nx))
+    d[16:48] = 0.5
+    sims = [H.HLBM(9, "f64", (nx, ny, 1), tau=0.8, force=(1e-6, 0, 0), bc_lo=(0, 1, 0), bc_hi=(0, 1, 0),
+                   pattern=p) for p in ("ab", "aa")]
+    try:
+        for s in sims:
+            s.set_porosity(d.ravel())
+            s.step(2000)
+        _assert_same(*sims)
+        sims[0].step(1)
+        sims[1].step(1)
+        _assert_same(*sims)
+    finally:
+        for s in sims:
+            s.close()
+
+
+def test_aa_walls_state_export(H):
+    """get_state from either slot order, device and host, with walls."""
+    import torch
+    shape = (30, 9, 8)
+    say(f"AA state export with walls {shape}")
+    ab, aa = _pair(H, 19, "f32", shape, seed=13, bc_lo=(1, 0, 1), bc_hi=(1, 0, 1))
+    lib = H.load()
+    try:
+        for n in (3, 2):
+            ab.step(n)
+            aa.step(n)
+            snap, s = aa.get_state()
+            host = np.empty(aa.state_bytes, dtype=np.uint8)
+            assert lib.hlbm_get_state(aa.ctx, host.ctypes.data, 0, None) == 0
+            assert np.array_equal(host, snap.cpu().numpy())
+            assert torch.equal(snap, ab.get_state()[0])
+    finally:
+        ab.close()
+        aa.close()
+
+
+def test_aa_diagnostics_equal_ab(H):
+    for walls in ((0, 0, 0), (1, 1, 0)):
+        say(f"AA vs AB in-sweep diagnostics, walls {walls}")
+        ab, aa = _pair(H, 19, "f32", (70, 12, 10), diag=True, seed=5, bc_lo=walls, bc_hi=walls)
+        try:
+            ab.step(9)
+            aa.step(9)
+            sa, ta, da = ab.read_diagnostics()
+            sb, tb, db = aa.read_diagnostics()
+            assert np.array_equal(sa, sb) and da == db == 0
+            assert np.array_equal(ta, tb)
+            _assert_same(ab, aa)
+        finally:
+            ab.close()
+            aa.close()
 
 
 def test_aa_state_roundtrip_and_host_paths(H):
@@ -134,7 +209,7 @@ def test_aa_state_roundtrip_and_host_paths(H):
             ab.step(n)
             aa.step(n)
             snap, s = aa.get_state()
-            host = np.empty(aa.pop_bytes, dtype=np.uint8)
+            host = np.empty(aa.state_bytes, dtype=np.uint8)
             step = ctypes.c_longlong()
             assert lib.hlbm_get_state(aa.ctx, host.ctypes.data, 0, ctypes.byref(step)) == 0
             assert step.value == s
@@ -240,8 +315,8 @@ def test_aa_full_size_equals_ab(H, storage):
 
 def test_aa_api_rules(H):
     import torch
-    with pytest.raises(H.HLBMError, match="periodic"):
-        H.HLBM(19, "f32", (8, 8, 8), bc_lo=(0, 1, 0), bc_hi=(0, 1, 0), pattern="aa")
+    with pytest.raises(H.HLBMError, match="open faces"):
+        H.HLBM(19, "f32", (8, 8, 8), bc_lo=(2, 1, 1), bc_hi=(3, 1, 1), inlet_u=(0.01, 0, 0), pattern="aa")
     sim = H.HLBM(19, "f32", (8, 8, 8), pattern="aa")
     lib = H.load()
     try:
