@@ -66,8 +66,12 @@ TIMING_PARTS = {}   # (storage, pattern, porosity, edge) -> ms per step in five 
 
 
 def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar", edge=N_EDGE,
-              pattern="ab"):
+              pattern="ab", row_pad=None):
+    """row_pad None: the tuned population row pad for this shape (0 if none)."""
     import torch
+    from paper_2310_14746_amd import tune
+    if row_pad is None:
+        row_pad = tune.lookup_row_pad(hlbm.D3Q19, storage, (edge,) * 3, pattern)
     reps = edge // 32
     dt = np.float32 if storage == "f32" else np.float16
     if porosity == "tensor":   # d_tile: (6, 32^3) rows of D
@@ -77,7 +81,7 @@ def time_form(hlbm, storage, d_tile, steps, warmup, block_x=0, porosity="scalar"
         d = np.tile(d_tile.astype(dt), (reps, reps, reps))
     sim = hlbm.HLBM(hlbm.D3Q19, storage, (edge,) * 3, tau=TAU, force=FORCE,
                     store_scale=SCALE_16 if storage != "f32" else 1.0, block_x=block_x,
-                    porosity=porosity, pattern=pattern)
+                    porosity=porosity, pattern=pattern, row_pad=row_pad)
     try:
         sim.set_porosity(d)
         del d
@@ -532,8 +536,10 @@ def main():
         st, pattern = storage_of(f), ("aa" if f.endswith("-aa") else "ab")
         tile = inputs.round_to(d_tile, "f32" if st == "f32" else "f16")
         bx = args.block_x if args.block_x >= 0 else tune.lookup(hlbm.D3Q19, st, (N_EDGE,) * 3, pattern)
-        ms, dr, u, tot, teq = time_form(hlbm, st, tile, args.steps, args.warmup, block_x=bx, pattern=pattern)
-        results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq, block_x=bx)
+        rp = tune.lookup_row_pad(hlbm.D3Q19, st, (N_EDGE,) * 3, pattern)
+        ms, dr, u, tot, teq = time_form(hlbm, st, tile, args.steps, args.warmup, block_x=bx, pattern=pattern,
+                                        row_pad=rp)
+        results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq, block_x=bx, row_pad=rp)
     copy_ref = None if args.no_copy_reference else copy_reference()
     batched = None if args.no_batched else time_batched(hlbm)
     gradient = None if args.no_gradient else time_gradient(hlbm)
@@ -606,6 +612,7 @@ def main():
             "speedup_vs_" + head: round(results[head]["ms"] / r["ms"], 3),
             "tiles_identical": r["tiles_equal"],
             "block_x": r["block_x"],
+            "row_pad_bytes": r["row_pad"],
             "ms_per_step_parts": [round(v, 4) for v in
                                   TIMING_PARTS.get((storage_of(f), "aa" if f.endswith("-aa") else "ab", "scalar",
                                                     N_EDGE), [])],

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define HLBM_ABI_VERSION 1
+#define HLBM_ABI_VERSION 2
 
 typedef struct hlbm_ctx hlbm_ctx;
 
@@ -120,6 +120,8 @@ typedef struct {
                             for a batch, items[0].block_x is the tile, <= 512); 0 = auto */
     void *hip_stream;    /* hipStream_t for all work of this context, NULL = default */
     int porosity_kind;   /* HLBM_POROSITY_SCALAR (default) or HLBM_POROSITY_TENSOR */
+    int row_pad_bytes;   /* bytes of padding after each population row: 0 (dense, default) or a
+                            multiple of 256 up to 2^24; must be 0 for batch items */
 } hlbm_config;
 
 /* Library ABI version (HLBM_ABI_VERSION). */
@@ -141,10 +143,13 @@ int hlbm_lattice_info(int lattice, int *c, double *w);
 /* Bytes of one population buffer and of the porosity field for *cfg (six
  * rows for a tensor control).  HLBM_AB uses two such buffers, HLBM_AA one.
  * A population buffer holds Q rows; each row stores the N = nx*ny*nz cells
- * followed by 8448 bytes of padding, which offsets consecutive rows by
- * 8.25 KiB modulo any power of two, so the 19 read and 19 write streams of a
- * sweep fall on different HBM channels even when N * element size is a large
- * power of two.  The porosity rows and state snapshots are dense. */
+ * followed by row_pad_bytes of padding.  The pad shifts the rows against
+ * each other modulo every power of two, which changes how the 19 read and 19
+ * write streams of a sweep fall on the HBM channels: where N * element size
+ * is a large power of two (512^3 FP32: 512 MiB rows) an 8448-byte pad makes
+ * the sweep about 6% faster, at 256^3 any pad makes it slower, so the value is
+ * chosen per shape by measurement.  The porosity rows and state snapshots are
+ * dense whatever the pad. */
 int hlbm_required_bytes(const hlbm_config *cfg, size_t *pop_bytes, size_t *porosity_bytes);
 
 /* Validate *cfg and create a context.  Unless cfg->external_memory is set the

@@ -194,6 +194,8 @@ int validate_config(const hlbm_config* c)
         return fail(HLBM_EINVAL, "block_x must be 0 or a multiple of 64 in [64, 1024]");
     if (c->porosity_kind != HLBM_POROSITY_SCALAR && c->porosity_kind != HLBM_POROSITY_TENSOR)
         return fail(HLBM_EINVAL, "unknown porosity_kind %d", c->porosity_kind);
+    if (c->row_pad_bytes < 0 || c->row_pad_bytes > hlbm::ROW_PAD_MAX || c->row_pad_bytes % 256)
+        return fail(HLBM_EINVAL, "row_pad_bytes must be a multiple of 256 in [0, %d]", hlbm::ROW_PAD_MAX);
     if (c->porosity_kind == HLBM_POROSITY_TENSOR && c->lattice != HLBM_D3Q19)
         return fail(HLBM_EUNSUPPORTED, "a tensor porosity control needs D3Q19");
     if (c->pattern == HLBM_AA) {
@@ -216,7 +218,7 @@ void fill_params(const hlbm_config* c, Params* p)
     p->ny = c->ny;
     p->nz = c->nz;
     p->N = (uint32_t)((unsigned long long)c->nx * c->ny * c->nz);
-    p->P = hlbm::row_pitch(p->N, elem_bytes(c->storage));
+    p->P = hlbm::row_pitch(p->N, elem_bytes(c->storage), c->row_pad_bytes);
     p->omega = 1.0 / c->tau;
     p->pref = 1.0 - 0.5 / c->tau;
     for (int a = 0; a < 3; ++a) {
@@ -453,7 +455,7 @@ int hlbm_required_bytes(const hlbm_config* cfg, size_t* pop_bytes, size_t* poros
     int rc = validate_config(cfg);
     if (rc) return rc;
     const size_t n = (size_t)cfg->nx * cfg->ny * cfg->nz;
-    const size_t pitch = hlbm::row_pitch((uint32_t)n, elem_bytes(cfg->storage));
+    const size_t pitch = hlbm::row_pitch((uint32_t)n, elem_bytes(cfg->storage), cfg->row_pad_bytes);
     if (pop_bytes) *pop_bytes = pitch * (size_t)cfg->lattice * elem_bytes(cfg->storage);
     if (porosity_bytes) *porosity_bytes = n * porosity_elem_bytes(cfg->storage) * porosity_rows(cfg);
     return HLBM_OK;
@@ -1025,6 +1027,7 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
             return fail(HLBM_EUNSUPPORTED, "item %d: batch items take a scalar porosity control", k);
         if (it->storage != storage) return fail(HLBM_EINVAL, "item %d: all items share one storage", k);
         if (it->pattern != HLBM_AB) return fail(HLBM_EUNSUPPORTED, "item %d: batch items use HLBM_AB", k);
+        if (it->row_pad_bytes != 0) return fail(HLBM_EINVAL, "item %d: batch items keep dense rows (row_pad_bytes = 0)", k);
         for (int a = 0; a < 3; ++a)
             if (it->bc_lo[a] != HLBM_PERIODIC || it->bc_hi[a] != HLBM_PERIODIC)
                 return fail(HLBM_EUNSUPPORTED, "item %d: batch items are fully periodic", k);

@@ -53,17 +53,15 @@ enum BcMode {
 };
 constexpr uint32_t LINK_SOLID_SELF = 1u << 31;
 
-// Population rows are ROW_PAD_BYTES longer than their N cells.  A box whose
-// row is a large power of two (512^3 FP32: 512 MiB) otherwise starts every
-// one of the 19 rows at the same offset modulo every power of two up to the
-// row size, so the 19 concurrent read streams of a wave and the 19 write
-// streams fall on the same few HBM channels at the same time.  Shifting row i
-// by i * 8.25 KiB spreads them; the pad was chosen by timing the 512^3 FP32
-// sweep over fresh allocations (8 KiB to 8.5 KiB pads: 3.51-3.57 ms per step
-// against 3.75 ms unpadded, means over 7 allocations each).  Snapshots
+// Population rows may run `pad_bytes` past their N cells (hlbm_config::
+// row_pad_bytes, a multiple of 256).  A box whose row is a large power of two
+// (512^3 FP32: 512 MiB) otherwise starts every one of the 19 rows at the same
+// offset modulo every power of two up to the row size, and the 19 concurrent
+// read streams of a wave and the 19 write streams fall on the same HBM
+// channels together; shifting row i by i * pad spreads them.  Snapshots
 // (hlbm_get_state / hlbm_set_state) keep the dense layout of N per row.
-constexpr size_t ROW_PAD_BYTES = 8448;
-inline uint32_t row_pitch(uint32_t n, size_t elem) { return n + (uint32_t)(ROW_PAD_BYTES / elem); }
+constexpr int ROW_PAD_MAX = 1 << 24;
+inline uint32_t row_pitch(uint32_t n, size_t elem, int pad_bytes) { return n + (uint32_t)(pad_bytes / elem); }
 // Porosity control kinds: one value d per cell, or a symmetric 3x3 D (6 rows).
 enum PorosityKind { PK_SCALAR = 0, PK_TENSOR = 1 };
 

@@ -60,6 +60,7 @@ class Config(ctypes.Structure):
         ("block_x", ctypes.c_int),
         ("hip_stream", ctypes.c_void_p),
         ("porosity_kind", ctypes.c_int),
+        ("row_pad_bytes", ctypes.c_int),
     ]
 
 
@@ -149,7 +150,7 @@ def make_config(lattice: int = D3Q19, storage="f32", shape=(32, 32, 32), tau: fl
                 force=(0.0, 0.0, 0.0), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0), inlet_u=(0.0, 0.0, 0.0),
                 outlet_rho: float = 1.0, rho0: float = 1.0, store_scale: float = 1.0,
                 block_x: int = 0, external_memory: int = 0, stream: Optional[int] = None,
-                porosity: str = "scalar", pattern: str = "ab") -> Config:
+                porosity: str = "scalar", pattern: str = "ab", row_pad: int = 0) -> Config:
     cfg = Config()
     _check(load().hlbm_config_default(ctypes.byref(cfg)))
     cfg.lattice = int(lattice)
@@ -169,6 +170,7 @@ def make_config(lattice: int = D3Q19, storage="f32", shape=(32, 32, 32), tau: fl
     cfg.external_memory = int(external_memory)
     cfg.hip_stream = stream
     cfg.porosity_kind = POROSITY_KINDS[porosity]
+    cfg.row_pad_bytes = int(row_pad)
     return cfg
 
 
@@ -177,13 +179,15 @@ class HLBM:
 
     ``shape`` is (nx, ny, nz); fields returned by :meth:`moments` have shape
     (nz, ny, nx) for drho and (3, nz, ny, nx) for u.  ``pattern`` "ab" keeps two
-    population buffers; "aa" updates one in place (fully periodic boxes only).
+    population buffers; "aa" updates one in place (periodic and wall faces).
+    ``row_pad`` pads every population row by that many bytes (a multiple of
+    256; :func:`tune.lookup_row_pad` gives the measured choice for a shape).
     """
 
     def __init__(self, lattice: int = D3Q19, storage="f32", shape=(32, 32, 32), tau=0.6,
                  force=(0.0, 0.0, 0.0), bc_lo=(0, 0, 0), bc_hi=(0, 0, 0),
                  inlet_u=(0.0, 0.0, 0.0), outlet_rho=1.0, rho0=1.0, store_scale=1.0,
-                 block_x=0, device="cuda:0", porosity="scalar", pattern="ab"):
+                 block_x=0, device="cuda:0", porosity="scalar", pattern="ab", row_pad=0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -191,7 +195,8 @@ class HLBM:
         lib = load()
         self.cfg = make_config(lattice, storage, shape, tau, force, bc_lo, bc_hi, inlet_u,
                                outlet_rho, rho0, store_scale, block_x, external_memory=1,
-                               stream=self.stream.cuda_stream, porosity=porosity, pattern=pattern)
+                               stream=self.stream.cuda_stream, porosity=porosity, pattern=pattern,
+                               row_pad=row_pad)
         self.pattern = pattern
         self.q = self.cfg.lattice
         self.porosity_rows = 6 if porosity == "tensor" else 1

@@ -1,4 +1,4 @@
-"""Block-shape autotuner for the sweep.
+"""Block-shape and row-pad autotuner for the sweep.
 
 For a lattice, storage form and box shape, every candidate number of threads
 per block along x (multiples of 64 up to 1024) is timed through the C-ABI with
@@ -8,6 +8,13 @@ HIP events on the sweep's own stream; the fastest is stored in
 threads per block) and shape.  :func:`lookup` returns the stored value
 (0 = library default).
 
+The padding after each population row (hlbm_config.row_pad_bytes) decides
+how the 19 read and 19 write streams of the sweep fall on the HBM channels.
+Its effect depends on where the allocator places the buffers, so each
+candidate pad is timed over several fresh allocations, interleaved with the
+other candidates, and the lowest mean wins (``--row-pad``);
+:func:`lookup_row_pad` returns it (0 = dense rows).
+
 For a batch of periodic boxes it times the persistent kernel's schedule in
 graph mode -- tile size (cells per tile = threads per block), resident blocks
 per CU and tiles per draw -- over every combination that fits, and stores the
@@ -15,6 +22,7 @@ fastest under a key naming the storage and the batch's item shapes;
 :func:`lookup_batch` returns it (None = library defaults).
 
 Run on the target GPU:  python -m paper_2310_14746_amd.tune --shape 512 512 512
+                        python -m paper_2310_14746_amd.tune --shape 512 512 512 --row-pad
                         python -m paper_2310_14746_amd.tune --batch 256
 """
 from __future__ import annotations
@@ -34,6 +42,7 @@ def _key(lattice: int, storage: str, shape, pattern: str = "ab") -> str:
     return f"{ARCH}/{lat}/{form}/" + "x".join(str(int(v)) for v in shape)
 
 
+ROW_PADS = (0, 4352, 8448, 16640, 65792)   # bytes, multiples of 256
 BATCH_TILES = (128, 256, 512)
 BATCH_CHUNKS = (1, 2, 4)
 
@@ -57,6 +66,12 @@ def lookup(lattice: int, storage: str, shape, pattern: str = "ab") -> int:
     """Tuned threads per block along x for this case, or 0 (library default)."""
     ent = load_cache().get(_key(lattice, storage, shape, pattern))
     return int(ent["block_x"]) if ent else 0
+
+
+def lookup_row_pad(lattice: int, storage: str, shape, pattern: str = "ab") -> int:
+    """Tuned padding in bytes after each population row for this case, or 0."""
+    ent = load_cache().get(_key(lattice, storage, shape, pattern))
+    return int(ent.get("row_pad", 0)) if ent else 0
 
 
 def lookup_batch(items, storage: str = "f32"):
@@ -119,12 +134,12 @@ def tune_batch(items, storage="f32", steps=40, tiles=BATCH_TILES, chunks=BATCH_C
     return ent
 
 
-def time_block(hlbm, lattice, storage, shape, block_x, steps, warmup, pattern="ab"):
+def time_block(hlbm, lattice, storage, shape, block_x, steps, warmup, pattern="ab", row_pad=0):
     import numpy as np
     import torch
     sim = hlbm.HLBM(lattice, storage, shape, tau=0.6, force=(1e-6, 0, 0),
                     store_scale=2.0 ** 24 if storage in ("f16s", "bf16s") else 1.0,
-                    block_x=block_x, pattern=pattern)
+                    block_x=block_x, pattern=pattern, row_pad=row_pad)
     try:
         n = shape[0] * shape[1] * shape[2]
         dt = {"f64": np.float64, "f32": np.float32}.get(storage, np.float16)
@@ -166,6 +181,45 @@ def tune(lattice, storage, shape, steps=20, warmup=5, write=True, out=CACHE, pat
     return ent
 
 
+def tune_row_pad(lattice, storage, shape, pattern="ab", reps=6, steps=20, warmup=5, pads=ROW_PADS,
+                 write=True, out=CACHE):
+    """Mean time per step of each candidate pad over `reps` fresh allocations
+    (the candidates interleaved within each repetition), at the tuned block
+    width; the lowest mean is stored beside the block width."""
+    import statistics
+    import torch
+    from . import hlbm
+    hlbm.load()
+    key = _key(lattice, storage, shape, pattern)
+    bx = lookup(lattice, storage, shape, pattern)
+    times = {pad: [] for pad in pads}
+    for r in range(reps):
+        # a differently sized allocation shifts where the buffers land
+        shift = torch.empty((r * 37 + 1) << 20, dtype=torch.uint8, device="cuda")
+        for pad in pads:
+            t = time_block(hlbm, lattice, storage, shape, bx, steps, warmup, pattern, row_pad=pad)
+            times[pad].append(t)
+            print(f"[tune] {storage} {shape} {pattern} block_x={bx} row_pad={pad} rep {r}: {t:.4f} ms/step",
+                  flush=True)
+        del shift
+        torch.cuda.empty_cache()
+    means = {pad: statistics.mean(v) for pad, v in times.items()}
+    best = min(means, key=means.get)
+    res = {"row_pad": best, "row_pad_ms_per_step": round(means[best], 4),
+           "row_pad_candidates": {str(k): round(v, 4) for k, v in means.items()}}
+    if write:
+        cache = load_cache()
+        if out != CACHE and os.path.exists(out):
+            with open(out) as f:
+                cache.update(json.load(f))
+        ent = cache.get(key, {"block_x": bx})
+        ent.update(res)
+        cache[key] = ent
+        with open(out, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--shape", type=int, nargs=3, default=(512, 512, 512))
@@ -176,6 +230,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="tune the batched kernel on this many homogenized unit cells instead")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--row-pad", action="store_true",
+                    help="tune the population row pad at the stored block width instead")
+    ap.add_argument("--reps", type=int, default=6)
     ap.add_argument("--out", default=CACHE, help="cache file to write (default: the package's)")
     a = ap.parse_args()
     if a.batch:
@@ -189,7 +246,10 @@ def main():
                   flush=True)
         return
     for st in a.storage.split(","):
-        ent = tune(a.lattice, st, tuple(a.shape), steps=a.steps, out=a.out, pattern=a.pattern)
+        if a.row_pad:
+            ent = tune_row_pad(a.lattice, st, tuple(a.shape), a.pattern, reps=a.reps, steps=a.steps, out=a.out)
+        else:
+            ent = tune(a.lattice, st, tuple(a.shape), steps=a.steps, out=a.out, pattern=a.pattern)
         print(json.dumps({"storage": st, "pattern": a.pattern, **ent}), flush=True)
 
 

@@ -18,7 +18,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 15
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.hlbm_version() == 1
+    assert lib.hlbm_version() == 2
 
 
 def test_header_matches_binding_struct():
@@ -54,20 +54,20 @@ def _rb(cfg):
     return hlbm.load().hlbm_required_bytes(ctypes.byref(cfg), ctypes.byref(pb), ctypes.byref(db)), pb.value, db.value
 
 
-ROW_PAD = 8448   # bytes each population row runs past its N cells
-
-
 def test_required_bytes():
-    # population buffers: q rows of N cells plus the row pad; control rows dense
     rc, pb, db = _rb(hlbm.make_config(19, "f32", (256, 256, 256)))
-    assert rc == 0 and pb == 19 * (4 * 256 ** 3 + ROW_PAD) and db == 4 * 256 ** 3
+    assert rc == 0 and pb == 19 * 4 * 256 ** 3 and db == 4 * 256 ** 3
     rc, pb, db = _rb(hlbm.make_config(19, "f16s", (64, 32, 16), store_scale=4096.0))
-    assert rc == 0 and pb == 19 * (2 * 64 * 32 * 16 + ROW_PAD) and db == 2 * 64 * 32 * 16
+    assert rc == 0 and pb == 19 * 2 * 64 * 32 * 16 and db == 2 * 64 * 32 * 16
     rc, pb, db = _rb(hlbm.make_config(9, "f64", (128, 64, 1), bc_lo=(0, 1, 0), bc_hi=(0, 1, 0)))
-    assert rc == 0 and pb == 9 * (8 * 128 * 64 + ROW_PAD) and db == 8 * 128 * 64
+    assert rc == 0 and pb == 9 * 8 * 128 * 64 and db == 8 * 128 * 64
     # a tensor control holds six rows
     rc, pb, db = _rb(hlbm.make_config(19, "f32", (32, 16, 8), porosity="tensor"))
-    assert rc == 0 and pb == 19 * (4 * 32 * 16 * 8 + ROW_PAD) and db == 6 * 4 * 32 * 16 * 8
+    assert rc == 0 and pb == 19 * 4 * 32 * 16 * 8 and db == 6 * 4 * 32 * 16 * 8
+    # padded population rows; the control rows stay dense
+    for st, e in (("f64", 8), ("f32", 4), ("bf16s", 2)):
+        rc, pb, db = _rb(hlbm.make_config(19, st, (48, 16, 8), row_pad=8448, store_scale=2.0 ** 10))
+        assert rc == 0 and pb == 19 * (e * 48 * 16 * 8 + 8448) and db == e * 48 * 16 * 8
     rc, pb, db = _rb(hlbm.make_config(19, "bf16s", (32, 16, 8), porosity="tensor", store_scale=2.0 ** 20))
     assert rc == 0 and db == 6 * 2 * 32 * 16 * 8
 
@@ -92,6 +92,9 @@ def test_required_bytes():
     (dict(pattern="aa", bc_lo=(2, 0, 0), bc_hi=(3, 0, 0)), hlbm.EUNSUPPORTED),
     (dict(pattern="aa", bc_lo=(1, 1, 0), bc_hi=(3, 1, 0)), hlbm.EUNSUPPORTED),
     (dict(pattern="aa", block_x=512), hlbm.EUNSUPPORTED),
+    (dict(row_pad=100), hlbm.EINVAL),
+    (dict(row_pad=-256), hlbm.EINVAL),
+    (dict(row_pad=(1 << 24) + 256), hlbm.EINVAL),
 ])
 def test_config_validation(kw, code):
     args = dict(lattice=19, storage="f32", shape=(16, 16, 16))
@@ -113,7 +116,7 @@ def test_pattern_field():
     # needs the same bytes per population buffer (it keeps one buffer instead
     # of two); open faces are refused
     rc, pb, db = _rb(hlbm.make_config(19, "f32", (64, 32, 16), pattern="aa"))
-    assert rc == 0 and pb == 19 * (4 * 64 * 32 * 16 + ROW_PAD)
+    assert rc == 0 and pb == 19 * 4 * 64 * 32 * 16
     rc, _, _ = _rb(hlbm.make_config(19, "f32", (64, 32, 16), pattern="aa", bc_lo=(0, 1, 1), bc_hi=(0, 1, 1)))
     assert rc == 0
     rc, _, _ = _rb(hlbm.make_config(9, "f16s", (64, 32, 1), pattern="aa", porosity="scalar"))
@@ -149,6 +152,7 @@ def _batch_rc(items):
     (dict(shape=(1000, 1000, 8)), hlbm.EUNSUPPORTED),   # multiply-high quotient bound
     (dict(tau=0.4), hlbm.EINVAL),
     (dict(pattern="aa"), hlbm.EUNSUPPORTED),
+    (dict(row_pad=8448), hlbm.EINVAL),
 ])
 def test_batch_validation(change, code):
     base = dict(lattice=19, storage="f32", shape=(32, 32, 32), tau=0.7)

@@ -13,6 +13,8 @@ def test_keys_distinguish_pattern_and_batch():
     assert ka != kb and ka.startswith("gfx950/batch/D3Q19/f32/2items-143360cells-")
     assert tune._batch_key("f32", a) == ka
     assert tune.lookup(19, "f32", (3, 5, 7)) == 0
+    assert tune.lookup_row_pad(19, "f32", (3, 5, 7)) == 0
+    assert all(p % 256 == 0 for p in tune.ROW_PADS) and 0 in tune.ROW_PADS
     assert tune.lookup_batch([dict(shape=(3, 5, 7))]) is None
 
 
@@ -25,4 +27,7 @@ def test_stored_entries_are_launchable():
             assert ent["blocks_per_cu"] >= 1 and 1 <= ent["chunk"] <= 64, key
         else:
             cap = 256 if "-aa/" in key else 1024
-            assert ent["block_x"] % 64 == 0 and 64 <= ent["block_x"] <= cap, key
+            # 0: the library's default width (an entry that only carries a row pad)
+            assert ent["block_x"] % 64 == 0 and 0 <= ent["block_x"] <= cap, key
+            pad = ent.get("row_pad", 0)
+            assert pad % 256 == 0 and 0 <= pad <= 1 << 24, key
