@@ -157,16 +157,24 @@ def time_block(hlbm, lattice, storage, shape, block_x, steps, warmup, pattern="a
         sim.close()
 
 
-def tune(lattice, storage, shape, steps=20, warmup=5, write=True, out=CACHE, pattern="ab"):
+def tune(lattice, storage, shape, steps=20, warmup=5, write=True, out=CACHE, pattern="ab", reps=1):
+    """Time every block width at the stored row pad, over `reps` fresh
+    allocations (the widths interleaved within each repetition); keep the
+    lowest mean."""
+    import statistics
     from . import hlbm
     hlbm.load()
     nx = shape[0]
     cap = 256 if pattern == "aa" else 1024
     cands = [b for b in CANDIDATES if b <= min(cap, max(64, ((nx + 63) // 64) * 64))]
-    times = {}
-    for b in cands:
-        times[b] = time_block(hlbm, lattice, storage, shape, b, steps, warmup, pattern)
-        print(f"[tune] {storage} {shape} block_x={b}: {times[b]:.4f} ms/step", flush=True)
+    pad = lookup_row_pad(lattice, storage, shape, pattern)
+    runs = {b: [] for b in cands}
+    for r in range(reps):
+        for b in cands:
+            t = time_block(hlbm, lattice, storage, shape, b, steps, warmup, pattern, row_pad=pad)
+            runs[b].append(t)
+            print(f"[tune] {storage} {shape} row_pad={pad} block_x={b} rep {r}: {t:.4f} ms/step", flush=True)
+    times = {b: statistics.mean(v) for b, v in runs.items()}
     best = min(times, key=times.get)
     ent = {"block_x": best, "ms_per_step": round(times[best], 4),
            "candidates": {str(k): round(v, 4) for k, v in times.items()}}
@@ -175,6 +183,8 @@ def tune(lattice, storage, shape, steps=20, warmup=5, write=True, out=CACHE, pat
         if out != CACHE and os.path.exists(out):
             with open(out) as f:
                 cache.update(json.load(f))
+        old = cache.get(_key(lattice, storage, shape, pattern), {})
+        ent.update({k: v for k, v in old.items() if k.startswith("row_pad")})
         cache[_key(lattice, storage, shape, pattern)] = ent
         with open(out, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
@@ -232,7 +242,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--row-pad", action="store_true",
                     help="tune the population row pad at the stored block width instead")
-    ap.add_argument("--reps", type=int, default=6)
+    ap.add_argument("--reps", type=int, default=None,
+                    help="fresh allocations per candidate (default: 6 for --row-pad, 1 for block widths)")
     ap.add_argument("--out", default=CACHE, help="cache file to write (default: the package's)")
     a = ap.parse_args()
     if a.batch:
@@ -247,9 +258,9 @@ def main():
         return
     for st in a.storage.split(","):
         if a.row_pad:
-            ent = tune_row_pad(a.lattice, st, tuple(a.shape), a.pattern, reps=a.reps, steps=a.steps, out=a.out)
+            ent = tune_row_pad(a.lattice, st, tuple(a.shape), a.pattern, reps=a.reps or 6, steps=a.steps, out=a.out)
         else:
-            ent = tune(a.lattice, st, tuple(a.shape), steps=a.steps, out=a.out, pattern=a.pattern)
+            ent = tune(a.lattice, st, tuple(a.shape), steps=a.steps, out=a.out, pattern=a.pattern, reps=a.reps or 1)
         print(json.dumps({"storage": st, "pattern": a.pattern, **ent}), flush=True)
 
 
