@@ -284,7 +284,8 @@ def test_aa_full_size_equals_ab(H, storage):
     from paper_2310_14746_amd import tune
     kw = dict(tau=0.6, force=(1e-6, -2e-7, 0), store_scale=SCALE16)
     # each pattern at the block width bench.py times it with
-    sims = [H.HLBM(19, storage, (n, n, n), pattern=p, block_x=tune.lookup(19, storage, (n, n, n), p), **kw)
+    sims = [H.HLBM(19, storage, (n, n, n), pattern=p, block_x=tune.lookup(19, storage, (n, n, n), p),
+                   row_pad=tune.lookup_row_pad(19, storage, (n, n, n), p), **kw)
             for p in ("ab", "aa")]
     try:
         for s in sims:

@@ -113,12 +113,14 @@ def _tiles_equal(t, tile):
 def _full_size_tile_check(H, n, storage, steps, scale=1.0):
     import torch
     from paper_2310_14746_amd import tune
-    bx = tune.lookup(19, storage, (n, n, n))    # the launch configuration bench.py times
-    say(f"full size D3Q19 {storage} {n}^3 x {steps} steps (tile check), block_x {bx or 'auto'}")
+    # the launch configuration and layout bench.py times
+    bx = tune.lookup(19, storage, (n, n, n))
+    pad = tune.lookup_row_pad(19, storage, (n, n, n))
+    say(f"full size D3Q19 {storage} {n}^3 x {steps} steps (tile check), block_x {bx or 'auto'}, row pad {pad}")
     dt = "f32" if storage == "f32" else "f16"
     dtile = inputs.round_to(inputs.sphere_array_tile(), dt)
     d = np.tile(dtile, (n // 32,) * 3)
-    kw = dict(tau=0.6, force=(1e-6, 0, 0), store_scale=scale, block_x=bx)
+    kw = dict(tau=0.6, force=(1e-6, 0, 0), store_scale=scale, block_x=bx, row_pad=pad)
     sim = H.HLBM(19, storage, (n, n, n), **kw)
     try:
         sim.set_porosity(d.astype(np.float32 if dt == "f32" else np.float16))

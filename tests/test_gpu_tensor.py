@@ -100,8 +100,11 @@ def test_fibre_tensor_sphere_array_full_size(H):
     tile_d = inputs.sphere_array(32)
     tile_D6 = inputs.round_to(inputs.fiber_tensor_field(tile_d), "f32")
     D6 = np.stack([np.tile(r.reshape(32, 32, 32), (n // 32,) * 3).ravel() for r in tile_D6])
+    from paper_2310_14746_amd import tune
+    # the launch configuration and layout bench.py times for the tensor form
     kw = dict(tau=0.6, force=(1e-6, 0, 0))
-    sim = H.HLBM(19, "f32", (n, n, n), porosity="tensor", **kw)
+    launch = dict(block_x=tune.lookup(19, "f32", (n, n, n)), row_pad=tune.lookup_row_pad(19, "f32", (n, n, n)))
+    sim = H.HLBM(19, "f32", (n, n, n), porosity="tensor", **kw, **launch)
     try:
         sim.set_porosity(torch.from_numpy(D6.astype(np.float32)).cuda())
         del D6
