@@ -72,12 +72,15 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
                                 S::load_d(ld(dfield + 5 * (size_t)N, cell))};
         collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
     }
+    // The in-place steps use plain stores: the lines they write were read into
+    // L2 by the same step, and there the non-temporal hint cost about 3% (FP32,
+    // 512^3) where in the two-buffer sweep it gains about 2%.
     if (BC == BC_AA_EVEN || BC == BC_AA_EVEN_W) {
         // post-collision population i into this cell's slot opp(i); a solid
         // cell stores zeros there
 #pragma unroll
         for (int i = 0; i < L::Q; ++i)
-            st_stream(dst + (size_t)opposite(i) * P, cell, S::store(sel(solid, R(0), g[i]), scale));
+            st(dst + (size_t)opposite(i) * P, cell, S::store(sel(solid, R(0), g[i]), scale));
     } else if (BC == BC_AA_ODD_W) {
         // post-collision population i into slot i of x + c_i, or into this
         // cell's own slot opp(i) where x + c_i is solid; a solid cell stores
@@ -87,7 +90,7 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
         for (int i = 0; i < L::Q; ++i) {
             uint32_t row, off;
             aa_odd_target_walls<L>(b, (int)x, (int)y, (int)z, solid, i, row, off);
-            st_stream(dst + (size_t)row * P, off, S::store(sel(solid, R(0), g[i]), scale));
+            st(dst + (size_t)row * P, off, S::store(sel(solid, R(0), g[i]), scale));
         }
     } else if (BC == BC_AA_ODD) {
         // post-collision population i into slot i of x + c_i
@@ -98,7 +101,7 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
             const uint32_t off = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
-            st_stream(dst + (size_t)i * P, off, S::store(g[i], scale));
+            st(dst + (size_t)i * P, off, S::store(g[i], scale));
         }
     } else {
         // solid cells (wall layers, masked cells) hold zeros; selected, not branched
