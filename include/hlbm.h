@@ -288,7 +288,11 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  *
  * The forward states are recovered from a tape: with a tape set, hlbm_step
  * stores the state every `every` steps (checkpoints); the reverse sweep
- * recomputes each segment of `every` steps from its checkpoint.  The tape
+ * recomputes each segment of `every` steps from its checkpoint.  The replay
+ * of the segment below runs on a second stream of the library's own (default
+ * priority) while the reverse steps of the current segment run on the
+ * context's stream; events order the two, and hlbm_adjoint_step waits for
+ * both before it returns.  The tape
  * records from the state current when it is set and restarts at the current
  * state whenever the state or the porosity changes otherwise (hlbm_set_state,
  * hlbm_reset, hlbm_set_porosity, hlbm_bind_buffers).
@@ -298,9 +302,9 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
 
 /* Allocate a tape for up to `max_steps` forward steps with a checkpoint every
  * `every` >= 1 steps, and start recording at the current state.  Device memory:
- * (max_steps/every + 1) checkpoints and every-1 replay states, each one
- * population buffer, plus two adjoint buffers of Q*N values (8 bytes each for
- * HLBM_F64, else 4).  every = 0
+ * (max_steps/every + 1) checkpoints and 2 * (every - 1) replay states (two
+ * segments, replayed alternately), each one population buffer, plus two
+ * adjoint buffers of Q*N values (8 bytes each for HLBM_F64, else 4).  every = 0
  * frees the tape.  hlbm_step returns EINVAL (and does nothing) if it would
  * take the recorded steps past max_steps.  Waits for the stream. */
 int hlbm_set_tape(hlbm_ctx *ctx, int every, int max_steps);

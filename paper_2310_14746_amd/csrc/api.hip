@@ -76,8 +76,15 @@ struct hlbm_ctx {
     long long tape_origin;
     int tape_ncp;
     char* tape_cps;
-    char* tape_seg;
+    char* tape_seg;      // two sets of every-1 replay states (segments alternate between them)
     char* tape_lam[2];
+    // The reverse sweep replays the segment below the current one on a second
+    // stream while the adjoint steps of the current one run on `stream`;
+    // replayed[k] marks set k's replay done, consumed[k] the adjoint steps that
+    // last read set k.
+    hipStream_t tape_stream;
+    hipEvent_t replayed[2];
+    hipEvent_t consumed[2];
     // in-sweep diagnostics (hlbm_set_diagnostics): FP64 totals of the time
     // levels n with n % diag_every == 0, appended to a device log
     int diag_every;
@@ -315,8 +322,16 @@ int aa_get_state(hlbm_ctx* c, void* dst, int on_device, long long* step)
 
 void tape_free(hlbm_ctx* c)
 {
+    if (c->tape_stream) (void)hipStreamSynchronize(c->tape_stream);
     if (c->tape_cps) (void)hipFree(c->tape_cps);
     if (c->tape_seg) (void)hipFree(c->tape_seg);
+    for (int k = 0; k < 2; ++k) {
+        if (c->replayed[k]) (void)hipEventDestroy(c->replayed[k]);
+        if (c->consumed[k]) (void)hipEventDestroy(c->consumed[k]);
+        c->replayed[k] = c->consumed[k] = nullptr;
+    }
+    if (c->tape_stream) (void)hipStreamDestroy(c->tape_stream);
+    c->tape_stream = nullptr;
     for (int k = 0; k < 2; ++k)
         if (c->tape_lam[k]) (void)hipFree(c->tape_lam[k]);
     c->tape_cps = nullptr;
@@ -898,9 +913,15 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
     const int ncp = max_steps / every + 1;
     const size_t lam_bytes = (size_t)c->p.N * (size_t)c->q * lam_elem;
     e = hipMalloc(&c->tape_cps, (size_t)ncp * c->pop_bytes);
-    if (e == hipSuccess && every > 1) e = hipMalloc(&c->tape_seg, (size_t)(every - 1) * c->pop_bytes);
+    if (e == hipSuccess && every > 1) e = hipMalloc(&c->tape_seg, 2 * (size_t)(every - 1) * c->pop_bytes);
     if (e == hipSuccess) e = hipMalloc(&c->tape_lam[0], lam_bytes);
     if (e == hipSuccess) e = hipMalloc(&c->tape_lam[1], lam_bytes);
+    // default priority (a stream of another priority is never used here)
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->tape_stream, hipStreamNonBlocking);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = hipEventCreateWithFlags(&c->replayed[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->consumed[k], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
         tape_free(c);
         return fail(HLBM_ENOMEM, "tape allocation (%d checkpoints of %zu bytes): %s", ncp, c->pop_bytes,
@@ -922,7 +943,7 @@ int hlbm_tape_info(const hlbm_ctx* c, int* every, int* max_steps, long long* rec
     if (device_bytes) {
         size_t b = 0;
         if (c->tape_every)
-            b = (size_t)(c->tape_ncp + c->tape_every - 1) * c->pop_bytes +
+            b = (size_t)(c->tape_ncp + 2 * (c->tape_every - 1)) * c->pop_bytes +
                 2 * (size_t)c->p.N * (size_t)c->q * hlbm::adjoint_elem_bytes(c->cfg.storage);
         *device_bytes = b;
     }
@@ -962,36 +983,56 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
     }
     const int K = c->tape_every;
     const int q = c->q, storage = c->cfg.storage, bc = c->bcmode, pk = c->cfg.porosity_kind;
-    // state with index r (relative to the tape origin) of the replayed segment
-    auto seg_state = [&](long long r) -> const void* {
-        const long long m = r / K, j = r - m * K;
+    // State j of segment m (index m*K + j relative to the tape origin): the
+    // checkpoint for j = 0, else replay state j - 1 of set m & 1.
+    auto state = [&](long long m, long long j) -> char* {
         if (j == 0) return c->tape_cps + (size_t)m * c->pop_bytes;
-        return c->tape_seg + (size_t)(j - 1) * c->pop_bytes;
+        return c->tape_seg + ((size_t)(m & 1) * (size_t)(K - 1) + (size_t)(j - 1)) * c->pop_bytes;
+    };
+    // Reverse steps t = R0 .. tlo + 1 read the states r = t - 1 in [tlo, R0 - 1].
+    const long long tlo = R0 - nsteps;
+    // Replay segment m on the replay stream into set m & 1: states 1 .. jmax
+    // (the highest one a reverse step of this call reads), after the reverse
+    // steps that last read that set.
+    auto replay = [&](long long m) -> hipError_t {
+        const int k = (int)(m & 1);
+        hipError_t r = hipStreamWaitEvent(c->tape_stream, c->consumed[k], 0);
+        const long long jmax = (R0 - 1 - m * K < K - 1) ? R0 - 1 - m * K : K - 1;
+        for (long long j = 1; j <= jmax && r == hipSuccess; ++j)
+            r = hlbm::launch_sweep(q, storage, bc, pk, c->p, state(m, j - 1), state(m, j), c->dfield, c->bx,
+                                   c->tape_stream);
+        if (r == hipSuccess) r = hipEventRecord(c->replayed[k], c->tape_stream);
+        return r;
     };
     int a = 0;
-    if (e == hipSuccess && nsteps > 0)
+    if (e == hipSuccess && nsteps > 0) {
         e = hlbm::launch_adjoint_seed(q, storage, bc, c->p, c->pop[c->cur], gr, gu, c->tape_lam[a], c->bx,
                                       c->stream);
-    long long seg_loaded = -1;
-    for (long long t = R0; e == hipSuccess && t > R0 - nsteps; --t) {
-        const long long r = t - 1;  // the step t reads x_{t-1}
-        const long long m = r / K;
-        if (m != seg_loaded) {
-            // replay segment m from its checkpoint up to the last state needed
-            const long long jmax = (r - m * K);
-            for (long long j = 1; j <= jmax && e == hipSuccess; ++j)
-                e = hlbm::launch_sweep(q, storage, bc, pk, c->p, seg_state(m * K + j - 1),
-                                       const_cast<void*>(seg_state(m * K + j)), c->dfield, c->bx, c->stream);
-            seg_loaded = m;
+        // both replay sets free, and the replay stream ordered after all work
+        // queued so far (the forward steps that wrote the checkpoints)
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventRecord(c->consumed[k], c->stream);
+        const long long mhi = (R0 - 1) / K, mlo = tlo / K;
+        if (e == hipSuccess && K > 1) e = replay(mhi);
+        for (long long m = mhi; e == hipSuccess && m >= mlo; --m) {
+            // the segment below replays while this one's reverse steps run
+            if (K > 1 && m - 1 >= mlo) e = replay(m - 1);
+            if (e == hipSuccess && K > 1) e = hipStreamWaitEvent(c->stream, c->replayed[m & 1], 0);
+            const long long thi = (R0 < m * K + K) ? R0 : m * K + K;
+            const long long tmin = (tlo + 1 > m * K + 1) ? tlo + 1 : m * K + 1;
+            for (long long t = thi; e == hipSuccess && t >= tmin; --t) {
+                e = hlbm::launch_adjoint(q, storage, bc, pk, c->p, c->tape_lam[a], c->tape_lam[a ^ 1],
+                                         state(m, t - 1 - m * K), c->dfield, gd, c->bx, c->stream);
+                a ^= 1;
+            }
+            if (e == hipSuccess && K > 1) e = hipEventRecord(c->consumed[m & 1], c->stream);
         }
-        if (e == hipSuccess)
-            e = hlbm::launch_adjoint(q, storage, bc, pk, c->p, c->tape_lam[a], c->tape_lam[a ^ 1], seg_state(r),
-                                     c->dfield, gd, c->bx, c->stream);
-        a ^= 1;
     }
     if (e == hipSuccess && tmp)
         e = hipMemcpyAsync(dJ_dd, gd, rows * n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    // after a failed launch the replay stream may still hold queued replays
+    const hipError_t e2 = hipStreamSynchronize(c->tape_stream);
+    if (e == hipSuccess) e = e2;
     if (tmp) (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(e, "adjoint");
     return HLBM_OK;
