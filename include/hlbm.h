@@ -121,7 +121,8 @@ typedef struct {
     void *hip_stream;    /* hipStream_t for all work of this context, NULL = default */
     int porosity_kind;   /* HLBM_POROSITY_SCALAR (default) or HLBM_POROSITY_TENSOR */
     int row_pad_bytes;   /* bytes of padding after each population row: 0 (dense, default) or a
-                            multiple of 256 up to 2^24; must be 0 for batch items */
+                            multiple of 256 up to 2^24; for a batch, items[0] pads the packed
+                            rows and the other items must give 0 */
 } hlbm_config;
 
 /* Library ABI version (HLBM_ABI_VERSION). */

@@ -1068,7 +1068,8 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
             return fail(HLBM_EUNSUPPORTED, "item %d: batch items take a scalar porosity control", k);
         if (it->storage != storage) return fail(HLBM_EINVAL, "item %d: all items share one storage", k);
         if (it->pattern != HLBM_AB) return fail(HLBM_EUNSUPPORTED, "item %d: batch items use HLBM_AB", k);
-        if (it->row_pad_bytes != 0) return fail(HLBM_EINVAL, "item %d: batch items keep dense rows (row_pad_bytes = 0)", k);
+        if (k > 0 && it->row_pad_bytes != 0)
+            return fail(HLBM_EINVAL, "item %d: items[0].row_pad_bytes pads the packed rows; the others must be 0", k);
         for (int a = 0; a < 3; ++a)
             if (it->bc_lo[a] != HLBM_PERIODIC || it->bc_hi[a] != HLBM_PERIODIC)
                 return fail(HLBM_EUNSUPPORTED, "item %d: batch items are fully periodic", k);
@@ -1098,12 +1099,13 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
     c->p.ny = 1;
     c->p.nz = 1;
     c->p.N = (uint32_t)ntot;
-    c->p.P = (uint32_t)ntot;  // the packed items keep dense rows
+    // items[0].row_pad_bytes pads the packed population rows (validated above)
+    c->p.P = hlbm::row_pitch((uint32_t)ntot, elem_bytes(storage), items[0].row_pad_bytes);
     c->bx = 256;
     c->elem = elem_bytes(storage);
     c->delem = porosity_elem_bytes(storage);
-    c->pop_bytes = (size_t)ntot * 19 * c->elem;
-    c->state_bytes = c->pop_bytes;
+    c->pop_bytes = (size_t)c->p.P * 19 * c->elem;
+    c->state_bytes = (size_t)ntot * 19 * c->elem;
     c->stream = static_cast<hipStream_t>(items[0].hip_stream);
     c->own_mem = true;
     c->gsteps[0] = c->gsteps[1] = -1;
@@ -1167,7 +1169,7 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
     c->bl.tile_item = c->tile_item_dev;
     c->bl.n_items = (uint32_t)n_items;
     c->bl.ntiles = (uint32_t)ntiles;
-    c->bl.Ntot = (uint32_t)ntot;
+    c->bl.Ntot = c->p.P;  // row stride of the packed populations
     c->bl.rho0 = c->p.rho0;
     c->bl.scale = c->p.scale;
     c->bl.sync = c->bar_sync;

@@ -4,7 +4,9 @@
 // steps.
 //
 // Layout: the items' cells are packed one after another, x fastest inside an
-// item, and each population row spans all items: buf[i*Ntot + base_k + local].
+// item, and each population row spans all items: buf[i*Ntot + base_k + local]
+// (Ntot: the packed cells plus the row pad, hlbm_config::row_pad_bytes of
+// items[0]).
 // The packed cells are cut into tiles of `tile` consecutive cells (one block
 // of `tile` threads; the block size of every batched launch) that never
 // straddle two items (a tile's tail past the item's end is masked).

@@ -215,7 +215,8 @@ struct BatchItem {
 struct BatchLaunch {
     const BatchItem* items;     // device, n_items
     const uint32_t* tile_item;  // device, ntiles
-    uint32_t n_items, ntiles, Ntot;
+    uint32_t n_items, ntiles;
+    uint32_t Ntot;              // population row stride: packed cells plus the row pad
     double rho0, scale;
     unsigned long long* sync;   // device: [0] barrier arrivals, [1] work chunks taken
     int* err;                   // device error flag

@@ -443,11 +443,12 @@ class HLBMBatch:
     and ``force``.  The library owns the packed device memory; torch supplies
     the stream.  ``tile`` (cells per tile = threads per block, 0 = 256),
     ``blocks_per_cu`` and ``chunk`` (0 = defaults) set the persistent kernel's
-    schedule; results do not depend on it.
+    schedule, ``row_pad`` the padding in bytes after each packed population
+    row; results depend on neither.
     """
 
     def __init__(self, items, storage="f32", store_scale=1.0, rho0=1.0, mode="graph",
-                 device="cuda:0", tile=0, blocks_per_cu=0, chunk=0):
+                 device="cuda:0", tile=0, blocks_per_cu=0, chunk=0, row_pad=0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -458,7 +459,7 @@ class HLBMBatch:
         for k, it in enumerate(items):
             c = make_config(D3Q19, storage, it["shape"], it["tau"], it.get("force", (0, 0, 0)),
                             rho0=rho0, store_scale=store_scale, stream=self.stream.cuda_stream,
-                            block_x=tile if k == 0 else 0)
+                            block_x=tile if k == 0 else 0, row_pad=row_pad if k == 0 else 0)
             arr[k] = c
         self.items = [dict(shape=tuple(int(v) for v in it["shape"]), tau=float(it["tau"]),
                            force=tuple(float(v) for v in it.get("force", (0, 0, 0))))

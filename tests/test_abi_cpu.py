@@ -152,7 +152,7 @@ def _batch_rc(items):
     (dict(shape=(1000, 1000, 8)), hlbm.EUNSUPPORTED),   # multiply-high quotient bound
     (dict(tau=0.4), hlbm.EINVAL),
     (dict(pattern="aa"), hlbm.EUNSUPPORTED),
-    (dict(row_pad=8448), hlbm.EINVAL),
+    (dict(row_pad=8448), hlbm.EINVAL),        # only items[0] carries the pad
 ])
 def test_batch_validation(change, code):
     base = dict(lattice=19, storage="f32", shape=(32, 32, 32), tau=0.7)

@@ -317,3 +317,29 @@ def test_barrier_bound_error_path(H):
             assert np.array_equal(b.get_state()[0].cpu().numpy(), ref)
         finally:
             b.close()
+
+
+@pytest.mark.parametrize("pad", [256, 8448])
+def test_padded_batch_rows_bitwise(H, pad):
+    """Padding the packed population rows (items[0].row_pad_bytes) changes
+    only where the rows sit: state, totals and per-item moments equal the
+    dense-row run bit for bit in every launch mode."""
+    fields = _fields(ITEMS, 12)
+    steps = 17
+    ref, ref_mom, ref_tot = _run_batch(H, ITEMS, fields, steps, "per_step")
+    for mode in ("graph", "persistent", "per_step"):
+        b = H.HLBMBatch(ITEMS, "f32", mode=mode, row_pad=pad)
+        try:
+            for k, d in enumerate(fields):
+                b.set_porosity(k, d)
+            b.step(steps)
+            b.sync()
+            st = b.get_state()[0].cpu().numpy()
+            tot = b.totals()
+            mom = [tuple(x.cpu().numpy() for x in b.moments(k)) for k in range(len(ITEMS))]
+        finally:
+            b.close()
+        say(f"row pad {pad}, mode {mode}")
+        assert np.array_equal(st, ref) and np.array_equal(tot, ref_tot), mode
+        for k in range(len(ITEMS)):
+            assert np.array_equal(mom[k][0], ref_mom[k][0]) and np.array_equal(mom[k][1], ref_mom[k][1]), (mode, k)
