@@ -1,0 +1,58 @@
+"""Boxes at the size limits of the library (FP32 population rows just under
+4 GiB), checked by a property that holds at any size: with a uniform control
+d the scheme keeps rho = rho0 and every cell follows the uniform-Darcy
+transient u_n = F tau/d - (F tau/d - F/2)(1 - d/tau)^n exactly (in FP64; FP32
+storage within 1e-5).  The FP64 moment fields of these boxes are larger than
+4 GiB, so any 32-bit wrap of an index would leave cells unwritten or
+overwritten, which the field-wide min/max comparisons catch.
+
+* in place (AA), 1024 x 1024 x 1023 = 1,072,693,248 cells: the largest FP32
+  box (19 x 4 x N bytes = 81.5 GB in one buffer), 9 steps;
+* two buffers, 1024 x 1024 x 520 = 545,259,520 cells (> 2^29), 7 steps.
+"""
+import numpy as np
+import pytest
+
+from tests.test_gpu_parity import H, say  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+TAU, D = 0.6, 0.3
+F = (1e-6, 2e-7, 0.0)
+
+
+def _exact(n, d):
+    return [Fa * TAU / d - (Fa * TAU / d - 0.5 * Fa) * (1.0 - d / TAU) ** n for Fa in F]
+
+
+@pytest.mark.parametrize("shape,pattern,steps", [((1024, 1024, 1023), "aa", 9),
+                                                 ((1024, 1024, 520), "ab", 7)])
+def test_uniform_darcy_at_maximum_size(H, shape, pattern, steps):
+    import torch
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    assert n * 4 < 2 ** 32 and (n > 2 ** 29)
+    say(f"maximum size {shape} ({n} cells), {pattern}, {steps} steps")
+    sim = H.HLBM(19, "f32", shape, tau=TAU, force=F, pattern=pattern)
+    try:
+        d = torch.full((n,), D, dtype=torch.float32, device="cuda")
+        d32 = float(d[0].item())
+        sim.set_porosity(d)
+        del d
+        sim.step(steps)
+        drho, u, tot = sim.moments("f64", totals=True)
+        assert drho.numel() * 8 > 2 ** 32
+        ex = _exact(steps, d32)
+        say(f"drho in [{float(drho.min()):.3e}, {float(drho.max()):.3e}]; exact u {ex}")
+        assert float(drho.abs().max()) <= 1e-9
+        for a in range(3):
+            lo, hi = float(u[a].min()), float(u[a].max())
+            say(f"u[{a}] in [{lo:.9e}, {hi:.9e}]")
+            scale = max(abs(ex[0]), 1e-30)
+            assert abs(lo - ex[a]) <= 1e-5 * scale and abs(hi - ex[a]) <= 1e-5 * scale
+        # the FP64 totals: sum rho u_x over all cells
+        assert abs(tot[1] - n * ex[0]) <= 1e-5 * n * abs(ex[0])
+        del drho, u
+    finally:
+        sim.close()
+        torch.cuda.empty_cache()
