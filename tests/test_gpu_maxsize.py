@@ -8,9 +8,10 @@ overwritten, which the field-wide min/max comparisons catch.
 
 * in place (AA), 1024 x 1024 x 1023 = 1,072,693,248 cells: the largest FP32
   box (19 x 4 x N bytes = 81.5 GB in one buffer), 9 steps;
-* two buffers, 1024 x 1024 x 520 = 545,259,520 cells (> 2^29), 7 steps.
+* two buffers, 1024 x 1024 x 520 = 545,259,520 cells (> 2^29), 7 steps;
+* the adjoint of one step on 1024 x 1024 x 513 cells (FP64 gradient rows
+  above 4 GiB) against its closed form.
 """
-import numpy as np
 import pytest
 
 from tests.test_gpu_parity import H, say  # noqa: F401
@@ -53,6 +54,39 @@ def test_uniform_darcy_at_maximum_size(H, shape, pattern, steps):
         # the FP64 totals: sum rho u_x over all cells
         assert abs(tot[1] - n * ex[0]) <= 1e-5 * n * abs(ex[0])
         del drho, u
+    finally:
+        sim.close()
+        torch.cuda.empty_cache()
+
+
+def test_adjoint_gradient_rows_above_4gib(H):
+    """The reverse sweep over a box of more than 2^29 cells (FP64 cotangent and
+    gradient rows larger than 4 GiB), 16-bit storage so that the tape fits:
+    one step from rest with a uniform control gives u_1 = 3F/2 - F d/(2 tau)
+    in every cell, so for J = sum over cells of u_x every cell's dJ/dd equals
+    -F_x/(2 tau) (translation invariance: the per-cell derivatives sum to
+    dJ/dd of the uniform control)."""
+    import torch
+    shape = (1024, 1024, 513)
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    assert n * 8 > 2 ** 32
+    say(f"adjoint at {shape} ({n} cells), f16s, one step")
+    sim = H.HLBM(19, "f16s", shape, tau=TAU, force=F, store_scale=2.0 ** 14)
+    try:
+        sim.set_porosity(torch.full((n,), D, dtype=torch.float16, device="cuda"))
+        sim.set_tape(1, 1)
+        sim.step(1)
+        gr = torch.zeros(n, dtype=torch.float64, device="cuda")
+        gu = torch.zeros(3 * n, dtype=torch.float64, device="cuda")
+        gu[:n] = 1.0
+        g = sim.adjoint(1, gr, gu)
+        del gr, gu
+        ex = -F[0] / (2 * TAU)
+        lo, hi = float(g.min()), float(g.max())
+        say(f"dJ/dd in [{lo:.9e}, {hi:.9e}], exact {ex:.9e}")
+        assert abs(lo - ex) <= 1e-6 * abs(ex) and abs(hi - ex) <= 1e-6 * abs(ex)
+        del g
     finally:
         sim.close()
         torch.cuda.empty_cache()
