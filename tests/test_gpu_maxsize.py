@@ -34,6 +34,7 @@ def test_uniform_darcy_at_maximum_size(H, shape, pattern, steps):
     n = nx * ny * nz
     assert n * 4 < 2 ** 32 and (n > 2 ** 29)
     say(f"maximum size {shape} ({n} cells), {pattern}, {steps} steps")
+    torch.cuda.empty_cache()   # memory cached by earlier tests
     sim = H.HLBM(19, "f32", shape, tau=TAU, force=F, pattern=pattern)
     try:
         d = torch.full((n,), D, dtype=torch.float32, device="cuda")
@@ -72,6 +73,7 @@ def test_adjoint_gradient_rows_above_4gib(H):
     n = nx * ny * nz
     assert n * 8 > 2 ** 32
     say(f"adjoint at {shape} ({n} cells), f16s, one step")
+    torch.cuda.empty_cache()   # memory cached by earlier tests
     sim = H.HLBM(19, "f16s", shape, tau=TAU, force=F, store_scale=2.0 ** 14)
     try:
         sim.set_porosity(torch.full((n,), D, dtype=torch.float16, device="cuda"))
