@@ -149,8 +149,10 @@ int hlbm_lattice_info(int lattice, int *c, double *w);
  * write streams of a sweep fall on the HBM channels: where N * element size
  * is a large power of two (512^3 FP32: 512 MiB rows) an 8448-byte pad makes
  * the sweep about 6% faster, at 256^3 any pad makes it slower, so the value is
- * chosen per shape by measurement.  The porosity rows and state snapshots are
- * dense whatever the pad. */
+ * chosen per shape by measurement.  The six rows of a tensor control take the
+ * same pitch (porosity_bytes = 6 * (N * element size + row_pad_bytes)); a
+ * scalar control is one dense row.  State snapshots are dense whatever the
+ * pad. */
 int hlbm_required_bytes(const hlbm_config *cfg, size_t *pop_bytes, size_t *porosity_bytes);
 
 /* Validate *cfg and create a context.  Unless cfg->external_memory is set the

@@ -248,15 +248,15 @@ struct AdjTensor {
     static constexpr int rows = 6;
     double xx, yy, zz, xy, xz, yz;
     template <class S>
-    __device__ __forceinline__ static AdjTensor load(const typename S::D* __restrict__ f, uint32_t N,
+    __device__ __forceinline__ static AdjTensor load(const typename S::D* __restrict__ f, uint32_t pitch,
                                                      uint32_t cell)
     {
         return AdjTensor{(double)S::load_d(ld(f, cell)),
-                         (double)S::load_d(ld(f + (size_t)N, cell)),
-                         (double)S::load_d(ld(f + 2 * (size_t)N, cell)),
-                         (double)S::load_d(ld(f + 3 * (size_t)N, cell)),
-                         (double)S::load_d(ld(f + 4 * (size_t)N, cell)),
-                         (double)S::load_d(ld(f + 5 * (size_t)N, cell))};
+                         (double)S::load_d(ld(f + (size_t)pitch, cell)),
+                         (double)S::load_d(ld(f + 2 * (size_t)pitch, cell)),
+                         (double)S::load_d(ld(f + 3 * (size_t)pitch, cell)),
+                         (double)S::load_d(ld(f + 4 * (size_t)pitch, cell)),
+                         (double)S::load_d(ld(f + 5 * (size_t)pitch, cell))};
     }
     __device__ __forceinline__ void eq(double ux, double uy, double uz, double& vx, double& vy, double& vz) const
     {
@@ -370,7 +370,7 @@ __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in,
     const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
     const Moms m = forward_moments<L, S, BC>(xprev, p, x, y, z);
     using Sh = AdjShift<PK>;
-    const Sh sh = Sh::template load<S>(dfield, N, cell);
+    const Sh sh = Sh::template load<S>(dfield, p.P, cell);  // control rows are P apart
     double pb[L::Q];
     bool solid = false;
     if (BC == BC_PERIODIC) {

@@ -163,6 +163,14 @@ size_t porosity_elem_bytes(int storage)
 
 int porosity_rows(const hlbm_config* c) { return c->porosity_kind == HLBM_POROSITY_TENSOR ? 6 : 1; }
 
+// Bytes of the porosity field: one dense row for a scalar control; six rows at
+// the population row pitch for a tensor control.
+size_t porosity_field_bytes(const hlbm_config* c, uint32_t n, uint32_t pitch)
+{
+    const size_t e = porosity_elem_bytes(c->storage);
+    return porosity_rows(c) == 1 ? (size_t)n * e : 6 * (size_t)pitch * e;
+}
+
 int validate_config(const hlbm_config* c)
 {
     if (!c) return fail(HLBM_EINVAL, "config is NULL");
@@ -472,7 +480,7 @@ int hlbm_required_bytes(const hlbm_config* cfg, size_t* pop_bytes, size_t* poros
     const size_t n = (size_t)cfg->nx * cfg->ny * cfg->nz;
     const size_t pitch = hlbm::row_pitch((uint32_t)n, elem_bytes(cfg->storage), cfg->row_pad_bytes);
     if (pop_bytes) *pop_bytes = pitch * (size_t)cfg->lattice * elem_bytes(cfg->storage);
-    if (porosity_bytes) *porosity_bytes = n * porosity_elem_bytes(cfg->storage) * porosity_rows(cfg);
+    if (porosity_bytes) *porosity_bytes = porosity_field_bytes(cfg, (uint32_t)n, (uint32_t)pitch);
     return HLBM_OK;
 }
 
@@ -502,7 +510,7 @@ int hlbm_create(const hlbm_config* cfg, hlbm_ctx** out)
     if (c->own_mem) {
         hipError_t e = hipMalloc(&c->pop[0], c->pop_bytes);
         if (e == hipSuccess && !c->aa) e = hipMalloc(&c->pop[1], c->pop_bytes);
-        if (e == hipSuccess) e = hipMalloc(&c->dfield, (size_t)c->p.N * c->delem * porosity_rows(cfg));
+        if (e == hipSuccess) e = hipMalloc(&c->dfield, porosity_field_bytes(cfg, c->p.N, c->p.P));
         if (e != hipSuccess) {
             hlbm_destroy(c);
             return fail(HLBM_ENOMEM, "device allocation of %zu bytes per buffer failed: %s",
@@ -605,7 +613,7 @@ int hlbm_set_porosity(hlbm_ctx* c, const void* d, int dtype, int on_device)
         }
         src = tmp;
     }
-    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, c->cfg.porosity_kind, c->dfield, (uint32_t)n,
+    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, c->cfg.porosity_kind, c->dfield, (uint32_t)n, c->p.P,
                                       c->flag_out,
                                       c->stream);
     int flag = 0;
@@ -1276,7 +1284,7 @@ int hlbm_batch_set_porosity(hlbm_ctx* c, int item, const void* d, int dtype, int
         src = tmp;
     }
     void* out = static_cast<char*>(c->dfield) + (size_t)it.base * c->delem;
-    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, hlbm::PK_SCALAR, out, (uint32_t)n, c->flag_out,
+    e = hlbm::launch_porosity_convert(dtype, src, c->cfg.storage, hlbm::PK_SCALAR, out, (uint32_t)n, (uint32_t)n, c->flag_out,
                                       c->stream);
     int flag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, c->flag_out, sizeof(int), hipMemcpyDeviceToHost, c->stream);

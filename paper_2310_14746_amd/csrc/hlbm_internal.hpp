@@ -182,8 +182,9 @@ hipError_t launch_reduce4(const double* partials, uint32_t nblocks, double* stag
                           hipStream_t s);
 // Convert and validate the porosity; *flag (device) ends nonzero if any value
 // is NaN or outside [0, 1].
+// A tensor control's six rows are written `pitch` elements apart.
 hipError_t launch_porosity_convert(int in_dtype, const void* in, int storage, int pk, void* out,
-                                   uint32_t n, int* flag, hipStream_t s);
+                                   uint32_t n, uint32_t pitch, int* flag, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Batched periodic boxes

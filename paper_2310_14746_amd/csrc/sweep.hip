@@ -30,7 +30,7 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
                                            typename S::R& ux, typename S::R& uy, typename S::R& uz)
 {
     using R = typename S::R;
-    const uint32_t N = p.N, P = p.P;  // control rows hold N values; population rows are P apart
+    const uint32_t P = p.P;  // population rows, and the rows of a tensor control, are P elements apart
     const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
     const R inv_scale = R(p.inv_scale), scale = R(p.scale);
     const R F0 = R(p.F[0]), F1 = R(p.F[1]), F2 = R(p.F[2]);
@@ -64,12 +64,13 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
         collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
     } else {
         // six rows xx, yy, zz, xy, xz, yz of the symmetric control D
+        // (rows P apart, like the population rows)
         const TensorShift<R> sh{S::load_d(ld(dfield, cell)),
-                                S::load_d(ld(dfield + (size_t)N, cell)),
-                                S::load_d(ld(dfield + 2 * (size_t)N, cell)),
-                                S::load_d(ld(dfield + 3 * (size_t)N, cell)),
-                                S::load_d(ld(dfield + 4 * (size_t)N, cell)),
-                                S::load_d(ld(dfield + 5 * (size_t)N, cell))};
+                                S::load_d(ld(dfield + (size_t)P, cell)),
+                                S::load_d(ld(dfield + 2 * (size_t)P, cell)),
+                                S::load_d(ld(dfield + 3 * (size_t)P, cell)),
+                                S::load_d(ld(dfield + 4 * (size_t)P, cell)),
+                                S::load_d(ld(dfield + 5 * (size_t)P, cell))};
         collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
     }
     // The in-place steps use plain stores: the lines they write were read into
@@ -417,10 +418,11 @@ __device__ __forceinline__ bool psd3(double a, double b, double c, double ab, do
            (det >= tol);
 }
 
+// The six output rows are `pitch` elements apart (the population row pitch).
 template <class I, class O>
 __global__ __launch_bounds__(256) void tensor_porosity_kernel(const I* __restrict__ in,
                                                               O* __restrict__ out, uint32_t n,
-                                                              int* __restrict__ flag)
+                                                              uint32_t pitch, int* __restrict__ flag)
 {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     int bad = 0;
@@ -429,7 +431,7 @@ __global__ __launch_bounds__(256) void tensor_porosity_kernel(const I* __restric
         for (int r = 0; r < 6; ++r) {
             v[r] = (double)in[(size_t)r * n + k];
             bad |= !(v[r] == v[r]) | !(v[r] - v[r] == 0.0);  // NaN or infinite
-            out[(size_t)r * n + k] = O(in[(size_t)r * n + k]);
+            out[(size_t)r * pitch + k] = O(in[(size_t)r * n + k]);
         }
         const bool ok = psd3(v[0], v[1], v[2], v[3], v[4], v[5]) &&
                         psd3(1.0 - v[0], 1.0 - v[1], 1.0 - v[2], -v[3], -v[4], -v[5]);
@@ -752,32 +754,32 @@ static hipError_t porosity_dispatch_out(const void* in, int storage, void* out, 
 }
 
 template <class I>
-static hipError_t tensor_dispatch_out(const void* in, int storage, void* out, uint32_t n, int* flag,
-                                      hipStream_t s)
+static hipError_t tensor_dispatch_out(const void* in, int storage, void* out, uint32_t n, uint32_t pitch,
+                                      int* flag, hipStream_t s)
 {
     const uint32_t nb = (n + 255) / 256;
     auto* src = static_cast<const I*>(in);
     if (storage == StoreF64::code)
         hipLaunchKernelGGL((tensor_porosity_kernel<I, double>), dim3(nb), dim3(256), 0, s, src,
-                           static_cast<double*>(out), n, flag);
+                           static_cast<double*>(out), n, pitch, flag);
     else if (storage == StoreF32::code)
         hipLaunchKernelGGL((tensor_porosity_kernel<I, float>), dim3(nb), dim3(256), 0, s, src,
-                           static_cast<float*>(out), n, flag);
+                           static_cast<float*>(out), n, pitch, flag);
     else
         hipLaunchKernelGGL((tensor_porosity_kernel<I, _Float16>), dim3(nb), dim3(256), 0, s, src,
-                           static_cast<_Float16*>(out), n, flag);
+                           static_cast<_Float16*>(out), n, pitch, flag);
     return hipGetLastError();
 }
 
 hipError_t launch_porosity_convert(int in_dtype, const void* in, int storage, int pk, void* out,
-                                   uint32_t n, int* flag, hipStream_t s)
+                                   uint32_t n, uint32_t pitch, int* flag, hipStream_t s)
 {
     hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), s);
     if (e != hipSuccess) return e;
     if (pk == PK_TENSOR) {
-        if (in_dtype == 0) return tensor_dispatch_out<double>(in, storage, out, n, flag, s);
-        if (in_dtype == 1) return tensor_dispatch_out<float>(in, storage, out, n, flag, s);
-        return tensor_dispatch_out<_Float16>(in, storage, out, n, flag, s);
+        if (in_dtype == 0) return tensor_dispatch_out<double>(in, storage, out, n, pitch, flag, s);
+        if (in_dtype == 1) return tensor_dispatch_out<float>(in, storage, out, n, pitch, flag, s);
+        return tensor_dispatch_out<_Float16>(in, storage, out, n, pitch, flag, s);
     }
     if (in_dtype == 0) return porosity_dispatch_out<double>(in, storage, out, n, flag, s);
     if (in_dtype == 1) return porosity_dispatch_out<float>(in, storage, out, n, flag, s);

@@ -64,10 +64,14 @@ def test_required_bytes():
     # a tensor control holds six rows
     rc, pb, db = _rb(hlbm.make_config(19, "f32", (32, 16, 8), porosity="tensor"))
     assert rc == 0 and pb == 19 * 4 * 32 * 16 * 8 and db == 6 * 4 * 32 * 16 * 8
-    # padded population rows; the control rows stay dense
+    # padded population rows; a scalar control stays one dense row, the six
+    # rows of a tensor control take the population pitch
     for st, e in (("f64", 8), ("f32", 4), ("bf16s", 2)):
         rc, pb, db = _rb(hlbm.make_config(19, st, (48, 16, 8), row_pad=8448, store_scale=2.0 ** 10))
         assert rc == 0 and pb == 19 * (e * 48 * 16 * 8 + 8448) and db == e * 48 * 16 * 8
+        rc, pb, db = _rb(hlbm.make_config(19, st, (48, 16, 8), row_pad=8448, store_scale=2.0 ** 10,
+                                          porosity="tensor"))
+        assert rc == 0 and db == 6 * (e * 48 * 16 * 8 + 8448)
     rc, pb, db = _rb(hlbm.make_config(19, "bf16s", (32, 16, 8), porosity="tensor", store_scale=2.0 ** 20))
     assert rc == 0 and db == 6 * 2 * 32 * 16 * 8
 
