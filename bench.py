@@ -582,6 +582,8 @@ def main():
                         f"sigma=2), tau={TAU}, F=1e-6 x, {head} storage, A/B buffers",
             "cells": n_cells,
             "storage": head,
+            "block_x": results[head]["block_x"],
+            "row_pad_bytes": results[head]["row_pad"],
             "parallelism": "1 GPU",
         },
         "roofline": {
