@@ -269,10 +269,12 @@ __device__ __forceinline__ void moments_of(const R (&g)[L::Q], R F0, R F1, R F2,
 
 // ---------------------------------------------------------------------------
 // Pull gather, fully periodic box: g*_i(x) = g_i(x - c_i) with wrap.  The box
-// starts at cell `base` of the population rows (0 for a single lattice).
+// starts at cell `base` of the population rows (0 for a single lattice).  In
+// all gathers below, population row i starts P elements after row i - 1
+// (the row pitch: N cells plus the row pad).
 // ---------------------------------------------------------------------------
 template <class L, class S>
-__device__ __forceinline__ void gather_periodic(const typename S::T* __restrict__ src, uint32_t N,
+__device__ __forceinline__ void gather_periodic(const typename S::T* __restrict__ src, uint32_t P,
                                                 uint32_t base, uint32_t nx, uint32_t ny, uint32_t nz,
                                                 uint32_t x, uint32_t y, uint32_t z,
                                                 typename S::R inv_scale, typename S::R (&g)[L::Q])
@@ -284,23 +286,23 @@ __device__ __forceinline__ void gather_periodic(const typename S::T* __restrict_
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const uint32_t off = base + xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
-        g[i] = S::load(ld(src + (size_t)i * N, off), inv_scale);
+        g[i] = S::load(ld(src + (size_t)i * P, off), inv_scale);
     }
 }
 
 // AA pattern, even step: the cell's own slots hold its pulled populations.
 template <class L, class S>
-__device__ __forceinline__ void gather_aa_even(const typename S::T* src, uint32_t N, uint32_t cell,
+__device__ __forceinline__ void gather_aa_even(const typename S::T* src, uint32_t P, uint32_t cell,
                                                typename S::R inv_scale, typename S::R (&g)[L::Q])
 {
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) g[i] = S::load(ld(src + (size_t)i * N, cell), inv_scale);
+    for (int i = 0; i < L::Q; ++i) g[i] = S::load(ld(src + (size_t)i * P, cell), inv_scale);
 }
 
 // AA pattern, odd step: population i arrives from slot opp(i) of x - c_i
 // (where the even step left the post-collision population i), with wrap.
 template <class L, class S>
-__device__ __forceinline__ void gather_aa_odd(const typename S::T* src, uint32_t N, uint32_t nx, uint32_t ny,
+__device__ __forceinline__ void gather_aa_odd(const typename S::T* src, uint32_t P, uint32_t nx, uint32_t ny,
                                               uint32_t nz, uint32_t x, uint32_t y, uint32_t z,
                                               typename S::R inv_scale, typename S::R (&g)[L::Q])
 {
@@ -310,7 +312,7 @@ __device__ __forceinline__ void gather_aa_odd(const typename S::T* src, uint32_t
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const uint32_t off = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
-        g[i] = S::load(ld(src + (size_t)opposite(i) * N, off), inv_scale);
+        g[i] = S::load(ld(src + (size_t)opposite(i) * P, off), inv_scale);
     }
 }
 
@@ -391,7 +393,7 @@ struct OpenFaces {
 //     to this cell (always in bounds) and the value is replaced.
 // ---------------------------------------------------------------------------
 template <class L, class S>
-__device__ __forceinline__ void gather_general(const typename S::T* __restrict__ src, uint32_t N,
+__device__ __forceinline__ void gather_general(const typename S::T* __restrict__ src, uint32_t P,
                                                const Box& b, const OpenFaces<typename S::R>& of,
                                                int x, int y, int z, typename S::R inv_scale,
                                                typename S::R (&g)[L::Q])
@@ -403,7 +405,7 @@ __device__ __forceinline__ void gather_general(const typename S::T* __restrict__
     R rho_b = of.rho0, jbx = R(0), jby = R(0), jbz = R(0);
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
-        const R gk = S::load(ld(src + (size_t)k * N, cell), inv_scale);
+        const R gk = S::load(ld(src + (size_t)k * P, cell), inv_scale);
         rho_b += gk;
         if (L::cx[k]) jbx += L::cx[k] > 0 ? gk : -gk;
         if (L::cy[k]) jby += L::cy[k] > 0 ? gk : -gk;
@@ -424,7 +426,7 @@ __device__ __forceinline__ void gather_general(const typename S::T* __restrict__
         const uint32_t noff = (uint32_t)sx + (uint32_t)b.nx * ((uint32_t)sy + (uint32_t)b.ny * (uint32_t)sz);
         const uint32_t row = sel(wall, (uint32_t)opposite(i), (uint32_t)i);
         const uint32_t off = sel(wall | outside, cell, noff);
-        const R loaded = S::load(ld(src + (size_t)row * N, off), inv_scale);
+        const R loaded = S::load(ld(src + (size_t)row * P, off), inv_scale);
         const int kx = sel(sx < 0, b.lo0, b.hi0);
         const int ky = sel(sy < 0, b.lo1, b.hi1);
         const int kz = sel(sz < 0, b.lo2, b.hi2);
@@ -448,7 +450,7 @@ __device__ __forceinline__ void gather_general(const typename S::T* __restrict__
 // in bounds.
 // ---------------------------------------------------------------------------
 template <class L, class S>
-__device__ __forceinline__ void gather_aa_odd_walls(const typename S::T* src, uint32_t N, const Box& b, int x,
+__device__ __forceinline__ void gather_aa_odd_walls(const typename S::T* src, uint32_t P, const Box& b, int x,
                                                     int y, int z, typename S::R inv_scale,
                                                     typename S::R (&g)[L::Q])
 {
@@ -464,7 +466,7 @@ __device__ __forceinline__ void gather_aa_odd_walls(const typename S::T* src, ui
         const uint32_t noff = (uint32_t)sx + (uint32_t)b.nx * ((uint32_t)sy + (uint32_t)b.ny * (uint32_t)sz);
         const uint32_t row = sel(own, (uint32_t)i, (uint32_t)opposite(i));
         const uint32_t off = sel(own, cell, noff);
-        g[i] = S::load(ld(src + (size_t)row * N, off), inv_scale);
+        g[i] = S::load(ld(src + (size_t)row * P, off), inv_scale);
     }
 }
 
@@ -496,7 +498,7 @@ __device__ __forceinline__ void aa_odd_target_walls(const Box& b, int x, int y, 
 // whether the cell itself is solid.
 // ---------------------------------------------------------------------------
 template <class L, class S>
-__device__ __forceinline__ bool gather_masked(const typename S::T* __restrict__ src, uint32_t N,
+__device__ __forceinline__ bool gather_masked(const typename S::T* __restrict__ src, uint32_t P,
                                               const uint32_t* __restrict__ linkmask, uint32_t nx,
                                               uint32_t ny, uint32_t nz, uint32_t x, uint32_t y,
                                               uint32_t z, typename S::R inv_scale,
@@ -513,7 +515,7 @@ __device__ __forceinline__ bool gather_masked(const typename S::T* __restrict__ 
         const uint32_t noff = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
         const uint32_t row = sel(back, (uint32_t)opposite(i), (uint32_t)i);
         const uint32_t off = sel(back, cell, noff);
-        g[i] = S::load(ld(src + (size_t)row * N, off), inv_scale);
+        g[i] = S::load(ld(src + (size_t)row * P, off), inv_scale);
     }
     return (lm & LINK_SOLID_SELF) != 0u;
 }
