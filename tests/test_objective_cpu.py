@@ -25,6 +25,6 @@ def test_value_and_gradient_match_oracle():
         t = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in (drho, u, d)]
         J = channel_objective(t[0], t[1], t[2], tau)
         J.backward()
-        assert abs(float(J) - J_o) <= 1e-13 * abs(J_o)
+        assert abs(float(J.detach()) - J_o) <= 1e-13 * abs(J_o)
         for got, want in zip((t[0].grad, t[1].grad, t[2].grad), (gr, gu, gd)):
             np.testing.assert_allclose(got.numpy(), want, rtol=1e-12, atol=1e-15 * np.abs(want).max())
