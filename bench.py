@@ -386,15 +386,18 @@ def time_tensor(hlbm, steps, warmup, block_x):
             "rel_l2_drho_vs_fp64": float("%.3e" % rel_l2_drho(dr, dr_o, u_o))}
 
 
-def time_adjoint_large(hlbm, edge=256, steps=40, every=10, porosity="scalar"):
+def time_adjoint_large(hlbm, edge=256, steps=40, every=10, porosity="scalar", row_pad=None):
     """Reverse sweep on a large periodic box (the sphere array, FP32 forward,
     FP32 adjoint populations, FP64 gradient): time of hlbm_adjoint_step over
     `steps` steps, which also replays the forward inside each checkpoint
     segment.  Shows the adjoint kernel away from the small-domain limits of the
     128x64x64 workload.  porosity="tensor": the fibre tensor of the same array
-    (six gradient rows)."""
+    (six gradient rows).  row_pad: bytes after each population and adjoint
+    row (None: the tuned pad of the FP32 sweep at this shape)."""
     import torch
-    from paper_2310_14746_amd import inputs
+    from paper_2310_14746_amd import inputs, tune
+    if row_pad is None:
+        row_pad = tune.lookup_row_pad(hlbm.D3Q19, "f32", (edge,) * 3)
     reps = edge // 32
     tensor = porosity == "tensor"
     if tensor:
@@ -403,7 +406,8 @@ def time_adjoint_large(hlbm, edge=256, steps=40, every=10, porosity="scalar"):
     else:
         field = np.tile(inputs.sphere_array_tile(), (reps, reps, reps))
     field = inputs.round_to(field, "f32").astype(np.float32)
-    sim = hlbm.HLBM(hlbm.D3Q19, "f32", (edge,) * 3, tau=TAU, force=FORCE, porosity=porosity)
+    sim = hlbm.HLBM(hlbm.D3Q19, "f32", (edge,) * 3, tau=TAU, force=FORCE, porosity=porosity,
+                    row_pad=row_pad)
     try:
         sim.set_porosity(field)
         sim.set_tape(every, steps)
@@ -429,7 +433,8 @@ def time_adjoint_large(hlbm, edge=256, steps=40, every=10, porosity="scalar"):
     what = "periodic sphere array with the fibre tensor" if tensor else "periodic sphere array"
     return {"workload": f"D3Q19 {edge}^3 {what}, {steps} reverse steps, checkpoint every {every}",
             "ms": round(ms, 2), "ms_per_reverse_step": round(ms / steps, 4),
-            "alg_GBs": round(moved / (ms * 1e-3) / 1e9, 1), "replay_steps": replays}
+            "alg_GBs": round(moved / (ms * 1e-3) / 1e9, 1), "replay_steps": replays,
+            "row_pad_bytes": row_pad}
 
 
 def time_c1(hlbm, block_x):

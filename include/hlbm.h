@@ -307,7 +307,9 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * `every` >= 1 steps, and start recording at the current state.  Device memory:
  * (max_steps/every + 1) checkpoints and 2 * (every - 1) replay states (two
  * segments, replayed alternately), each one population buffer, plus two
- * adjoint buffers of Q*N values (8 bytes each for HLBM_F64, else 4).  every = 0
+ * adjoint buffers of Q rows of P values (P = N + row_pad_bytes divided by the
+ * storage's element size, the population row pitch; 8 bytes each for
+ * HLBM_F64, else 4).  every = 0
  * frees the tape.  hlbm_step returns EINVAL (and does nothing) if it would
  * take the recorded steps past max_steps.  Waits for the stream. */
 int hlbm_set_tape(hlbm_ctx *ctx, int every, int max_steps);

@@ -30,8 +30,8 @@
 //     (mass kept, momentum (1 - omega) j + omega rho u_eq + (1 - 1/(2 tau)) F),
 //     so x_t itself is never read.
 //
-// Layout: adjoint populations are rows lam[k*N + cell] (the forward state's
-// layout), FP64 for the FP64 form and FP32 for the others; all adjoint
+// Layout: adjoint populations are rows lam[k*P + cell], P elements apart like
+// the forward state's rows, FP64 for the FP64 form and FP32 for the others; all adjoint
 // arithmetic is FP64 and dJ/dd is one FP64 value per cell and control row,
 // accumulated.  Blocks
 // hold at most 256 threads (the FP64 adjoint needs more registers than a
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* 
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         const double v = base + double(L::cx[k]) * bx + double(L::cy[k]) * by + double(L::cz[k]) * bz;
-        st(lam + (size_t)k * N, cell, LamT<S>(sel(solid, 0.0, v)));
+        st(lam + (size_t)k * p.P, cell, LamT<S>(sel(solid, 0.0, v)));
     }
 }
 
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* 
 // adjoint of the next step's pre-collision populations.
 // ---------------------------------------------------------------------------
 template <class L, class LT>
-__device__ __forceinline__ void stream_adjoint_periodic(const LT* __restrict__ lam, uint32_t N,
+__device__ __forceinline__ void stream_adjoint_periodic(const LT* __restrict__ lam, uint32_t P,
                                                         const Params& p, uint32_t x, uint32_t y,
                                                         uint32_t z, double (&pb)[L::Q])
 {
@@ -138,7 +138,7 @@ __device__ __forceinline__ void stream_adjoint_periodic(const LT* __restrict__ l
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         const uint32_t off = xs[L::cx[k] + 1] + nx * (ys[L::cy[k] + 1] + ny * zs[L::cz[k] + 1]);
-        pb[k] = (double)ld(lam + (size_t)k * N, off);
+        pb[k] = (double)ld(lam + (size_t)k * P, off);
     }
 }
 
@@ -146,7 +146,7 @@ __device__ __forceinline__ void stream_adjoint_periodic(const LT* __restrict__ l
 // post-collision density and velocity j_b/rho_b at the forward step whose
 // open-face equilibria are being differentiated.
 template <class L, class LT>
-__device__ __forceinline__ void stream_adjoint_general(const LT* __restrict__ lam, uint32_t N,
+__device__ __forceinline__ void stream_adjoint_general(const LT* __restrict__ lam, uint32_t P,
                                                        const Params& p, int x, int y, int z,
                                                        double rho_b, double ubx, double uby,
                                                        double ubz, double (&pb)[L::Q])
@@ -173,7 +173,7 @@ __device__ __forceinline__ void stream_adjoint_general(const LT* __restrict__ la
         const uint32_t noff = (uint32_t)sx + (uint32_t)b.nx * ((uint32_t)sy + (uint32_t)b.ny * (uint32_t)sz);
         const uint32_t row = sel(own, (uint32_t)opposite(k), (uint32_t)k);
         const uint32_t off = sel(own, cell, noff);
-        const double v = (double)ld(lam + (size_t)row * N, off);
+        const double v = (double)ld(lam + (size_t)row * P, off);
         const bool open = outside & !wall;
         pb[k] = sel(open, 0.0, v);
         // open face: v is the adjoint of this cell's pre-collision population
@@ -374,7 +374,7 @@ __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in,
     double pb[L::Q];
     bool solid = false;
     if (BC == BC_PERIODIC) {
-        stream_adjoint_periodic<L, LamT<S>>(lam_in, N, p, x, y, z, pb);
+        stream_adjoint_periodic<L, LamT<S>>(lam_in, p.P, p, x, y, z, pb);
     } else {
         // post-collision moments of this cell at step t (balance laws)
         const double rho = p.rho0 + m.s, inv_rho = 1.0 / rho;
@@ -384,14 +384,14 @@ __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in,
         const double jbx = (1.0 - om) * m.jx + rvx + p.pref * p.F[0];
         const double jby = (1.0 - om) * m.jy + rvy + p.pref * p.F[1];
         const double jbz = (1.0 - om) * m.jz + rvz + p.pref * p.F[2];
-        stream_adjoint_general<L, LamT<S>>(lam_in, N, p, (int)x, (int)y, (int)z, rho, jbx * inv_rho,
+        stream_adjoint_general<L, LamT<S>>(lam_in, p.P, p, (int)x, (int)y, (int)z, rho, jbx * inv_rho,
                                   jby * inv_rho, jbz * inv_rho, pb);
         solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
     }
     double g[Sh::rows];
     collide_adjoint<L>(m, sh, p, pb, g);
 #pragma unroll
-    for (int k = 0; k < L::Q; ++k) st(lam_out + (size_t)k * N, cell, LamT<S>(sel(solid, 0.0, pb[k])));
+    for (int k = 0; k < L::Q; ++k) st(lam_out + (size_t)k * p.P, cell, LamT<S>(sel(solid, 0.0, pb[k])));
 #pragma unroll
     for (int r = 0; r < Sh::rows; ++r) {
         // FP64 gradient rows can pass 4 GiB: 64-bit indexing

@@ -919,7 +919,8 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
     if ((unsigned long long)c->p.N * lam_elem >= (1ull << 32))
         return fail(HLBM_EUNSUPPORTED, "an adjoint population row (nx*ny*nz elements) must be < 4 GiB");
     const int ncp = max_steps / every + 1;
-    const size_t lam_bytes = (size_t)c->p.N * (size_t)c->q * lam_elem;
+    // adjoint rows take the population row pitch P (in elements of the adjoint type)
+    const size_t lam_bytes = (size_t)c->p.P * (size_t)c->q * lam_elem;
     e = hipMalloc(&c->tape_cps, (size_t)ncp * c->pop_bytes);
     if (e == hipSuccess && every > 1) e = hipMalloc(&c->tape_seg, 2 * (size_t)(every - 1) * c->pop_bytes);
     if (e == hipSuccess) e = hipMalloc(&c->tape_lam[0], lam_bytes);
@@ -952,7 +953,7 @@ int hlbm_tape_info(const hlbm_ctx* c, int* every, int* max_steps, long long* rec
         size_t b = 0;
         if (c->tape_every)
             b = (size_t)(c->tape_ncp + 2 * (c->tape_every - 1)) * c->pop_bytes +
-                2 * (size_t)c->p.N * (size_t)c->q * hlbm::adjoint_elem_bytes(c->cfg.storage);
+                2 * (size_t)c->p.P * (size_t)c->q * hlbm::adjoint_elem_bytes(c->cfg.storage);
         *device_bytes = b;
     }
     return HLBM_OK;
