@@ -88,22 +88,32 @@ def test_padded_rows_bitwise_equal_dense(H, case):
         assert np.array_equal(ref[-1][0], got[-1][0]) and np.array_equal(ref[-1][1], got[-1][1])
 
 
-def test_padded_rows_adjoint_equal_dense(H):
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_padded_rows_adjoint_equal_dense(H, storage):
+    """The adjoint rows take the population pitch P too (P counts storage
+    elements; FP16S keeps FP32 adjoint rows, so their pad is twice as many
+    bytes); the tape's device bytes follow it."""
     shape = (40, 12, 10)
     nx, ny, nz = shape
-    say("adjoint gradient with padded rows, 40x12x10 channel")
+    n = nx * ny * nz
+    say(f"adjoint gradient with padded rows, 40x12x10 channel, {storage}")
     kw = dict(tau=0.6, bc_lo=(2, 1, 1), bc_hi=(3, 1, 1), inlet_u=(0.02, 0, 0))
+    elem, dt, scale = {"f32": (4, np.float32, 1.0), "f16s": (2, np.float16, 2.0 ** 14)}[storage]
     d = smooth_noise((nz, ny, nx), seed=3).ravel()
     rng = np.random.default_rng(4)
-    a, b = rng.standard_normal(nx * ny * nz), rng.standard_normal((3, nx * ny * nz))
+    a, b = rng.standard_normal(n), rng.standard_normal((3, n))
     grads = []
     for pad in (0, 8448):
-        sim = H.HLBM(19, "f32", shape, row_pad=pad, **kw)
+        sim = H.HLBM(19, storage, shape, row_pad=pad, store_scale=scale, **kw)
         try:
-            sim.set_porosity(d.astype(np.float32))
+            sim.set_porosity(d.astype(dt))
             sim.set_tape(6, 30)
+            pitch = n + pad // elem
+            # 6 checkpoints + 2 x 5 replay states, two FP32 adjoint buffers
+            assert sim.tape_info()["device_bytes"] == 16 * 19 * pitch * elem + 2 * 19 * pitch * 4
             sim.step(30)
             grads.append(sim.adjoint(30, a, b).cpu().numpy())
         finally:
             sim.close()
+    assert np.any(grads[0])
     assert np.array_equal(grads[0], grads[1])
