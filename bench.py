@@ -315,7 +315,7 @@ ADJ_BYTES = 19 * 4 * 2 + 19 * 4 + 4 + 16  # adjoint kernel, FP32 form: lam in/ou
 ADJT_BYTES = 19 * 4 * 2 + 19 * 4 + 6 * 4 + 6 * 16  # tensor control: six rows of D and of dJ/dD
 
 
-def time_gradient(hlbm, steps=500, every=50, seed=0):
+def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4):
     """Differentiation workload: D3Q19 128x64x64 channel, inlet u = 0.02,
     outlet rho = 1, walls in y and z, d ~ U[0,1), FP32 forward / FP64 adjoint,
     500 steps with a checkpoint every 50; gradient of the channel objective
@@ -332,7 +332,7 @@ def time_gradient(hlbm, steps=500, every=50, seed=0):
         d = torch.tensor(inputs.uniform_noise((nz, ny, nx), seed), dtype=torch.float64,
                          device=sim.device, requires_grad=True)
         times = []
-        for rep in range(4):
+        for rep in range(max(2, reps)):
             d.grad = None
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -508,6 +508,11 @@ def main():
     ap.add_argument("--no-gradient", action="store_true")
     ap.add_argument("--no-tensor", action="store_true")
     ap.add_argument("--no-c1", action="store_true")
+    ap.add_argument("--no-adjoint-large", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=2000,
+                    help="steps of the batched workload (2000 is the workload; fewer for profiling runs)")
+    ap.add_argument("--gradient-reps", type=int, default=4,
+                    help="forward+backward repetitions of the gradient workload (the first is untimed)")
     ap.add_argument("--block-x", type=int, default=-1,
                     help="threads per block along x (-1: tuned value, 0: library default)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -546,9 +551,9 @@ def main():
                                         row_pad=rp)
         results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq, block_x=bx, row_pad=rp)
     copy_ref = None if args.no_copy_reference else copy_reference()
-    batched = None if args.no_batched else time_batched(hlbm)
-    gradient = None if args.no_gradient else time_gradient(hlbm)
-    if gradient is not None:
+    batched = None if args.no_batched else time_batched(hlbm, steps=args.batched_steps)
+    gradient = None if args.no_gradient else time_gradient(hlbm, reps=args.gradient_reps)
+    if gradient is not None and not args.no_adjoint_large:
         gradient["large_periodic"] = time_adjoint_large(hlbm)
         gradient["large_periodic_tensor"] = time_adjoint_large(hlbm, porosity="tensor")
     c1 = None if args.no_c1 else time_c1(hlbm, tune.lookup(hlbm.D3Q19, "f32", (256,) * 3))
