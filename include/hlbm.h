@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define HLBM_ABI_VERSION 2
+#define HLBM_ABI_VERSION 3
 
 typedef struct hlbm_ctx hlbm_ctx;
 
@@ -243,8 +243,8 @@ int hlbm_sync(hlbm_ctx *ctx);
  * Solid cells hold zeros and report zero moments; the porosity control still
  * applies in fluid cells.  mask = NULL removes the obstacles.  The link mask
  * (4 bytes per cell) is built on the device.  EUNSUPPORTED unless every face
- * is periodic, for HLBM_AA or for a batch; ESTATE while an adjoint tape is
- * set.
+ * is periodic, for HLBM_AA or for a batch (hlbm_batch_set_solid_mask sets an
+ * item's obstacles); ESTATE while an adjoint tape is set.
  * Synchronous. */
 int hlbm_set_solid_mask(hlbm_ctx *ctx, const unsigned char *mask, int on_device);
 
@@ -342,11 +342,17 @@ int hlbm_adjoint_step(hlbm_ctx *ctx, int nsteps, const double *dJ_drho, const do
  * inside an item) and each population row spans all items.
  *
  * hlbm_step advances every item.  Modes:
- *   HLBM_BATCH_GRAPH      (default) one executable HIP graph per call: a
- *                         reset node, then one persistent kernel that runs all
- *                         steps with a grid-wide barrier between them;
- *   HLBM_BATCH_PERSISTENT the same persistent kernel launched directly;
- *   HLBM_BATCH_PER_STEP   one kernel launch per step.
+ *   HLBM_BATCH_GRAPH      (default) one executable HIP graph per call that
+ *                         holds one node of the per-step kernel per step, each
+ *                         node depending on the one before: the whole call is
+ *                         one graph launch;
+ *   HLBM_BATCH_PERSISTENT one persistent kernel that runs all steps with a
+ *                         grid-wide barrier between them, launched directly;
+ *   HLBM_BATCH_PER_STEP   one kernel launch per step;
+ *   HLBM_BATCH_GRAPH_PERSISTENT one executable HIP graph per call holding a
+ *                         reset node and the persistent kernel.
+ * A graph is built on the first call with a given step count and starting
+ * buffer and reused by later calls with the same ones.
  * Schedule: the packed cells are cut into tiles of `tile` cells that never
  * straddle two items; a tile is one block of `tile` threads in every mode.
  * The persistent kernel keeps blocks_per_cu blocks resident on each CU (at
@@ -356,11 +362,13 @@ int hlbm_adjoint_step(hlbm_ctx *ctx, int nsteps, const double *dJ_drho, const do
  * follows the tile size.
  * Its barrier waits with a bounded spin; if the bound is hit, every block
  * leaves and the next syncing call returns HLBM_EDEVICE.
+ * Items may hold resolved obstacles (hlbm_batch_set_solid_mask), with the
+ * rule of hlbm_set_solid_mask inside each item's periodic box.
  * hlbm_get_state / hlbm_set_state / hlbm_reset / hlbm_get_step work on the
- * packed state; hlbm_set_porosity and hlbm_moments return
- * HLBM_EUNSUPPORTED for a batch (use the calls below).
+ * packed state; hlbm_set_porosity, hlbm_moments and hlbm_set_solid_mask
+ * return HLBM_EUNSUPPORTED for a batch (use the calls below).
  * ------------------------------------------------------------------------ */
-enum { HLBM_BATCH_GRAPH = 0, HLBM_BATCH_PERSISTENT = 1, HLBM_BATCH_PER_STEP = 2 };
+enum { HLBM_BATCH_GRAPH = 0, HLBM_BATCH_PERSISTENT = 1, HLBM_BATCH_PER_STEP = 2, HLBM_BATCH_GRAPH_PERSISTENT = 3 };
 
 /* Create a batch of n_items >= 1 boxes.  items[k] gives box k's nx, ny, nz
  * (each in [2, 1024], with nx*ny*nz*max(nx, ny) < 2^32), tau and force; all
@@ -402,6 +410,21 @@ int hlbm_batch_get_schedule(const hlbm_ctx *ctx, int *tile, int *blocks_per_cu, 
 /* Porosity control d = 1 - varpi of one item (nx*ny*nz values, x fastest),
  * same rules as hlbm_set_porosity.  Every item must be set before stepping. */
 int hlbm_batch_set_porosity(hlbm_ctx *ctx, int item, const void *d, int dtype, int on_device);
+
+/* Resolved obstacles in item `item` (the periodic unit-cell Stokes problem
+ * behind the permeability, Sec. 2.2, with no-slip on the obstacle, Sec. 2.4
+ * eq:targetEBTL): mask[cell] != 0 marks a solid cell of that item
+ * (nx*ny*nz bytes, x fastest; device memory if on_device, else host).  Within
+ * the item's periodic box the rule is that of hlbm_set_solid_mask: halfway
+ * bounce-back at every fluid-solid link, zeros in solid cells, which report
+ * zero moments and add nothing to the totals; the porosity control still
+ * applies in fluid cells.  mask = NULL removes the item's obstacles.  While
+ * any item holds obstacles every item runs the masked kernels (4 more bytes
+ * per cell: a link mask over all packed cells, allocated on first use); an
+ * item without obstacles then evolves bit for bit as without them.  The
+ * state is left as it is (a solid cell's populations become zeros at the next
+ * step).  Synchronous. */
+int hlbm_batch_set_solid_mask(hlbm_ctx *ctx, int item, const unsigned char *mask, int on_device);
 
 /* Moments of a batch at the current time level (definitions as for
  * hlbm_moments), FP64.  If drho or u is not NULL they receive the fields of

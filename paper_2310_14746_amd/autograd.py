@@ -26,7 +26,10 @@ class HLBMFunction(torch.autograd.Function):
     records a tape with a checkpoint every ``every`` steps and runs ``nsteps``
     sweeps; returns FP64 device tensors drho (nz, ny, nx) and u (3, nz, ny, nx).
     backward: the reverse sweep over the same steps.  ``sim`` must not be
-    stepped, reset or given a new porosity between the two passes (checked).
+    stepped, reset, given a new state, tape, mask or porosity between the two
+    passes: the wrapper counts every such call (``sim.generation``), and a
+    backward whose forward was followed by one raises instead of
+    differentiating another run's tape.
     """
 
     @staticmethod
@@ -38,7 +41,7 @@ class HLBMFunction(torch.autograd.Function):
         drho, u = sim.moments("f64")
         ctx.sim = sim
         ctx.nsteps = int(nsteps)
-        ctx.stamp = (sim.step_count, sim.tape_info()["recorded"])
+        ctx.generation = sim.generation
         ctx.d_dtype = d.dtype
         ctx.d_shape = d.shape
         return drho, u
@@ -46,9 +49,10 @@ class HLBMFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_drho, g_u):
         sim = ctx.sim
-        if (sim.step_count, sim.tape_info()["recorded"]) != ctx.stamp:
-            raise RuntimeError("the lattice was changed after the forward pass; its tape no "
-                               "longer matches this graph")
+        if sim.generation != ctx.generation:
+            raise RuntimeError("the lattice was changed after the forward pass (stepped, reset, "
+                               "or given a new state, tape, mask or porosity); its tape no longer "
+                               "matches this graph")
         if g_drho is None:
             g_drho = torch.zeros(sim.N, dtype=torch.float64, device=sim.device)
         if g_u is None:

@@ -63,8 +63,11 @@ struct hlbm_ctx {
     unsigned long long* bar_sync;  // barrier arrivals and work counter
     int* bar_err;
     hlbm::BatchLaunch bl;
-    hipGraphExec_t gexec[2];
-    int gsteps[2];
+    hipGraphExec_t gexec[2];  // cached graph per starting buffer
+    int gsteps[2];            // its step count (-1: none)
+    int gkind[2];             // its kind: HLBM_BATCH_GRAPH or HLBM_BATCH_GRAPH_PERSISTENT
+    std::vector<char> item_masked;  // items holding resolved obstacles (link mask rows in use)
+    int n_masked;
     int cus;             // compute units of the device
     int batch_bpc;       // resident blocks per CU of the persistent kernel
     int max_blocks_per_cu;  // resident blocks of the persistent kernel that fit
@@ -409,14 +412,16 @@ int batch_step(hlbm_ctx* c, int nsteps)
         if (e == hipSuccess) c->cur ^= (nsteps & 1);
     } else {
         const int k = c->cur;
-        if (!c->gexec[k] || c->gsteps[k] != nsteps) {
+        const int kind = c->batch_mode;
+        if (!c->gexec[k] || c->gsteps[k] != nsteps || c->gkind[k] != kind) {
             if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
             c->gexec[k] = nullptr;
             c->gsteps[k] = -1;
             e = hlbm::build_batch_graph(storage, c->bl, c->pop[0], c->pop[1], c->dfield, nsteps, k,
-                                        &c->gexec[k]);
+                                        kind == HLBM_BATCH_GRAPH_PERSISTENT, &c->gexec[k]);
             if (e != hipSuccess) return hip_fail(e, "building the batch graph");
             c->gsteps[k] = nsteps;
+            c->gkind[k] = kind;
         }
         e = hipGraphLaunch(c->gexec[k], c->stream);
         if (e == hipSuccess) c->cur ^= (nsteps & 1);
@@ -1120,6 +1125,8 @@ int hlbm_create_batch(const hlbm_config* items, int n_items, hlbm_ctx** out)
     c->gsteps[0] = c->gsteps[1] = -1;
     c->items.resize(n_items);
     c->item_porosity.assign(n_items, 0);
+    c->item_masked.assign(n_items, 0);
+    c->n_masked = 0;
     std::vector<uint32_t> tile_item((size_t)ntiles);
     uint32_t base = 0, tile0 = 0;
     for (int k = 0; k < n_items; ++k) {
@@ -1211,7 +1218,8 @@ int hlbm_batch_set_mode(hlbm_ctx* c, int mode)
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!c->batch) return fail(HLBM_EINVAL, "not a batch context");
-    if (mode < HLBM_BATCH_GRAPH || mode > HLBM_BATCH_PER_STEP) return fail(HLBM_EINVAL, "unknown batch mode %d", mode);
+    if (mode < HLBM_BATCH_GRAPH || mode > HLBM_BATCH_GRAPH_PERSISTENT)
+        return fail(HLBM_EINVAL, "unknown batch mode %d", mode);
     c->batch_mode = mode;
     return HLBM_OK;
 }
@@ -1301,6 +1309,64 @@ int hlbm_batch_set_porosity(hlbm_ctx* c, int item, const void* d, int dtype, int
     bool all = true;
     for (int k = 0; k < c->n_items; ++k) all = all && c->item_porosity[k];
     c->porosity_set = all;
+    return HLBM_OK;
+}
+
+int hlbm_batch_set_solid_mask(hlbm_ctx* c, int item, const unsigned char* mask, int on_device)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!c->batch) return fail(HLBM_EINVAL, "not a batch context");
+    if (item < 0 || item >= c->n_items) return fail(HLBM_EINVAL, "item %d out of range", item);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch_set_solid_mask: outstanding work failed");
+    const hlbm::BatchItem& it = c->items[item];
+    const size_t ntot = c->p.N;
+    if (!mask && !c->item_masked[item]) return HLBM_OK;
+    if (!c->linkmask) {
+        // zero link masks: items without obstacles load what the periodic gather loads
+        e = hipMalloc(&c->linkmask, ntot * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            c->linkmask = nullptr;
+            return fail(HLBM_ENOMEM, "link mask allocation: %s", hipGetErrorString(e));
+        }
+        e = hipMemsetAsync(c->linkmask, 0, ntot * sizeof(uint32_t), c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_fail(e, "clearing the link mask");
+    }
+    uint32_t* rows = c->linkmask + it.base;
+    if (!mask) {
+        e = hipMemsetAsync(rows, 0, (size_t)it.cells * sizeof(uint32_t), c->stream);
+    } else {
+        const unsigned char* src = mask;
+        void* tmp = nullptr;
+        if (!on_device) {
+            e = hipMalloc(&tmp, it.cells);
+            if (e != hipSuccess) return fail(HLBM_ENOMEM, "staging allocation: %s", hipGetErrorString(e));
+            e = hipMemcpyAsync(tmp, mask, it.cells, hipMemcpyHostToDevice, c->stream);
+            src = static_cast<const unsigned char*>(tmp);
+        }
+        hlbm::Params ip = c->p;
+        ip.nx = (int)it.nx;
+        ip.ny = (int)it.ny;
+        ip.nz = (int)it.nz;
+        ip.N = it.cells;
+        if (e == hipSuccess) e = hlbm::launch_linkmask(19, ip, src, rows, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (tmp) (void)hipFree(tmp);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch solid mask");
+    c->n_masked += (mask ? 1 : 0) - (c->item_masked[item] ? 1 : 0);
+    c->item_masked[item] = mask ? 1 : 0;
+    // the masked kernels run while any item holds obstacles; the graphs hold
+    // the old kernels
+    c->bl.linkmask = c->n_masked ? c->linkmask : nullptr;
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        c->gexec[k] = nullptr;
+        c->gsteps[k] = -1;
+    }
     return HLBM_OK;
 }
 

@@ -96,11 +96,15 @@ __global__ void batch_reset_kernel(unsigned long long* sync, int* err)
 }
 
 // One cell of one item: periodic pull inside the item's box, collision,
-// store.  `l` is the cell's index inside the item.
-template <class S>
+// store.  `l` is the cell's index inside the item.  MASKED: items may hold
+// resolved solid cells (link mask over the packed cells; all zero for an item
+// without obstacles, which then loads exactly what the periodic gather loads):
+// bounce-back at solid links, zeros in solid cells.
+template <class S, bool MASKED>
 __device__ __forceinline__ void batch_cell(const typename S::T* __restrict__ src,
                                            typename S::T* __restrict__ dst,
-                                           const typename S::D* __restrict__ dfield, uint32_t Ntot,
+                                           const typename S::D* __restrict__ dfield,
+                                           const uint32_t* __restrict__ linkmask, uint32_t Ntot,
                                            const BatchItem& it, uint32_t l, typename S::R rho0,
                                            typename S::R scale, typename S::R inv_scale)
 {
@@ -111,20 +115,26 @@ __device__ __forceinline__ void batch_cell(const typename S::T* __restrict__ src
     const uint32_t z = div_magic(t, it.my);
     const uint32_t y = t - z * it.ny;
     R g[L::Q];
-    gather_periodic<L, S>(src, Ntot, it.base, it.nx, it.ny, it.nz, x, y, z, inv_scale, g);
+    bool solid = false;
+    if (MASKED)
+        solid = gather_masked<L, S>(src, Ntot, linkmask, it.base, it.nx, it.ny, it.nz, x, y, z, inv_scale, g);
+    else
+        gather_periodic<L, S>(src, Ntot, it.base, it.nx, it.ny, it.nz, x, y, z, inv_scale, g);
     const uint32_t cell = it.base + l;
     const R d = S::load_d(ld(dfield, cell));
     R drho, ux, uy, uz;
     collide<L, R, ScalarShift<R>, S::exact_moments>(g, ScalarShift<R>{d}, R(it.F[0]), R(it.F[1]), R(it.F[2]), rho0, R(it.omega), R(it.pref), drho, ux,
                   uy, uz);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) st_stream(dst + (size_t)i * Ntot, cell, S::store(g[i], scale));
+    for (int i = 0; i < L::Q; ++i)
+        st_stream(dst + (size_t)i * Ntot, cell, S::store(MASKED ? sel(solid, R(0), g[i]) : g[i], scale));
 }
 
-template <class S>
+template <class S, bool MASKED>
 __global__ __launch_bounds__(TILE_MAX) void batch_persistent_kernel(
     typename S::T* __restrict__ buf_a, typename S::T* __restrict__ buf_b,
-    const typename S::D* __restrict__ dfield, const BatchItem* __restrict__ items,
+    const typename S::D* __restrict__ dfield, const uint32_t* __restrict__ linkmask,
+    const BatchItem* __restrict__ items,
     const uint32_t* __restrict__ tile_item, uint32_t ntiles, uint32_t chunk, uint32_t Ntot, int nsteps,
     int start_in_b, double rho0_d, double scale_d, unsigned long long* __restrict__ sync,
     int* __restrict__ err, unsigned spin_limit)
@@ -152,7 +162,8 @@ __global__ __launch_bounds__(TILE_MAX) void batch_persistent_kernel(
             for (uint32_t t = t0; t < t1; ++t) {
                 const BatchItem it = items[tile_item[t]];
                 const uint32_t l = (t - it.tile0) * tile + threadIdx.x;
-                if (l < it.cells) batch_cell<S>(src, dst, dfield, Ntot, it, l, rho0, scale, inv_scale);
+                if (l < it.cells)
+                    batch_cell<S, MASKED>(src, dst, dfield, linkmask, Ntot, it, l, rho0, scale, inv_scale);
             }
             __syncthreads();  // every thread has read `next` for this chunk
             if (threadIdx.x == 0) next = drawn;
@@ -167,28 +178,29 @@ __global__ __launch_bounds__(TILE_MAX) void batch_persistent_kernel(
 
 // One launch per step over all tiles (no barrier); used for the non-persistent
 // form and as the reference the persistent form must match bit for bit.
-template <class S>
+template <class S, bool MASKED>
 __global__ __launch_bounds__(TILE_MAX) void batch_step_kernel(
     const typename S::T* __restrict__ src, typename S::T* __restrict__ dst,
-    const typename S::D* __restrict__ dfield, const BatchItem* __restrict__ items,
-    const uint32_t* __restrict__ tile_item, uint32_t Ntot, double rho0_d, double scale_d)
+    const typename S::D* __restrict__ dfield, const uint32_t* __restrict__ linkmask,
+    const BatchItem* __restrict__ items, const uint32_t* __restrict__ tile_item, uint32_t Ntot,
+    double rho0_d, double scale_d)
 {
     using R = typename S::R;
     const uint32_t t = blockIdx.x;
     const BatchItem it = items[tile_item[t]];
     const uint32_t l = (t - it.tile0) * blockDim.x + threadIdx.x;
     if (l < it.cells)
-        batch_cell<S>(src, dst, dfield, Ntot, it, l, R(rho0_d), R(scale_d), R(1.0 / scale_d));
+        batch_cell<S, MASKED>(src, dst, dfield, linkmask, Ntot, it, l, R(rho0_d), R(scale_d), R(1.0 / scale_d));
 }
 
 // Moments of every item at the current time level: one block per tile writes
 // FP64 partials (sum drho, sum rho u); optionally the fields of one item.
-template <class S>
+template <class S, bool MASKED>
 __global__ __launch_bounds__(TILE_MAX) void batch_moments_kernel(
-    const typename S::T* __restrict__ src, const BatchItem* __restrict__ items,
-    const uint32_t* __restrict__ tile_item, uint32_t Ntot, double rho0_d, double scale_d,
-    double* __restrict__ partials, int sel_item, double* __restrict__ drho_out,
-    double* __restrict__ u_out)
+    const typename S::T* __restrict__ src, const uint32_t* __restrict__ linkmask,
+    const BatchItem* __restrict__ items, const uint32_t* __restrict__ tile_item, uint32_t Ntot,
+    double rho0_d, double scale_d, double* __restrict__ partials, int sel_item,
+    double* __restrict__ drho_out, double* __restrict__ u_out)
 {
     using R = typename S::R;
     using L = D3Q19;
@@ -203,9 +215,19 @@ __global__ __launch_bounds__(TILE_MAX) void batch_moments_kernel(
         const uint32_t z = div_magic(q, it.my);
         const uint32_t y = q - z * it.ny;
         R g[L::Q];
-        gather_periodic<L, S>(src, Ntot, it.base, it.nx, it.ny, it.nz, x, y, z, R(1.0 / scale_d), g);
+        bool solid = false;
+        if (MASKED)
+            solid = gather_masked<L, S>(src, Ntot, linkmask, it.base, it.nx, it.ny, it.nz, x, y, z,
+                                        R(1.0 / scale_d), g);
+        else
+            gather_periodic<L, S>(src, Ntot, it.base, it.nx, it.ny, it.nz, x, y, z, R(1.0 / scale_d), g);
         R drho, ux, uy, uz;
         moments_of<L, R, S::exact_moments>(g, R(it.F[0]), R(it.F[1]), R(it.F[2]), R(rho0_d), drho, ux, uy, uz);
+        // solid cells report zeros and add nothing to the totals
+        drho = sel(solid, R(0), drho);
+        ux = sel(solid, R(0), ux);
+        uy = sel(solid, R(0), uy);
+        uz = sel(solid, R(0), uz);
         const double rho = rho0_d + (double)drho;
         m0 = (double)drho;
         m1 = rho * (double)ux;
@@ -242,151 +264,197 @@ __global__ __launch_bounds__(256) void batch_item_reduce_kernel(const double* __
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <class S>
-static hipError_t persistent_dispatch(const BatchLaunch& b, void* buf_a, void* buf_b, const void* dfield,
-                                      int nsteps, int start_in_b, hipStream_t s)
+// Calls f.template operator()<S, MASKED>() for the storage code and whether a
+// link mask is present.
+template <class F>
+static hipError_t with_storage(int storage, bool masked, F&& f)
 {
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b.sync, b.err);
-    hipLaunchKernelGGL((batch_persistent_kernel<S>), dim3(b.grid), dim3(b.tile), 0, s,
-                       static_cast<typename S::T*>(buf_a), static_cast<typename S::T*>(buf_b),
-                       static_cast<const typename S::D*>(dfield), b.items, b.tile_item, b.ntiles, b.chunk,
-                       b.Ntot, nsteps, start_in_b, b.rho0, b.scale, b.sync, b.err, b.spin_limit);
-    return hipGetLastError();
+    switch (storage) {
+    case StoreF32::code: return masked ? f.template run<StoreF32, true>() : f.template run<StoreF32, false>();
+    case StoreF16S::code: return masked ? f.template run<StoreF16S, true>() : f.template run<StoreF16S, false>();
+    case StoreBF16S::code:
+        return masked ? f.template run<StoreBF16S, true>() : f.template run<StoreBF16S, false>();
+    case StoreF64::code: return masked ? f.template run<StoreF64, true>() : f.template run<StoreF64, false>();
+    default: return hipErrorInvalidValue;
+    }
 }
+
+struct PersistentLaunch {
+    const BatchLaunch& b;
+    void *buf_a, *buf_b;
+    const void* dfield;
+    int nsteps, start_in_b;
+    hipStream_t s;
+    template <class S, bool M>
+    hipError_t run() const
+    {
+        hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, b.sync, b.err);
+        hipLaunchKernelGGL((batch_persistent_kernel<S, M>), dim3(b.grid), dim3(b.tile), 0, s,
+                           static_cast<typename S::T*>(buf_a), static_cast<typename S::T*>(buf_b),
+                           static_cast<const typename S::D*>(dfield), b.linkmask, b.items, b.tile_item,
+                           b.ntiles, b.chunk, b.Ntot, nsteps, start_in_b, b.rho0, b.scale, b.sync, b.err,
+                           b.spin_limit);
+        return hipGetLastError();
+    }
+};
 
 hipError_t launch_batch_persistent(int storage, const BatchLaunch& b, void* buf_a, void* buf_b,
                                    const void* dfield, int nsteps, int start_in_b, hipStream_t s)
 {
-    switch (storage) {
-    case StoreF32::code: return persistent_dispatch<StoreF32>(b, buf_a, buf_b, dfield, nsteps, start_in_b, s);
-    case StoreF16S::code: return persistent_dispatch<StoreF16S>(b, buf_a, buf_b, dfield, nsteps, start_in_b, s);
-    case StoreBF16S::code: return persistent_dispatch<StoreBF16S>(b, buf_a, buf_b, dfield, nsteps, start_in_b, s);
-    case StoreF64::code: return persistent_dispatch<StoreF64>(b, buf_a, buf_b, dfield, nsteps, start_in_b, s);
-    default: return hipErrorInvalidValue;
-    }
+    return with_storage(storage, b.linkmask != nullptr,
+                        PersistentLaunch{b, buf_a, buf_b, dfield, nsteps, start_in_b, s});
 }
 
-template <class S>
-static hipError_t step_dispatch(const BatchLaunch& b, const void* src, void* dst, const void* dfield,
-                                hipStream_t s)
-{
-    hipLaunchKernelGGL((batch_step_kernel<S>), dim3(b.ntiles), dim3(b.tile), 0, s,
-                       static_cast<const typename S::T*>(src), static_cast<typename S::T*>(dst),
-                       static_cast<const typename S::D*>(dfield), b.items, b.tile_item, b.Ntot,
-                       b.rho0, b.scale);
-    return hipGetLastError();
-}
+struct StepLaunch {
+    const BatchLaunch& b;
+    const void* src;
+    void* dst;
+    const void* dfield;
+    hipStream_t s;
+    template <class S, bool M>
+    hipError_t run() const
+    {
+        hipLaunchKernelGGL((batch_step_kernel<S, M>), dim3(b.ntiles), dim3(b.tile), 0, s,
+                           static_cast<const typename S::T*>(src), static_cast<typename S::T*>(dst),
+                           static_cast<const typename S::D*>(dfield), b.linkmask, b.items, b.tile_item, b.Ntot,
+                           b.rho0, b.scale);
+        return hipGetLastError();
+    }
+};
 
 hipError_t launch_batch_step(int storage, const BatchLaunch& b, const void* src, void* dst,
                              const void* dfield, hipStream_t s)
 {
-    switch (storage) {
-    case StoreF32::code: return step_dispatch<StoreF32>(b, src, dst, dfield, s);
-    case StoreF16S::code: return step_dispatch<StoreF16S>(b, src, dst, dfield, s);
-    case StoreBF16S::code: return step_dispatch<StoreBF16S>(b, src, dst, dfield, s);
-    case StoreF64::code: return step_dispatch<StoreF64>(b, src, dst, dfield, s);
-    default: return hipErrorInvalidValue;
-    }
+    return with_storage(storage, b.linkmask != nullptr, StepLaunch{b, src, dst, dfield, s});
 }
 
-template <class S>
-static hipError_t moments_dispatch(const BatchLaunch& b, const void* src, double* partials,
-                                   int sel_item, double* drho, double* u, double* totals,
-                                   hipStream_t s)
-{
-    hipLaunchKernelGGL((batch_moments_kernel<S>), dim3(b.ntiles), dim3(b.tile), 0, s,
-                       static_cast<const typename S::T*>(src), b.items, b.tile_item, b.Ntot, b.rho0,
-                       b.scale, partials, sel_item, drho, u);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_item_reduce_kernel, dim3(b.n_items), dim3(256), 0, s, partials, b.items,
-                       b.tile, totals);
-    return hipGetLastError();
-}
+struct MomentsLaunch {
+    const BatchLaunch& b;
+    const void* src;
+    double* partials;
+    int sel_item;
+    double *drho, *u, *totals;
+    hipStream_t s;
+    template <class S, bool M>
+    hipError_t run() const
+    {
+        hipLaunchKernelGGL((batch_moments_kernel<S, M>), dim3(b.ntiles), dim3(b.tile), 0, s,
+                           static_cast<const typename S::T*>(src), b.linkmask, b.items, b.tile_item, b.Ntot,
+                           b.rho0, b.scale, partials, sel_item, drho, u);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(batch_item_reduce_kernel, dim3(b.n_items), dim3(256), 0, s, partials, b.items,
+                           b.tile, totals);
+        return hipGetLastError();
+    }
+};
 
 hipError_t launch_batch_moments(int storage, const BatchLaunch& b, const void* src, double* partials,
                                 int sel_item, double* drho, double* u, double* totals, hipStream_t s)
 {
-    switch (storage) {
-    case StoreF32::code: return moments_dispatch<StoreF32>(b, src, partials, sel_item, drho, u, totals, s);
-    case StoreF16S::code: return moments_dispatch<StoreF16S>(b, src, partials, sel_item, drho, u, totals, s);
-    case StoreBF16S::code: return moments_dispatch<StoreBF16S>(b, src, partials, sel_item, drho, u, totals, s);
-    case StoreF64::code: return moments_dispatch<StoreF64>(b, src, partials, sel_item, drho, u, totals, s);
-    default: return hipErrorInvalidValue;
-    }
+    return with_storage(storage, b.linkmask != nullptr, MomentsLaunch{b, src, partials, sel_item, drho, u, totals, s});
 }
 
-// An executable graph of two kernel nodes (barrier reset, then the persistent
-// kernel for `nsteps` steps), built from explicit nodes so that it can be
+// Executable graphs, built from explicit kernel nodes so that they can be
 // launched on any stream, the legacy default stream included.  No memset
-// nodes: the reset is a kernel.
-template <class S>
-static hipError_t graph_dispatch(const BatchLaunch& b, void* buf_a, void* buf_b, const void* dfield,
-                                 int nsteps, int start_in_b, hipGraphExec_t* out)
-{
-    hipGraph_t g = nullptr;
-    hipError_t e = hipGraphCreate(&g, 0);
-    if (e != hipSuccess) return e;
-    unsigned long long* sync = b.sync;
-    int* err = b.err;
-    void* reset_args[] = {&sync, &err};
-    hipKernelNodeParams rp = {};
-    rp.func = reinterpret_cast<void*>(batch_reset_kernel);
-    rp.gridDim = dim3(1);
-    rp.blockDim = dim3(64);
-    rp.sharedMemBytes = 0;
-    rp.kernelParams = reset_args;
-    rp.extra = nullptr;
-    hipGraphNode_t n_reset = nullptr, n_run = nullptr;
-    e = hipGraphAddKernelNode(&n_reset, g, nullptr, 0, &rp);
-    auto* pa = static_cast<typename S::T*>(buf_a);
-    auto* pb = static_cast<typename S::T*>(buf_b);
-    auto* pd = static_cast<const typename S::D*>(dfield);
-    const BatchItem* items = b.items;
-    const uint32_t* tile_item = b.tile_item;
-    uint32_t ntiles = b.ntiles, chunk = b.chunk, Ntot = b.Ntot;
-    double rho0 = b.rho0, scale = b.scale;
-    unsigned spin = b.spin_limit;
-    void* run_args[] = {&pa, &pb, &pd, &items, &tile_item, &ntiles, &chunk, &Ntot, &nsteps,
-                        &start_in_b, &rho0, &scale, &sync, &err, &spin};
-    hipKernelNodeParams kp = {};
-    kp.func = reinterpret_cast<void*>(batch_persistent_kernel<S>);
-    kp.gridDim = dim3(b.grid);
-    kp.blockDim = dim3(b.tile);
-    kp.sharedMemBytes = 0;
-    kp.kernelParams = run_args;
-    kp.extra = nullptr;
-    if (e == hipSuccess) e = hipGraphAddKernelNode(&n_run, g, &n_reset, 1, &kp);
-    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    return e;
-}
+// nodes: the barrier reset is a kernel.
+//   steps:      one node of the per-step kernel per step, each depending on
+//               the one before (buffers alternate from node to node);
+//   persistent: a reset node, then the persistent kernel for all steps.
+struct GraphBuild {
+    const BatchLaunch& b;
+    void *buf_a, *buf_b;
+    const void* dfield;
+    int nsteps, start_in_b;
+    bool persistent;
+    hipGraphExec_t* out;
+    template <class S, bool M>
+    hipError_t run() const
+    {
+        hipGraph_t g = nullptr;
+        hipError_t e = hipGraphCreate(&g, 0);
+        if (e != hipSuccess) return e;
+        auto* pa = static_cast<typename S::T*>(buf_a);
+        auto* pb = static_cast<typename S::T*>(buf_b);
+        auto* pd = static_cast<const typename S::D*>(dfield);
+        const uint32_t* lm = b.linkmask;
+        const BatchItem* items = b.items;
+        const uint32_t* tile_item = b.tile_item;
+        uint32_t ntiles = b.ntiles, chunk = b.chunk, Ntot = b.Ntot;
+        double rho0 = b.rho0, scale = b.scale;
+        unsigned long long* sync = b.sync;
+        int* err = b.err;
+        unsigned spin = b.spin_limit;
+        int steps = nsteps, start = start_in_b;
+        if (persistent) {
+            void* reset_args[] = {&sync, &err};
+            hipKernelNodeParams rp = {};
+            rp.func = reinterpret_cast<void*>(batch_reset_kernel);
+            rp.gridDim = dim3(1);
+            rp.blockDim = dim3(64);
+            rp.kernelParams = reset_args;
+            hipGraphNode_t n_reset = nullptr, n_run = nullptr;
+            e = hipGraphAddKernelNode(&n_reset, g, nullptr, 0, &rp);
+            void* run_args[] = {&pa, &pb, &pd, &lm, &items, &tile_item, &ntiles, &chunk, &Ntot, &steps,
+                                &start, &rho0, &scale, &sync, &err, &spin};
+            hipKernelNodeParams kp = {};
+            kp.func = reinterpret_cast<void*>(batch_persistent_kernel<S, M>);
+            kp.gridDim = dim3(b.grid);
+            kp.blockDim = dim3(b.tile);
+            kp.kernelParams = run_args;
+            if (e == hipSuccess) e = hipGraphAddKernelNode(&n_run, g, &n_reset, 1, &kp);
+        } else {
+            // node k reads the buffer written by node k - 1; the arguments are
+            // copied when the node is added
+            hipGraphNode_t prev = nullptr;
+            for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+                const bool from_b = ((k + start_in_b) & 1) != 0;
+                const typename S::T* src = from_b ? pb : pa;
+                typename S::T* dst = from_b ? pa : pb;
+                void* args[] = {&src, &dst, &pd, &lm, &items, &tile_item, &Ntot, &rho0, &scale};
+                hipKernelNodeParams kp = {};
+                kp.func = reinterpret_cast<void*>(batch_step_kernel<S, M>);
+                kp.gridDim = dim3(b.ntiles);
+                kp.blockDim = dim3(b.tile);
+                kp.kernelParams = args;
+                hipGraphNode_t node = nullptr;
+                e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+                prev = node;
+            }
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        return e;
+    }
+};
 
 hipError_t build_batch_graph(int storage, const BatchLaunch& b, void* buf_a, void* buf_b,
-                             const void* dfield, int nsteps, int start_in_b, hipGraphExec_t* out)
+                             const void* dfield, int nsteps, int start_in_b, bool persistent, hipGraphExec_t* out)
 {
-    switch (storage) {
-    case StoreF32::code: return graph_dispatch<StoreF32>(b, buf_a, buf_b, dfield, nsteps, start_in_b, out);
-    case StoreF16S::code: return graph_dispatch<StoreF16S>(b, buf_a, buf_b, dfield, nsteps, start_in_b, out);
-    case StoreBF16S::code: return graph_dispatch<StoreBF16S>(b, buf_a, buf_b, dfield, nsteps, start_in_b, out);
-    case StoreF64::code: return graph_dispatch<StoreF64>(b, buf_a, buf_b, dfield, nsteps, start_in_b, out);
-    default: return hipErrorInvalidValue;
-    }
+    return with_storage(storage, b.linkmask != nullptr,
+                        GraphBuild{b, buf_a, buf_b, dfield, nsteps, start_in_b, persistent, out});
 }
 
+struct Occupancy {
+    int tile;
+    int* blocks_per_cu;
+    template <class S, bool M>
+    hipError_t run() const
+    {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<S, M>, tile, 0);
+    }
+};
+
+// Resident blocks of `tile` threads per CU of the persistent kernel: the
+// fewer of the unmasked and the masked form, so that a schedule stays valid
+// when obstacles are added.
 hipError_t batch_occupancy(int storage, int tile, int* blocks_per_cu)
 {
-    switch (storage) {
-    case StoreF32::code:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF32>, tile, 0);
-    case StoreF16S::code:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF16S>, tile, 0);
-    case StoreBF16S::code:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreBF16S>, tile, 0);
-    case StoreF64::code:
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent_kernel<StoreF64>, tile, 0);
-    default: return hipErrorInvalidValue;
-    }
+    int plain = 0, masked = 0;
+    hipError_t e = with_storage(storage, false, Occupancy{tile, &plain});
+    if (e == hipSuccess) e = with_storage(storage, true, Occupancy{tile, &masked});
+    *blocks_per_cu = plain < masked ? plain : masked;
+    return e;
 }
 
 }  // namespace hlbm

@@ -495,16 +495,17 @@ __device__ __forceinline__ void aa_odd_target_walls(const Box& b, int x, int y, 
 // direction i is solid, halfway bounce-back g*_i(x) = g_opp(i)(x) (the link
 // mask, precomputed per cell, says which sources are solid).  Straight-line:
 // the load address switches to this cell's opposite population.  Returns
-// whether the cell itself is solid.
+// whether the cell itself is solid.  `base` offsets the box inside the
+// population rows and the link mask (an item of a batch; 0 otherwise).
 // ---------------------------------------------------------------------------
 template <class L, class S>
 __device__ __forceinline__ bool gather_masked(const typename S::T* __restrict__ src, uint32_t P,
-                                              const uint32_t* __restrict__ linkmask, uint32_t nx,
-                                              uint32_t ny, uint32_t nz, uint32_t x, uint32_t y,
-                                              uint32_t z, typename S::R inv_scale,
+                                              const uint32_t* __restrict__ linkmask, uint32_t base,
+                                              uint32_t nx, uint32_t ny, uint32_t nz, uint32_t x,
+                                              uint32_t y, uint32_t z, typename S::R inv_scale,
                                               typename S::R (&g)[L::Q])
 {
-    const uint32_t cell = x + nx * (y + ny * z);
+    const uint32_t cell = base + x + nx * (y + ny * z);
     const uint32_t lm = linkmask[cell];  // 4 B per cell: may pass 4 GiB under 16-bit storage
     const uint32_t xs[3] = {x + 1 == nx ? 0u : x + 1, x, x == 0 ? nx - 1 : x - 1};
     const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
@@ -512,7 +513,7 @@ __device__ __forceinline__ bool gather_masked(const typename S::T* __restrict__ 
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const bool back = ((lm >> i) & 1u) != 0u;
-        const uint32_t noff = xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+        const uint32_t noff = base + xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
         const uint32_t row = sel(back, (uint32_t)opposite(i), (uint32_t)i);
         const uint32_t off = sel(back, cell, noff);
         g[i] = S::load(ld(src + (size_t)row * P, off), inv_scale);

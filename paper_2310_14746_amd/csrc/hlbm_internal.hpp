@@ -216,6 +216,7 @@ struct BatchItem {
 struct BatchLaunch {
     const BatchItem* items;     // device, n_items
     const uint32_t* tile_item;  // device, ntiles
+    const uint32_t* linkmask;   // device, packed cells: solid links of items with obstacles, or null
     uint32_t n_items, ntiles;
     uint32_t Ntot;              // population row stride: packed cells plus the row pad
     double rho0, scale;
@@ -235,6 +236,7 @@ hipError_t launch_batch_moments(int storage, const BatchLaunch& b, const void* s
                                 int sel_item, double* drho, double* u, double* totals, hipStream_t s);
 hipError_t batch_occupancy(int storage, int tile, int* blocks_per_cu);
 hipError_t build_batch_graph(int storage, const BatchLaunch& b, void* buf_a, void* buf_b,
-                             const void* dfield, int nsteps, int start_in_b, hipGraphExec_t* out);
+                             const void* dfield, int nsteps, int start_in_b, bool persistent,
+                             hipGraphExec_t* out);
 
 }  // namespace hlbm

@@ -51,7 +51,7 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
         gather_aa_odd_walls<L, S>(src, P, b, (int)x, (int)y, (int)z, inv_scale, g);
         solid = in_wall_layer(b, (int)x, (int)y, (int)z);
     } else if (BC == BC_MASKED) {
-        solid = gather_masked<L, S>(src, P, p.linkmask, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+        solid = gather_masked<L, S>(src, P, p.linkmask, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
     } else {
         const Box b = box_of(p);
         const OpenFaces<R> of{rho0, R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(1024) void moments_kernel(const typename S::T* __re
             gather_aa_odd_walls<L, S>(src, p.P, b, (int)x, (int)y, (int)z, inv_scale, g);
             fluid = !in_wall_layer(b, (int)x, (int)y, (int)z);
         } else if (BC == BC_MASKED) {
-            fluid = !gather_masked<L, S>(src, p.P, p.linkmask, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+            fluid = !gather_masked<L, S>(src, p.P, p.linkmask, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
         } else {
             const Box b = box_of(p);
             fluid = !in_wall_layer(b, (int)x, (int)y, (int)z);

@@ -20,8 +20,9 @@ LIB_PATH = os.path.join(_HERE, "libhlbm.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "hlbm.h")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
-BATCH_GRAPH, BATCH_PERSISTENT, BATCH_PER_STEP = 0, 1, 2
-BATCH_MODES = {"graph": BATCH_GRAPH, "persistent": BATCH_PERSISTENT, "per_step": BATCH_PER_STEP}
+BATCH_GRAPH, BATCH_PERSISTENT, BATCH_PER_STEP, BATCH_GRAPH_PERSISTENT = 0, 1, 2, 3
+BATCH_MODES = {"graph": BATCH_GRAPH, "persistent": BATCH_PERSISTENT, "per_step": BATCH_PER_STEP,
+               "graph_persistent": BATCH_GRAPH_PERSISTENT}
 D2Q9, D3Q19 = 9, 19
 F64, F32, F16S, BF16S = 0, 1, 2, 3
 AB, AA = 0, 1
@@ -116,6 +117,7 @@ def load() -> ctypes.CDLL:
         "hlbm_batch_get_schedule": ([vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_int)], i),
         "hlbm_batch_set_porosity": ([vp, i, vp, i, i], i),
         "hlbm_batch_moments": ([vp, i, vp, vp, i, P(ctypes.c_double)], i),
+        "hlbm_batch_set_solid_mask": ([vp, i, vp, i], i),
         "hlbm_set_solid_mask": ([vp, vp, i], i),
         "hlbm_set_diagnostics": ([vp, i, i], i),
         "hlbm_read_diagnostics": ([vp, P(ctypes.c_double), i, P(ctypes.c_int), P(ctypes.c_longlong)], i),
@@ -215,6 +217,10 @@ class HLBM:
         ctx = ctypes.c_void_p()
         _check(lib.hlbm_create(ctypes.byref(self.cfg), ctypes.byref(ctx)))
         self.ctx = ctx
+        # bumped by every call that changes the state, the control or the tape:
+        # a gradient taken from a tape is valid only at the generation it was
+        # recorded in
+        self.generation = 0
         _check(lib.hlbm_bind_buffers(self.ctx, self._pop_a.data_ptr(),
                                      None if self._pop_b is None else self._pop_b.data_ptr(),
                                      self._dfield.data_ptr()))
@@ -243,6 +249,7 @@ class HLBM:
         """d = 1 - varpi per cell (or, for porosity="tensor", rows xx, yy, zz, xy,
         xz, yz of D, shape (6, N)): numpy array (host) or torch tensor (host or
         device)."""
+        self.generation += 1
         t = self.torch
         if isinstance(d, t.Tensor):
             dd = d.contiguous()
@@ -269,6 +276,7 @@ class HLBM:
 
     # -- stepping ----------------------------------------------------------
     def step(self, n: int = 1):
+        self.generation += 1
         _check(load().hlbm_step(self.ctx, int(n)))
 
     @property
@@ -281,6 +289,7 @@ class HLBM:
         _check(load().hlbm_sync(self.ctx))
 
     def reset(self):
+        self.generation += 1
         _check(load().hlbm_reset(self.ctx))
 
     # -- observation -------------------------------------------------------
@@ -327,6 +336,7 @@ class HLBM:
         return buf, s.value
 
     def set_state(self, buf, step: int):
+        self.generation += 1
         if buf.numel() != self.state_bytes:
             raise ValueError("state size mismatch")
         _check(load().hlbm_set_state(self.ctx, buf.contiguous().data_ptr(), 1 if buf.is_cuda else 0,
@@ -335,6 +345,7 @@ class HLBM:
     # -- resolved obstacles ------------------------------------------------
     def set_solid_mask(self, mask):
         """Solid cells (nonzero) of a periodic box, shape (nz, ny, nx) or N; None removes them."""
+        self.generation += 1
         if mask is None:
             _check(load().hlbm_set_solid_mask(self.ctx, None, 0))
             return
@@ -367,6 +378,7 @@ class HLBM:
     # -- adjoint -----------------------------------------------------------
     def set_tape(self, every: int, max_steps: int):
         """Record checkpoints every `every` steps for up to `max_steps` steps from now."""
+        self.generation += 1
         _check(load().hlbm_set_tape(self.ctx, int(every), int(max_steps)))
 
     def tape_info(self) -> dict:
@@ -518,6 +530,25 @@ class HLBMBatch:
         ptr, code, on_dev, keep = _host_or_device(d, nx * ny * nz, self.torch)
         _check(load().hlbm_batch_set_porosity(self.ctx, int(item), ptr, code, on_dev))
         del keep
+
+    def set_solid_mask(self, item: int, mask):
+        """Resolved obstacles of one item: nonzero cells of `mask` (shape
+        (nz, ny, nx) or nx*ny*nz) are solid; None removes them."""
+        if mask is None:
+            _check(load().hlbm_batch_set_solid_mask(self.ctx, int(item), None, 0))
+            return
+        nx, ny, nz = self.items[item]["shape"]
+        t = self.torch
+        if isinstance(mask, t.Tensor):
+            m = mask.reshape(-1).to(t.uint8).contiguous()
+            if m.numel() != nx * ny * nz:
+                raise ValueError("mask needs nx*ny*nz values")
+            _check(load().hlbm_batch_set_solid_mask(self.ctx, int(item), m.data_ptr(), 1 if m.is_cuda else 0))
+            return
+        m = np.ascontiguousarray(np.asarray(mask).reshape(-1) != 0, dtype=np.uint8)
+        if m.size != nx * ny * nz:
+            raise ValueError("mask needs nx*ny*nz values")
+        _check(load().hlbm_batch_set_solid_mask(self.ctx, int(item), m.ctypes.data, 0))
 
     def step(self, n: int = 1):
         _check(load().hlbm_step(self.ctx, int(n)))

@@ -96,9 +96,10 @@ def _time_graph(b, steps):
 
 
 def tune_batch(items, storage="f32", steps=40, tiles=BATCH_TILES, chunks=BATCH_CHUNKS, write=True, out=CACHE):
-    """Time every (tile, blocks_per_cu, chunk) of the persistent kernel in
-    graph mode on this batch (porosity 0.1 everywhere: the sweep does the same
-    work whatever the values) and store the fastest."""
+    """Time every (tile, blocks_per_cu, chunk) of the persistent kernel, launched
+    from a graph, on this batch (porosity 0.1 everywhere: the sweep does the
+    same work whatever the values) and store the fastest.  The tile is also the
+    block of the per-step kernel."""
     import numpy as np
     from . import hlbm
     hlbm.load()
@@ -106,7 +107,7 @@ def tune_batch(items, storage="f32", steps=40, tiles=BATCH_TILES, chunks=BATCH_C
     dt = {"f64": np.float64, "f32": np.float32}.get(storage, np.float16)
     times = {}
     for tile in tiles:
-        b = hlbm.HLBMBatch(items, storage, store_scale=scale, mode="graph", tile=tile)
+        b = hlbm.HLBMBatch(items, storage, store_scale=scale, mode="graph_persistent", tile=tile)
         try:
             for k, it in enumerate(items):
                 nx, ny, nz = it["shape"]

@@ -18,7 +18,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 15
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.hlbm_version() == 2
+    assert lib.hlbm_version() == 3
 
 
 def test_header_matches_binding_struct():

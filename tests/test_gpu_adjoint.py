@@ -10,8 +10,9 @@ adjoint and against finite differences of the GPU's own FP64 forward.
 * The differentiation workload at full size (128x64x64 channel, inlet
   u = 0.02, outlet rho = 1, walls in y and z, d ~ U[0,1), 500 steps, a
   checkpoint every 50) through ``torch.autograd``: the gradient of the channel
-  objective matches central differences of the FP64 GPU forward at 20 seeded
-  cells, and the oracle's gradient on a 64x32x32, 100-step crop of the same
+  objective matches the oracle's full-size gradient (field and 20 seeded
+  cells) and central differences of the FP64 GPU forward at those cells, and
+  the oracle's gradient on a 64x32x32, 100-step crop of the same
   configuration.
 """
 import os
@@ -228,37 +229,88 @@ def _autograd_gradient(H, torch, storage, shape, d64, steps, every):
         sim.close()
 
 
-def test_c4_full_size_autograd_vs_finite_differences(H):
-    import torch
-    shape, steps, every = (128, 64, 64), 500, 50
+C4_FULL = {}
+
+
+def _c4_full(H):
+    """The differentiation workload at full size (128x64x64, 500 steps, a
+    checkpoint every 50), gradients of the channel objective through
+    torch.autograd with an FP32 and an FP64 forward; computed once."""
+    if not C4_FULL:
+        import torch
+        shape, steps, every = (128, 64, 64), 500, 50
+        nx, ny, nz = shape
+        d = inputs.uniform_noise((nz, ny, nx), seed=4).ravel()
+        d32 = inputs.round_to(d, "f32")          # the FP32 form stores d in FP32
+        J32, g32 = _autograd_gradient(H, torch, "f32", shape, d32, steps, every)
+        J64, g64 = _autograd_gradient(H, torch, "f64", shape, d32, steps, every)
+        C4_FULL.update(shape=shape, steps=steps, every=every, d=d32, J32=J32, g32=g32, J64=J64, g64=g64)
+    return C4_FULL
+
+
+def _c4_fd_cells(shape):
     nx, ny, nz = shape
-    say("C4 128x64x64, 500 steps, K=50: autograd (f32 and f64 forward) vs FD of the f64 forward")
-    d = inputs.uniform_noise((nz, ny, nx), seed=4).ravel()
-    d32 = inputs.round_to(d, "f32")          # the FP32 form stores d in FP32
-    J32, g32 = _autograd_gradient(H, torch, "f32", shape, d32, steps, every)
-    J64, g64 = _autograd_gradient(H, torch, "f64", shape, d32, steps, every)
-    assert abs(J32 - J64) <= 1e-4 * abs(J64)
     rng = np.random.default_rng(20)
     fluid = np.zeros((nz, ny, nx), dtype=bool)
     fluid[2:nz - 2, 2:ny - 2, 1:nx - 1] = True
-    cells = rng.choice(np.flatnonzero(fluid.ravel()), size=20, replace=False)
+    return rng.choice(np.flatnonzero(fluid.ravel()), size=20, replace=False)
+
+
+def test_c4_full_size_autograd_vs_finite_differences(H):
+    import torch
+    say("C4 128x64x64, 500 steps, K=50: autograd (f32 and f64 forward) vs FD of the f64 forward")
+    c = _c4_full(H)
+    shape, steps, d32 = c["shape"], c["steps"], c["d"]
+    assert abs(c["J32"] - c["J64"]) <= 1e-4 * abs(c["J64"])
+    cells = _c4_fd_cells(shape)
     h = 1e-4
     fd = np.zeros(len(cells))
     sim = H.HLBM(19, "f64", shape, **C4)
     try:
-        for k, c in enumerate(cells):
+        for k, cell in enumerate(cells):
             dp, dm = d32.copy(), d32.copy()
-            dp[c] += h
-            dm[c] -= h
+            dp[cell] += h
+            dm[cell] -= h
             fd[k] = (_objective_value(H, torch, sim, dp, steps) -
                      _objective_value(H, torch, sim, dm, steps)) / (2 * h)
     finally:
         sim.close()
-    e64 = _rel(g64[cells], fd)
-    e32 = _rel(g32[cells], fd)
+    e64 = _rel(c["g64"][cells], fd)
+    e32 = _rel(c["g32"][cells], fd)
     say(f"FD at 20 cells: f64 adjoint {e64:.2e}, f32-forward adjoint {e32:.2e}")
     assert e64 <= 1e-6
     assert e32 <= 1e-3
+
+
+@pytest.mark.timeout(1200)
+def test_c4_full_size_autograd_vs_oracle(H):
+    """The full-size gradient against the FP64 oracle's gradient (forward on the
+    host cores, then its adjoint with explicit 19x19 collision Jacobians and the
+    scatter transpose of streaming, plus the objective's explicit term): field
+    relative L2 1e-9 with the FP64 forward, 1e-3 with the FP32 forward, and the
+    same at the 20 finite-difference cells.  Several minutes of host time."""
+    c = _c4_full(H)
+    nx, ny, nz = c["shape"]
+    d = c["d"]
+    cfg = OracleConfig(q=19, nx=nx, ny=ny, nz=nz, **C4)
+    say(f"C4 oracle gradient at full size on {NT} host threads")
+    t0 = time.perf_counter()
+    g = oracle.run(cfg, d, c["steps"], nthreads=NT)
+    dr, u = oracle.observe(cfg, g, nthreads=NT)
+    dr3, u3, d3 = dr.reshape(nz, ny, nx), u.reshape(3, nz, ny, nx), d.reshape(nz, ny, nx)
+    Jo = oobj.objective(dr3, u3, d3, C4["tau"])
+    gr, gu, gd = oobj.objective_grad(dr3, u3, d3, C4["tau"])
+    say(f"oracle forward {time.perf_counter() - t0:.0f} s; J oracle {Jo:.9e} gpu f64 {c['J64']:.9e}")
+    go = oracle.gradient(cfg, d, c["steps"], gr.ravel(), gu.reshape(3, -1), every=c["every"], nthreads=NT)
+    go = go + gd.ravel()
+    cells = _c4_fd_cells(c["shape"])
+    e64, e32 = _rel(c["g64"], go), _rel(c["g32"], go)
+    c64, c32 = _rel(c["g64"][cells], go[cells]), _rel(c["g32"][cells], go[cells])
+    say(f"oracle gradient in {time.perf_counter() - t0:.0f} s; rel-L2 field f64 {e64:.2e} f32 {e32:.2e}; "
+        f"20 cells f64 {c64:.2e} f32 {c32:.2e}")
+    assert abs(c["J64"] - Jo) <= 1e-10 * abs(Jo)
+    assert e64 <= 1e-9 and c64 <= 1e-9
+    assert e32 <= 1e-3 and c32 <= 1e-3
 
 
 def test_c4_crop_autograd_vs_oracle(H):
@@ -282,3 +334,38 @@ def test_c4_crop_autograd_vs_oracle(H):
     assert abs(J64 - Jo) <= 1e-10 * abs(Jo)
     assert _rel(g64, go) <= 1e-9
     assert _rel(g32, go) <= 1e-3
+
+
+def test_autograd_rejects_a_graph_whose_lattice_was_reused(H):
+    """Two forwards on one context (as an optimiser or line search does): the
+    second re-records the tape, so the backward of the first must raise; the
+    backward of the second still runs and equals a fresh context's gradient."""
+    import torch
+    from paper_2310_14746_amd.autograd import channel_objective, moments_of_porosity
+    shape, steps, every = (24, 12, 10), 12, 4
+    nx, ny, nz = shape
+    kw = dict(tau=0.7, bc_lo=(2, 1, 1), bc_hi=(3, 1, 1), inlet_u=(0.02, 0, 0), outlet_rho=1.0)
+    sim = H.HLBM(19, "f64", shape, **kw)
+    try:
+        d1 = torch.tensor(inputs.uniform_noise((nz, ny, nx), seed=1), device=sim.device, requires_grad=True)
+        d2 = torch.tensor(inputs.uniform_noise((nz, ny, nx), seed=2), device=sim.device, requires_grad=True)
+        J1 = channel_objective(*moments_of_porosity(d1, sim, steps, every), d1, kw["tau"])
+        J2 = channel_objective(*moments_of_porosity(d2, sim, steps, every), d2, kw["tau"])
+        with pytest.raises(RuntimeError, match="changed after the forward pass"):
+            J1.backward()
+        J2.backward()
+        g2 = d2.grad.detach().cpu().numpy()
+        # also after a plain step or reset between the passes
+        J3 = channel_objective(*moments_of_porosity(d2, sim, steps, every), d2, kw["tau"])
+        sim.reset()
+        with pytest.raises(RuntimeError, match="changed after the forward pass"):
+            J3.backward()
+    finally:
+        sim.close()
+    fresh = H.HLBM(19, "f64", shape, **kw)
+    try:
+        d2b = torch.tensor(inputs.uniform_noise((nz, ny, nx), seed=2), device=fresh.device, requires_grad=True)
+        channel_objective(*moments_of_porosity(d2b, fresh, steps, every), d2b, kw["tau"]).backward()
+        assert np.array_equal(d2b.grad.detach().cpu().numpy(), g2)
+    finally:
+        fresh.close()

@@ -164,15 +164,34 @@ def test_c2_full_size_f32(H):
 
 
 # 16-bit storage: one read of the state already carries the rounding of the
-# 19 pulled populations, whose magnitude (~ w 3 c.u) is far above drho.  The
-# test computes that floor from the oracle's populations; the run accumulates
-# about as much again (measured totals 1.8-2.4 x the floor).  Velocity is
-# held to the stated 2e-3; drho to max(2e-3, 3 x its floor).  BF16 (7 mantissa
-# bits) is reported against 3 x its floors.
+# 19 pulled populations, each about as large as drho itself.  The test computes
+# that floor from the oracle's populations; the run accumulates about as much
+# again (measured totals 1.2-2.4 x the floor).  Velocity meets the stated 2e-3.
+# drho, 2.3e-3, stays within 3 x its floor but above the stated 2e-3, a known miss
+# that the strict xfail below records (it fails the suite if the miss ever
+# disappears, so that the statement is updated).  BF16 (7 mantissa bits) is
+# reported against 3 x its floors.
+_C2_F16S = {}
+
+
+def _c2_f16s(H):
+    if not _C2_F16S:
+        _C2_F16S["r"] = _full_size_tile_check(H, 512, "f16s", 500, scale=C2_SCALE)
+    return _C2_F16S["r"]
+
+
 def test_c2_full_size_f16s(H):
-    eu, er, (fu, fr) = _full_size_tile_check(H, 512, "f16s", 500, scale=C2_SCALE)
+    eu, er, (fu, fr) = _c2_f16s(H)
     assert eu <= TOL["f16s"]
-    assert er <= max(TOL["f16s"], 3.0 * fr)
+    assert er <= 3.0 * fr       # at the quantization floor of one read of the state
+
+
+@pytest.mark.xfail(strict=True, reason="FP16S drho at 512^3 / 500 steps measures 2.3e-3, within 3x the "
+                                        "quantization floor of one read of the stored state; the stated "
+                                        "tolerance is 2e-3")
+def test_c2_full_size_f16s_drho_stated_tolerance(H):
+    eu, er, _ = _c2_f16s(H)
+    assert er <= TOL["f16s"]
 
 
 def test_c2_full_size_bf16s_reported(H):

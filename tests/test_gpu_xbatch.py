@@ -1,5 +1,6 @@
-"""GPU tests of batched periodic boxes (persistent kernel with grid barrier,
-graph launch, per-step launches).  Collected after the other GPU tests.
+"""GPU tests of batched periodic boxes (graph of per-step kernel nodes,
+persistent kernel with grid barrier launched directly or from a graph,
+per-step launches).  Collected after the other GPU tests.
 
 * every mode gives the same bits, under every schedule (tile size, resident
   blocks per CU, tiles per draw);
@@ -83,7 +84,7 @@ def test_single_item_batch_equals_single_context(H):
     it = dict(shape=(40, 24, 16), tau=0.7, force=(1e-5, 0, 0))
     d = _fields([it], 7)[0]
     ref_state, _, _ = _run_single(H, it, d, 30)
-    for mode in ("per_step", "persistent", "graph"):
+    for mode in ("per_step", "persistent", "graph", "graph_persistent"):
         say(f"one item, mode {mode}")
         st, _, _ = _run_batch(H, [it], [d], 30, mode)
         assert np.array_equal(st, ref_state), mode
@@ -93,7 +94,7 @@ def test_modes_bitwise_and_items_match_single_contexts(H):
     fields = _fields(ITEMS, 3)
     steps = 41
     ref = None
-    for mode in ("per_step", "persistent", "graph"):
+    for mode in ("per_step", "persistent", "graph", "graph_persistent"):
         say(f"{len(ITEMS)} items, mode {mode}, {steps} steps")
         st, mom, tot = _run_batch(H, ITEMS, fields, steps, mode)
         if ref is None:
@@ -116,7 +117,7 @@ def test_schedules_bitwise(H, tile, bpc, chunk):
     fields = _fields(ITEMS, 11)
     steps = 23
     ref, _, ref_tot = _run_batch(H, ITEMS, fields, steps, "per_step")
-    for mode in ("graph", "persistent", "per_step"):
+    for mode in ("graph", "graph_persistent", "persistent", "per_step"):
         b = H.HLBMBatch(ITEMS, "f32", mode=mode, tile=tile)
         try:
             sc = b.schedule()
@@ -162,21 +163,25 @@ def test_schedule_rules(H):
         b.close()
 
 
-def test_graph_relaunch_and_odd_even_steps(H):
-    """Graph cached per (steps, start buffer): 7 + 7 + 3 steps == 17 per-step."""
+@pytest.mark.parametrize("mode", ["graph", "graph_persistent"])
+def test_graph_relaunch_and_odd_even_steps(H, mode):
+    """Graph cached per (steps, start buffer, kind): 7 + 7 + 3 steps, then a
+    switch of graph kind for 4 more, == 21 per-step."""
     fields = _fields(ITEMS[:2], 5)
-    b = H.HLBMBatch(ITEMS[:2], "f32", mode="graph")
+    b = H.HLBMBatch(ITEMS[:2], "f32", mode=mode)
     try:
         for k, d in enumerate(fields):
             b.set_porosity(k, d)
         for n in (7, 7, 3):
             b.step(n)
+        b.set_mode("graph_persistent" if mode == "graph" else "graph")
+        b.step(4)
         b.sync()
-        assert b.step_count == 17
+        assert b.step_count == 21
         st = b.get_state()[0].cpu().numpy()
     finally:
         b.close()
-    st2, _, _ = _run_batch(H, ITEMS[:2], fields, 17, "per_step")
+    st2, _, _ = _run_batch(H, ITEMS[:2], fields, 21, "per_step")
     assert np.array_equal(st, st2)
 
 
@@ -268,7 +273,8 @@ def test_storage_forms_match_single_contexts(H, storage):
             refs.append(sim.get_state()[0].cpu().numpy())
         finally:
             sim.close()
-    for mode, tile in (("graph", 0), ("graph", 64), ("persistent", 0), ("per_step", 0)):
+    for mode, tile in (("graph", 0), ("graph", 64), ("graph_persistent", 0), ("graph_persistent", 64),
+                       ("persistent", 0), ("per_step", 0)):
         say(f"{storage} batch, mode {mode}, tile {tile or 'default'}")
         b = H.HLBMBatch(items, storage, store_scale=scale, mode=mode, tile=tile)
         try:
@@ -297,7 +303,7 @@ def test_barrier_bound_error_path(H):
     after a reset the batch runs again and matches one launch per step."""
     fields = _fields(ITEMS, 17)
     ref, _, _ = _run_batch(H, ITEMS, fields, 9, "per_step")
-    for mode in ("persistent", "graph"):
+    for mode in ("persistent", "graph_persistent"):
         say(f"barrier bound 0, mode {mode}")
         b = H.HLBMBatch(ITEMS, "f32", mode=mode)
         try:
@@ -327,7 +333,7 @@ def test_padded_batch_rows_bitwise(H, pad):
     fields = _fields(ITEMS, 12)
     steps = 17
     ref, ref_mom, ref_tot = _run_batch(H, ITEMS, fields, steps, "per_step")
-    for mode in ("graph", "persistent", "per_step"):
+    for mode in ("graph", "graph_persistent", "persistent", "per_step"):
         b = H.HLBMBatch(ITEMS, "f32", mode=mode, row_pad=pad)
         try:
             for k, d in enumerate(fields):
@@ -343,3 +349,109 @@ def test_padded_batch_rows_bitwise(H, pad):
         assert np.array_equal(st, ref) and np.array_equal(tot, ref_tot), mode
         for k in range(len(ITEMS)):
             assert np.array_equal(mom[k][0], ref_mom[k][0]) and np.array_equal(mom[k][1], ref_mom[k][1]), (mode, k)
+
+
+def _masks(items, seed):
+    """Random obstacles (about 15% of the cells solid) for every item."""
+    out = []
+    for k, it in enumerate(items):
+        n = int(np.prod(it["shape"]))
+        out.append((np.random.default_rng(seed + k).random(n) < 0.15).astype(np.uint8))
+    return out
+
+
+def test_masked_items_match_single_contexts(H):
+    """Resolved obstacles per item: an item with a mask evolves bit for bit as
+    a single context with the same mask (hlbm_set_solid_mask), an item without
+    one as the plain single context, in every launch mode; moments and totals
+    follow; removing the masks gives the unmasked batch back."""
+    items = ITEMS
+    fields = _fields(items, 21)
+    masks = _masks(items, 30)
+    masked = {0, 2}      # items 1 and 3 stay free of obstacles
+    steps = 19
+    refs, ref_mom = [], []
+    for k, (it, d) in enumerate(zip(items, fields)):
+        sim = H.HLBM(19, "f32", it["shape"], tau=it["tau"], force=it["force"])
+        try:
+            sim.set_porosity(d)
+            if k in masked:
+                sim.set_solid_mask(masks[k])
+            sim.step(steps)
+            refs.append(sim.state_f64())
+            dr, u = sim.moments("f64")
+            ref_mom.append((dr.cpu().numpy(), u.cpu().numpy()))
+        finally:
+            sim.close()
+    for mode in ("graph", "graph_persistent", "persistent", "per_step"):
+        say(f"masked items {sorted(masked)}, mode {mode}")
+        b = H.HLBMBatch(items, "f32", mode=mode)
+        try:
+            for k, d in enumerate(fields):
+                b.set_porosity(k, d)
+                if k in masked:
+                    b.set_solid_mask(k, masks[k])
+            b.step(steps)
+            b.sync()
+            st = b.get_state()[0].cpu().numpy().view(np.float32).reshape(19, -1)
+            mom = [tuple(x.cpu().numpy() for x in b.moments(k)) for k in range(len(items))]
+            tot = b.totals()
+        finally:
+            b.close()
+        base = 0
+        for k, it in enumerate(items):
+            n = int(np.prod(it["shape"]))
+            assert np.array_equal(st[:, base:base + n].astype(np.float64), refs[k]), (mode, k)
+            assert np.array_equal(mom[k][0], ref_mom[k][0]) and np.array_equal(mom[k][1], ref_mom[k][1]), (mode, k)
+            if k in masked:
+                solid = masks[k].reshape(mom[k][0].shape) != 0
+                assert (mom[k][0][solid] == 0).all() and (mom[k][1][:, solid] == 0).all()
+            # totals: sums over fluid cells of drho and rho u
+            dr, u = mom[k]
+            want = [dr.sum()] + [((1.0 + dr) * u[a]).sum() for a in range(3)]
+            assert np.allclose(tot[k], want, rtol=1e-9, atol=1e-15), (mode, k)
+            base += n
+    # masks removed: the plain batch again
+    ref_plain, _, _ = _run_batch(H, items, fields, steps, "per_step")
+    b = H.HLBMBatch(items, "f32", mode="graph")
+    try:
+        for k, d in enumerate(fields):
+            b.set_porosity(k, d)
+            b.set_solid_mask(k, masks[k])
+        for k in range(len(items)):
+            b.set_solid_mask(k, None)
+        b.step(steps)
+        b.sync()
+        assert np.array_equal(b.get_state()[0].cpu().numpy(), ref_plain)
+    finally:
+        b.close()
+
+
+def test_masked_sphere_item_vs_oracle(H):
+    """A resolved sphere in a periodic 32^3 unit cell, inside a batch, against
+    the FP64 oracle's masked run."""
+    e, tau = 32, 0.8
+    r = inputs.radius_for_porosity(e, 0.6)
+    mask = (inputs.sphere_indicator(e, r) > 0.5).astype(np.uint8).ravel()
+    it = dict(shape=(e, e, e), tau=tau, force=(1e-6, 0, 0))
+    items = [ITEMS[2], it]
+    fields = _fields(items, 4)
+    fields[1] = np.zeros(e ** 3, dtype=np.float32)
+    steps = 300
+    say("masked sphere item vs oracle, 300 steps")
+    b = H.HLBMBatch(items, "f32", mode="graph")
+    try:
+        for k, d in enumerate(fields):
+            b.set_porosity(k, d)
+        b.set_solid_mask(1, mask)
+        b.step(steps)
+        dr, u = (x.cpu().numpy() for x in b.moments(1))
+    finally:
+        b.close()
+    cfg = OracleConfig(q=19, nx=e, ny=e, nz=e, tau=tau, force=(1e-6, 0, 0))
+    g = oracle.run_masked(cfg, mask, np.zeros(e ** 3), steps, nthreads=NT)
+    dr_o, u_o = oracle.observe_masked(cfg, mask, g)
+    eu = rel_l2_u(u.reshape(3, -1), u_o)
+    er = rel_l2_drho(dr.ravel(), dr_o, u_o)
+    say(f"rel-L2 u {eu:.2e} drho {er:.2e}")
+    assert eu <= 1e-5 and er <= 1e-5
