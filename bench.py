@@ -282,34 +282,38 @@ def summarize_counters(fetch_dir, write_dir, n_cells=N_EDGE ** 3):
     ])
 
 
-def _timed_batch(hlbm, items, fields, steps, mode, sched, masks=None, warm_same=False):
-    """One timed hlbm_step call of `steps` over a batch; returns (ms, cells,
-    totals, schedule).  warm_same: run the same call once untimed first and
-    reset (a graph is built on the first call with a given step count)."""
+def _timed_batch(hlbm, items, fields, steps, modes, sched, masks=None, rounds=2):
+    """Timed hlbm_step calls of `steps` over one batch (one allocation), from
+    rest, in each of `modes`, alternating over `rounds`; each mode's first call
+    with this step count runs untimed first (a graph is built on the first
+    call with a given step count and starting buffer).  Returns
+    ({mode: min ms}, cells, {mode: totals after the last timed call}, schedule)."""
     import torch
-    b = hlbm.HLBMBatch(items, "f32", mode=mode, **sched)
+    b = hlbm.HLBMBatch(items, "f32", mode=modes[0], **sched)
     try:
         for k, d in enumerate(fields):
             b.set_porosity(k, d)
             if masks is not None:
                 b.set_solid_mask(k, masks[k])
-        if warm_same:           # builds the graph that the timed call (from rest, buffer A) reuses
-            b.step(steps)
-            b.sync()
-            b.reset()
-        else:
-            b.step(2)
-            b.sync()
-            b.reset()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(b.stream)
-        b.step(steps)
-        e1.record(b.stream)
-        b.sync()
-        ms = e0.elapsed_time(e1)
+        ms, tot = {}, {}
+        for r in range(rounds):
+            for mode in modes:
+                b.set_mode(mode)
+                if r == 0:
+                    b.step(steps if mode.startswith("graph") else 2)
+                    b.sync()
+                b.reset()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(b.stream)
+                b.step(steps)
+                e1.record(b.stream)
+                b.sync()
+                t = e0.elapsed_time(e1)
+                ms[mode] = min(ms.get(mode, t), t)
+                tot[mode] = b.totals()
         _, cells = b.info()
-        return ms, cells, b.totals(), b.schedule()
+        return ms, cells, tot, b.schedule()
     finally:
         b.close()
 
@@ -321,9 +325,10 @@ def time_batched(hlbm, steps=2000, seed=0):
     * "graph_persistent": one graph launch of the persistent kernel, which
       runs all steps with a grid barrier between them;
     * "per_step": one kernel launch per step.
-    Algorithmic bytes as for the FP32 sweep.  The same cells with the sphere
-    resolved (solid mask, bounce-back links, d = 0) run as one graph too, and
-    the permeabilities of both are reported."""
+    The modes alternate on one allocation (two rounds, the faster of each is
+    reported).  Algorithmic bytes as for the FP32 sweep.  The same cells with
+    the sphere resolved (solid mask, bounce-back links, d = 0) run as one graph
+    too, and the permeabilities of both are reported."""
     from paper_2310_14746_amd import inputs, permeability, tune
     spec = inputs.batch_items(256, seed=seed)
     items = [dict(shape=(e, e, e), tau=t, force=(1e-6, 0, 0)) for e, _, t in spec]
@@ -338,31 +343,31 @@ def time_batched(hlbm, steps=2000, seed=0):
                        f"tau U[0.55,1.0], F=1e-6, FP32, seed {seed}", "steps": steps}
     cells_k = np.array([e ** 3 for e, _, _ in spec], dtype=float)
     nu = (np.array([t for _, _, t in spec]) - 0.5) / 3.0
-    k_hom = None
-    for mode in ("graph", "graph_persistent", "per_step"):
-        ms, cells, tot, sc = _timed_batch(hlbm, items, item_fields, steps, mode, sched,
-                                          warm_same=mode.startswith("graph"))
-        log(f"batched {mode}: {steps} steps in {ms:.0f} ms")
-        out["cells"] = cells
-        out[mode] = {"ms": round(ms, 1), "mlups": round(cells * steps / (ms * 1e-3) / 1e6, 1),
-                     "alg_GBs": round(156 * cells * steps / (ms * 1e-3) / 1e9, 1)}
-        out["schedule"] = dict(sc, tuned=bool(sched))
-        if mode == "graph":
-            k_hom = nu * (tot[:, 1] / cells_k) / 1e-6
+    modes = ("graph", "graph_persistent", "per_step")
+    ms, cells, tot, sc = _timed_batch(hlbm, items, item_fields, steps, modes, sched)
+    out["cells"] = cells
+    out["schedule"] = dict(sc, tuned=bool(sched))
+    for mode in modes:
+        log(f"batched {mode}: {steps} steps in {ms[mode]:.0f} ms")
+        out[mode] = {"ms": round(ms[mode], 1), "mlups": round(cells * steps / (ms[mode] * 1e-3) / 1e6, 1),
+                     "alg_GBs": round(156 * cells * steps / (ms[mode] * 1e-3) / 1e9, 1)}
+    # every mode gives the same bits (the totals of its last run)
+    out["modes_bitwise_equal"] = bool(all(np.array_equal(tot[m], tot["per_step"]) for m in modes))
+    k_hom = nu * (tot["graph"][:, 1] / cells_k) / 1e-6
     out["permeability"] = {"min": float(k_hom.min()), "median": float(np.median(k_hom)),
                            "max": float(k_hom.max()),
                            "all_finite_positive": bool((k_hom > 0).all() and np.isfinite(k_hom).all())}
     # resolved spheres: the geometry of the unit-cell Stokes problem
     log("batched: resolved spheres (solid masks)")
     r_items, r_fields, r_masks, _ = permeability.resolved_cells(256, seed=seed)
-    ms, cells_r, tot_r, _ = _timed_batch(hlbm, r_items, r_fields, steps, "graph", sched, masks=r_masks,
-                                         warm_same=True)
-    log(f"batched resolved graph: {steps} steps in {ms:.0f} ms")
-    k_res = nu * (tot_r[:, 1] / cells_k) / 1e-6
+    ms_r, cells_r, tot_r, _ = _timed_batch(hlbm, r_items, r_fields, steps, ("graph",), sched, masks=r_masks,
+                                           rounds=1)
+    log(f"batched resolved graph: {steps} steps in {ms_r['graph']:.0f} ms")
+    k_res = nu * (tot_r["graph"][:, 1] / cells_k) / 1e-6
     ratio = k_hom / k_res
     out["resolved"] = {
         "workload": "the same 256 cells with the sphere resolved: solid mask, bounce-back links, d = 0",
-        "ms": round(ms, 1), "mlups": round(cells_r * steps / (ms * 1e-3) / 1e6, 1),
+        "ms": round(ms_r["graph"], 1), "mlups": round(cells_r * steps / (ms_r["graph"] * 1e-3) / 1e6, 1),
         "alg_bytes_per_cell": 160,
         "permeability": {"min": float(k_res.min()), "median": float(np.median(k_res)), "max": float(k_res.max())},
         "homogenized_over_resolved": {"min": float(ratio.min()), "median": float(np.median(ratio)),
