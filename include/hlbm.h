@@ -206,6 +206,24 @@ int hlbm_get_step(const hlbm_ctx *ctx, long long *step);
  * a total is not finite. */
 int hlbm_moments(hlbm_ctx *ctx, void *drho, void *u, int dtype, int on_device, double *totals);
 
+/* hlbm_moments for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same moments kernel and fixed-order FP64 reduction, with the block
+ * partials in a static device array of the library instead of memory
+ * allocated on first use, and nothing else allocated, copied or awaited.
+ * drho, u: device arrays as for hlbm_moments with on_device = 1 (either may
+ * be NULL); totals: a device array of 4 doubles (or NULL), written with the
+ * same values hlbm_moments returns.  Only enqueues work on the context's
+ * stream: results are there once the stream reaches this point (hlbm_sync or
+ * a wait on the stream), and a non-finite total is not reported.  The static
+ * array holds the partials of at most 2^19 blocks (16 MiB per GPU the library
+ * runs on, held until the process ends): totals of a box with more blocks of
+ * block_x cells -> EINVAL (512^3 cells at block_x 256 fit).  Every call on a
+ * GPU shares that GPU's array, so calls whose work overlaps on one GPU (two
+ * streams, two threads) race on it; serialize them.  ESTATE if buffers are
+ * not bound, EUNSUPPORTED for a batch. */
+int hlbm_moments_noalloc(hlbm_ctx *ctx, void *drho, void *u, int dtype, double *totals);
+
 /* Size in bytes of a raw state snapshot: Q dense rows of N stored values
  * (smaller than a population buffer, whose rows are padded). */
 int hlbm_state_bytes(const hlbm_ctx *ctx, size_t *bytes);

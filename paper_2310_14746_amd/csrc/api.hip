@@ -9,6 +9,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -21,6 +22,17 @@ using hlbm::Params;
 // Polls of the persistent batch kernel's grid barrier before it gives up
 // (each poll sleeps about 0.1 us): far beyond any step of the workloads here.
 constexpr unsigned kBarrierPollsDefault = 1u << 20;
+
+// Static device scratch of hlbm_moments_noalloc: the moments kernel's FP64
+// block partials (4 per block, at most kScratchBlocks blocks) followed by the
+// first-pass results of the two-pass reduction (4 * REDUCE_STAGE).  Every GPU
+// the library runs on holds its own copy (16 MiB) until the process ends.
+// Host code never passes `scratch` itself to a kernel (in host code the name
+// is a stand-in, not a device address): it uses the per-device address that
+// hipGetSymbolAddress returns, below.
+constexpr uint32_t kScratchBlocks = 1u << 19;
+constexpr size_t kScratchDoubles = 4 * ((size_t)kScratchBlocks + hlbm::REDUCE_STAGE);
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 struct hlbm_ctx {
     hlbm_config cfg;
@@ -431,6 +443,29 @@ int batch_step(hlbm_ctx* c, int nsteps)
     return HLBM_OK;
 }
 
+// Device address of this device's copy of `scratch`, looked up once per
+// device (with that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices];
+
+int scratch_address(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "moments_noalloc: current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(HLBM_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "moments_noalloc: address of the static scratch");
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return HLBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -737,6 +772,32 @@ int hlbm_moments(hlbm_ctx* c, void* drho, void* u, int dtype, int on_device, dou
     if (totals)
         for (int k = 0; k < 4; ++k)
             if (!isfinite(totals[k])) return fail(HLBM_ENUMERIC, "non-finite total (component %d)", k);
+    return HLBM_OK;
+}
+
+int hlbm_moments_noalloc(hlbm_ctx* c, void* drho, void* u, int dtype, double* totals)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->batch) return fail(HLBM_EUNSUPPORTED, "moments_noalloc takes a single context, not a batch");
+    if (dtype != HLBM_DT_F64 && dtype != HLBM_DT_F32) return fail(HLBM_EINVAL, "dtype must be F64 or F32");
+    const hlbm::Launch l = hlbm::cell_launch(c->p, c->bx);
+    if (totals && l.nblocks > kScratchBlocks)
+        return fail(HLBM_EINVAL, "totals of %u blocks exceed the static scratch (%u blocks of block_x cells)",
+                    l.nblocks, kScratchBlocks);
+    if (!c->bound) return fail(HLBM_ESTATE, "buffers not bound");
+    double* sc = nullptr;
+    if (totals) {
+        rc = scratch_address(&sc);
+        if (rc) return rc;
+    }
+    double* partials = sc;
+    double* stage = sc ? sc + 4 * (size_t)kScratchBlocks : nullptr;
+    const int mbc = c->aa ? aa_mode(c) : c->bcmode;
+    hipError_t e = hlbm::launch_moments(c->q, c->cfg.storage, mbc, c->p, c->pop[c->cur], drho, u,
+                                        dtype == HLBM_DT_F64, partials, c->bx, c->stream);
+    if (e == hipSuccess && totals) e = hlbm::launch_reduce4(partials, l.nblocks, stage, totals, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "moments_noalloc launch");
     return HLBM_OK;
 }
 

@@ -104,6 +104,7 @@ def load() -> ctypes.CDLL:
         "hlbm_step": ([vp, i], i),
         "hlbm_get_step": ([vp, P(ctypes.c_longlong)], i),
         "hlbm_moments": ([vp, vp, vp, i, i, P(ctypes.c_double)], i),
+        "hlbm_moments_noalloc": ([vp, vp, vp, i, vp], i),
         "hlbm_state_bytes": ([vp, P(ctypes.c_size_t)], i),
         "hlbm_get_state": ([vp, vp, i, P(ctypes.c_longlong)], i),
         "hlbm_set_state": ([vp, vp, i, ctypes.c_longlong], i),
@@ -317,6 +318,21 @@ class HLBM:
         tot = (ctypes.c_double * 4)()
         _check(load().hlbm_moments(self.ctx, None, None, DT_F64, 1, tot))
         return np.array(tot)
+
+    def moments_noalloc(self, drho=None, u=None, totals=None):
+        """Enqueue hlbm_moments_noalloc into caller-owned device tensors (drho
+        (nz, ny, nx) and u (3, nz, ny, nx), both f64 or both f32; totals 4 f64);
+        nothing is allocated or awaited."""
+        t = self.torch
+        ref = drho if drho is not None else u
+        cdt = DT_F32 if ref is not None and ref.dtype == t.float32 else DT_F64
+        for a in (drho, u, totals):
+            if a is not None and not (a.is_cuda and a.is_contiguous()):
+                raise ValueError("moments_noalloc writes contiguous device tensors")
+        if totals is not None and (totals.dtype != t.float64 or totals.numel() < 4):
+            raise ValueError("totals must hold 4 float64 values")
+        ptr = (lambda a: None if a is None else a.data_ptr())
+        _check(load().hlbm_moments_noalloc(self.ctx, ptr(drho), ptr(u), cdt, ptr(totals)))
 
     # -- state -------------------------------------------------------------
     @property
