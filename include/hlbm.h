@@ -332,6 +332,26 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * take the recorded steps past max_steps.  Waits for the stream. */
 int hlbm_set_tape(hlbm_ctx *ctx, int every, int max_steps);
 
+/* What the tape keeps for the reverse sweep.
+ *   HLBM_TAPE_REPLAY  (default) checkpoints every `every` steps; the reverse
+ *                     sweep replays each segment from its checkpoint (two sets
+ *                     of every - 1 replay states), as described above.
+ *   HLBM_TAPE_MOMENTS the same checkpoints, and every recorded forward step
+ *                     also writes the FP64 pre-collision moments (rho - rho0,
+ *                     j) of every cell -- all the reverse step needs of the
+ *                     forward state, since the collision is linearized at
+ *                     them -- to a record of 32 bytes per cell and step
+ *                     (max_steps * 32 * N bytes of device memory, no replay
+ *                     states).  The reverse sweep reads the record instead of
+ *                     replaying segments; the gradients are the same bit for
+ *                     bit.  This trades memory (at the 288 GB of one MI355X,
+ *                     plenty for the sizes here) for the replay's forward
+ *                     sweeps.
+ * Takes effect at once: a tape already set is rebuilt in the new kind and
+ * restarts at the current state.  EINVAL for another kind. */
+enum { HLBM_TAPE_REPLAY = 0, HLBM_TAPE_MOMENTS = 1 };
+int hlbm_set_tape_kind(hlbm_ctx *ctx, int kind);
+
 /* The tape's every and max_steps (0 when none), the steps recorded since its
  * origin, and its device bytes.  Any output may be NULL. */
 int hlbm_tape_info(const hlbm_ctx *ctx, int *every, int *max_steps, long long *recorded,

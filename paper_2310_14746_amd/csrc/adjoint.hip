@@ -46,26 +46,6 @@ namespace hlbm {
 template <class S>
 using LamT = typename std::conditional<std::is_same<S, StoreF64>::value, double, float>::type;
 
-// FP64 moments of the pre-collision populations gathered at one cell.
-struct Moms {
-    double s, jx, jy, jz;
-};
-
-template <class L, class R>
-__device__ __forceinline__ Moms moments_f64(const R (&g)[L::Q])
-{
-    Moms m{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const double gi = (double)g[i];
-        m.s += gi;
-        if (L::cx[i]) m.jx += L::cx[i] > 0 ? gi : -gi;
-        if (L::cy[i]) m.jy += L::cy[i] > 0 ? gi : -gi;
-        if (L::cz[i]) m.jz += L::cz[i] > 0 ? gi : -gi;
-    }
-    return m;
-}
-
 // Gather of the forward pre-collision populations y at (x, y, z) from the
 // post-collision state `src`, reduced at once to FP64 moments.
 template <class L, class S, int BC>
@@ -360,15 +340,19 @@ __device__ __forceinline__ void collide_adjoint(const Moms& m, const Sh& sh, con
 // forward state x_{t-1} in `xprev`; each control row of dbar += this step's
 // cotangent of that row.
 // ---------------------------------------------------------------------------
-template <class L, class S, int BC, int PK>
+// REC: the forward step's moments come from its moment record (`rec`, four
+// rows of N doubles written by the recording sweep) instead of a gather of
+// x_{t-1}; the values are the same bit for bit.
+template <class L, class S, int BC, int PK, bool REC>
 __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in, LamT<S>* __restrict__ lam_out,
                                              const typename S::T* __restrict__ xprev,
+                                             const double* __restrict__ rec,
                                              const typename S::D* __restrict__ dfield, double* __restrict__ dbar,
                                              const Params& p, uint32_t x, uint32_t y, uint32_t z)
 {
     const uint32_t N = p.N;
     const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
-    const Moms m = forward_moments<L, S, BC>(xprev, p, x, y, z);
+    const Moms m = REC ? recorded_moments(rec, N, cell) : forward_moments<L, S, BC>(xprev, p, x, y, z);
     using Sh = AdjShift<PK>;
     const Sh sh = Sh::template load<S>(dfield, p.P, cell);  // control rows are P apart
     double pb[L::Q];
@@ -400,16 +384,17 @@ __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in,
     }
 }
 
-template <class L, class S, int BC, int PK>
+template <class L, class S, int BC, int PK, bool REC>
 __global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict__ lam_in,
                                                        LamT<S>* __restrict__ lam_out,
                                                        const typename S::T* __restrict__ xprev,
+                                                       const double* __restrict__ rec,
                                                        const typename S::D* __restrict__ dfield,
                                                        double* __restrict__ dbar, Params p)
 {
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)p.nx) return;
-    adjoint_cell<L, S, BC, PK>(lam_in, lam_out, xprev, dfield, dbar, p, x, blockIdx.y, blockIdx.z);
+    adjoint_cell<L, S, BC, PK, REC>(lam_in, lam_out, xprev, rec, dfield, dbar, p, x, blockIdx.y, blockIdx.z);
 }
 
 // Interior and shell of a box with walls or open faces (see Split), in one
@@ -418,10 +403,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict_
 // rule.  The choice is uniform per block.  The shell's blocks come first:
 // they are the slow ones, and blocks start in index order, so the interior
 // blocks fill in behind them instead of leaving them as the tail.
-template <class L, class S, int PK>
+template <class L, class S, int PK, bool REC>
 __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __restrict__ lam_in,
                                                              LamT<S>* __restrict__ lam_out,
                                                              const typename S::T* __restrict__ xprev,
+                                                             const double* __restrict__ rec,
                                                              const typename S::D* __restrict__ dfield,
                                                              double* __restrict__ dbar, Params p, Split sp)
 {
@@ -431,7 +417,7 @@ __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __res
         if (k >= sp.n_shell) return;
         uint32_t x, y, z;
         shell_cell(sp, (uint32_t)p.nx, (uint32_t)p.ny, k, x, y, z);
-        adjoint_cell<L, S, BC_GENERAL, PK>(lam_in, lam_out, xprev, dfield, dbar, p, x, y, z);
+        adjoint_cell<L, S, BC_GENERAL, PK, REC>(lam_in, lam_out, xprev, rec, dfield, dbar, p, x, y, z);
     } else {
         const uint32_t bi = b - sp.blocks_shell;
         const uint32_t row = bi / sp.gx, bxi = bi - row * sp.gx;
@@ -439,7 +425,8 @@ __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __res
         const uint32_t zz = row / iy, yy = row - zz * iy;
         const uint32_t x = sp.lo[0] + bxi * blockDim.x + threadIdx.x;
         if (x >= sp.hi[0]) return;
-        adjoint_cell<L, S, BC_PERIODIC, PK>(lam_in, lam_out, xprev, dfield, dbar, p, x, sp.lo[1] + yy, sp.lo[2] + zz);
+        adjoint_cell<L, S, BC_PERIODIC, PK, REC>(lam_in, lam_out, xprev, rec, dfield, dbar, p, x, sp.lo[1] + yy,
+                                                 sp.lo[2] + zz);
     }
 }
 
@@ -461,10 +448,10 @@ static hipError_t seed_dispatch_bc(int bcmode, const Params& p, const void* src,
     return hipGetLastError();
 }
 
-template <class L, class S, int PK>
-static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* lam_in, void* lam_out,
-                                      const void* xprev, const void* dfield, double* dbar, int bx,
-                                      hipStream_t s)
+template <class L, class S, int PK, bool REC>
+static hipError_t adjoint_dispatch_rec(int bcmode, const Params& p, const void* lam_in, void* lam_out,
+                                       const void* xprev, const double* rec, const void* dfield, double* dbar,
+                                       int bx, hipStream_t s)
 {
     const Launch l = cell_launch(p, bx < 256 ? bx : 256);
     auto* a = static_cast<const typename S::T*>(xprev);
@@ -472,17 +459,28 @@ static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* l
     auto* li = static_cast<const LamT<S>*>(lam_in);
     auto* lo = static_cast<LamT<S>*>(lam_out);
     if (bcmode == BC_PERIODIC) {
-        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, li, lo, a, d, dbar, p);
+        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC, PK, REC>), l.grid, l.block, 0, s, li, lo, a, rec, d, dbar,
+                           p);
         return hipGetLastError();
     }
     const Split sp = split_of(p, (int)l.block.x);
     if (!sp.interior()) {
-        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL, PK>), l.grid, l.block, 0, s, li, lo, a, d, dbar, p);
+        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL, PK, REC>), l.grid, l.block, 0, s, li, lo, a, rec, d, dbar,
+                           p);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((adjoint_split_kernel<L, S, PK>), dim3(sp.blocks_in + sp.blocks_shell), l.block, 0, s, li, lo, a,
-                       d, dbar, p, sp);
+    hipLaunchKernelGGL((adjoint_split_kernel<L, S, PK, REC>), dim3(sp.blocks_in + sp.blocks_shell), l.block, 0, s, li,
+                       lo, a, rec, d, dbar, p, sp);
     return hipGetLastError();
+}
+
+template <class L, class S, int PK>
+static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* lam_in, void* lam_out,
+                                      const void* xprev, const double* rec, const void* dfield, double* dbar,
+                                      int bx, hipStream_t s)
+{
+    if (rec) return adjoint_dispatch_rec<L, S, PK, true>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
+    return adjoint_dispatch_rec<L, S, PK, false>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
 }
 
 template <class L>
@@ -501,18 +499,18 @@ static hipError_t seed_dispatch_store(int storage, int bcmode, const Params& p, 
 
 template <class L, int PK>
 static hipError_t adjoint_dispatch_store(int storage, int bcmode, const Params& p, const void* lam_in,
-                                         void* lam_out, const void* xprev, const void* dfield,
+                                         void* lam_out, const void* xprev, const double* rec, const void* dfield,
                                          double* dbar, int bx, hipStream_t s)
 {
     switch (storage) {
     case StoreF64::code:
-        return adjoint_dispatch_bc<L, StoreF64, PK>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+        return adjoint_dispatch_bc<L, StoreF64, PK>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
     case StoreF32::code:
-        return adjoint_dispatch_bc<L, StoreF32, PK>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+        return adjoint_dispatch_bc<L, StoreF32, PK>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
     case StoreF16S::code:
-        return adjoint_dispatch_bc<L, StoreF16S, PK>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+        return adjoint_dispatch_bc<L, StoreF16S, PK>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
     case StoreBF16S::code:
-        return adjoint_dispatch_bc<L, StoreBF16S, PK>(bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+        return adjoint_dispatch_bc<L, StoreBF16S, PK>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -528,16 +526,18 @@ hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, 
 
 hipError_t launch_adjoint(int q, int storage, int bcmode, int pk, const Params& p, const void* lam_in,
                           void* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
-                          hipStream_t s)
+                          hipStream_t s, const double* moment_record)
 {
+    const double* rec = moment_record;
     if (q == 9 && pk == PK_SCALAR)
-        return adjoint_dispatch_store<D2Q9, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx, s);
+        return adjoint_dispatch_store<D2Q9, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar,
+                                                       bx, s);
     if (q == 19 && pk == PK_SCALAR)
-        return adjoint_dispatch_store<D3Q19, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx,
-                                                        s);
+        return adjoint_dispatch_store<D3Q19, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar,
+                                                        bx, s);
     if (q == 19 && pk == PK_TENSOR)
-        return adjoint_dispatch_store<D3Q19, PK_TENSOR>(storage, bcmode, p, lam_in, lam_out, xprev, dfield, dbar, bx,
-                                                        s);
+        return adjoint_dispatch_store<D3Q19, PK_TENSOR>(storage, bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar,
+                                                        bx, s);
     return hipErrorInvalidValue;
 }
 

@@ -93,6 +93,11 @@ struct hlbm_ctx {
     char* tape_cps;
     char* tape_seg;      // two sets of every-1 replay states (segments alternate between them)
     char* tape_lam[2];
+    // HLBM_TAPE_MOMENTS: every recorded step also writes the FP64 pre-collision
+    // moments of each cell (4 rows of N doubles per step), and the reverse
+    // sweep reads them instead of replaying segments (no replay states)
+    int tape_kind;
+    double* tape_rec;
     // The reverse sweep replays the segment below the current one on a second
     // stream while the adjoint steps of the current one run on `stream`;
     // replayed[k] marks set k's replay done, consumed[k] the adjoint steps that
@@ -357,12 +362,20 @@ void tape_free(hlbm_ctx* c)
     c->tape_stream = nullptr;
     for (int k = 0; k < 2; ++k)
         if (c->tape_lam[k]) (void)hipFree(c->tape_lam[k]);
+    if (c->tape_rec) (void)hipFree(c->tape_rec);
+    c->tape_rec = nullptr;
     c->tape_cps = nullptr;
     c->tape_seg = nullptr;
     c->tape_lam[0] = c->tape_lam[1] = nullptr;
     c->tape_every = 0;
     c->tape_max = 0;
     c->tape_ncp = 0;
+}
+
+// Bytes of a moment record of `steps` steps: 4 rows of N doubles per step.
+size_t tape_record_bytes(const hlbm_ctx* c, int steps)
+{
+    return (size_t)steps * 4 * (size_t)c->p.N * sizeof(double);
 }
 
 // Start recording at the current state: checkpoint 0 is the current state.
@@ -683,6 +696,7 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
                     c->step - c->tape_origin, nsteps);
     for (int t = 0; t < nsteps; ++t) {
         hipError_t e;
+        double* mrec = nullptr;  // this step's moment record (HLBM_TAPE_MOMENTS)
         if (c->tape_every) {
             const long long rel = c->step - c->tape_origin;
             if (rel > 0 && rel % c->tape_every == 0) {
@@ -690,16 +704,28 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
                                    c->pop_bytes, hipMemcpyDeviceToDevice, c->stream);
                 if (e != hipSuccess) return hip_fail(e, "tape checkpoint");
             }
+            if (c->tape_rec) mrec = c->tape_rec + (size_t)rel * 4 * (size_t)c->p.N;
         }
         const bool diag = c->diag_every && c->step % c->diag_every == 0;
         const bool record = diag && c->diag_count < c->diag_cap;
         if (diag && !record) c->diag_dropped += 1;
-        if (c->aa)
+        if (c->aa) {
             e = hlbm::launch_sweep(c->q, c->cfg.storage, aa_mode(c), c->cfg.porosity_kind, c->p, c->pop[0], c->pop[0], c->dfield, c->bx, c->stream,
                                    record ? c->partials : nullptr);
-        else
+        } else if (mrec) {
+            // a recording step: the diagnostics' partials, if due, from the
+            // moments kernel (the same arithmetic as the diagnostic sweep)
+            e = hipSuccess;
+            if (record)
+                e = hlbm::launch_moments(c->q, c->cfg.storage, c->bcmode, c->p, c->pop[c->cur], nullptr, nullptr, 1,
+                                         c->partials, c->bx, c->stream);
+            if (e == hipSuccess)
+                e = hlbm::launch_sweep(c->q, c->cfg.storage, c->bcmode, c->cfg.porosity_kind, c->p, c->pop[c->cur],
+                                       c->pop[c->cur ^ 1], c->dfield, c->bx, c->stream, nullptr, mrec);
+        } else {
             e = hlbm::launch_sweep(c->q, c->cfg.storage, c->bcmode, c->cfg.porosity_kind, c->p, c->pop[c->cur],
                                    c->pop[c->cur ^ 1], c->dfield, c->bx, c->stream, record ? c->partials : nullptr);
+        }
         if (e == hipSuccess && record)
             e = hlbm::launch_reduce4(c->partials, hlbm::cell_launch(c->p, c->bx).nblocks, c->reduce_stage,
                                      c->diag_log + 4 * (size_t)c->diag_count, c->stream);
@@ -987,8 +1013,11 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
     const int ncp = max_steps / every + 1;
     // adjoint rows take the population row pitch P (in elements of the adjoint type)
     const size_t lam_bytes = (size_t)c->p.P * (size_t)c->q * lam_elem;
+    const bool rec = c->tape_kind == HLBM_TAPE_MOMENTS;
     e = hipMalloc(&c->tape_cps, (size_t)ncp * c->pop_bytes);
-    if (e == hipSuccess && every > 1) e = hipMalloc(&c->tape_seg, 2 * (size_t)(every - 1) * c->pop_bytes);
+    if (e == hipSuccess && every > 1 && !rec)
+        e = hipMalloc(&c->tape_seg, 2 * (size_t)(every - 1) * c->pop_bytes);
+    if (e == hipSuccess && rec) e = hipMalloc(&c->tape_rec, tape_record_bytes(c, max_steps));
     if (e == hipSuccess) e = hipMalloc(&c->tape_lam[0], lam_bytes);
     if (e == hipSuccess) e = hipMalloc(&c->tape_lam[1], lam_bytes);
     // default priority (a stream of another priority is never used here)
@@ -1008,6 +1037,19 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
     return tape_restart(c);
 }
 
+int hlbm_set_tape_kind(hlbm_ctx* c, int kind)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->batch) return fail(HLBM_EUNSUPPORTED, "a batch has no adjoint");
+    if (kind != HLBM_TAPE_REPLAY && kind != HLBM_TAPE_MOMENTS) return fail(HLBM_EINVAL, "unknown tape kind %d", kind);
+    if (kind == c->tape_kind) return HLBM_OK;
+    c->tape_kind = kind;
+    // a tape in use is rebuilt in the new kind and restarts at the current state
+    if (c->tape_every) return hlbm_set_tape(c, c->tape_every, c->tape_max);
+    return HLBM_OK;
+}
+
 int hlbm_tape_info(const hlbm_ctx* c, int* every, int* max_steps, long long* recorded, size_t* device_bytes)
 {
     int rc = check_ctx(c);
@@ -1017,9 +1059,12 @@ int hlbm_tape_info(const hlbm_ctx* c, int* every, int* max_steps, long long* rec
     if (recorded) *recorded = c->tape_every ? c->step - c->tape_origin : 0;
     if (device_bytes) {
         size_t b = 0;
-        if (c->tape_every)
-            b = (size_t)(c->tape_ncp + 2 * (c->tape_every - 1)) * c->pop_bytes +
-                2 * (size_t)c->p.P * (size_t)c->q * hlbm::adjoint_elem_bytes(c->cfg.storage);
+        if (c->tape_every) {
+            const size_t replay_states = c->tape_rec ? 0 : 2 * (size_t)(c->tape_every - 1);
+            b = ((size_t)c->tape_ncp + replay_states) * c->pop_bytes +
+                2 * (size_t)c->p.P * (size_t)c->q * hlbm::adjoint_elem_bytes(c->cfg.storage) +
+                (c->tape_rec ? tape_record_bytes(c, c->tape_max) : 0);
+        }
         *device_bytes = b;
     }
     return HLBM_OK;
@@ -1080,7 +1125,18 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
         return r;
     };
     int a = 0;
-    if (e == hipSuccess && nsteps > 0) {
+    if (e == hipSuccess && nsteps > 0 && c->tape_rec) {
+        // moment record: reverse step t reads the record of forward step t
+        // (relative index t - 1); no segment is replayed
+        e = hlbm::launch_adjoint_seed(q, storage, bc, c->p, c->pop[c->cur], gr, gu, c->tape_lam[a], c->bx,
+                                      c->stream);
+        for (long long t = R0; e == hipSuccess && t > tlo; --t) {
+            e = hlbm::launch_adjoint(q, storage, bc, pk, c->p, c->tape_lam[a], c->tape_lam[a ^ 1], nullptr,
+                                     c->dfield, gd, c->bx, c->stream,
+                                     c->tape_rec + (size_t)(t - 1) * 4 * (size_t)c->p.N);
+            a ^= 1;
+        }
+    } else if (e == hipSuccess && nsteps > 0) {
         e = hlbm::launch_adjoint_seed(q, storage, bc, c->p, c->pop[c->cur], gr, gu, c->tape_lam[a], c->bx,
                                       c->stream);
         // both replay sets free, and the replay stream ordered after all work

@@ -267,6 +267,43 @@ __device__ __forceinline__ void moments_of(const R (&g)[L::Q], R F0, R F1, R F2,
     uz = R((jz + 0.5 * (double)F2) * inv_rho);
 }
 
+// FP64 moments of the pre-collision populations gathered at one cell:
+// s = sum g*, j = sum c g*, summed in population order.  The adjoint
+// linearizes the collision at them; the forward sweep can record them.
+struct Moms {
+    double s, jx, jy, jz;
+};
+
+template <class L, class R>
+__device__ __forceinline__ Moms moments_f64(const R (&g)[L::Q])
+{
+    Moms m{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const double gi = (double)g[i];
+        m.s += gi;
+        if (L::cx[i]) m.jx += L::cx[i] > 0 ? gi : -gi;
+        if (L::cy[i]) m.jy += L::cy[i] > 0 ? gi : -gi;
+        if (L::cz[i]) m.jz += L::cz[i] > 0 ? gi : -gi;
+    }
+    return m;
+}
+
+// Moment record of one forward step: four rows of N doubles (s, jx, jy, jz;
+// cell index x + nx(y + ny z)); rows can pass 4 GiB together: 64-bit offsets.
+__device__ __forceinline__ void record_moments(double* __restrict__ rec, uint32_t N, uint32_t cell, const Moms& m)
+{
+    rec[cell] = m.s;
+    rec[(size_t)N + cell] = m.jx;
+    rec[2 * (size_t)N + cell] = m.jy;
+    rec[3 * (size_t)N + cell] = m.jz;
+}
+
+__device__ __forceinline__ Moms recorded_moments(const double* __restrict__ rec, uint32_t N, uint32_t cell)
+{
+    return Moms{rec[cell], rec[(size_t)N + cell], rec[2 * (size_t)N + cell], rec[3 * (size_t)N + cell]};
+}
+
 // ---------------------------------------------------------------------------
 // Pull gather, fully periodic box: g*_i(x) = g_i(x - c_i) with wrap.  The box
 // starts at cell `base` of the population rows (0 for a single lattice).  In

@@ -149,9 +149,12 @@ Launch cell_launch(const Params& p, int bx, int cells_per_thread = 1);
 // Kernel launchers (sweep.hip).  All return the launch status.
 // One sweep.  With diag_partials != NULL the diagnostic variant also writes
 // FP64 block partials of the totals (one 4-double record per block).
+// With moment_record != NULL (A/B, periodic or general faces, no diagnostics)
+// the sweep also writes each cell's FP64 pre-collision moments s, jx, jy, jz
+// as four rows of N doubles there (the reverse sweep's linearization point).
 hipError_t launch_sweep(int q, int storage, int bcmode, int pk, const Params& p, const void* src,
                         void* dst, const void* dfield, int bx, hipStream_t s,
-                        double* diag_partials = nullptr);
+                        double* diag_partials = nullptr, double* moment_record = nullptr);
 hipError_t launch_moments(int q, int storage, int bcmode, const Params& p, const void* src,
                           void* drho, void* u, int out_f64, double* partials, int bx,
                           hipStream_t s);
@@ -163,9 +166,11 @@ hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, 
                                const double* drho_bar, const double* u_bar, void* lam, int bx,
                                hipStream_t s);
 // dbar holds one row of N values per row of the control (1 scalar, 6 tensor).
+// With moment_record != NULL the forward moments come from that record of the
+// forward step (as written by launch_sweep) and xprev is not read.
 hipError_t launch_adjoint(int q, int storage, int bcmode, int pk, const Params& p, const void* lam_in,
                           void* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
-                          hipStream_t s);
+                          hipStream_t s, const double* moment_record = nullptr);
 // Fixed-order two-pass sum of `nblocks` partials of 4 doubles into out[4];
 // `stage` holds 4*REDUCE_STAGE doubles.
 constexpr uint32_t REDUCE_STAGE = 256;

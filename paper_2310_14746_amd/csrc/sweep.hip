@@ -23,11 +23,12 @@ namespace hlbm {
 // ---------------------------------------------------------------------------
 // src and dst are one buffer in the AA modes, so they carry no restrict here
 // (the A/B kernels' own arguments do).
-template <class L, class S, int BC, int PK>
+template <class L, class S, int BC, int PK, bool REC = false>
 __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S::T* dst,
                                            const typename S::D* __restrict__ dfield, const Params& p,
                                            uint32_t x, uint32_t y, uint32_t z, typename S::R& drho,
-                                           typename S::R& ux, typename S::R& uy, typename S::R& uz)
+                                           typename S::R& ux, typename S::R& uy, typename S::R& uz,
+                                           double* __restrict__ rec = nullptr)
 {
     using R = typename S::R;
     const uint32_t P = p.P;  // population rows, and the rows of a tensor control, are P elements apart
@@ -59,6 +60,9 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
         gather_general<L, S>(src, P, b, of, (int)x, (int)y, (int)z, inv_scale, g);
         solid = in_wall_layer(b, (int)x, (int)y, (int)z);
     }
+    // REC: the FP64 moments of the pulled populations, which the reverse
+    // sweep linearizes the collision at, into this step's moment record
+    if (REC) record_moments(rec, p.N, cell, moments_f64<L, R>(g));
     if (PK == PK_SCALAR) {
         const ScalarShift<R> sh{S::load_d(ld(dfield, cell))};
         collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
@@ -124,6 +128,21 @@ __global__ __launch_bounds__(1024) void sweep_kernel(const typename S::T* __rest
     if (x >= (uint32_t)p.nx) return;
     R drho, ux, uy, uz;
     (void)sweep_cell<L, S, BC, PK>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
+}
+
+// The same sweep on a step that an adjoint tape records: it also writes each
+// cell's FP64 pre-collision moments (four rows of N doubles) to `rec`.
+template <class L, class S, int BC, int PK>
+__global__ __launch_bounds__(1024) void sweep_record_kernel(const typename S::T* __restrict__ src,
+                                                             typename S::T* __restrict__ dst,
+                                                             const typename S::D* __restrict__ dfield,
+                                                             double* __restrict__ rec, Params p)
+{
+    using R = typename S::R;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (uint32_t)p.nx) return;
+    R drho, ux, uy, uz;
+    (void)sweep_cell<L, S, BC, PK, true>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz, rec);
 }
 
 // In-place (AA) step: one buffer, even or odd mode.  Blocks of at most 256
@@ -515,12 +534,23 @@ Launch cell_launch(const Params& p, int bx, int cells_per_thread)
 
 template <class L, class S, int PK>
 static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src, void* dst,
-                                    const void* dfield, int bx, hipStream_t s, double* diag)
+                                    const void* dfield, int bx, hipStream_t s, double* diag, double* rec)
 {
     const Launch l = cell_launch(p, bx);
     auto* a = static_cast<const typename S::T*>(src);
     auto* b = static_cast<typename S::T*>(dst);
     auto* d = static_cast<const typename S::D*>(dfield);
+    if (rec) {
+        // recording steps of an adjoint tape: A/B, periodic or walls / open faces
+        if (diag) return hipErrorInvalidValue;
+        if (bcmode == BC_PERIODIC)
+            hipLaunchKernelGGL((sweep_record_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, a, b, d, rec, p);
+        else if (bcmode == BC_GENERAL)
+            hipLaunchKernelGGL((sweep_record_kernel<L, S, BC_GENERAL, PK>), l.grid, l.block, 0, s, a, b, d, rec, p);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (bcmode == BC_AA_EVEN || bcmode == BC_AA_ODD || bcmode == BC_AA_EVEN_W || bcmode == BC_AA_ODD_W) {
         // one buffer: src and dst are the same address
         if (src != dst || bx > 256) return hipErrorInvalidValue;
@@ -576,26 +606,31 @@ static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src
 template <class L, int PK>
 static hipError_t sweep_dispatch_store(int storage, int bcmode, const Params& p, const void* src,
                                        void* dst, const void* dfield, int bx, hipStream_t s,
-                                       double* diag)
+                                       double* diag, double* rec)
 {
     switch (storage) {
-    case StoreF64::code: return sweep_dispatch_bc<L, StoreF64, PK>(bcmode, p, src, dst, dfield, bx, s, diag);
-    case StoreF32::code: return sweep_dispatch_bc<L, StoreF32, PK>(bcmode, p, src, dst, dfield, bx, s, diag);
-    case StoreF16S::code: return sweep_dispatch_bc<L, StoreF16S, PK>(bcmode, p, src, dst, dfield, bx, s, diag);
-    case StoreBF16S::code: return sweep_dispatch_bc<L, StoreBF16S, PK>(bcmode, p, src, dst, dfield, bx, s, diag);
+    case StoreF64::code: return sweep_dispatch_bc<L, StoreF64, PK>(bcmode, p, src, dst, dfield, bx, s, diag, rec);
+    case StoreF32::code: return sweep_dispatch_bc<L, StoreF32, PK>(bcmode, p, src, dst, dfield, bx, s, diag, rec);
+    case StoreF16S::code: return sweep_dispatch_bc<L, StoreF16S, PK>(bcmode, p, src, dst, dfield, bx, s, diag, rec);
+    case StoreBF16S::code:
+        return sweep_dispatch_bc<L, StoreBF16S, PK>(bcmode, p, src, dst, dfield, bx, s, diag, rec);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_sweep(int q, int storage, int bcmode, int pk, const Params& p, const void* src,
-                        void* dst, const void* dfield, int bx, hipStream_t s, double* diag_partials)
+                        void* dst, const void* dfield, int bx, hipStream_t s, double* diag_partials,
+                        double* moment_record)
 {
     if (q == 9 && pk == PK_SCALAR)
-        return sweep_dispatch_store<D2Q9, PK_SCALAR>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials);
+        return sweep_dispatch_store<D2Q9, PK_SCALAR>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials,
+                                                     moment_record);
     if (q == 19 && pk == PK_SCALAR)
-        return sweep_dispatch_store<D3Q19, PK_SCALAR>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials);
+        return sweep_dispatch_store<D3Q19, PK_SCALAR>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials,
+                                                      moment_record);
     if (q == 19 && pk == PK_TENSOR)
-        return sweep_dispatch_store<D3Q19, PK_TENSOR>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials);
+        return sweep_dispatch_store<D3Q19, PK_TENSOR>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials,
+                                                      moment_record);
     return hipErrorInvalidValue;
 }
 

@@ -29,6 +29,7 @@ AB, AA = 0, 1
 PATTERNS = {"ab": AB, "aa": AA}
 PERIODIC, WALL, INLET_U, OUTLET_RHO = 0, 1, 2, 3
 POROSITY_SCALAR, POROSITY_TENSOR = 0, 1
+TAPE_REPLAY, TAPE_MOMENTS = 0, 1
 POROSITY_KINDS = {"scalar": POROSITY_SCALAR, "tensor": POROSITY_TENSOR}
 DT_F64, DT_F32, DT_F16 = 0, 1, 2
 
@@ -69,10 +70,17 @@ _lib = None
 
 
 def declared_functions() -> list:
-    """Names of the functions declared in include/hlbm.h."""
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(hlbm_\w+)\s*\(", text, flags=re.M)
+    """Names of the functions declared in the headers under include/ (hlbm.h
+    and the bandwidth reference beside it)."""
+    names = []
+    inc = os.path.dirname(HEADER)
+    for h in sorted(os.listdir(inc)):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(hlbm_\w+)\s*\(", text, flags=re.M)
+    return names
 
 
 def load() -> ctypes.CDLL:
@@ -123,9 +131,11 @@ def load() -> ctypes.CDLL:
         "hlbm_set_diagnostics": ([vp, i, i], i),
         "hlbm_read_diagnostics": ([vp, P(ctypes.c_double), i, P(ctypes.c_int), P(ctypes.c_longlong)], i),
         "hlbm_set_tape": ([vp, i, i], i),
+        "hlbm_set_tape_kind": ([vp, i], i),
         "hlbm_tape_info": ([vp, P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_longlong),
                             P(ctypes.c_size_t)], i),
         "hlbm_adjoint_step": ([vp, i, vp, vp, vp, i], i),
+        "hlbm_ref_stream_pattern": ([vp, vp, vp, i, i, i, i, i, vp], i),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -396,6 +406,13 @@ class HLBM:
         """Record checkpoints every `every` steps for up to `max_steps` steps from now."""
         self.generation += 1
         _check(load().hlbm_set_tape(self.ctx, int(every), int(max_steps)))
+
+    def set_tape_kind(self, kind: str):
+        """"replay" (checkpoints, segments replayed in the reverse sweep) or
+        "moments" (every recorded step also keeps each cell's FP64 moments, so
+        the reverse sweep replays nothing)."""
+        self.generation += 1
+        _check(load().hlbm_set_tape_kind(self.ctx, {"replay": TAPE_REPLAY, "moments": TAPE_MOMENTS}[kind]))
 
     def tape_info(self) -> dict:
         e, m, r, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_longlong(), ctypes.c_size_t()

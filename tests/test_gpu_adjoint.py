@@ -369,3 +369,66 @@ def test_autograd_rejects_a_graph_whose_lattice_was_reused(H):
         assert np.array_equal(d2b.grad.detach().cpu().numpy(), g2)
     finally:
         fresh.close()
+
+
+@pytest.mark.parametrize("case", CASES[:6], ids=[_ids(c) for c in CASES[:6]])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_moment_record_tape_equals_replay(H, case, storage):
+    """HLBM_TAPE_MOMENTS: the forward records each cell's FP64 pre-collision
+    moments and the reverse sweep reads them instead of replaying segments.
+    They are the moments the replay's gather would form, so the gradient is
+    the same bit for bit; partial reverse sweeps (fewer steps than recorded)
+    and the in-sweep diagnostics while recording are unchanged too."""
+    q, shape, tau, F, lo, hi, inu, steps, every = case
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    d = smooth_noise((nz, ny, nx), seed=steps).ravel()
+    if storage == "f32":
+        d = d.astype(np.float32)
+    a, b = _cotangents(n, q, seed=3)
+    out = {}
+    for kind in ("replay", "moments"):
+        sim = H.HLBM(q, storage, shape, tau=tau, force=F, bc_lo=lo, bc_hi=hi, inlet_u=inu)
+        try:
+            sim.set_porosity(d)
+            sim.set_tape_kind(kind)
+            sim.set_tape(every, steps)
+            sim.set_diagnostics(3, capacity=64)
+            sim.step(steps)
+            info = sim.tape_info()
+            g_all = sim.adjoint(steps, a, b).cpu().numpy()
+            g_part = sim.adjoint(max(1, steps // 2), a, b).cpu().numpy()
+            diag = sim.read_diagnostics()
+            out[kind] = (g_all, g_part, diag[1], info)
+        finally:
+            sim.close()
+    say(f"{_ids(case)} {storage}: tape bytes replay {out['replay'][3]['device_bytes']}, "
+        f"moments {out['moments'][3]['device_bytes']}")
+    assert np.array_equal(out["replay"][0], out["moments"][0])
+    assert np.array_equal(out["replay"][1], out["moments"][1])
+    assert np.array_equal(out["replay"][2], out["moments"][2])
+    assert np.any(out["moments"][0])
+
+
+def test_moment_record_tape_equals_replay_tensor(H):
+    """The same for the tensor control (six gradient rows), FP32, channel with
+    walls and open faces."""
+    shape, steps, every = (24, 10, 9), 20, 6
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    kw = dict(tau=0.65, bc_lo=(2, 1, 1), bc_hi=(3, 1, 1), inlet_u=(0.02, 0, 0))
+    D6 = inputs.random_tensor_field((nz, ny, nx), seed=8).reshape(6, -1).astype(np.float32)
+    a, b = _cotangents(n, 19, seed=9)
+    grads = {}
+    for kind in ("replay", "moments"):
+        sim = H.HLBM(19, "f32", shape, porosity="tensor", **kw)
+        try:
+            sim.set_porosity(D6)
+            sim.set_tape_kind(kind)
+            sim.set_tape(every, steps)
+            sim.step(steps)
+            grads[kind] = sim.adjoint(steps, a, b).cpu().numpy()
+        finally:
+            sim.close()
+    assert grads["moments"].shape == (6, nz, ny, nx)
+    assert np.array_equal(grads["replay"], grads["moments"])
