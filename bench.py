@@ -167,6 +167,45 @@ def copy_reference(gib=4.0, reps=10):
     return out
 
 
+def pattern_reference(hlbm, block_x, row_pad, edge=N_EDGE, steps=50):
+    """The sweep's own loads and stores with the collision left out
+    (hlbm_ref_stream_pattern: pull streaming of the 19 FP32 rows with the
+    sweep's gather, row pitch, block width and stores, plus the porosity read)
+    at the headline's shape, block width and row pad; counted with the sweep's
+    algorithmic 156 bytes per cell."""
+    import ctypes
+    import torch
+    lib = hlbm.load()
+    n = edge ** 3
+    P = n + row_pad // 4
+    a = torch.zeros(19 * P, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    d = torch.zeros(n, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def run(src, dst):
+        rc = lib.hlbm_ref_stream_pattern(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                         ctypes.c_void_p(d.data_ptr()), edge, edge, edge, row_pad, block_x,
+                                         ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"hlbm_ref_stream_pattern failed ({rc})")
+    for k in range(4):
+        run(a, b) if k % 2 == 0 else run(b, a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(steps):
+        run(a, b) if k % 2 == 0 else run(b, a)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del a, b, d
+    torch.cuda.empty_cache()
+    return {"ms": round(ms, 4), "GBs": round(156 * n / (ms * 1e-3) / 1e9, 1), "block_x": block_x,
+            "row_pad_bytes": row_pad}
+
+
 def summarize_profile(path):
     """Per-kernel duration summary of a rocprofv3 --kernel-trace output
     (SQLite results database or kernel_stats CSV) under `path`."""
@@ -318,6 +357,75 @@ def _timed_batch(hlbm, items, fields, steps, modes, sched, masks=None, rounds=2)
         b.close()
 
 
+# Algorithmic bytes per dispatch of the kernels the counter summary covers,
+# by kernel name (up to its argument list) and total threads of the grid.
+def _alg_bytes_per_dispatch(name, grid_threads, batched_steps):
+    c512, cbatch, c4 = N_EDGE ** 3, 98254848, 128 * 64 * 64
+    table = {
+        ("void hlbm::sweep_kernel<hlbm::D3Q19, hlbm::StoreF32, 0, 0>", c512): 156 * c512,
+        ("void hlbm::sweep_pair_kernel<hlbm::StoreF16S>", c512 // 2): 78 * c512,
+        ("void hlbm::sweep_aa_kernel<hlbm::D3Q19, hlbm::StoreF32, 3, 0>", c512): 156 * c512,
+        ("void hlbm::sweep_aa_kernel<hlbm::D3Q19, hlbm::StoreF32, 4, 0>", c512): 156 * c512,
+        ("hlbm::stream_pattern_kernel", c512): 156 * c512,
+        ("void hlbm::batch_step_kernel<hlbm::StoreF32, false>", None): 156 * cbatch,
+        ("void hlbm::batch_persistent_kernel<hlbm::StoreF32, false>", None): 156 * cbatch * batched_steps,
+        ("void hlbm::adjoint_split_kernel<hlbm::D3Q19, hlbm::StoreF32, 0, false>", None): ADJ_BYTES * c4,
+        ("void hlbm::adjoint_split_kernel<hlbm::D3Q19, hlbm::StoreF32, 0, true>", None):
+            (ADJ_BYTES - 19 * 4 + 32) * c4,
+        ("void hlbm::sweep_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): 156 * c4,
+        ("void hlbm::sweep_record_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): (156 + 32) * c4,
+    }
+    for (n, g), v in table.items():
+        if name == n and (g is None or g == grid_threads):
+            return v
+    return None
+
+
+def summarize_counters_all(fetch_dir, write_dir, batched_steps):
+    """HBM traffic per dispatch of every kernel in the table above, from two
+    rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each counter scaled by what
+    it reads for the same run's 4 GiB blit copy; against the algorithmic bytes."""
+    import csv
+    import glob
+
+    def per_kernel(path, counter):
+        rows = []
+        for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
+            rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
+        # the 4 GiB copy: the blit dispatches that read the most (smaller
+        # blits, such as tape checkpoints, run on the same grid)
+        big = max(float(r["Counter_Value"]) for r in rows if r["Kernel_Name"].startswith(COPY_KERNEL))
+        vals = {}
+        for r in rows:
+            name = r["Kernel_Name"].split("(")[0]
+            g = int(r["Grid_Size"])
+            if name.startswith(COPY_KERNEL):
+                if float(r["Counter_Value"]) >= 0.5 * big:
+                    vals.setdefault("copy", []).append(float(r["Counter_Value"]))
+                continue
+            vals.setdefault((name, g), []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
+
+    fetch, nf = per_kernel(fetch_dir, "FETCH_SIZE")
+    write, nw = per_kernel(write_dir, "WRITE_SIZE")
+    copy_bytes = 4.0 * 2 ** 30
+    f_scale = copy_bytes / (fetch["copy"] * 1024)
+    w_scale = copy_bytes / (write["copy"] * 1024)
+    out = [f"Calibration (the same runs' 4 GiB blit copy): FETCH_SIZE x{f_scale:.4f}, WRITE_SIZE x{w_scale:.4f}.",
+           "", "| kernel | grid threads | dispatches | HBM read | HBM write | "
+               "HBM total | algorithmic | total / algorithmic |", "|---|---|---|---|---|---|---|---|"]
+    for key in sorted(k for k in fetch if k != "copy"):
+        name, g = key
+        alg = _alg_bytes_per_dispatch(name, g, batched_steps)
+        if alg is None or key not in write:
+            continue
+        rd = fetch[key] * 1024 * f_scale
+        wr = write[key] * 1024 * w_scale
+        out.append(f"| `{name.replace('void hlbm::', '')}` | {g} | {nf[key]} | {rd / 1e9:.4f} GB | "
+                   f"{wr / 1e9:.4f} GB | {(rd + wr) / 1e9:.4f} GB | {alg / 1e9:.4f} GB | {(rd + wr) / alg:.4f} |")
+    return "\n".join(out)
+
+
 def time_batched(hlbm, steps=2000, seed=0):
     """256 homogenized periodic unit cells (edges 32..96), 2000 steps:
     * "graph": one HIP graph launch holding one per-step kernel node per step
@@ -408,11 +516,14 @@ ADJ_BYTES = 19 * 4 * 2 + 19 * 4 + 4 + 16  # adjoint kernel, FP32 form: lam in/ou
 ADJT_BYTES = 19 * 4 * 2 + 19 * 4 + 6 * 4 + 6 * 16  # tensor control: six rows of D and of dJ/dD
 
 
-def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4):
+def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4, kind="replay"):
     """Differentiation workload: D3Q19 128x64x64 channel, inlet u = 0.02,
     outlet rho = 1, walls in y and z, d ~ U[0,1), FP32 forward / FP64 adjoint,
     500 steps with a checkpoint every 50; gradient of the channel objective
-    through torch.autograd (forward with tape, objective, backward)."""
+    through torch.autograd (forward with tape, objective, backward).
+    kind "replay": the reverse sweep replays each segment from its checkpoint;
+    "moments": the forward also records each cell's moments per step, and the
+    reverse sweep replays nothing (same gradient bit for bit)."""
     import torch
     from paper_2310_14746_amd import inputs
     from paper_2310_14746_amd.autograd import channel_objective, moments_of_porosity
@@ -422,6 +533,7 @@ def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4):
     kw = dict(tau=0.6, bc_lo=(2, 1, 1), bc_hi=(3, 1, 1), inlet_u=(0.02, 0, 0), outlet_rho=1.0)
     sim = hlbm.HLBM(19, "f32", shape, **kw)
     try:
+        sim.set_tape_kind(kind)
         d = torch.tensor(inputs.uniform_noise((nz, ny, nx), seed), dtype=torch.float64,
                          device=sim.device, requires_grad=True)
         times = []
@@ -440,19 +552,27 @@ def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4):
                 times.append((t1 - t0, t2 - t1))
         fwd = float(np.median([a for a, _ in times]))
         bwd = float(np.median([b for _, b in times]))
-        replays = steps - (steps + every - 1) // every
-        moved = cells * (steps * ADJ_BYTES + replays * 156)
+        grad = d.grad.detach().cpu().numpy()
+        if kind == "replay":
+            replays = steps - (steps + every - 1) // every
+            adj = ADJ_BYTES
+        else:
+            replays = 0
+            adj = ADJ_BYTES - 19 * 4 + 32     # reads the 32-byte moment record instead of the gathered state
+        moved = cells * (steps * adj + replays * 156)
         tape = sim.tape_info()["device_bytes"]
     finally:
         sim.close()
-    log(f"gradient: forward {fwd * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms")
-    return {"workload": "D3Q19 128x64x64 channel, inlet u=0.02, outlet rho=1, walls y/z, d~U[0,1) seed 0, "
-                        "tau=0.6, 500 steps, checkpoint every 50, FP32 forward / FP64 adjoint, "
-                        "J = pressure drop + 0.1 dissipation",
-            "forward_ms": round(fwd * 1e3, 2), "backward_ms": round(bwd * 1e3, 2),
-            "backward_alg_GBs": round(moved / bwd / 1e9, 1),
-            "adjoint_bytes_per_cell_step": ADJ_BYTES, "replay_steps": replays,
-            "tape_MiB": round(tape / 2 ** 20, 1)}
+    log(f"gradient ({kind}): forward {fwd * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms")
+    out = {"workload": "D3Q19 128x64x64 channel, inlet u=0.02, outlet rho=1, walls y/z, d~U[0,1) seed 0, "
+                       "tau=0.6, 500 steps, checkpoint every 50, FP32 forward / FP64 adjoint, "
+                       "J = pressure drop + 0.1 dissipation",
+           "tape": kind,
+           "forward_ms": round(fwd * 1e3, 2), "backward_ms": round(bwd * 1e3, 2),
+           "backward_alg_GBs": round(moved / bwd / 1e9, 1),
+           "adjoint_bytes_per_cell_step": adj, "replay_steps": replays,
+           "tape_MiB": round(tape / 2 ** 20, 1)}
+    return out, grad
 
 
 def time_tensor(hlbm, steps, warmup, block_x):
@@ -625,6 +745,9 @@ def main():
                     help="threads per block along x (-1: tuned value, 0: library default)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the sweep's HBM traffic record from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-counters-all", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="per-kernel HBM traffic against algorithmic bytes from two rocprofv3 --pmc runs "
+                         "(the batched step count of those runs: --batched-steps)")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print a per-kernel summary of a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
@@ -633,6 +756,9 @@ def main():
         return
     if args.summarize_counters:
         print(summarize_counters(*args.summarize_counters))
+        return
+    if args.summarize_counters_all:
+        print(summarize_counters_all(*args.summarize_counters_all, args.batched_steps))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -659,10 +785,19 @@ def main():
                                         row_pad=rp)
         results[f] = dict(ms=ms, dr=dr, u=u, tot=tot, tiles_equal=teq, block_x=bx, row_pad=rp)
     copy_ref = None if args.no_copy_reference else copy_reference()
+    pattern = None
+    if not args.no_copy_reference and storage_of(forms[0]) == "f32":
+        pattern = pattern_reference(hlbm, results[forms[0]]["block_x"] or 256, results[forms[0]]["row_pad"])
+        log(f"pattern reference: {pattern['ms']:.4f} ms, {pattern['GBs']:.0f} GB/s")
     batched = None if args.no_batched else time_batched(hlbm, steps=args.batched_steps)
     if batched is not None and not args.no_permeability_tensor:
         batched["permeability_tensor"] = time_permeability_tensor(hlbm, steps=args.batched_steps)
-    gradient = None if args.no_gradient else time_gradient(hlbm, reps=args.gradient_reps)
+    gradient = None
+    if not args.no_gradient:
+        gradient, g_replay = time_gradient(hlbm, reps=args.gradient_reps)
+        rec, g_rec = time_gradient(hlbm, reps=args.gradient_reps, kind="moments")
+        rec["gradient_equals_replay_bitwise"] = bool(np.array_equal(g_rec, g_replay))
+        gradient["moment_record"] = rec
     if gradient is not None and not args.no_adjoint_large:
         gradient["large_periodic"] = time_adjoint_large(hlbm)
         gradient["large_periodic_tensor"] = time_adjoint_large(hlbm, porosity="tensor")
@@ -717,6 +852,8 @@ def main():
             "copy_reference_GBs": copy_ref["GBs"] if copy_ref else None,
             "copy_reference": copy_ref,
             "frac_of_copy": round(achieved / copy_ref["GBs"], 4) if copy_ref else None,
+            "pattern_reference": pattern,
+            "frac_of_pattern": round(achieved / pattern["GBs"], 4) if pattern else None,
         },
         "cpu_baseline": cpu,
         "forms": {},

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhlbm.so")
-SOURCES = ["sweep.hip", "batch.hip", "adjoint.hip", "api.hip"]
+SOURCES = ["sweep.hip", "batch.hip", "adjoint.hip", "api.hip", "reference.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
