@@ -281,13 +281,14 @@ def summarize_counters(fetch_dir, write_dir, n_cells=N_EDGE ** 3):
         for f in glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True):
             rows += [r for r in csv.DictReader(open(f)) if r["Counter_Name"] == counter]
         # the calibration copy is the runtime's blit of 4 GiB: the blit
-        # dispatches of the largest grid (smaller blits move other data)
-        copy_grid = max(int(r["Grid_Size"]) for r in rows if r["Kernel_Name"].startswith(COPY_KERNEL))
+        # dispatches that read the most (smaller blits, such as tape
+        # checkpoints, run on the same grid)
+        big = max(float(r["Counter_Value"]) for r in rows if r["Kernel_Name"].startswith(COPY_KERNEL))
         vals = {}
         for r in rows:
             name = r["Kernel_Name"]
-            key = ("sweep" if name.startswith("void " + SWEEP_F32) else
-                   "copy" if name.startswith(COPY_KERNEL) and int(r["Grid_Size"]) == copy_grid else None)
+            key = ("sweep" if name.startswith("void " + SWEEP_F32) and int(r["Grid_Size"]) == n_cells else
+                   "copy" if name.startswith(COPY_KERNEL) and float(r["Counter_Value"]) >= 0.5 * big else None)
             if key:
                 vals.setdefault(key, []).append(float(r["Counter_Value"]))
         return {k: sum(v) / len(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
