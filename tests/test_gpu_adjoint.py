@@ -432,3 +432,36 @@ def test_moment_record_tape_equals_replay_tensor(H):
             sim.close()
     assert grads["moments"].shape == (6, nz, ny, nx)
     assert np.array_equal(grads["replay"], grads["moments"])
+
+
+def test_tape_kind_rules(H):
+    """hlbm_set_tape_kind: unknown kinds are rejected; switching kinds with a
+    tape set rebuilds it and restarts recording at the current state; the
+    recorded-steps bound holds for both kinds."""
+    lib = H.load()
+    shape = (20, 8, 6)
+    sim = H.HLBM(19, "f32", shape, tau=0.7, force=(1e-5, 0, 0))
+    try:
+        sim.set_porosity(np.full(int(np.prod(shape)), 0.2, dtype=np.float32))
+        assert lib.hlbm_set_tape_kind(sim.ctx, 2) == H.EINVAL
+        assert lib.hlbm_set_tape_kind(sim.ctx, -1) == H.EINVAL
+        sim.set_tape(4, 10)
+        sim.step(3)
+        assert sim.tape_info()["recorded"] == 3
+        replay_bytes = sim.tape_info()["device_bytes"]
+        sim.set_tape_kind("moments")
+        info = sim.tape_info()
+        assert info["recorded"] == 0 and info["every"] == 4 and info["max_steps"] == 10
+        n = int(np.prod(shape))
+        # 3 checkpoints, no replay states, two FP32 adjoint buffers, 10 steps of 4 FP64 rows
+        assert info["device_bytes"] == 3 * sim.pop_bytes + 2 * 19 * n * 4 + 10 * 4 * n * 8
+        assert replay_bytes == (3 + 2 * 3) * sim.pop_bytes + 2 * 19 * n * 4
+        sim.step(10)
+        with pytest.raises(H.HLBMError):
+            sim.step(1)                         # past max_steps
+        with pytest.raises(H.HLBMError):
+            sim.adjoint(11, np.zeros(n), np.zeros(3 * n))
+        g = sim.adjoint(10, np.ones(n), np.zeros(3 * n)).cpu().numpy()
+        assert np.isfinite(g).all() and np.any(g)
+    finally:
+        sim.close()
