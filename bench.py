@@ -370,9 +370,7 @@ def _alg_bytes_per_dispatch(name, grid_threads, batched_steps):
         ("hlbm::stream_pattern_kernel", c512): 156 * c512,
         ("void hlbm::batch_step_kernel<hlbm::StoreF32, false>", None): 156 * cbatch,
         ("void hlbm::batch_persistent_kernel<hlbm::StoreF32, false>", None): 156 * cbatch * batched_steps,
-        ("void hlbm::adjoint_split_kernel<hlbm::D3Q19, hlbm::StoreF32, 0, false>", None): ADJ_BYTES * c4,
-        ("void hlbm::adjoint_split_kernel<hlbm::D3Q19, hlbm::StoreF32, 0, true>", None):
-            (ADJ_BYTES - 19 * 4 + 32) * c4,
+        ("void hlbm::adjoint_split_kernel<hlbm::D3Q19, hlbm::StoreF32, 0>", None): ADJ_BYTES_REC * c4,
         ("void hlbm::sweep_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): 156 * c4,
         ("void hlbm::sweep_record_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): (156 + 32) * c4,
     }
@@ -513,8 +511,9 @@ def time_permeability_tensor(hlbm, steps=2000, seed=0):
     }
 
 
-ADJ_BYTES = 19 * 4 * 2 + 19 * 4 + 4 + 16  # adjoint kernel, FP32 form: lam in/out, x, d, dJ/dd r+w
-ADJT_BYTES = 19 * 4 * 2 + 19 * 4 + 6 * 4 + 6 * 16  # tensor control: six rows of D and of dJ/dD
+ADJ_BYTES_REC = 19 * 4 * 2 + 32 + 4 + 16  # the reverse step as built: lam in/out, moment record, d, dJ/dd r+w
+REC_SWEEP_BYTES = 156 + 32                 # forward sweep that also writes the moment record
+ADJT_BYTES_REC = 19 * 4 * 2 + 32 + 6 * 4 + 6 * 16  # tensor control: six rows of D and of dJ/dD
 
 
 def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4, kind="replay"):
@@ -554,13 +553,12 @@ def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4, kind="replay"):
         fwd = float(np.median([a for a, _ in times]))
         bwd = float(np.median([b for _, b in times]))
         grad = d.grad.detach().cpu().numpy()
-        if kind == "replay":
-            replays = steps - (steps + every - 1) // every
-            adj = ADJ_BYTES
-        else:
-            replays = 0
-            adj = ADJ_BYTES - 19 * 4 + 32     # reads the 32-byte moment record instead of the gathered state
-        moved = cells * (steps * adj + replays * 156)
+        # a reverse step reads the 32-byte moment record of its forward step;
+        # the replayed tape recomputes every step from the checkpoints with the
+        # recording sweep (156 + 32 bytes per cell)
+        adj = ADJ_BYTES_REC
+        replays = steps if kind == "replay" else 0
+        moved = cells * (steps * adj + replays * REC_SWEEP_BYTES)
         tape = sim.tape_info()["device_bytes"]
     finally:
         sim.close()
@@ -642,8 +640,10 @@ def time_adjoint_large(hlbm, edge=256, steps=40, every=10, porosity="scalar", ro
         ms = e0.elapsed_time(e1)
     finally:
         sim.close()
-    replays = steps - (steps + every - 1) // every
-    adj, fwd = (ADJT_BYTES, TENSOR_BYTES) if tensor else (ADJ_BYTES, 156)
+    # every reverse step reads its forward step's 32-byte moment record, which
+    # the replay recomputes from the checkpoints with the recording sweep
+    replays = steps
+    adj, fwd = (ADJT_BYTES_REC, TENSOR_BYTES + 32) if tensor else (ADJ_BYTES_REC, REC_SWEEP_BYTES)
     moved = edge ** 3 * (steps * adj + replays * fwd)
     what = "periodic sphere array with the fibre tensor" if tensor else "periodic sphere array"
     return {"workload": f"D3Q19 {edge}^3 {what}, {steps} reverse steps, checkpoint every {every}",

@@ -307,13 +307,17 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * variable standing at (a, b) and (b, a), so its derivative counts both
  * places.  At D = d I the three diagonal rows sum to the scalar dJ/dd.
  *
- * The forward states are recovered from a tape: with a tape set, hlbm_step
- * stores the state every `every` steps (checkpoints); the reverse sweep
- * recomputes each segment of `every` steps from its checkpoint.  The replay
- * of the segment below runs on a second stream of the library's own (default
- * priority) while the reverse steps of the current segment run on the
- * context's stream; events order the two, and hlbm_adjoint_step waits for
- * both before it returns.  The tape
+ * A reverse step needs only the FP64 pre-collision moments (rho - rho0, j) of
+ * every cell at its forward step: the collision is linearized at them.  They
+ * come from a tape: with a tape set, hlbm_step stores the state every `every`
+ * steps (checkpoints); the reverse sweep recomputes each segment of `every`
+ * steps from its checkpoint with a sweep that also writes those moments (a
+ * moment record of the segment), and the reverse steps read the record.  The
+ * replay of the segment below runs on a second stream of the library's own
+ * (default priority) while the reverse steps of the current segment run on
+ * the context's stream; events order the two, and hlbm_adjoint_step waits
+ * for both before it returns.  (HLBM_TAPE_MOMENTS records the moments during
+ * the forward steps instead.)  The tape
  * records from the state current when it is set and restarts at the current
  * state whenever the state or the porosity changes otherwise (hlbm_set_state,
  * hlbm_reset, hlbm_set_porosity, hlbm_bind_buffers).
@@ -323,30 +327,28 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
 
 /* Allocate a tape for up to `max_steps` forward steps with a checkpoint every
  * `every` >= 1 steps, and start recording at the current state.  Device memory:
- * (max_steps/every + 1) checkpoints and 2 * (every - 1) replay states (two
- * segments, replayed alternately), each one population buffer, plus two
- * adjoint buffers of Q rows of P values (P = N + row_pad_bytes divided by the
- * storage's element size, the population row pitch; 8 bytes each for
- * HLBM_F64, else 4).  every = 0
+ * (max_steps/every + 1) checkpoints and 4 replay states (two segments,
+ * replayed alternately, whose sweeps alternate between two buffers), each one
+ * population buffer, two moment records of `every` steps (every * 32 * N
+ * bytes each), plus two adjoint buffers of Q rows of P values (P = N +
+ * row_pad_bytes divided by the storage's element size, the population row
+ * pitch; 8 bytes each for HLBM_F64, else 4).  every = 0
  * frees the tape.  hlbm_step returns EINVAL (and does nothing) if it would
  * take the recorded steps past max_steps.  Waits for the stream. */
 int hlbm_set_tape(hlbm_ctx *ctx, int every, int max_steps);
 
 /* What the tape keeps for the reverse sweep.
  *   HLBM_TAPE_REPLAY  (default) checkpoints every `every` steps; the reverse
- *                     sweep replays each segment from its checkpoint (two sets
- *                     of every - 1 replay states), as described above.
+ *                     sweep replays each segment from its checkpoint into a
+ *                     moment record of the segment, as described above.
  *   HLBM_TAPE_MOMENTS the same checkpoints, and every recorded forward step
- *                     also writes the FP64 pre-collision moments (rho - rho0,
- *                     j) of every cell -- all the reverse step needs of the
- *                     forward state, since the collision is linearized at
- *                     them -- to a record of 32 bytes per cell and step
- *                     (max_steps * 32 * N bytes of device memory, no replay
- *                     states).  The reverse sweep reads the record instead of
- *                     replaying segments; the gradients are the same bit for
- *                     bit.  This trades memory (at the 288 GB of one MI355X,
- *                     plenty for the sizes here) for the replay's forward
- *                     sweeps.
+ *                     also writes the moments of every cell to a record of
+ *                     32 bytes per cell and step (max_steps * 32 * N bytes of
+ *                     device memory, no replay states or segment records).
+ *                     The reverse sweep reads that record and replays
+ *                     nothing; the gradients are the same bit for bit.  This
+ *                     trades memory (at the 288 GB of one MI355X, plenty for
+ *                     the sizes here) for the replay's forward sweeps.
  * Takes effect at once: a tape already set is rebuilt in the new kind and
  * restarts at the current state.  EINVAL for another kind. */
 enum { HLBM_TAPE_REPLAY = 0, HLBM_TAPE_MOMENTS = 1 };

@@ -25,10 +25,12 @@
 //     and B = sum_i pb_i S_i, the adjoint needs only the weighted moments
 //     P0 = sum w pb, P1 = sum w c pb, P2 = sum w c c pb of the incoming adjoint
 //     pb, not the 19x19 Jacobian.
-//   * The post-collision moments of this cell at step t, needed by the
-//     open-face derivatives, follow from y_t by the collision's balance laws
-//     (mass kept, momentum (1 - omega) j + omega rho u_eq + (1 - 1/(2 tau)) F),
-//     so x_t itself is never read.
+//   * The collision is linearized at the FP64 moments (rho, j) of y_t, which
+//     the recording forward sweep wrote to a moment record (four rows of N
+//     doubles per step), so no forward population is read.  The
+//     post-collision moments of this cell at step t, needed by the open-face
+//     derivatives, follow from them by the collision's balance laws (mass
+//     kept, momentum (1 - omega) j + omega rho u_eq + (1 - 1/(2 tau)) F).
 //
 // Layout: adjoint populations are rows lam[k*P + cell], P elements apart like
 // the forward state's rows, FP64 for the FP64 form and FP32 for the others; all adjoint
@@ -337,22 +339,18 @@ __device__ __forceinline__ void collide_adjoint(const Moms& m, const Sh& sh, con
 
 // ---------------------------------------------------------------------------
 // One reverse step t: lam_out = lambda_t from lam_in = lambda_{t+1}, with the
-// forward state x_{t-1} in `xprev`; each control row of dbar += this step's
-// cotangent of that row.
+// forward step's moment record in `rec`; each control row of dbar += this
+// step's cotangent of that row.
 // ---------------------------------------------------------------------------
-// REC: the forward step's moments come from its moment record (`rec`, four
-// rows of N doubles written by the recording sweep) instead of a gather of
-// x_{t-1}; the values are the same bit for bit.
-template <class L, class S, int BC, int PK, bool REC>
+template <class L, class S, int BC, int PK>
 __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in, LamT<S>* __restrict__ lam_out,
-                                             const typename S::T* __restrict__ xprev,
                                              const double* __restrict__ rec,
                                              const typename S::D* __restrict__ dfield, double* __restrict__ dbar,
                                              const Params& p, uint32_t x, uint32_t y, uint32_t z)
 {
     const uint32_t N = p.N;
     const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
-    const Moms m = REC ? recorded_moments(rec, N, cell) : forward_moments<L, S, BC>(xprev, p, x, y, z);
+    const Moms m = recorded_moments(rec, N, cell);
     using Sh = AdjShift<PK>;
     const Sh sh = Sh::template load<S>(dfield, p.P, cell);  // control rows are P apart
     double pb[L::Q];
@@ -384,17 +382,16 @@ __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in,
     }
 }
 
-template <class L, class S, int BC, int PK, bool REC>
+template <class L, class S, int BC, int PK>
 __global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict__ lam_in,
                                                        LamT<S>* __restrict__ lam_out,
-                                                       const typename S::T* __restrict__ xprev,
                                                        const double* __restrict__ rec,
                                                        const typename S::D* __restrict__ dfield,
                                                        double* __restrict__ dbar, Params p)
 {
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)p.nx) return;
-    adjoint_cell<L, S, BC, PK, REC>(lam_in, lam_out, xprev, rec, dfield, dbar, p, x, blockIdx.y, blockIdx.z);
+    adjoint_cell<L, S, BC, PK>(lam_in, lam_out, rec, dfield, dbar, p, x, blockIdx.y, blockIdx.z);
 }
 
 // Interior and shell of a box with walls or open faces (see Split), in one
@@ -403,10 +400,9 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict_
 // rule.  The choice is uniform per block.  The shell's blocks come first:
 // they are the slow ones, and blocks start in index order, so the interior
 // blocks fill in behind them instead of leaving them as the tail.
-template <class L, class S, int PK, bool REC>
+template <class L, class S, int PK>
 __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __restrict__ lam_in,
                                                              LamT<S>* __restrict__ lam_out,
-                                                             const typename S::T* __restrict__ xprev,
                                                              const double* __restrict__ rec,
                                                              const typename S::D* __restrict__ dfield,
                                                              double* __restrict__ dbar, Params p, Split sp)
@@ -417,7 +413,7 @@ __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __res
         if (k >= sp.n_shell) return;
         uint32_t x, y, z;
         shell_cell(sp, (uint32_t)p.nx, (uint32_t)p.ny, k, x, y, z);
-        adjoint_cell<L, S, BC_GENERAL, PK, REC>(lam_in, lam_out, xprev, rec, dfield, dbar, p, x, y, z);
+        adjoint_cell<L, S, BC_GENERAL, PK>(lam_in, lam_out, rec, dfield, dbar, p, x, y, z);
     } else {
         const uint32_t bi = b - sp.blocks_shell;
         const uint32_t row = bi / sp.gx, bxi = bi - row * sp.gx;
@@ -425,8 +421,7 @@ __global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __res
         const uint32_t zz = row / iy, yy = row - zz * iy;
         const uint32_t x = sp.lo[0] + bxi * blockDim.x + threadIdx.x;
         if (x >= sp.hi[0]) return;
-        adjoint_cell<L, S, BC_PERIODIC, PK, REC>(lam_in, lam_out, xprev, rec, dfield, dbar, p, x, sp.lo[1] + yy,
-                                                 sp.lo[2] + zz);
+        adjoint_cell<L, S, BC_PERIODIC, PK>(lam_in, lam_out, rec, dfield, dbar, p, x, sp.lo[1] + yy, sp.lo[2] + zz);
     }
 }
 
@@ -448,39 +443,26 @@ static hipError_t seed_dispatch_bc(int bcmode, const Params& p, const void* src,
     return hipGetLastError();
 }
 
-template <class L, class S, int PK, bool REC>
-static hipError_t adjoint_dispatch_rec(int bcmode, const Params& p, const void* lam_in, void* lam_out,
-                                       const void* xprev, const double* rec, const void* dfield, double* dbar,
-                                       int bx, hipStream_t s)
+template <class L, class S, int PK>
+static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* lam_in, void* lam_out,
+                                      const double* rec, const void* dfield, double* dbar, int bx, hipStream_t s)
 {
     const Launch l = cell_launch(p, bx < 256 ? bx : 256);
-    auto* a = static_cast<const typename S::T*>(xprev);
     auto* d = static_cast<const typename S::D*>(dfield);
     auto* li = static_cast<const LamT<S>*>(lam_in);
     auto* lo = static_cast<LamT<S>*>(lam_out);
     if (bcmode == BC_PERIODIC) {
-        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC, PK, REC>), l.grid, l.block, 0, s, li, lo, a, rec, d, dbar,
-                           p);
+        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, li, lo, rec, d, dbar, p);
         return hipGetLastError();
     }
     const Split sp = split_of(p, (int)l.block.x);
     if (!sp.interior()) {
-        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL, PK, REC>), l.grid, l.block, 0, s, li, lo, a, rec, d, dbar,
-                           p);
+        hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL, PK>), l.grid, l.block, 0, s, li, lo, rec, d, dbar, p);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((adjoint_split_kernel<L, S, PK, REC>), dim3(sp.blocks_in + sp.blocks_shell), l.block, 0, s, li,
-                       lo, a, rec, d, dbar, p, sp);
+    hipLaunchKernelGGL((adjoint_split_kernel<L, S, PK>), dim3(sp.blocks_in + sp.blocks_shell), l.block, 0, s, li, lo,
+                       rec, d, dbar, p, sp);
     return hipGetLastError();
-}
-
-template <class L, class S, int PK>
-static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* lam_in, void* lam_out,
-                                      const void* xprev, const double* rec, const void* dfield, double* dbar,
-                                      int bx, hipStream_t s)
-{
-    if (rec) return adjoint_dispatch_rec<L, S, PK, true>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
-    return adjoint_dispatch_rec<L, S, PK, false>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
 }
 
 template <class L>
@@ -499,18 +481,16 @@ static hipError_t seed_dispatch_store(int storage, int bcmode, const Params& p, 
 
 template <class L, int PK>
 static hipError_t adjoint_dispatch_store(int storage, int bcmode, const Params& p, const void* lam_in,
-                                         void* lam_out, const void* xprev, const double* rec, const void* dfield,
-                                         double* dbar, int bx, hipStream_t s)
+                                         void* lam_out, const double* rec, const void* dfield, double* dbar, int bx,
+                                         hipStream_t s)
 {
     switch (storage) {
-    case StoreF64::code:
-        return adjoint_dispatch_bc<L, StoreF64, PK>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
-    case StoreF32::code:
-        return adjoint_dispatch_bc<L, StoreF32, PK>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
+    case StoreF64::code: return adjoint_dispatch_bc<L, StoreF64, PK>(bcmode, p, lam_in, lam_out, rec, dfield, dbar, bx, s);
+    case StoreF32::code: return adjoint_dispatch_bc<L, StoreF32, PK>(bcmode, p, lam_in, lam_out, rec, dfield, dbar, bx, s);
     case StoreF16S::code:
-        return adjoint_dispatch_bc<L, StoreF16S, PK>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
+        return adjoint_dispatch_bc<L, StoreF16S, PK>(bcmode, p, lam_in, lam_out, rec, dfield, dbar, bx, s);
     case StoreBF16S::code:
-        return adjoint_dispatch_bc<L, StoreBF16S, PK>(bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar, bx, s);
+        return adjoint_dispatch_bc<L, StoreBF16S, PK>(bcmode, p, lam_in, lam_out, rec, dfield, dbar, bx, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -525,19 +505,17 @@ hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, 
 }
 
 hipError_t launch_adjoint(int q, int storage, int bcmode, int pk, const Params& p, const void* lam_in,
-                          void* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
-                          hipStream_t s, const double* moment_record)
+                          void* lam_out, const void* dfield, double* dbar, int bx, hipStream_t s,
+                          const double* moment_record)
 {
     const double* rec = moment_record;
+    if (!rec) return hipErrorInvalidValue;
     if (q == 9 && pk == PK_SCALAR)
-        return adjoint_dispatch_store<D2Q9, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar,
-                                                       bx, s);
+        return adjoint_dispatch_store<D2Q9, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, rec, dfield, dbar, bx, s);
     if (q == 19 && pk == PK_SCALAR)
-        return adjoint_dispatch_store<D3Q19, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar,
-                                                        bx, s);
+        return adjoint_dispatch_store<D3Q19, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, rec, dfield, dbar, bx, s);
     if (q == 19 && pk == PK_TENSOR)
-        return adjoint_dispatch_store<D3Q19, PK_TENSOR>(storage, bcmode, p, lam_in, lam_out, xprev, rec, dfield, dbar,
-                                                        bx, s);
+        return adjoint_dispatch_store<D3Q19, PK_TENSOR>(storage, bcmode, p, lam_in, lam_out, rec, dfield, dbar, bx, s);
     return hipErrorInvalidValue;
 }
 

@@ -91,7 +91,9 @@ struct hlbm_ctx {
     long long tape_origin;
     int tape_ncp;
     char* tape_cps;
-    char* tape_seg;      // two sets of every-1 replay states (segments alternate between them)
+    char* tape_seg;      // replay states: two sets (segments alternate between them) of two
+                         // population buffers (the replay's sweeps alternate between them)
+    double* tape_segrec; // the replay's moment records: two sets of `every` steps of 4 rows of N
     char* tape_lam[2];
     // HLBM_TAPE_MOMENTS: every recorded step also writes the FP64 pre-collision
     // moments of each cell (4 rows of N doubles per step), and the reverse
@@ -353,6 +355,8 @@ void tape_free(hlbm_ctx* c)
     if (c->tape_stream) (void)hipStreamSynchronize(c->tape_stream);
     if (c->tape_cps) (void)hipFree(c->tape_cps);
     if (c->tape_seg) (void)hipFree(c->tape_seg);
+    if (c->tape_segrec) (void)hipFree(c->tape_segrec);
+    c->tape_segrec = nullptr;
     for (int k = 0; k < 2; ++k) {
         if (c->replayed[k]) (void)hipEventDestroy(c->replayed[k]);
         if (c->consumed[k]) (void)hipEventDestroy(c->consumed[k]);
@@ -1015,8 +1019,8 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
     const size_t lam_bytes = (size_t)c->p.P * (size_t)c->q * lam_elem;
     const bool rec = c->tape_kind == HLBM_TAPE_MOMENTS;
     e = hipMalloc(&c->tape_cps, (size_t)ncp * c->pop_bytes);
-    if (e == hipSuccess && every > 1 && !rec)
-        e = hipMalloc(&c->tape_seg, 2 * (size_t)(every - 1) * c->pop_bytes);
+    if (e == hipSuccess && !rec) e = hipMalloc(&c->tape_seg, 4 * c->pop_bytes);
+    if (e == hipSuccess && !rec) e = hipMalloc(&c->tape_segrec, 2 * tape_record_bytes(c, every));
     if (e == hipSuccess && rec) e = hipMalloc(&c->tape_rec, tape_record_bytes(c, max_steps));
     if (e == hipSuccess) e = hipMalloc(&c->tape_lam[0], lam_bytes);
     if (e == hipSuccess) e = hipMalloc(&c->tape_lam[1], lam_bytes);
@@ -1060,10 +1064,10 @@ int hlbm_tape_info(const hlbm_ctx* c, int* every, int* max_steps, long long* rec
     if (device_bytes) {
         size_t b = 0;
         if (c->tape_every) {
-            const size_t replay_states = c->tape_rec ? 0 : 2 * (size_t)(c->tape_every - 1);
-            b = ((size_t)c->tape_ncp + replay_states) * c->pop_bytes +
+            const bool rec = c->tape_kind == HLBM_TAPE_MOMENTS;
+            b = ((size_t)c->tape_ncp + (rec ? 0 : 4)) * c->pop_bytes +
                 2 * (size_t)c->p.P * (size_t)c->q * hlbm::adjoint_elem_bytes(c->cfg.storage) +
-                (c->tape_rec ? tape_record_bytes(c, c->tape_max) : 0);
+                (rec ? tape_record_bytes(c, c->tape_max) : 2 * tape_record_bytes(c, c->tape_every));
         }
         *device_bytes = b;
     }
@@ -1103,59 +1107,65 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
     }
     const int K = c->tape_every;
     const int q = c->q, storage = c->cfg.storage, bc = c->bcmode, pk = c->cfg.porosity_kind;
-    // State j of segment m (index m*K + j relative to the tape origin): the
-    // checkpoint for j = 0, else replay state j - 1 of set m & 1.
-    auto state = [&](long long m, long long j) -> char* {
-        if (j == 0) return c->tape_cps + (size_t)m * c->pop_bytes;
-        return c->tape_seg + ((size_t)(m & 1) * (size_t)(K - 1) + (size_t)(j - 1)) * c->pop_bytes;
-    };
-    // Reverse steps t = R0 .. tlo + 1 read the states r = t - 1 in [tlo, R0 - 1].
+    const size_t rec_step = 4 * (size_t)c->p.N;  // doubles of one step's moment record
+    // Reverse steps t = R0 .. tlo + 1 linearize at the moments of forward steps t.
     const long long tlo = R0 - nsteps;
-    // Replay segment m on the replay stream into set m & 1: states 1 .. jmax
-    // (the highest one a reverse step of this call reads), after the reverse
-    // steps that last read that set.
-    auto replay = [&](long long m) -> hipError_t {
-        const int k = (int)(m & 1);
-        hipError_t r = hipStreamWaitEvent(c->tape_stream, c->consumed[k], 0);
-        const long long jmax = (R0 - 1 - m * K < K - 1) ? R0 - 1 - m * K : K - 1;
-        for (long long j = 1; j <= jmax && r == hipSuccess; ++j)
-            r = hlbm::launch_sweep(q, storage, bc, pk, c->p, state(m, j - 1), state(m, j), c->dfield, c->bx,
-                                   c->tape_stream);
-        if (r == hipSuccess) r = hipEventRecord(c->replayed[k], c->tape_stream);
-        return r;
-    };
     int a = 0;
     if (e == hipSuccess && nsteps > 0 && c->tape_rec) {
-        // moment record: reverse step t reads the record of forward step t
-        // (relative index t - 1); no segment is replayed
+        // moment record of the whole run: reverse step t reads the record of
+        // forward step t (relative index t - 1); nothing is replayed
         e = hlbm::launch_adjoint_seed(q, storage, bc, c->p, c->pop[c->cur], gr, gu, c->tape_lam[a], c->bx,
                                       c->stream);
         for (long long t = R0; e == hipSuccess && t > tlo; --t) {
-            e = hlbm::launch_adjoint(q, storage, bc, pk, c->p, c->tape_lam[a], c->tape_lam[a ^ 1], nullptr,
-                                     c->dfield, gd, c->bx, c->stream,
-                                     c->tape_rec + (size_t)(t - 1) * 4 * (size_t)c->p.N);
+            e = hlbm::launch_adjoint(q, storage, bc, pk, c->p, c->tape_lam[a], c->tape_lam[a ^ 1], c->dfield, gd,
+                                     c->bx, c->stream, c->tape_rec + (size_t)(t - 1) * rec_step);
             a ^= 1;
         }
     } else if (e == hipSuccess && nsteps > 0) {
+        // Segment m (forward steps mK + 1 .. mK + K) is replayed from its
+        // checkpoint on the replay stream into set m & 1: its sweeps alternate
+        // between the set's two state buffers and write the moments of each
+        // step (record j = step mK + j + 1), up to the highest step a reverse
+        // step of this call needs; after the reverse steps that last read
+        // that set.
+        auto seg_state = [&](int k, long long j) -> char* {
+            return c->tape_seg + (size_t)(2 * k + (int)(j & 1)) * c->pop_bytes;
+        };
+        auto seg_rec = [&](int k, long long j) -> double* {
+            return c->tape_segrec + ((size_t)k * (size_t)K + (size_t)j) * rec_step;
+        };
+        auto thi_of = [&](long long m) { return (R0 < m * K + K) ? R0 : m * K + K; };
+        auto replay = [&](long long m) -> hipError_t {
+            const int k = (int)(m & 1);
+            hipError_t r = hipStreamWaitEvent(c->tape_stream, c->consumed[k], 0);
+            const long long jn = thi_of(m) - m * K;
+            for (long long j = 0; j < jn && r == hipSuccess; ++j) {
+                const char* src = j == 0 ? c->tape_cps + (size_t)m * c->pop_bytes : seg_state(k, j - 1);
+                r = hlbm::launch_sweep(q, storage, bc, pk, c->p, src, seg_state(k, j), c->dfield, c->bx,
+                                       c->tape_stream, nullptr, seg_rec(k, j));
+            }
+            if (r == hipSuccess) r = hipEventRecord(c->replayed[k], c->tape_stream);
+            return r;
+        };
         e = hlbm::launch_adjoint_seed(q, storage, bc, c->p, c->pop[c->cur], gr, gu, c->tape_lam[a], c->bx,
                                       c->stream);
         // both replay sets free, and the replay stream ordered after all work
         // queued so far (the forward steps that wrote the checkpoints)
         for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventRecord(c->consumed[k], c->stream);
         const long long mhi = (R0 - 1) / K, mlo = tlo / K;
-        if (e == hipSuccess && K > 1) e = replay(mhi);
+        if (e == hipSuccess) e = replay(mhi);
         for (long long m = mhi; e == hipSuccess && m >= mlo; --m) {
             // the segment below replays while this one's reverse steps run
-            if (K > 1 && m - 1 >= mlo) e = replay(m - 1);
-            if (e == hipSuccess && K > 1) e = hipStreamWaitEvent(c->stream, c->replayed[m & 1], 0);
-            const long long thi = (R0 < m * K + K) ? R0 : m * K + K;
+            if (m - 1 >= mlo) e = replay(m - 1);
+            if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->replayed[m & 1], 0);
+            const long long thi = thi_of(m);
             const long long tmin = (tlo + 1 > m * K + 1) ? tlo + 1 : m * K + 1;
             for (long long t = thi; e == hipSuccess && t >= tmin; --t) {
-                e = hlbm::launch_adjoint(q, storage, bc, pk, c->p, c->tape_lam[a], c->tape_lam[a ^ 1],
-                                         state(m, t - 1 - m * K), c->dfield, gd, c->bx, c->stream);
+                e = hlbm::launch_adjoint(q, storage, bc, pk, c->p, c->tape_lam[a], c->tape_lam[a ^ 1], c->dfield,
+                                         gd, c->bx, c->stream, seg_rec((int)(m & 1), t - 1 - m * K));
                 a ^= 1;
             }
-            if (e == hipSuccess && K > 1) e = hipEventRecord(c->consumed[m & 1], c->stream);
+            if (e == hipSuccess) e = hipEventRecord(c->consumed[m & 1], c->stream);
         }
     }
     if (e == hipSuccess && tmp)

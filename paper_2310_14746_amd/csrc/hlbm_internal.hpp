@@ -166,11 +166,11 @@ hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, 
                                const double* drho_bar, const double* u_bar, void* lam, int bx,
                                hipStream_t s);
 // dbar holds one row of N values per row of the control (1 scalar, 6 tensor).
-// With moment_record != NULL the forward moments come from that record of the
-// forward step (as written by launch_sweep) and xprev is not read.
+// The forward step's moments come from its moment record, as the recording
+// sweep of launch_sweep wrote it.
 hipError_t launch_adjoint(int q, int storage, int bcmode, int pk, const Params& p, const void* lam_in,
-                          void* lam_out, const void* xprev, const void* dfield, double* dbar, int bx,
-                          hipStream_t s, const double* moment_record = nullptr);
+                          void* lam_out, const void* dfield, double* dbar, int bx, hipStream_t s,
+                          const double* moment_record);
 // Fixed-order two-pass sum of `nblocks` partials of 4 doubles into out[4];
 // `stage` holds 4*REDUCE_STAGE doubles.
 constexpr uint32_t REDUCE_STAGE = 256;

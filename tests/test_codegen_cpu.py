@@ -63,9 +63,9 @@ def test_in_place_kernels_are_straight_line(asm):
 
 def test_adjoint_kernels_are_straight_line(asm):
     kern = {**_kernels(asm, "_ZN4hlbm14adjoint_kernel"), **_kernels(asm, "_ZN4hlbm19adjoint_seed_kernel")}
-    # reverse step: (2 lattices x 4 storages scalar + 4 storages tensor) x 2 boundary modes
-    # x (state gathered, moments read from a record); seed: 2 lattices x 4 storages x 2 boundary modes
-    assert len(kern) == 48 + 16
+    # reverse step: (2 lattices x 4 storages scalar + 4 storages tensor) x 2 boundary modes;
+    # seed: 2 lattices x 4 storages x 2 boundary modes
+    assert len(kern) == 24 + 16
     for name, body in kern.items():
         branches = len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
         assert branches <= 1, (name, branches)

@@ -455,7 +455,7 @@ def test_tape_kind_rules(H):
         n = int(np.prod(shape))
         # 3 checkpoints, no replay states, two FP32 adjoint buffers, 10 steps of 4 FP64 rows
         assert info["device_bytes"] == 3 * sim.pop_bytes + 2 * 19 * n * 4 + 10 * 4 * n * 8
-        assert replay_bytes == (3 + 2 * 3) * sim.pop_bytes + 2 * 19 * n * 4
+        assert replay_bytes == (3 + 4) * sim.pop_bytes + 2 * 19 * n * 4 + 2 * 4 * 4 * n * 8
         sim.step(10)
         with pytest.raises(H.HLBMError):
             sim.step(1)                         # past max_steps
