@@ -370,7 +370,7 @@ def _alg_bytes_per_dispatch(name, grid_threads, batched_steps):
         ("hlbm::stream_pattern_kernel", c512): 156 * c512,
         ("void hlbm::batch_step_kernel<hlbm::StoreF32, false>", None): 156 * cbatch,
         ("void hlbm::batch_persistent_kernel<hlbm::StoreF32, false>", None): 156 * cbatch * batched_steps,
-        ("void hlbm::adjoint_split_kernel<hlbm::D3Q19, hlbm::StoreF32, 0>", None): ADJ_BYTES_REC * c4,
+        ("void hlbm::adjoint_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): ADJ_BYTES_REC * c4,
         ("void hlbm::sweep_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): 156 * c4,
         ("void hlbm::sweep_record_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): (156 + 32) * c4,
     }
@@ -518,7 +518,7 @@ ADJT_BYTES_REC = 19 * 4 * 2 + 32 + 6 * 4 + 6 * 16  # tensor control: six rows of
 
 def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4, kind="replay"):
     """Differentiation workload: D3Q19 128x64x64 channel, inlet u = 0.02,
-    outlet rho = 1, walls in y and z, d ~ U[0,1), FP32 forward / FP64 adjoint,
+    outlet rho = 1, walls in y and z, d ~ U[0,1), FP32 forward and reverse steps / FP64 gradient accumulation,
     500 steps with a checkpoint every 50; gradient of the channel objective
     through torch.autograd (forward with tape, objective, backward).
     kind "replay": the reverse sweep replays each segment from its checkpoint;
@@ -564,7 +564,7 @@ def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4, kind="replay"):
         sim.close()
     log(f"gradient ({kind}): forward {fwd * 1e3:.1f} ms, backward {bwd * 1e3:.1f} ms")
     out = {"workload": "D3Q19 128x64x64 channel, inlet u=0.02, outlet rho=1, walls y/z, d~U[0,1) seed 0, "
-                       "tau=0.6, 500 steps, checkpoint every 50, FP32 forward / FP64 adjoint, "
+                       "tau=0.6, 500 steps, checkpoint every 50, FP32 forward and reverse steps / FP64 gradient accumulation, "
                        "J = pressure drop + 0.1 dissipation",
            "tape": kind,
            "forward_ms": round(fwd * 1e3, 2), "backward_ms": round(bwd * 1e3, 2),

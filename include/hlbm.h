@@ -296,8 +296,9 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * J observes the moments (drho, u) of the current time level (definitions as
  * for hlbm_moments).  Given dJ/d(drho) and dJ/du at the current time level,
  * hlbm_adjoint_step applies the transposed Jacobians of the last `nsteps`
- * steps in reverse order, carrying adjoint populations (stored in FP64 for
- * HLBM_F64, in FP32 for the other forms; all arithmetic in FP64), and adds
+ * steps in reverse order, carrying adjoint populations (FP64 storage and
+ * arithmetic for HLBM_F64, FP32 for the other forms; each step's contribution
+ * to dJ_dd is added in FP64), and adds
  *   sum over those steps of (dJ/dx_t) . dC(y_t, d)/dd
  * to dJ_dd: the derivative of J with respect to d through those steps (the
  * state before them held fixed).  Explicit dependences of J on d are the

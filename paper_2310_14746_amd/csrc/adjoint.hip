@@ -6,7 +6,7 @@
 // One forward step is y_t = S(x_{t-1}) (pull streaming) followed by
 // x_t = C(y_t, d) (the homogenized BGK collision of Sec. 3.2, cell-local), and
 // the objective observes the moments M(S(x_T)).  The reverse sweep carries the
-// adjoint of the pre-collision populations, lambda_t = dJ/dy_t, in FP64:
+// adjoint of the pre-collision populations, lambda_t = dJ/dy_t:
 //
 //   lambda_{T+1} = M^T (dJ/drho, dJ/du)                         (seed kernel)
 //   lambda_t     = C_y(y_t, d)^T S^T lambda_{t+1},
@@ -33,11 +33,12 @@
 //     kept, momentum (1 - omega) j + omega rho u_eq + (1 - 1/(2 tau)) F).
 //
 // Layout: adjoint populations are rows lam[k*P + cell], P elements apart like
-// the forward state's rows, FP64 for the FP64 form and FP32 for the others; all adjoint
-// arithmetic is FP64 and dJ/dd is one FP64 value per cell and control row,
-// accumulated.  Blocks
-// hold at most 256 threads (the FP64 adjoint needs more registers than a
-// 1024-thread block leaves per thread); the launchers clamp the block width.
+// the forward state's rows, FP64 for the FP64 form and FP32 for the others.
+// The reverse step computes in that precision (the seed in FP64); dJ/dd is one
+// FP64 value per cell and control row, and each step's contribution is added
+// to it in FP64.  Blocks hold at most 256 threads (the reverse step needs more
+// registers than a 1024-thread block leaves per thread); the launchers clamp
+// the block width.
 #include <type_traits>
 
 #include "cell.hpp"
@@ -107,10 +108,10 @@ __global__ __launch_bounds__(256) void adjoint_seed_kernel(const typename S::T* 
 // S^T: adjoint of the post-collision populations of this cell from the
 // adjoint of the next step's pre-collision populations.
 // ---------------------------------------------------------------------------
-template <class L, class LT>
-__device__ __forceinline__ void stream_adjoint_periodic(const LT* __restrict__ lam, uint32_t P,
+template <class L, class A>
+__device__ __forceinline__ void stream_adjoint_periodic(const A* __restrict__ lam, uint32_t P,
                                                         const Params& p, uint32_t x, uint32_t y,
-                                                        uint32_t z, double (&pb)[L::Q])
+                                                        uint32_t z, A (&pb)[L::Q])
 {
     const uint32_t nx = p.nx, ny = p.ny, nz = p.nz;
     // x + c for c = -1, 0, +1 (index c + 1), wrapped
@@ -120,26 +121,25 @@ __device__ __forceinline__ void stream_adjoint_periodic(const LT* __restrict__ l
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         const uint32_t off = xs[L::cx[k] + 1] + nx * (ys[L::cy[k] + 1] + ny * zs[L::cz[k] + 1]);
-        pb[k] = (double)ld(lam + (size_t)k * P, off);
+        pb[k] = ld(lam + (size_t)k * P, off);
     }
 }
 
 // Walls and open faces.  `rho_b`, (ubx, uby, ubz) are this cell's
 // post-collision density and velocity j_b/rho_b at the forward step whose
 // open-face equilibria are being differentiated.
-template <class L, class LT>
-__device__ __forceinline__ void stream_adjoint_general(const LT* __restrict__ lam, uint32_t P,
+template <class L, class A>
+__device__ __forceinline__ void stream_adjoint_general(const A* __restrict__ lam, uint32_t P,
                                                        const Params& p, int x, int y, int z,
-                                                       double rho_b, double ubx, double uby,
-                                                       double ubz, double (&pb)[L::Q])
+                                                       A rho_b, A ubx, A uby, A ubz, A (&pb)[L::Q])
 {
     const Box b = box_of(p);
     const uint32_t cell = (uint32_t)x + (uint32_t)b.nx * ((uint32_t)y + (uint32_t)b.ny * (uint32_t)z);
     const bool px = b.lo0 == 0, py = b.lo1 == 0, pz = b.lo2 == 0;
-    const double uix = p.inlet_u[0], uiy = p.inlet_u[1], uiz = p.inlet_u[2];
-    const double uin2 = uix * uix + uiy * uiy + uiz * uiz;
-    const double rout = p.outlet_rho;
-    double a_in = 0.0, bvx = 0.0, bvy = 0.0, bvz = 0.0;
+    const A uix = A(p.inlet_u[0]), uiy = A(p.inlet_u[1]), uiz = A(p.inlet_u[2]);
+    const A uin2 = uix * uix + uiy * uiy + uiz * uiz;
+    const A rout = A(p.outlet_rho);
+    A a_in = 0, bvx = 0, bvy = 0, bvz = 0;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k) {
         // neighbour x + c_k = x - c_opp(k): the forward source of direction opp(k) at x
@@ -155,9 +155,9 @@ __device__ __forceinline__ void stream_adjoint_general(const LT* __restrict__ la
         const uint32_t noff = (uint32_t)sx + (uint32_t)b.nx * ((uint32_t)sy + (uint32_t)b.ny * (uint32_t)sz);
         const uint32_t row = sel(own, (uint32_t)opposite(k), (uint32_t)k);
         const uint32_t off = sel(own, cell, noff);
-        const double v = (double)ld(lam + (size_t)row * P, off);
+        const A v = ld(lam + (size_t)row * P, off);
         const bool open = outside & !wall;
-        pb[k] = sel(open, 0.0, v);
+        pb[k] = sel(open, A(0), v);
         // open face: v is the adjoint of this cell's pre-collision population
         // i = opp(k), which the forward step took from an equilibrium
         const int kx = sel(sx < 0, b.lo0, b.hi0);
@@ -166,97 +166,141 @@ __device__ __forceinline__ void stream_adjoint_general(const LT* __restrict__ la
         const int kind = sel(out_x, kx, sel(out_y, ky, kz));
         const bool inlet = kind == 2;
         const int i = opposite(k);
-        const double w = L::w[i];
-        const double cix = L::cx[i], ciy = L::cy[i], ciz = L::cz[i];
-        const double cin = cix * uix + ciy * uiy + ciz * uiz;
+        const A w = A(L::w[i]);
+        const A cix = A(L::cx[i]), ciy = A(L::cy[i]), ciz = A(L::cz[i]);
+        const A cin = cix * uix + ciy * uiy + ciz * uiz;
         // inlet f^eq(rho_b, u_in): d/d rho_b
-        const double d_in = w * (1.0 + 3.0 * cin + 4.5 * cin * cin - 1.5 * uin2);
-        a_in += sel(open & inlet, v * d_in, 0.0);
+        const A d_in = w * (A(1) + A(3) * cin + A(4.5) * cin * cin - A(1.5) * uin2);
+        a_in += sel(open & inlet, v * d_in, A(0));
         // outlet f^eq(rho_out, u_b): d/d u_b
-        const double cub = cix * ubx + ciy * uby + ciz * ubz;
-        const double wv = sel(open & !inlet, v * w * rout, 0.0);
-        bvx += wv * (3.0 * cix + 9.0 * cub * cix - 3.0 * ubx);
-        bvy += wv * (3.0 * ciy + 9.0 * cub * ciy - 3.0 * uby);
-        bvz += wv * (3.0 * ciz + 9.0 * cub * ciz - 3.0 * ubz);
+        const A cub = cix * ubx + ciy * uby + ciz * ubz;
+        const A wv = sel(open & !inlet, v * w * rout, A(0));
+        bvx += wv * (A(3) * cix + A(9) * cub * cix - A(3) * ubx);
+        bvy += wv * (A(3) * ciy + A(9) * cub * ciy - A(3) * uby);
+        bvz += wv * (A(3) * ciz + A(9) * cub * ciz - A(3) * ubz);
     }
     // rho_b depends on every own population with weight 1, u_b = j_b/rho_b
-    const double inv_b = 1.0 / rho_b;
-    const double common = a_in - (bvx * ubx + bvy * uby + bvz * ubz) * inv_b;
-    const double gx = bvx * inv_b, gy = bvy * inv_b, gz = bvz * inv_b;
+    const A inv_b = A(1) / rho_b;
+    const A common = a_in - (bvx * ubx + bvy * uby + bvz * ubz) * inv_b;
+    const A gx = bvx * inv_b, gy = bvy * inv_b, gz = bvz * inv_b;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k)
-        pb[k] += common + double(L::cx[k]) * gx + double(L::cy[k]) * gy + double(L::cz[k]) * gz;
+        pb[k] += common + A(L::cx[k]) * gx + A(L::cy[k]) * gy + A(L::cz[k]) * gz;
+}
+
+// The x ends of a plain row, after stream_adjoint_periodic: the transpose of
+// fix_x_ends.  Direction k pulls from x + c_k, which crosses the lo face
+// where c_x = -1 (at the lo end cell) and the hi face where c_x = +1 (at the
+// hi end cell).  There the forward step took population opp(k) of this cell
+// by bounce-back (wall: read this cell's adjoint of opp(k)) or from an open
+// face's equilibrium (nothing from the neighbour; the equilibrium's
+// derivatives, as in stream_adjoint_general).  Only the end lanes of a row
+// call it; every load stays at this cell.
+template <class L, class A>
+__device__ __forceinline__ void stream_adjoint_x_ends(const A* __restrict__ lam, uint32_t P, const Params& p,
+                                                      const Box& b, bool at_lo, bool at_hi, uint32_t cell,
+                                                      A rho_b, A ubx, A uby, A ubz, A (&pb)[L::Q])
+{
+    const A uix = A(p.inlet_u[0]), uiy = A(p.inlet_u[1]), uiz = A(p.inlet_u[2]);
+    const A uin2 = uix * uix + uiy * uiy + uiz * uiz;
+    const A rout = A(p.outlet_rho);
+    A a_in = 0, bvx = 0, bvy = 0, bvz = 0;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        if (L::cx[k] == 0) continue;
+        const bool hit = L::cx[k] < 0 ? at_lo : at_hi;
+        const int kind = L::cx[k] < 0 ? b.lo0 : b.hi0;
+        const A v = ld(lam + (size_t)opposite(k) * P, cell);
+        const bool open = hit & (kind >= 2);
+        pb[k] = sel(open, A(0), sel(hit, v, pb[k]));
+        const bool inlet = kind == 2;
+        const int i = opposite(k);
+        const A w = A(L::w[i]);
+        const A cix = A(L::cx[i]), ciy = A(L::cy[i]), ciz = A(L::cz[i]);
+        const A cin = cix * uix + ciy * uiy + ciz * uiz;
+        const A d_in = w * (A(1) + A(3) * cin + A(4.5) * cin * cin - A(1.5) * uin2);
+        a_in += sel(open & inlet, v * d_in, A(0));
+        const A cub = cix * ubx + ciy * uby + ciz * ubz;
+        const A wv = sel(open & !inlet, v * w * rout, A(0));
+        bvx += wv * (A(3) * cix + A(9) * cub * cix - A(3) * ubx);
+        bvy += wv * (A(3) * ciy + A(9) * cub * ciy - A(3) * uby);
+        bvz += wv * (A(3) * ciz + A(9) * cub * ciz - A(3) * ubz);
+    }
+    const A inv_b = A(1) / rho_b;
+    const A common = a_in - (bvx * ubx + bvy * uby + bvz * ubz) * inv_b;
+    const A gx = bvx * inv_b, gy = bvy * inv_b, gz = bvz * inv_b;
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k)
+        pb[k] += common + A(L::cx[k]) * gx + A(L::cy[k]) * gy + A(L::cz[k]) * gz;
 }
 
 // ---------------------------------------------------------------------------
-// The control in the adjoint's FP64: u_eq = M u with M = (1 - d) I (scalar) or
-// M = I - D (tensor; symmetric, so M^T = M).
+// The control in the adjoint's arithmetic A: u_eq = M u with M = (1 - d) I
+// (scalar) or M = I - D (tensor; symmetric, so M^T = M).
 //   om_m(om, a) = omega M a
 //   grad(om, Av, u, g): g_r = omega Av . (dM/dtheta_r) u, the cotangent of
 //   control row r, with dM/dd = -I for the scalar d, -e_a e_a^T for a
 //   diagonal row and -(e_a e_b^T + e_b e_a^T) for an off-diagonal row (a, b).
 // ---------------------------------------------------------------------------
+template <class A>
 struct AdjScalar {
     static constexpr int rows = 1;
-    double d;
+    A d;
     template <class S>
     __device__ __forceinline__ static AdjScalar load(const typename S::D* __restrict__ f, uint32_t, uint32_t cell)
     {
-        return AdjScalar{(double)S::load_d(ld(f, cell))};
+        return AdjScalar{A(S::load_d(ld(f, cell)))};
     }
-    __device__ __forceinline__ void eq(double ux, double uy, double uz, double& vx, double& vy, double& vz) const
+    __device__ __forceinline__ void eq(A ux, A uy, A uz, A& vx, A& vy, A& vz) const
     {
-        const double sh = 1.0 - d;
+        const A sh = A(1) - d;
         vx = sh * ux;
         vy = sh * uy;
         vz = sh * uz;
     }
-    __device__ __forceinline__ void om_m(double om, double ax, double ay, double az, double& bx, double& by,
-                                         double& bz) const
+    __device__ __forceinline__ void om_m(A om, A ax, A ay, A az, A& bx, A& by, A& bz) const
     {
-        const double s = om * (1.0 - d);
+        const A s = om * (A(1) - d);
         bx = s * ax;
         by = s * ay;
         bz = s * az;
     }
-    __device__ __forceinline__ void grad(double om, double Avx, double Avy, double Avz, double ux, double uy,
-                                         double uz, double (&g)[1]) const
+    __device__ __forceinline__ void grad(A om, A Avx, A Avy, A Avz, A ux, A uy, A uz, A (&g)[1]) const
     {
         g[0] = -om * (Avx * ux + Avy * uy + Avz * uz);
     }
 };
 
+template <class A>
 struct AdjTensor {
     static constexpr int rows = 6;
-    double xx, yy, zz, xy, xz, yz;
+    A xx, yy, zz, xy, xz, yz;
     template <class S>
     __device__ __forceinline__ static AdjTensor load(const typename S::D* __restrict__ f, uint32_t pitch,
                                                      uint32_t cell)
     {
-        return AdjTensor{(double)S::load_d(ld(f, cell)),
-                         (double)S::load_d(ld(f + (size_t)pitch, cell)),
-                         (double)S::load_d(ld(f + 2 * (size_t)pitch, cell)),
-                         (double)S::load_d(ld(f + 3 * (size_t)pitch, cell)),
-                         (double)S::load_d(ld(f + 4 * (size_t)pitch, cell)),
-                         (double)S::load_d(ld(f + 5 * (size_t)pitch, cell))};
+        return AdjTensor{A(S::load_d(ld(f, cell))),
+                         A(S::load_d(ld(f + (size_t)pitch, cell))),
+                         A(S::load_d(ld(f + 2 * (size_t)pitch, cell))),
+                         A(S::load_d(ld(f + 3 * (size_t)pitch, cell))),
+                         A(S::load_d(ld(f + 4 * (size_t)pitch, cell))),
+                         A(S::load_d(ld(f + 5 * (size_t)pitch, cell)))};
     }
-    __device__ __forceinline__ void eq(double ux, double uy, double uz, double& vx, double& vy, double& vz) const
+    __device__ __forceinline__ void eq(A ux, A uy, A uz, A& vx, A& vy, A& vz) const
     {
         vx = ux - (xx * ux + xy * uy + xz * uz);
         vy = uy - (xy * ux + yy * uy + yz * uz);
         vz = uz - (xz * ux + yz * uy + zz * uz);
     }
-    __device__ __forceinline__ void om_m(double om, double ax, double ay, double az, double& bx, double& by,
-                                         double& bz) const
+    __device__ __forceinline__ void om_m(A om, A ax, A ay, A az, A& bx, A& by, A& bz) const
     {
-        double mx, my, mz;
+        A mx, my, mz;
         eq(ax, ay, az, mx, my, mz);
         bx = om * mx;
         by = om * my;
         bz = om * mz;
     }
-    __device__ __forceinline__ void grad(double om, double Avx, double Avy, double Avz, double ux, double uy,
-                                         double uz, double (&g)[6]) const
+    __device__ __forceinline__ void grad(A om, A Avx, A Avy, A Avz, A ux, A uy, A uz, A (&g)[6]) const
     {
         g[0] = -om * (Avx * ux);
         g[1] = -om * (Avy * uy);
@@ -267,11 +311,11 @@ struct AdjTensor {
     }
 };
 
-template <int PK>
-using AdjShift = typename std::conditional<PK == PK_TENSOR, AdjTensor, AdjScalar>::type;
+template <int PK, class A>
+using AdjShift = typename std::conditional<PK == PK_TENSOR, AdjTensor<A>, AdjScalar<A>>::type;
 
 // ---------------------------------------------------------------------------
-// C^T of one fluid cell.  In: the FP64 moments of y, the control, and pb =
+// C^T of one fluid cell.  In: the recorded moments of y, the control, and pb =
 // adjoint of the post-collision populations.  Out: pb overwritten with the
 // adjoint of the pre-collision populations, and this step's cotangent of each
 // control row in g.
@@ -283,23 +327,24 @@ using AdjShift = typename std::conditional<PK == PK_TENSOR, AdjTensor, AdjScalar
 //   pre_k   = (1 - omega) pb_k + omega dA/drho - ubar.u/rho + c_k.ubar/rho
 //   g_r     = omega dA/dv . (dM/dtheta_r) u
 // ---------------------------------------------------------------------------
-template <class L, class Sh>
+template <class L, class A, class Sh>
 __device__ __forceinline__ void collide_adjoint(const Moms& m, const Sh& sh, const Params& p,
-                                                double (&pb)[L::Q], double (&g)[Sh::rows])
+                                                A (&pb)[L::Q], A (&g)[Sh::rows])
 {
-    const double om = p.omega, pref = p.pref;
-    const double F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
-    const double rho = p.rho0 + m.s, inv_rho = 1.0 / rho;
-    const double ux = (m.jx + 0.5 * F0) * inv_rho;
-    const double uy = (m.jy + 0.5 * F1) * inv_rho;
-    const double uz = (m.jz + 0.5 * F2) * inv_rho;
-    double vx, vy, vz;
+    const A om = A(p.omega), pref = A(p.pref);
+    const A F0 = A(p.F[0]), F1 = A(p.F[1]), F2 = A(p.F[2]);
+    // rho0 + drho and j + F/2 formed in FP64, then taken to A
+    const A rho = A(p.rho0 + m.s), inv_rho = A(1) / rho;
+    const A ux = A(m.jx + 0.5 * p.F[0]) * inv_rho;
+    const A uy = A(m.jy + 0.5 * p.F[1]) * inv_rho;
+    const A uz = A(m.jz + 0.5 * p.F[2]) * inv_rho;
+    A vx, vy, vz;
     sh.eq(ux, uy, uz, vx, vy, vz);
-    double P0 = 0.0, Px = 0.0, Py = 0.0, Pz = 0.0;
-    double Pxx = 0.0, Pyy = 0.0, Pzz = 0.0, Pxy = 0.0, Pxz = 0.0, Pyz = 0.0;
+    A P0 = 0, Px = 0, Py = 0, Pz = 0;
+    A Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const double wp = L::w[i] * pb[i];
+        const A wp = A(L::w[i]) * pb[i];
         P0 += wp;
         if (L::cx[i]) Px += L::cx[i] > 0 ? wp : -wp;
         if (L::cy[i]) Py += L::cy[i] > 0 ? wp : -wp;
@@ -311,36 +356,35 @@ __device__ __forceinline__ void collide_adjoint(const Moms& m, const Sh& sh, con
         if (L::cx[i] * L::cz[i]) Pxz += L::cx[i] * L::cz[i] > 0 ? wp : -wp;
         if (L::cy[i] * L::cz[i]) Pyz += L::cy[i] * L::cz[i] > 0 ? wp : -wp;
     }
-    const double Pvx = Pxx * vx + Pxy * vy + Pxz * vz;
-    const double Pvy = Pxy * vx + Pyy * vy + Pyz * vz;
-    const double Pvz = Pxz * vx + Pyz * vy + Pzz * vz;
-    const double vv = vx * vx + vy * vy + vz * vz;
-    const double A_rho = P0 * (1.0 - 1.5 * vv) + 3.0 * (Px * vx + Py * vy + Pz * vz) +
-                         4.5 * (vx * Pvx + vy * Pvy + vz * Pvz);
-    const double Avx = rho * (3.0 * Px + 9.0 * Pvx - 3.0 * vx * P0);
-    const double Avy = rho * (3.0 * Py + 9.0 * Pvy - 3.0 * vy * P0);
-    const double Avz = rho * (3.0 * Pz + 9.0 * Pvz - 3.0 * vz * P0);
-    const double PFx = Pxx * F0 + Pxy * F1 + Pxz * F2;
-    const double PFy = Pxy * F0 + Pyy * F1 + Pyz * F2;
-    const double PFz = Pxz * F0 + Pyz * F1 + Pzz * F2;
-    double mAx, mAy, mAz;
+    const A Pvx = Pxx * vx + Pxy * vy + Pxz * vz;
+    const A Pvy = Pxy * vx + Pyy * vy + Pyz * vz;
+    const A Pvz = Pxz * vx + Pyz * vy + Pzz * vz;
+    const A vv = vx * vx + vy * vy + vz * vz;
+    const A A_rho = P0 * (A(1) - A(1.5) * vv) + A(3) * (Px * vx + Py * vy + Pz * vz) +
+                    A(4.5) * (vx * Pvx + vy * Pvy + vz * Pvz);
+    const A Avx = rho * (A(3) * Px + A(9) * Pvx - A(3) * vx * P0);
+    const A Avy = rho * (A(3) * Py + A(9) * Pvy - A(3) * vy * P0);
+    const A Avz = rho * (A(3) * Pz + A(9) * Pvz - A(3) * vz * P0);
+    const A PFx = Pxx * F0 + Pxy * F1 + Pxz * F2;
+    const A PFy = Pxy * F0 + Pyy * F1 + Pyz * F2;
+    const A PFz = Pxz * F0 + Pyz * F1 + Pzz * F2;
+    A mAx, mAy, mAz;
     sh.om_m(om, Avx, Avy, Avz, mAx, mAy, mAz);
-    const double ubx = mAx + pref * (9.0 * PFx - 3.0 * F0 * P0);
-    const double uby = mAy + pref * (9.0 * PFy - 3.0 * F1 * P0);
-    const double ubz = mAz + pref * (9.0 * PFz - 3.0 * F2 * P0);
-    const double rbar = om * A_rho - (ubx * ux + uby * uy + ubz * uz) * inv_rho;
-    const double jbx = ubx * inv_rho, jby = uby * inv_rho, jbz = ubz * inv_rho;
+    const A ubx = mAx + pref * (A(9) * PFx - A(3) * F0 * P0);
+    const A uby = mAy + pref * (A(9) * PFy - A(3) * F1 * P0);
+    const A ubz = mAz + pref * (A(9) * PFz - A(3) * F2 * P0);
+    const A rbar = om * A_rho - (ubx * ux + uby * uy + ubz * uz) * inv_rho;
+    const A jbx = ubx * inv_rho, jby = uby * inv_rho, jbz = ubz * inv_rho;
 #pragma unroll
     for (int k = 0; k < L::Q; ++k)
-        pb[k] = (1.0 - om) * pb[k] + rbar + double(L::cx[k]) * jbx + double(L::cy[k]) * jby +
-                double(L::cz[k]) * jbz;
+        pb[k] = (A(1) - om) * pb[k] + rbar + A(L::cx[k]) * jbx + A(L::cy[k]) * jby + A(L::cz[k]) * jbz;
     sh.grad(om, Avx, Avy, Avz, ux, uy, uz, g);
 }
 
 // ---------------------------------------------------------------------------
 // One reverse step t: lam_out = lambda_t from lam_in = lambda_{t+1}, with the
 // forward step's moment record in `rec`; each control row of dbar += this
-// step's cotangent of that row.
+// step's cotangent of that row (added in FP64).
 // ---------------------------------------------------------------------------
 template <class L, class S, int BC, int PK>
 __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in, LamT<S>* __restrict__ lam_out,
@@ -348,42 +392,70 @@ __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in,
                                              const typename S::D* __restrict__ dfield, double* __restrict__ dbar,
                                              const Params& p, uint32_t x, uint32_t y, uint32_t z)
 {
+    using A = LamT<S>;
     const uint32_t N = p.N;
     const uint32_t cell = x + (uint32_t)p.nx * (y + (uint32_t)p.ny * z);
     const Moms m = recorded_moments(rec, N, cell);
-    using Sh = AdjShift<PK>;
+    using Sh = AdjShift<PK, A>;
     const Sh sh = Sh::template load<S>(dfield, p.P, cell);  // control rows are P apart
-    double pb[L::Q];
+    A pb[L::Q];
     bool solid = false;
     if (BC == BC_PERIODIC) {
-        stream_adjoint_periodic<L, LamT<S>>(lam_in, p.P, p, x, y, z, pb);
+        stream_adjoint_periodic<L, A>(lam_in, p.P, p, x, y, z, pb);
     } else {
-        // post-collision moments of this cell at step t (balance laws)
-        const double rho = p.rho0 + m.s, inv_rho = 1.0 / rho;
-        const double om = p.omega;
-        double rvx, rvy, rvz;  // omega rho u_eq = omega M (j + F/2)
-        sh.om_m(om, m.jx + 0.5 * p.F[0], m.jy + 0.5 * p.F[1], m.jz + 0.5 * p.F[2], rvx, rvy, rvz);
-        const double jbx = (1.0 - om) * m.jx + rvx + p.pref * p.F[0];
-        const double jby = (1.0 - om) * m.jy + rvy + p.pref * p.F[1];
-        const double jbz = (1.0 - om) * m.jz + rvz + p.pref * p.F[2];
-        stream_adjoint_general<L, LamT<S>>(lam_in, p.P, p, (int)x, (int)y, (int)z, rho, jbx * inv_rho,
-                                  jby * inv_rho, jbz * inv_rho, pb);
-        solid = in_wall_layer(box_of(p), (int)x, (int)y, (int)z);
+        const Box b = box_of(p);
+        // post-collision density and velocity of this cell at step t, from
+        // the recorded moments by the balance laws (open faces only)
+        auto post = [&](A& rho, A& ubx, A& uby, A& ubz) {
+            rho = A(p.rho0 + m.s);
+            const A inv_rho = A(1) / rho;
+            const A om = A(p.omega);
+            A rvx, rvy, rvz;  // omega rho u_eq = omega M (j + F/2)
+            sh.om_m(om, A(m.jx + 0.5 * p.F[0]), A(m.jy + 0.5 * p.F[1]), A(m.jz + 0.5 * p.F[2]), rvx, rvy, rvz);
+            ubx = ((A(1) - om) * A(m.jx) + rvx + A(p.pref * p.F[0])) * inv_rho;
+            uby = ((A(1) - om) * A(m.jy) + rvy + A(p.pref * p.F[1])) * inv_rho;
+            ubz = ((A(1) - om) * A(m.jz) + rvz + A(p.pref * p.F[2])) * inv_rho;
+        };
+        A rho_b, ubx, uby, ubz;
+        if (BC == BC_PLAIN_ROW) {
+            // the periodic transpose, then the row's x ends
+            stream_adjoint_periodic<L, A>(lam_in, p.P, p, x, y, z, pb);
+            const bool at_lo = (int)x == x_end_lo(b.lo0), at_hi = (int)x == x_end_hi(b.hi0, b.nx);
+            if (at_lo | at_hi) {
+                post(rho_b, ubx, uby, ubz);
+                stream_adjoint_x_ends<L, A>(lam_in, p.P, p, b, at_lo, at_hi, cell, rho_b, ubx, uby, ubz, pb);
+            }
+        } else {
+            post(rho_b, ubx, uby, ubz);
+            stream_adjoint_general<L, A>(lam_in, p.P, p, (int)x, (int)y, (int)z, rho_b, ubx, uby, ubz, pb);
+        }
+        solid = in_wall_layer(b, (int)x, (int)y, (int)z);
     }
-    double g[Sh::rows];
-    collide_adjoint<L>(m, sh, p, pb, g);
+    A g[Sh::rows];
+    collide_adjoint<L, A>(m, sh, p, pb, g);
 #pragma unroll
-    for (int k = 0; k < L::Q; ++k) st(lam_out + (size_t)k * p.P, cell, LamT<S>(sel(solid, 0.0, pb[k])));
+    for (int k = 0; k < L::Q; ++k) st(lam_out + (size_t)k * p.P, cell, sel(solid, A(0), pb[k]));
 #pragma unroll
     for (int r = 0; r < Sh::rows; ++r) {
         // FP64 gradient rows can pass 4 GiB: 64-bit indexing
         double* const at = dbar + (size_t)r * N + cell;
-        *at = *at + sel(solid, 0.0, g[r]);
+        *at = *at + double(sel(solid, A(0), g[r]));
     }
 }
 
+// Waves per SIMD that a reverse step kernel asks the register allocator for:
+// in FP32 arithmetic with walls or open faces, 6 (5 with the tensor control's
+// six rows), which fit without spilling to scratch.  Otherwise, and in FP64:
+// no request.
+template <class S, int BC, int PK>
+struct AdjWaves {
+    static constexpr int value =
+        (std::is_same<S, StoreF64>::value || BC == BC_PERIODIC) ? 1 : (PK == PK_TENSOR ? 5 : 6);
+};
+
 template <class L, class S, int BC, int PK>
-__global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict__ lam_in,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjWaves<S, BC, PK>::value))) void
+adjoint_kernel(const LamT<S>* __restrict__ lam_in,
                                                        LamT<S>* __restrict__ lam_out,
                                                        const double* __restrict__ rec,
                                                        const typename S::D* __restrict__ dfield,
@@ -391,38 +463,21 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict_
 {
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)p.nx) return;
-    adjoint_cell<L, S, BC, PK>(lam_in, lam_out, rec, dfield, dbar, p, x, blockIdx.y, blockIdx.z);
-}
-
-// Interior and shell of a box with walls or open faces (see Split), in one
-// launch: in the interior the periodic forms of the gather and of its
-// transpose load what the general rule would; the shell takes the general
-// rule.  The choice is uniform per block.  The shell's blocks come first:
-// they are the slow ones, and blocks start in index order, so the interior
-// blocks fill in behind them instead of leaving them as the tail.
-template <class L, class S, int PK>
-__global__ __launch_bounds__(256) void adjoint_split_kernel(const LamT<S>* __restrict__ lam_in,
-                                                             LamT<S>* __restrict__ lam_out,
-                                                             const double* __restrict__ rec,
-                                                             const typename S::D* __restrict__ dfield,
-                                                             double* __restrict__ dbar, Params p, Split sp)
-{
-    const uint32_t b = blockIdx.x;
-    if (b < sp.blocks_shell) {
-        const uint32_t k = b * blockDim.x + threadIdx.x;
-        if (k >= sp.n_shell) return;
-        uint32_t x, y, z;
-        shell_cell(sp, (uint32_t)p.nx, (uint32_t)p.ny, k, x, y, z);
-        adjoint_cell<L, S, BC_GENERAL, PK>(lam_in, lam_out, rec, dfield, dbar, p, x, y, z);
-    } else {
-        const uint32_t bi = b - sp.blocks_shell;
-        const uint32_t row = bi / sp.gx, bxi = bi - row * sp.gx;
-        const uint32_t iy = sp.hi[1] - sp.lo[1];
-        const uint32_t zz = row / iy, yy = row - zz * iy;
-        const uint32_t x = sp.lo[0] + bxi * blockDim.x + threadIdx.x;
-        if (x >= sp.hi[0]) return;
-        adjoint_cell<L, S, BC_PERIODIC, PK>(lam_in, lam_out, rec, dfield, dbar, p, x, sp.lo[1] + yy, sp.lo[2] + zz);
+    if (BC != BC_GENERAL) {
+        adjoint_cell<L, S, BC, PK>(lam_in, lam_out, rec, dfield, dbar, p, x, blockIdx.y, blockIdx.z);
+        return;
     }
+    // with walls or open faces the rows are taken in row_of order (the rows
+    // that are not plain first); plain rows take the periodic transpose and
+    // their x ends, the others the general rule; the choice is uniform per
+    // block and each path keeps its own collision and stores
+    int y, z;
+    row_of((int)(blockIdx.y + gridDim.y * blockIdx.z), p.ny, p.nz, p.bc_lo[1], p.bc_hi[1], p.bc_lo[2], p.bc_hi[2],
+           y, z);
+    if (plain_row(y, z, p.ny, p.nz, p.bc_lo[1], p.bc_hi[1], p.bc_lo[2], p.bc_hi[2]))
+        adjoint_cell<L, S, BC_PLAIN_ROW, PK>(lam_in, lam_out, rec, dfield, dbar, p, x, (uint32_t)y, (uint32_t)z);
+    else
+        adjoint_cell<L, S, BC, PK>(lam_in, lam_out, rec, dfield, dbar, p, x, (uint32_t)y, (uint32_t)z);
 }
 
 // ---------------------------------------------------------------------------
@@ -451,17 +506,10 @@ static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* l
     auto* d = static_cast<const typename S::D*>(dfield);
     auto* li = static_cast<const LamT<S>*>(lam_in);
     auto* lo = static_cast<LamT<S>*>(lam_out);
-    if (bcmode == BC_PERIODIC) {
+    if (bcmode == BC_PERIODIC)
         hipLaunchKernelGGL((adjoint_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, li, lo, rec, d, dbar, p);
-        return hipGetLastError();
-    }
-    const Split sp = split_of(p, (int)l.block.x);
-    if (!sp.interior()) {
+    else
         hipLaunchKernelGGL((adjoint_kernel<L, S, BC_GENERAL, PK>), l.grid, l.block, 0, s, li, lo, rec, d, dbar, p);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL((adjoint_split_kernel<L, S, PK>), dim3(sp.blocks_in + sp.blocks_shell), l.block, 0, s, li, lo,
-                       rec, d, dbar, p, sp);
     return hipGetLastError();
 }
 

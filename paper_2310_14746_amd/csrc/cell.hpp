@@ -416,10 +416,93 @@ struct OpenFaces {
     R rho0, in_ux, in_uy, in_uz, out_rho;
 };
 
+// Own post-collision density and velocity j_b/rho_b of a cell (what an open
+// face's equilibrium is built from).
+template <class L, class S>
+__device__ __forceinline__ void own_state(const typename S::T* __restrict__ src, uint32_t P, uint32_t cell,
+                                          typename S::R rho0, typename S::R inv_scale, typename S::R& rho_b,
+                                          typename S::R& ubx, typename S::R& uby, typename S::R& ubz)
+{
+    using R = typename S::R;
+    R r = rho0, jbx = R(0), jby = R(0), jbz = R(0);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        const R gk = S::load(ld(src + (size_t)k * P, cell), inv_scale);
+        r += gk;
+        if (L::cx[k]) jbx += L::cx[k] > 0 ? gk : -gk;
+        if (L::cy[k]) jby += L::cy[k] > 0 ? gk : -gk;
+        if (L::cz[k]) jbz += L::cz[k] > 0 ? gk : -gk;
+    }
+    const R inv_b = R(1) / r;
+    rho_b = r;
+    ubx = jbx * inv_b;
+    uby = jby * inv_b;
+    ubz = jbz * inv_b;
+}
+
+// The x ends of a plain row, after its periodic gather: each direction whose
+// pull crosses an x face (c_x = +1 at the lo end cell, -1 at the hi end cell)
+// takes that face's rule in place of the wrapped value: from a wall layer,
+// halfway bounce-back (this cell's opposite population); across an open face,
+// the equilibrium from this cell's own post-collision state.  Only the end
+// lanes of a row take the branch; they load this cell's own populations once
+// (every load stays at this cell).
+template <class L, class S>
+__device__ __forceinline__ void fix_x_ends(const typename S::T* __restrict__ src, uint32_t P, const Box& b,
+                                           const OpenFaces<typename S::R>& of, int x, uint32_t cell,
+                                           typename S::R inv_scale, typename S::R (&g)[L::Q])
+{
+    using R = typename S::R;
+    const bool at_lo = x == x_end_lo(b.lo0), at_hi = x == x_end_hi(b.hi0, b.nx);
+    if (!(at_lo | at_hi)) return;
+    R own[L::Q];
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) own[k] = S::load(ld(src + (size_t)k * P, cell), inv_scale);
+    // own post-collision state, summed as own_state does
+    R rho_b = of.rho0, jbx = R(0), jby = R(0), jbz = R(0);
+#pragma unroll
+    for (int k = 0; k < L::Q; ++k) {
+        rho_b += own[k];
+        if (L::cx[k]) jbx += L::cx[k] > 0 ? own[k] : -own[k];
+        if (L::cy[k]) jby += L::cy[k] > 0 ? own[k] : -own[k];
+        if (L::cz[k]) jbz += L::cz[k] > 0 ? own[k] : -own[k];
+    }
+    const R inv_b = R(1) / rho_b;
+    const R ubx = jbx * inv_b, uby = jby * inv_b, ubz = jbz * inv_b;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        if (L::cx[i] == 0) continue;
+        const bool hit = L::cx[i] > 0 ? at_lo : at_hi;
+        const int kind = L::cx[i] > 0 ? b.lo0 : b.hi0;
+        const bool inlet = kind == 2;
+        const R e_rho = sel(inlet, rho_b, of.out_rho);
+        const R e_ux = sel(inlet, of.in_ux, ubx);
+        const R e_uy = sel(inlet, of.in_uy, uby);
+        const R e_uz = sel(inlet, of.in_uz, ubz);
+        const R eq = feq_shifted<L, R>(i, e_rho, of.rho0, e_ux, e_uy, e_uz);
+        g[i] = sel(hit, sel(kind == 1, own[opposite(i)], eq), g[i]);
+    }
+}
+
+// Pull gather of a cell on a plain row (see plain_row): the periodic gather,
+// then the row's x ends.  Loads what gather_general would, value for value.
+template <class L, class S>
+__device__ __forceinline__ void gather_plain_row(const typename S::T* __restrict__ src, uint32_t P, const Box& b,
+                                                 const OpenFaces<typename S::R>& of, int x, int y, int z,
+                                                 typename S::R inv_scale, typename S::R (&g)[L::Q])
+{
+    const uint32_t cell = (uint32_t)x + (uint32_t)b.nx * ((uint32_t)y + (uint32_t)b.ny * (uint32_t)z);
+    gather_periodic<L, S>(src, P, 0u, (uint32_t)b.nx, (uint32_t)b.ny, (uint32_t)b.nz, (uint32_t)x, (uint32_t)y,
+                          (uint32_t)z, inv_scale, g);
+    fix_x_ends<L, S>(src, P, b, of, x, cell, inv_scale, g);
+}
+
 // ---------------------------------------------------------------------------
-// Pull gather with walls and open faces.  Straight-line code: every address
-// stays inside the box for any cell, solid ones included (the caller discards
-// their result).  Per direction:
+// Pull gather with walls and open faces (the general rule).  Straight-line
+// code: every address stays inside the box for any cell, solid ones included
+// (the caller discards their result).  The sweep kernels use it on the rows
+// next to a y or z face and gather_plain_row on the others (a choice per
+// row).  Per direction:
 //   * periodic axes wrap;
 //   * a source in a wall layer -> halfway bounce-back g*_i(x) = g_opp(i)(x)
 //     (takes precedence on edges): the load address switches to this cell's
@@ -439,17 +522,8 @@ __device__ __forceinline__ void gather_general(const typename S::T* __restrict__
     const uint32_t cell = (uint32_t)x + (uint32_t)b.nx * ((uint32_t)y + (uint32_t)b.ny * (uint32_t)z);
     const bool px = b.lo0 == 0, py = b.lo1 == 0, pz = b.lo2 == 0;
     // own post-collision state (used only where a source lies beyond an open face)
-    R rho_b = of.rho0, jbx = R(0), jby = R(0), jbz = R(0);
-#pragma unroll
-    for (int k = 0; k < L::Q; ++k) {
-        const R gk = S::load(ld(src + (size_t)k * P, cell), inv_scale);
-        rho_b += gk;
-        if (L::cx[k]) jbx += L::cx[k] > 0 ? gk : -gk;
-        if (L::cy[k]) jby += L::cy[k] > 0 ? gk : -gk;
-        if (L::cz[k]) jbz += L::cz[k] > 0 ? gk : -gk;
-    }
-    const R inv_b = R(1) / rho_b;
-    const R ubx = jbx * inv_b, uby = jby * inv_b, ubz = jbz * inv_b;
+    R rho_b, ubx, uby, ubz;
+    own_state<L, S>(src, P, cell, of.rho0, inv_scale, rho_b, ubx, uby, ubz);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const int sx = wrap_source(x, L::cx[i], b.nx, px);

@@ -49,7 +49,10 @@ enum BcMode {
     BC_AA_EVEN = 3,
     BC_AA_ODD = 4,
     BC_AA_EVEN_W = 5,
-    BC_AA_ODD_W = 6
+    BC_AA_ODD_W = 6,
+    // device-side only: a plain row (see plain_row) inside the BC_GENERAL
+    // kernels, which choose it per row
+    BC_PLAIN_ROW = 7
 };
 constexpr uint32_t LINK_SOLID_SELF = 1u << 31;
 
@@ -65,78 +68,58 @@ inline uint32_t row_pitch(uint32_t n, size_t elem, int pad_bytes) { return n + (
 // Porosity control kinds: one value d per cell, or a symmetric 3x3 D (6 rows).
 enum PorosityKind { PK_SCALAR = 0, PK_TENSOR = 1 };
 
-// Boxes with walls or open faces.  The cells at least two layers away from
-// every wall face and one layer away from every open face (the "interior")
-// pull only from in-box fluid cells, so the periodic gather and its transpose
-// load exactly what the general rule would.  The adjoint sweep runs them there
-// and the general rule, whose open-face terms are costly in FP64, on the rest
-// (the "shell").  Interior range per axis: [lo, hi), the whole axis when
-// periodic, else lo = 2 past a wall face or 1 past an open face, likewise hi
-// (possibly empty).  rows_out counts the rows (y, z) outside the interior
-// rows; n_shell = rows_out * nx + interior rows * (nx - (hi[0] - lo[0])).  One
-// launch of blocks of bx threads covers both: blocks_shell shell blocks, then
-// blocks_in interior blocks (gx per interior row).
-struct Split {
-    uint32_t lo[3], hi[3];
-    uint32_t rows_out, n_shell;
-    uint32_t gx, blocks_in, blocks_shell;
-    bool interior() const { return hi[0] > lo[0] && hi[1] > lo[1] && hi[2] > lo[2]; }
-};
-inline Split split_of(const Params& p, int bx)
+// Boxes with walls or open faces: which pulls need the boundary rules.  Face
+// kinds: 0 periodic, 1 wall, 2 inlet, 3 outlet.  Along an axis, the cells
+// whose pulls cross a face are its depth layers: a wall face's solid layer and
+// the layer that bounces back against it (2), an open face's own layer (1),
+// none on a periodic axis.
+__host__ __device__ inline int face_depth(int kind) { return kind == 0 ? 0 : (kind == 1 ? 2 : 1); }
+
+// A plain row (y, z): no pull of any of its cells crosses a y or z face, so
+// the periodic gather (and its transpose) loads what the boundary rules would
+// everywhere but at the row's x ends.  Bitwise operators: no branches.
+__host__ __device__ inline bool plain_row(int y, int z, int ny, int nz, int lo1, int hi1, int lo2, int hi2)
 {
-    Split s;
-    const uint32_t n[3] = {(uint32_t)p.nx, (uint32_t)p.ny, (uint32_t)p.nz};
-    for (int a = 0; a < 3; ++a) {
-        if (p.bc_lo[a] == 0) {
-            s.lo[a] = 0;
-            s.hi[a] = n[a];
-        } else {
-            // a wall face: its solid layer and the layer that bounces back
-            // against it; an open face: its own layer only
-            const uint32_t dlo = p.bc_lo[a] == 1 ? 2u : 1u, dhi = p.bc_hi[a] == 1 ? 2u : 1u;
-            s.lo[a] = n[a] < dlo ? n[a] : dlo;
-            s.hi[a] = n[a] >= dhi + s.lo[a] ? n[a] - dhi : s.lo[a];
-        }
-    }
-    const uint32_t ix = s.hi[0] - s.lo[0], iy = s.hi[1] - s.lo[1], iz = s.hi[2] - s.lo[2];
-    s.rows_out = n[1] * n[2] - iy * iz;
-    s.n_shell = s.rows_out * n[0] + iy * iz * (n[0] - ix);
-    s.gx = (ix + (uint32_t)bx - 1) / (uint32_t)bx;
-    s.blocks_in = s.gx * iy * iz;
-    s.blocks_shell = (s.n_shell + (uint32_t)bx - 1) / (uint32_t)bx;
-    return s;
+    return (int(y >= face_depth(lo1)) & int(y < ny - face_depth(hi1)) & int(z >= face_depth(lo2)) &
+            int(z < nz - face_depth(hi2))) != 0;
 }
 
-// Coordinates of shell cell k < n_shell: first every cell of the rows outside
-// the interior rows (z below the interior; then interior z with y outside
-// the interior; then z above), x fastest; then, row by row, the cells of the
-// interior rows outside the interior x-range.  Written with selects (the
-// discarded candidates may wrap; they are never used as addresses).
-__host__ __device__ inline void shell_cell(const Split& s, uint32_t nx, uint32_t ny, uint32_t k, uint32_t& x,
-                                           uint32_t& y, uint32_t& z)
+// Row order of the kernels with walls or open faces: row r (r = blockIdx.y +
+// ny blockIdx.z) -> (y, z), the rows that are not plain first (they take the
+// slower general rule, and blocks start in index order, so the plain rows
+// fill in behind them instead of leaving them as the tail), then the plain
+// rows, each part in z-major order.  A bijection of [0, ny nz); scalar
+// arithmetic with selects, once per block.
+__host__ __device__ inline void row_of(int r, int ny, int nz, int lo1, int hi1, int lo2, int hi2, int& y, int& z)
 {
-    const uint32_t ix = s.hi[0] - s.lo[0], iy = s.hi[1] - s.lo[1], iz = s.hi[2] - s.lo[2];
-    const uint32_t full = s.rows_out * nx;
-    // rows outside the interior rows
-    const uint32_t r = k / nx, xa = k - r * nx;
-    const uint32_t below = s.lo[2] * ny, mid = iz * (ny - iy);
-    const uint32_t wy = ny - iy > 0u ? ny - iy : 1u;
-    const uint32_t z1 = r / ny, y1 = r - z1 * ny;
-    const uint32_t q2 = r - below, zz2 = q2 / wy, yy2 = q2 - zz2 * wy;
-    const uint32_t y2 = yy2 < s.lo[1] ? yy2 : s.hi[1] + (yy2 - s.lo[1]), z2 = s.lo[2] + zz2;
-    const uint32_t q3 = r - below - mid, zz3 = q3 / ny, y3 = q3 - zz3 * ny, z3 = s.hi[2] + zz3;
-    const uint32_t ya = r < below ? y1 : (r < below + mid ? y2 : y3);
-    const uint32_t za = r < below ? z1 : (r < below + mid ? z2 : z3);
-    // interior rows, x outside the interior range
-    const uint32_t wx = nx - ix > 0u ? nx - ix : 1u, wiy = iy > 0u ? iy : 1u;
-    const uint32_t q4 = k - full, r4 = q4 / wx, j4 = q4 - r4 * wx;
-    const uint32_t xb = j4 < s.lo[0] ? j4 : s.hi[0] + (j4 - s.lo[0]);
-    const uint32_t zz4 = r4 / wiy, yb = s.lo[1] + (r4 - zz4 * wiy), zb = s.lo[2] + zz4;
-    const bool a = k < full;
-    x = a ? xa : xb;
-    y = a ? ya : yb;
-    z = a ? za : zb;
+    const int ylo = face_depth(lo1), zlo = face_depth(lo2);
+    const int yhi = ny - face_depth(hi1) > ylo ? ny - face_depth(hi1) : ylo;
+    const int zhi = nz - face_depth(hi2) > zlo ? nz - face_depth(hi2) : zlo;
+    const int iy = yhi - ylo, iz = zhi - zlo;
+    const int general = ny * nz - iy * iz;
+    const int below = zlo * ny, mid = iz * (ny - iy);
+    // every candidate, then selects (no branches; a discarded candidate's
+    // divisor is never zero)
+    const int q4 = r - general, d4 = iy > 0 ? iy : 1;  // plain rows
+    const int z4 = zlo + q4 / d4, y4 = ylo + q4 % d4;
+    const int z1 = r / ny, y1 = r % ny;  // planes below the plain z range
+    const int q2 = r - below, wy = ny - iy > 0 ? ny - iy : 1;  // plain z range, y outside
+    const int z2 = zlo + q2 / wy, yy2 = q2 % wy;
+    const int y2 = yy2 < ylo ? yy2 : yhi + (yy2 - ylo);
+    const int q3 = r - below - mid;  // planes above
+    const int z3 = zhi + q3 / ny, y3 = q3 % ny;
+    const bool plain = r >= general, lower = r < below, middle = r < below + mid;
+    z = plain ? z4 : (lower ? z1 : (middle ? z2 : z3));
+    y = plain ? y4 : (lower ? y1 : (middle ? y2 : y3));
 }
+
+// The x end cells of a plain row whose pulls cross an x face: at the lo face
+// x = 0 beside an open face and x = 1 beside a wall (whose solid layer x = 0
+// pulls nothing that is kept), and likewise at the hi face; -1 on a periodic
+// axis.  Directions with c_x = +1 cross the lo face there, c_x = -1 the hi
+// face (the adjoint's transposed pulls: the opposite directions).
+__host__ __device__ inline int x_end_lo(int lo0) { return lo0 == 0 ? -1 : face_depth(lo0) - 1; }
+__host__ __device__ inline int x_end_hi(int hi0, int nx) { return hi0 == 0 ? -1 : nx - face_depth(hi0); }
 
 // Launch geometry shared by every per-cell kernel: blocks of `bx` threads
 // along x, grid (ceil(nx/bx), ny, nz).

@@ -53,6 +53,12 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
         solid = in_wall_layer(b, (int)x, (int)y, (int)z);
     } else if (BC == BC_MASKED) {
         solid = gather_masked<L, S>(src, P, p.linkmask, 0u, p.nx, p.ny, p.nz, x, y, z, inv_scale, g);
+    } else if (BC == BC_PLAIN_ROW) {
+        const Box b = box_of(p);
+        const OpenFaces<R> of{rho0, R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
+                              R(p.outlet_rho)};
+        gather_plain_row<L, S>(src, P, b, of, (int)x, (int)y, (int)z, inv_scale, g);
+        solid = in_wall_layer(b, (int)x, (int)y, (int)z);
     } else {
         const Box b = box_of(p);
         const OpenFaces<R> of{rho0, R(p.inlet_u[0]), R(p.inlet_u[1]), R(p.inlet_u[2]),
@@ -117,6 +123,29 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
     return solid;
 }
 
+// One cell of a sweep kernel on the row of block (blockIdx.y, blockIdx.z).
+// With walls or open faces (BC_GENERAL) the rows are taken in row_of order
+// (the rows that are not plain first), plain rows take gather_plain_row and
+// the others the general rule: the choice is uniform per block, and each path
+// keeps its own collision and stores.
+template <class L, class S, int BC, int PK, bool REC = false>
+__device__ __forceinline__ bool sweep_row_cell(const typename S::T* src, typename S::T* dst,
+                                               const typename S::D* __restrict__ dfield, const Params& p,
+                                               uint32_t x, typename S::R& drho, typename S::R& ux,
+                                               typename S::R& uy, typename S::R& uz,
+                                               double* __restrict__ rec = nullptr)
+{
+    if (BC != BC_GENERAL)
+        return sweep_cell<L, S, BC, PK, REC>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz, rec);
+    int y, z;
+    row_of((int)(blockIdx.y + gridDim.y * blockIdx.z), p.ny, p.nz, p.bc_lo[1], p.bc_hi[1], p.bc_lo[2], p.bc_hi[2],
+           y, z);
+    if (plain_row(y, z, p.ny, p.nz, p.bc_lo[1], p.bc_hi[1], p.bc_lo[2], p.bc_hi[2]))
+        return sweep_cell<L, S, BC_PLAIN_ROW, PK, REC>(src, dst, dfield, p, x, (uint32_t)y, (uint32_t)z, drho, ux,
+                                                       uy, uz, rec);
+    return sweep_cell<L, S, BC, PK, REC>(src, dst, dfield, p, x, (uint32_t)y, (uint32_t)z, drho, ux, uy, uz, rec);
+}
+
 template <class L, class S, int BC, int PK>
 __global__ __launch_bounds__(1024) void sweep_kernel(const typename S::T* __restrict__ src,
                                                       typename S::T* __restrict__ dst,
@@ -127,7 +156,7 @@ __global__ __launch_bounds__(1024) void sweep_kernel(const typename S::T* __rest
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)p.nx) return;
     R drho, ux, uy, uz;
-    (void)sweep_cell<L, S, BC, PK>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
+    (void)sweep_row_cell<L, S, BC, PK>(src, dst, dfield, p, x, drho, ux, uy, uz);
 }
 
 // The same sweep on a step that an adjoint tape records: it also writes each
@@ -142,7 +171,7 @@ __global__ __launch_bounds__(1024) void sweep_record_kernel(const typename S::T*
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)p.nx) return;
     R drho, ux, uy, uz;
-    (void)sweep_cell<L, S, BC, PK, true>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz, rec);
+    (void)sweep_row_cell<L, S, BC, PK, true>(src, dst, dfield, p, x, drho, ux, uy, uz, rec);
 }
 
 // In-place (AA) step: one buffer, even or odd mode.  Blocks of at most 256
@@ -176,15 +205,20 @@ __global__ __launch_bounds__(1024) void sweep_diag_kernel(const typename S::T* _
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
     if (x < (uint32_t)p.nx) {
         R drho, ux, uy, uz;
-        const bool solid =
-            sweep_cell<L, S, BC, PK>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz);
+        const bool solid = sweep_row_cell<L, S, BC, PK>(src, dst, dfield, p, x, drho, ux, uy, uz);
         const double rho = p.rho0 + (double)drho;
         m0 = sel(solid, 0.0, (double)drho);
         m1 = sel(solid, 0.0, rho * (double)ux);
         m2 = sel(solid, 0.0, rho * (double)uy);
         m3 = sel(solid, 0.0, rho * (double)uz);
     }
-    const uint32_t bk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    // the partial of the cells of row (y, z), x-block blockIdx.x, whatever
+    // order the rows were taken in: the totals are summed in one order
+    int y = (int)blockIdx.y, z = (int)blockIdx.z;
+    if (BC == BC_GENERAL)
+        row_of((int)(blockIdx.y + gridDim.y * blockIdx.z), p.ny, p.nz, p.bc_lo[1], p.bc_hi[1], p.bc_lo[2],
+               p.bc_hi[2], y, z);
+    const uint32_t bk = blockIdx.x + gridDim.x * ((uint32_t)y + gridDim.y * (uint32_t)z);
     block_sum4(m0, m1, m2, m3, partials + 4 * (size_t)bk);
 }
 

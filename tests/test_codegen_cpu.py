@@ -5,8 +5,12 @@ Regression guard for a memory fault seen with an earlier boundary gather: it
 chose face kinds with conditionals over fields of the kernel-argument block, so
 the compiler selected between addresses inside that block, and on the
 wall-row path the register holding such an address was never written before a
-load used it.  The sweep kernels are now straight-line code (one guard branch),
-keep no operands in private memory, and never write through the scalar cache.
+load used it.  Boundary rules are now selects over register copies of the
+parameters: the kernels without walls or open faces are straight-line code
+(one guard branch); with walls or open faces a kernel adds only its choice of
+path per row (plain rows or the general rule) and the branch of a plain row's
+x-end lanes.  No kernel keeps operands in private memory or writes through the
+scalar cache.
 """
 import os
 import re
@@ -40,13 +44,31 @@ def _kernels(funcs, prefix):
     return {k: v for k, v in funcs.items() if k.startswith(prefix)}
 
 
+def _bc(name):
+    """Boundary mode of a sweep/reverse-step kernel <L, S, BC, PK> from its mangled name."""
+    return int(re.search(r"ELi(\d)ELi\dEEEv", name).group(1))
+
+
+def _branches(body):
+    return len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
+
+
+# the guard, the row order's scalar divisions, the choice of path per block
+# and the x-end lanes, each of which the compiler may emit as one or two
+# branches
+GENERAL_BRANCHES = 10
+
+
 def test_sweep_kernels_are_straight_line(asm):
     sweeps = _kernels(asm, "_ZN4hlbm12sweep_kernel")
     # (2 lattices x 4 storages scalar + 4 storages tensor) x 3 boundary modes
     assert len(sweeps) == 36
     for name, body in sweeps.items():
-        branches = len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
-        assert branches <= 1, (name, branches)
+        assert _branches(body) <= (GENERAL_BRANCHES if _bc(name) == 1 else 1), (name, _branches(body))
+    records = _kernels(asm, "_ZN4hlbm19sweep_record_kernel")
+    assert len(records) == 24
+    for name, body in records.items():
+        assert _branches(body) <= (GENERAL_BRANCHES if _bc(name) == 1 else 1), (name, _branches(body))
 
 
 def test_in_place_kernels_are_straight_line(asm):
@@ -67,15 +89,14 @@ def test_adjoint_kernels_are_straight_line(asm):
     # seed: 2 lattices x 4 storages x 2 boundary modes
     assert len(kern) == 24 + 16
     for name, body in kern.items():
-        branches = len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
-        assert branches <= 1, (name, branches)
+        general = "adjoint_kernel" in name and _bc(name) == 1
+        assert _branches(body) <= (GENERAL_BRANCHES if general else 1), (name, _branches(body))
 
 
 def test_no_private_memory_in_sweep_and_moments(asm):
     for name, body in {**_kernels(asm, "_ZN4hlbm12sweep_kernel"),
                        **_kernels(asm, "_ZN4hlbm14moments_kernel"),
                        **_kernels(asm, "_ZN4hlbm14adjoint_kernel"),
-                       **_kernels(asm, "_ZN4hlbm20adjoint_split_kernel"),
                        **_kernels(asm, "_ZN4hlbm17sweep_pair_kernel"),
                        **_kernels(asm, "_ZN4hlbm19sweep_record_kernel"),
                        **_kernels(asm, "_ZN4hlbm15sweep_aa_kernel"),
@@ -118,12 +139,51 @@ def test_no_scalar_cache_writes(asm):
                              flags=re.M), name
 
 
+_SDEST = re.compile(r"^\s+(?!s_cmp|s_bitcmp|s_cbranch|s_branch|s_waitcnt|s_nop)(?:s_\w+|v_readlane_b32|v_readfirstlane_b32)"
+                    r"\s+(?:s\[(\d+):(\d+)\]|s(\d+)\b)")
+
+
+def _written_in_block(lines, i, regs):
+    """Whether every SGPR in `regs` is written between the start of the basic
+    block holding line i and line i."""
+    left = set(regs)
+    for line in reversed(lines[:i]):
+        if line.startswith(".LBB") or re.match(r"^\s+s_(?:c)?branch", line):
+            break
+        m = _SDEST.match(line)
+        if m:
+            lo, hi = (int(m.group(1)), int(m.group(2))) if m.group(1) else (int(m.group(3)),) * 2
+            left -= set(range(lo, hi + 1))
+        if not left:
+            return True
+    return False
+
+
 def test_no_undefined_sgpr_copied_to_vgpr(asm):
-    """No SGPR pair marked implicit-def is copied into a VGPR pair (the faulting pattern)."""
+    """No SGPR pair marked implicit-def (undefined on some path) is copied into
+    a VGPR pair (the faulting pattern) unless the same basic block writes the
+    pair before the copy."""
     for name, body in asm.items():
         undef = set(re.findall(r"implicit-def: \$sgpr(\d+)_sgpr(\d+)", body))
-        for a, b in undef:
-            assert not re.search(r"v_mov_b64_e32 v\[\d+:\d+\], s\[%s:%s\]" % (a, b), body), name
+        if not undef:
+            continue
+        lines = body.splitlines()
+        for i, line in enumerate(lines):
+            m = re.search(r"v_mov_b64_e32 v\[\d+:\d+\], s\[(\d+):(\d+)\]", line)
+            if m and (m.group(1), m.group(2)) in undef:
+                assert _written_in_block(lines, i, (int(m.group(1)), int(m.group(2)))), (name, i, line)
+
+
+def test_block_write_scan_sees_the_faulting_pattern():
+    """The scan above on hand-made code: a pair written in the block passes, a
+    pair defined only on another path does not."""
+    ok = ["\ts_mov_b32 s7, 0x3fac71c7", "\ts_mov_b32 s6, 0x1c71c71c", "\tv_mov_b64_e32 v[68:69], s[6:7]"]
+    assert _written_in_block(ok, 2, (6, 7))
+    bad = [".LBB0_3:", "\t; implicit-def: $sgpr6_sgpr7", ".LBB0_4:", "\ts_mov_b32 s6, 0",
+           "\tv_mov_b64_e32 v[2:3], s[6:7]"]
+    assert not _written_in_block(bad, 4, (6, 7))
+    wide = ["\ts_load_dwordx4 s[4:7], s[0:1], 0x8", "\tv_mov_b64_e32 v[2:3], s[6:7]"]
+    assert _written_in_block(wide, 1, (6, 7))
 
 
 def test_barrier_polling_keeps_caches(asm):

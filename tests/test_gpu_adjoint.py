@@ -5,7 +5,8 @@ adjoint and against finite differences of the GPU's own FP64 forward.
   equals the oracle gradient (explicit 19x19 Jacobians, scatter transpose of
   streaming) to relative L2 1e-10, over periodic boxes, bounce-back walls and
   inlet/outlet faces, several checkpoint spacings and a single step.
-* FP32 storage (FP64 adjoint): relative L2 1e-3 against the oracle; FP16S and
+* FP32 storage (FP32 reverse steps, FP64 accumulation): relative L2 1e-3
+  against the oracle; FP16S and
   BF16S storage: 2e-3 and 1e-2 (measured 3.2e-4 and 2.3e-3; the forward's own storage error).
 * The differentiation workload at full size (128x64x64 channel, inlet
   u = 0.02, outlet rho = 1, walls in y and z, d ~ U[0,1), 500 steps, a
@@ -111,8 +112,8 @@ def test_adjoint_f32_forward_matches_oracle(H):
 
 @pytest.mark.parametrize("storage,bar", [("f16s", 2e-3), ("bf16s", 1e-2)])
 def test_adjoint_16bit_forward_vs_oracle(H, storage, bar):
-    """16-bit stored forward (FP32 adjoint populations, FP64 adjoint
-    arithmetic): the gradient of the stored-precision forward map against the
+    """16-bit stored forward (FP32 adjoint populations and arithmetic, FP64
+    gradient accumulation): the gradient of the stored-precision forward map against the
     oracle's FP64 gradient.  The storage rounding is not differentiated, so the
     difference follows the forward's own error (reported against a bar)."""
     q, shape, tau, F, lo, hi, inu, steps, every = CASES[4]

@@ -4,9 +4,9 @@ oracle's tensor adjoint (explicit 19x19 and 19x6 Jacobians).
 The gradient has six rows (xx, yy, zz, xy, xz, yz) of N values.
 
 * FP64 storage: relative L2 1e-10 per row over periodic boxes, walls, open
-  faces (the split launch with an interior), several checkpoint spacings and a
+  faces (plain rows and the general rule in one launch), several checkpoint spacings and a
   single step.
-* FP32 and FP16S storage (FP64 adjoint arithmetic): relative L2 1e-3 and 2e-3
+* FP32 and FP16S storage (FP32 reverse-step arithmetic): relative L2 1e-3 and 2e-3
   over all six rows, the forward's own storage error.
 * At D = d I the diagonal rows of the GPU tensor gradient sum to the GPU scalar
   gradient of the same run.
