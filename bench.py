@@ -372,7 +372,7 @@ def _alg_bytes_per_dispatch(name, grid_threads, batched_steps):
         ("void hlbm::batch_persistent_kernel<hlbm::StoreF32, false>", None): 156 * cbatch * batched_steps,
         ("void hlbm::adjoint_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): ADJ_BYTES_REC * c4,
         ("void hlbm::sweep_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): 156 * c4,
-        ("void hlbm::sweep_record_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): (156 + 32) * c4,
+        ("void hlbm::sweep_record_kernel<hlbm::D3Q19, hlbm::StoreF32, 1, 0>", c4): REC_SWEEP_BYTES * c4,
     }
     for (n, g), v in table.items():
         if name == n and (g is None or g == grid_threads):
@@ -511,9 +511,10 @@ def time_permeability_tensor(hlbm, steps=2000, seed=0):
     }
 
 
-ADJ_BYTES_REC = 19 * 4 * 2 + 32 + 4 + 16  # the reverse step as built: lam in/out, moment record, d, dJ/dd r+w
-REC_SWEEP_BYTES = 156 + 32                 # forward sweep that also writes the moment record
-ADJT_BYTES_REC = 19 * 4 * 2 + 32 + 6 * 4 + 6 * 16  # tensor control: six rows of D and of dJ/dD
+REC_BYTES = 4 * 4                          # moment record of one cell and step: 4 FP32 values
+ADJ_BYTES_REC = 19 * 4 * 2 + REC_BYTES + 4 + 16  # the reverse step as built: lam in/out, moment record, d, dJ/dd r+w
+REC_SWEEP_BYTES = 156 + REC_BYTES          # forward sweep that also writes the moment record
+ADJT_BYTES_REC = 19 * 4 * 2 + REC_BYTES + 6 * 4 + 6 * 16  # tensor control: six rows of D and of dJ/dD
 
 
 def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4, kind="replay"):
@@ -553,9 +554,9 @@ def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4, kind="replay"):
         fwd = float(np.median([a for a, _ in times]))
         bwd = float(np.median([b for _, b in times]))
         grad = d.grad.detach().cpu().numpy()
-        # a reverse step reads the 32-byte moment record of its forward step;
+        # a reverse step reads the 16-byte moment record of its forward step;
         # the replayed tape recomputes every step from the checkpoints with the
-        # recording sweep (156 + 32 bytes per cell)
+        # recording sweep (156 + 16 bytes per cell)
         adj = ADJ_BYTES_REC
         replays = steps if kind == "replay" else 0
         moved = cells * (steps * adj + replays * REC_SWEEP_BYTES)
@@ -640,10 +641,10 @@ def time_adjoint_large(hlbm, edge=256, steps=40, every=10, porosity="scalar", ro
         ms = e0.elapsed_time(e1)
     finally:
         sim.close()
-    # every reverse step reads its forward step's 32-byte moment record, which
+    # every reverse step reads its forward step's 16-byte moment record, which
     # the replay recomputes from the checkpoints with the recording sweep
     replays = steps
-    adj, fwd = (ADJT_BYTES_REC, TENSOR_BYTES + 32) if tensor else (ADJ_BYTES_REC, REC_SWEEP_BYTES)
+    adj, fwd = (ADJT_BYTES_REC, TENSOR_BYTES + REC_BYTES) if tensor else (ADJ_BYTES_REC, REC_SWEEP_BYTES)
     moved = edge ** 3 * (steps * adj + replays * fwd)
     what = "periodic sphere array with the fibre tensor" if tensor else "periodic sphere array"
     return {"workload": f"D3Q19 {edge}^3 {what}, {steps} reverse steps, checkpoint every {every}",

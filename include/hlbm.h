@@ -308,17 +308,22 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * variable standing at (a, b) and (b, a), so its derivative counts both
  * places.  At D = d I the three diagonal rows sum to the scalar dJ/dd.
  *
- * A reverse step needs only the FP64 pre-collision moments (rho - rho0, j) of
- * every cell at its forward step: the collision is linearized at them.  They
- * come from a tape: with a tape set, hlbm_step stores the state every `every`
+ * A reverse step needs only the pre-collision moments (rho - rho0, j) of
+ * every cell at its forward step: the collision is linearized at them.  The
+ * forward sweep sums them in FP64; a moment record keeps them in the
+ * adjoint's precision (FP64 for HLBM_F64, FP32 for the other forms: 4
+ * values, R = 32 or 16 bytes, per cell and step).  They come from a tape: with a tape set, hlbm_step stores the state every `every`
  * steps (checkpoints); the reverse sweep recomputes each segment of `every`
  * steps from its checkpoint with a sweep that also writes those moments (a
  * moment record of the segment), and the reverse steps read the record.  The
  * replay of the segment below runs on a second stream of the library's own
  * (default priority) while the reverse steps of the current segment run on
  * the context's stream; events order the two, and hlbm_adjoint_step waits
- * for both before it returns.  (HLBM_TAPE_MOMENTS records the moments during
- * the forward steps instead.)  The tape
+ * for both before it returns.  The forward steps of the tape's top segment
+ * (the one that holds step max_steps) write that segment's record
+ * themselves, so that a reverse sweep starting there replays only the
+ * segments below it.  (HLBM_TAPE_MOMENTS records the moments of every forward
+ * step instead.)  The tape
  * records from the state current when it is set and restarts at the current
  * state whenever the state or the porosity changes otherwise (hlbm_set_state,
  * hlbm_reset, hlbm_set_porosity, hlbm_bind_buffers).
@@ -330,8 +335,8 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * `every` >= 1 steps, and start recording at the current state.  Device memory:
  * (max_steps/every + 1) checkpoints and 4 replay states (two segments,
  * replayed alternately, whose sweeps alternate between two buffers), each one
- * population buffer, two moment records of `every` steps (every * 32 * N
- * bytes each), plus two adjoint buffers of Q rows of P values (P = N +
+ * population buffer, two moment records of `every` steps (every * R * N
+ * bytes each, R as above), plus two adjoint buffers of Q rows of P values (P = N +
  * row_pad_bytes divided by the storage's element size, the population row
  * pitch; 8 bytes each for HLBM_F64, else 4).  every = 0
  * frees the tape.  hlbm_step returns EINVAL (and does nothing) if it would
@@ -344,7 +349,7 @@ int hlbm_set_tape(hlbm_ctx *ctx, int every, int max_steps);
  *                     moment record of the segment, as described above.
  *   HLBM_TAPE_MOMENTS the same checkpoints, and every recorded forward step
  *                     also writes the moments of every cell to a record of
- *                     32 bytes per cell and step (max_steps * 32 * N bytes of
+ *                     R bytes per cell and step (max_steps * R * N bytes of
  *                     device memory, no replay states or segment records).
  *                     The reverse sweep reads that record and replays
  *                     nothing; the gradients are the same bit for bit.  This

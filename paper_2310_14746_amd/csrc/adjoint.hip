@@ -45,9 +45,10 @@
 
 namespace hlbm {
 
-// Element type of the adjoint populations for storage policy S.
+// Element type of the adjoint populations (and of the moment record) for
+// storage policy S.
 template <class S>
-using LamT = typename std::conditional<std::is_same<S, StoreF64>::value, double, float>::type;
+using LamT = AdjReal<S>;
 
 // Gather of the forward pre-collision populations y at (x, y, z) from the
 // post-collision state `src`, reduced at once to FP64 moments.
@@ -388,7 +389,7 @@ __device__ __forceinline__ void collide_adjoint(const Moms& m, const Sh& sh, con
 // ---------------------------------------------------------------------------
 template <class L, class S, int BC, int PK>
 __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in, LamT<S>* __restrict__ lam_out,
-                                             const double* __restrict__ rec,
+                                             const LamT<S>* __restrict__ rec,
                                              const typename S::D* __restrict__ dfield, double* __restrict__ dbar,
                                              const Params& p, uint32_t x, uint32_t y, uint32_t z)
 {
@@ -457,7 +458,7 @@ template <class L, class S, int BC, int PK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjWaves<S, BC, PK>::value))) void
 adjoint_kernel(const LamT<S>* __restrict__ lam_in,
                                                        LamT<S>* __restrict__ lam_out,
-                                                       const double* __restrict__ rec,
+                                                       const LamT<S>* __restrict__ rec,
                                                        const typename S::D* __restrict__ dfield,
                                                        double* __restrict__ dbar, Params p)
 {
@@ -500,8 +501,9 @@ static hipError_t seed_dispatch_bc(int bcmode, const Params& p, const void* src,
 
 template <class L, class S, int PK>
 static hipError_t adjoint_dispatch_bc(int bcmode, const Params& p, const void* lam_in, void* lam_out,
-                                      const double* rec, const void* dfield, double* dbar, int bx, hipStream_t s)
+                                      const void* rec_v, const void* dfield, double* dbar, int bx, hipStream_t s)
 {
+    auto* rec = static_cast<const LamT<S>*>(rec_v);
     const Launch l = cell_launch(p, bx < 256 ? bx : 256);
     auto* d = static_cast<const typename S::D*>(dfield);
     auto* li = static_cast<const LamT<S>*>(lam_in);
@@ -529,7 +531,7 @@ static hipError_t seed_dispatch_store(int storage, int bcmode, const Params& p, 
 
 template <class L, int PK>
 static hipError_t adjoint_dispatch_store(int storage, int bcmode, const Params& p, const void* lam_in,
-                                         void* lam_out, const double* rec, const void* dfield, double* dbar, int bx,
+                                         void* lam_out, const void* rec, const void* dfield, double* dbar, int bx,
                                          hipStream_t s)
 {
     switch (storage) {
@@ -554,9 +556,9 @@ hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, 
 
 hipError_t launch_adjoint(int q, int storage, int bcmode, int pk, const Params& p, const void* lam_in,
                           void* lam_out, const void* dfield, double* dbar, int bx, hipStream_t s,
-                          const double* moment_record)
+                          const void* moment_record)
 {
-    const double* rec = moment_record;
+    const void* rec = moment_record;
     if (!rec) return hipErrorInvalidValue;
     if (q == 9 && pk == PK_SCALAR)
         return adjoint_dispatch_store<D2Q9, PK_SCALAR>(storage, bcmode, p, lam_in, lam_out, rec, dfield, dbar, bx, s);

@@ -93,13 +93,18 @@ struct hlbm_ctx {
     char* tape_cps;
     char* tape_seg;      // replay states: two sets (segments alternate between them) of two
                          // population buffers (the replay's sweeps alternate between them)
-    double* tape_segrec; // the replay's moment records: two sets of `every` steps of 4 rows of N
+    char* tape_segrec;   // the replay's moment records: two sets of `every` steps of 4 rows of N
+    // The forward steps of the tape's top segment (the one holding step
+    // max_steps) also write their moment record, into that segment's set, so
+    // that a reverse sweep from there needs no replay of it: tape_top_valid
+    // says that the set holds them from the segment's first step on.
+    bool tape_top_valid;
     char* tape_lam[2];
     // HLBM_TAPE_MOMENTS: every recorded step also writes the FP64 pre-collision
     // moments of each cell (4 rows of N doubles per step), and the reverse
     // sweep reads them instead of replaying segments (no replay states)
     int tape_kind;
-    double* tape_rec;
+    char* tape_rec;
     // The reverse sweep replays the segment below the current one on a second
     // stream while the adjoint steps of the current one run on `stream`;
     // replayed[k] marks set k's replay done, consumed[k] the adjoint steps that
@@ -376,17 +381,22 @@ void tape_free(hlbm_ctx* c)
     c->tape_ncp = 0;
 }
 
-// Bytes of a moment record of `steps` steps: 4 rows of N doubles per step.
-size_t tape_record_bytes(const hlbm_ctx* c, int steps)
+// Bytes of one step of a moment record: 4 rows of N values in the adjoint's
+// precision (FP64 for the FP64 form, FP32 otherwise).
+size_t record_step_bytes(const hlbm_ctx* c)
 {
-    return (size_t)steps * 4 * (size_t)c->p.N * sizeof(double);
+    return 4 * (size_t)c->p.N * hlbm::adjoint_elem_bytes(c->cfg.storage);
 }
+
+// Bytes of a moment record of `steps` steps.
+size_t tape_record_bytes(const hlbm_ctx* c, int steps) { return (size_t)steps * record_step_bytes(c); }
 
 // Start recording at the current state: checkpoint 0 is the current state.
 int tape_restart(hlbm_ctx* c)
 {
     if (!c->tape_every) return HLBM_OK;
     c->tape_origin = c->step;
+    c->tape_top_valid = false;
     hipError_t e = hipMemcpyAsync(c->tape_cps, c->pop[c->cur], c->pop_bytes, hipMemcpyDeviceToDevice,
                                   c->stream);
     if (e != hipSuccess) return hip_fail(e, "tape checkpoint");
@@ -700,7 +710,7 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
                     c->step - c->tape_origin, nsteps);
     for (int t = 0; t < nsteps; ++t) {
         hipError_t e;
-        double* mrec = nullptr;  // this step's moment record (HLBM_TAPE_MOMENTS)
+        char* mrec = nullptr;  // this step's moment record (HLBM_TAPE_MOMENTS)
         if (c->tape_every) {
             const long long rel = c->step - c->tape_origin;
             if (rel > 0 && rel % c->tape_every == 0) {
@@ -708,7 +718,18 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
                                    c->pop_bytes, hipMemcpyDeviceToDevice, c->stream);
                 if (e != hipSuccess) return hip_fail(e, "tape checkpoint");
             }
-            if (c->tape_rec) mrec = c->tape_rec + (size_t)rel * 4 * (size_t)c->p.N;
+            if (c->tape_rec) {
+                mrec = c->tape_rec + (size_t)rel * record_step_bytes(c);
+            } else if (c->tape_segrec) {
+                // forward step rel + 1 of the top segment: its moment record,
+                // as the replay would write it (record j = step mtop K + j + 1)
+                const long long K = c->tape_every, mtop = (c->tape_max - 1) / K;
+                if (rel >= mtop * K) {
+                    mrec = c->tape_segrec + ((size_t)(mtop & 1) * (size_t)K + (size_t)(rel - mtop * K)) *
+                                                record_step_bytes(c);
+                    if (rel == mtop * K) c->tape_top_valid = true;
+                }
+            }
         }
         const bool diag = c->diag_every && c->step % c->diag_every == 0;
         const bool record = diag && c->diag_count < c->diag_cap;
@@ -1020,8 +1041,8 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
     const bool rec = c->tape_kind == HLBM_TAPE_MOMENTS;
     e = hipMalloc(&c->tape_cps, (size_t)ncp * c->pop_bytes);
     if (e == hipSuccess && !rec) e = hipMalloc(&c->tape_seg, 4 * c->pop_bytes);
-    if (e == hipSuccess && !rec) e = hipMalloc(&c->tape_segrec, 2 * tape_record_bytes(c, every));
-    if (e == hipSuccess && rec) e = hipMalloc(&c->tape_rec, tape_record_bytes(c, max_steps));
+    if (e == hipSuccess && !rec) e = hipMalloc((void**)&c->tape_segrec, 2 * tape_record_bytes(c, every));
+    if (e == hipSuccess && rec) e = hipMalloc((void**)&c->tape_rec, tape_record_bytes(c, max_steps));
     if (e == hipSuccess) e = hipMalloc(&c->tape_lam[0], lam_bytes);
     if (e == hipSuccess) e = hipMalloc(&c->tape_lam[1], lam_bytes);
     // default priority (a stream of another priority is never used here)
@@ -1107,7 +1128,7 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
     }
     const int K = c->tape_every;
     const int q = c->q, storage = c->cfg.storage, bc = c->bcmode, pk = c->cfg.porosity_kind;
-    const size_t rec_step = 4 * (size_t)c->p.N;  // doubles of one step's moment record
+    const size_t rec_step = record_step_bytes(c);  // bytes of one step's moment record
     // Reverse steps t = R0 .. tlo + 1 linearize at the moments of forward steps t.
     const long long tlo = R0 - nsteps;
     int a = 0;
@@ -1131,7 +1152,7 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
         auto seg_state = [&](int k, long long j) -> char* {
             return c->tape_seg + (size_t)(2 * k + (int)(j & 1)) * c->pop_bytes;
         };
-        auto seg_rec = [&](int k, long long j) -> double* {
+        auto seg_rec = [&](int k, long long j) -> char* {
             return c->tape_segrec + ((size_t)k * (size_t)K + (size_t)j) * rec_step;
         };
         auto thi_of = [&](long long m) { return (R0 < m * K + K) ? R0 : m * K + K; };
@@ -1153,7 +1174,12 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
         // queued so far (the forward steps that wrote the checkpoints)
         for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventRecord(c->consumed[k], c->stream);
         const long long mhi = (R0 - 1) / K, mlo = tlo / K;
-        if (e == hipSuccess) e = replay(mhi);
+        // the top segment's record, if the forward steps wrote it, needs no
+        // replay (it holds steps mtop K + 1 .. R0, which is all this call reads)
+        const long long mtop = (c->tape_max - 1) / K;
+        const bool top_recorded = c->tape_top_valid && mhi == mtop;
+        if (e == hipSuccess)
+            e = top_recorded ? hipEventRecord(c->replayed[mhi & 1], c->stream) : replay(mhi);
         for (long long m = mhi; e == hipSuccess && m >= mlo; --m) {
             // the segment below replays while this one's reverse steps run
             if (m - 1 >= mlo) e = replay(m - 1);
@@ -1167,6 +1193,8 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
             }
             if (e == hipSuccess) e = hipEventRecord(c->consumed[m & 1], c->stream);
         }
+        // a replay into the top segment's set from another segment overwrote it
+        if (mlo <= mtop - 2) c->tape_top_valid = false;
     }
     if (e == hipSuccess && tmp)
         e = hipMemcpyAsync(dJ_dd, gd, rows * n * sizeof(double), hipMemcpyDeviceToHost, c->stream);

@@ -1,6 +1,8 @@
 // Per-cell device code of the HLBM sweep: addressing, pull gathers, moments
 // and the homogenized BGK collision.  Included by the kernels in sweep.hip.
 #pragma once
+#include <type_traits>
+
 #include "hlbm_internal.hpp"
 #include "lattice.hpp"
 #include "storage.hpp"
@@ -289,19 +291,29 @@ __device__ __forceinline__ Moms moments_f64(const R (&g)[L::Q])
     return m;
 }
 
-// Moment record of one forward step: four rows of N doubles (s, jx, jy, jz;
-// cell index x + nx(y + ny z)); rows can pass 4 GiB together: 64-bit offsets.
-__device__ __forceinline__ void record_moments(double* __restrict__ rec, uint32_t N, uint32_t cell, const Moms& m)
+// Precision of the adjoint: FP64 for the FP64 form, FP32 for the others.  The
+// adjoint populations, the reverse step's arithmetic and the moment record
+// take it.
+template <class S>
+using AdjReal = typename std::conditional<std::is_same<S, StoreF64>::value, double, float>::type;
+
+// Moment record of one forward step: four rows of N values in the adjoint's
+// precision T (s, jx, jy, jz, rounded from the FP64 sums; cell index
+// x + nx(y + ny z)); rows can pass 4 GiB together: 64-bit offsets.
+template <class T>
+__device__ __forceinline__ void record_moments(T* __restrict__ rec, uint32_t N, uint32_t cell, const Moms& m)
 {
-    rec[cell] = m.s;
-    rec[(size_t)N + cell] = m.jx;
-    rec[2 * (size_t)N + cell] = m.jy;
-    rec[3 * (size_t)N + cell] = m.jz;
+    rec[cell] = T(m.s);
+    rec[(size_t)N + cell] = T(m.jx);
+    rec[2 * (size_t)N + cell] = T(m.jy);
+    rec[3 * (size_t)N + cell] = T(m.jz);
 }
 
-__device__ __forceinline__ Moms recorded_moments(const double* __restrict__ rec, uint32_t N, uint32_t cell)
+template <class T>
+__device__ __forceinline__ Moms recorded_moments(const T* __restrict__ rec, uint32_t N, uint32_t cell)
 {
-    return Moms{rec[cell], rec[(size_t)N + cell], rec[2 * (size_t)N + cell], rec[3 * (size_t)N + cell]};
+    return Moms{double(rec[cell]), double(rec[(size_t)N + cell]), double(rec[2 * (size_t)N + cell]),
+                double(rec[3 * (size_t)N + cell])};
 }
 
 // ---------------------------------------------------------------------------

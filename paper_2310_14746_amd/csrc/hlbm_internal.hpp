@@ -133,11 +133,13 @@ Launch cell_launch(const Params& p, int bx, int cells_per_thread = 1);
 // One sweep.  With diag_partials != NULL the diagnostic variant also writes
 // FP64 block partials of the totals (one 4-double record per block).
 // With moment_record != NULL (A/B, periodic or general faces, no diagnostics)
-// the sweep also writes each cell's FP64 pre-collision moments s, jx, jy, jz
-// as four rows of N doubles there (the reverse sweep's linearization point).
+// the sweep also writes each cell's pre-collision moments s, jx, jy, jz (the
+// reverse sweep's linearization point) there as four rows of N values of
+// adjoint_elem_bytes(storage) bytes (the FP64 sums, rounded to FP32 for the
+// forms other than FP64).
 hipError_t launch_sweep(int q, int storage, int bcmode, int pk, const Params& p, const void* src,
                         void* dst, const void* dfield, int bx, hipStream_t s,
-                        double* diag_partials = nullptr, double* moment_record = nullptr);
+                        double* diag_partials = nullptr, void* moment_record = nullptr);
 hipError_t launch_moments(int q, int storage, int bcmode, const Params& p, const void* src,
                           void* drho, void* u, int out_f64, double* partials, int bx,
                           hipStream_t s);
@@ -153,7 +155,7 @@ hipError_t launch_adjoint_seed(int q, int storage, int bcmode, const Params& p, 
 // sweep of launch_sweep wrote it.
 hipError_t launch_adjoint(int q, int storage, int bcmode, int pk, const Params& p, const void* lam_in,
                           void* lam_out, const void* dfield, double* dbar, int bx, hipStream_t s,
-                          const double* moment_record);
+                          const void* moment_record);
 // Fixed-order two-pass sum of `nblocks` partials of 4 doubles into out[4];
 // `stage` holds 4*REDUCE_STAGE doubles.
 constexpr uint32_t REDUCE_STAGE = 256;

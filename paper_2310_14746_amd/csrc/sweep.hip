@@ -28,7 +28,7 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
                                            const typename S::D* __restrict__ dfield, const Params& p,
                                            uint32_t x, uint32_t y, uint32_t z, typename S::R& drho,
                                            typename S::R& ux, typename S::R& uy, typename S::R& uz,
-                                           double* __restrict__ rec = nullptr)
+                                           AdjReal<S>* __restrict__ rec = nullptr)
 {
     using R = typename S::R;
     const uint32_t P = p.P;  // population rows, and the rows of a tensor control, are P elements apart
@@ -123,24 +123,31 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
     return solid;
 }
 
-// One cell of a sweep kernel on the row of block (blockIdx.y, blockIdx.z).
-// With walls or open faces (BC_GENERAL) the rows are taken in row_of order
-// (the rows that are not plain first), plain rows take gather_plain_row and
-// the others the general rule: the choice is uniform per block, and each path
+// The row (y, z) of this block: (blockIdx.y, blockIdx.z), or with walls or
+// open faces (BC_GENERAL) the row_of order (the rows that are not plain
+// first).
+template <int BC>
+__device__ __forceinline__ void block_row(const Params& p, int& y, int& z)
+{
+    y = (int)blockIdx.y;
+    z = (int)blockIdx.z;
+    if (BC == BC_GENERAL)
+        row_of((int)(blockIdx.y + gridDim.y * blockIdx.z), p.ny, p.nz, p.bc_lo[1], p.bc_hi[1], p.bc_lo[2],
+               p.bc_hi[2], y, z);
+}
+
+// One cell x < nx of a sweep kernel on row (y, z) (from block_row).  With
+// walls or open faces (BC_GENERAL) plain rows take gather_plain_row and the
+// others the general rule: the choice is uniform per block, and each path
 // keeps its own collision and stores.
 template <class L, class S, int BC, int PK, bool REC = false>
 __device__ __forceinline__ bool sweep_row_cell(const typename S::T* src, typename S::T* dst,
                                                const typename S::D* __restrict__ dfield, const Params& p,
-                                               uint32_t x, typename S::R& drho, typename S::R& ux,
+                                               uint32_t x, int y, int z, typename S::R& drho, typename S::R& ux,
                                                typename S::R& uy, typename S::R& uz,
-                                               double* __restrict__ rec = nullptr)
+                                               AdjReal<S>* __restrict__ rec = nullptr)
 {
-    if (BC != BC_GENERAL)
-        return sweep_cell<L, S, BC, PK, REC>(src, dst, dfield, p, x, blockIdx.y, blockIdx.z, drho, ux, uy, uz, rec);
-    int y, z;
-    row_of((int)(blockIdx.y + gridDim.y * blockIdx.z), p.ny, p.nz, p.bc_lo[1], p.bc_hi[1], p.bc_lo[2], p.bc_hi[2],
-           y, z);
-    if (plain_row(y, z, p.ny, p.nz, p.bc_lo[1], p.bc_hi[1], p.bc_lo[2], p.bc_hi[2]))
+    if (BC == BC_GENERAL && plain_row(y, z, p.ny, p.nz, p.bc_lo[1], p.bc_hi[1], p.bc_lo[2], p.bc_hi[2]))
         return sweep_cell<L, S, BC_PLAIN_ROW, PK, REC>(src, dst, dfield, p, x, (uint32_t)y, (uint32_t)z, drho, ux,
                                                        uy, uz, rec);
     return sweep_cell<L, S, BC, PK, REC>(src, dst, dfield, p, x, (uint32_t)y, (uint32_t)z, drho, ux, uy, uz, rec);
@@ -155,8 +162,10 @@ __global__ __launch_bounds__(1024) void sweep_kernel(const typename S::T* __rest
     using R = typename S::R;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)p.nx) return;
+    int y, z;
+    block_row<BC>(p, y, z);
     R drho, ux, uy, uz;
-    (void)sweep_row_cell<L, S, BC, PK>(src, dst, dfield, p, x, drho, ux, uy, uz);
+    (void)sweep_row_cell<L, S, BC, PK>(src, dst, dfield, p, x, y, z, drho, ux, uy, uz);
 }
 
 // The same sweep on a step that an adjoint tape records: it also writes each
@@ -165,13 +174,15 @@ template <class L, class S, int BC, int PK>
 __global__ __launch_bounds__(1024) void sweep_record_kernel(const typename S::T* __restrict__ src,
                                                              typename S::T* __restrict__ dst,
                                                              const typename S::D* __restrict__ dfield,
-                                                             double* __restrict__ rec, Params p)
+                                                             AdjReal<S>* __restrict__ rec, Params p)
 {
     using R = typename S::R;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)p.nx) return;
+    int y, z;
+    block_row<BC>(p, y, z);
     R drho, ux, uy, uz;
-    (void)sweep_row_cell<L, S, BC, PK, true>(src, dst, dfield, p, x, drho, ux, uy, uz, rec);
+    (void)sweep_row_cell<L, S, BC, PK, true>(src, dst, dfield, p, x, y, z, drho, ux, uy, uz, rec);
 }
 
 // In-place (AA) step: one buffer, even or odd mode.  Blocks of at most 256
@@ -202,10 +213,12 @@ __global__ __launch_bounds__(1024) void sweep_diag_kernel(const typename S::T* _
 {
     using R = typename S::R;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    int y, z;
+    block_row<BC>(p, y, z);
     double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
     if (x < (uint32_t)p.nx) {
         R drho, ux, uy, uz;
-        const bool solid = sweep_row_cell<L, S, BC, PK>(src, dst, dfield, p, x, drho, ux, uy, uz);
+        const bool solid = sweep_row_cell<L, S, BC, PK>(src, dst, dfield, p, x, y, z, drho, ux, uy, uz);
         const double rho = p.rho0 + (double)drho;
         m0 = sel(solid, 0.0, (double)drho);
         m1 = sel(solid, 0.0, rho * (double)ux);
@@ -214,10 +227,6 @@ __global__ __launch_bounds__(1024) void sweep_diag_kernel(const typename S::T* _
     }
     // the partial of the cells of row (y, z), x-block blockIdx.x, whatever
     // order the rows were taken in: the totals are summed in one order
-    int y = (int)blockIdx.y, z = (int)blockIdx.z;
-    if (BC == BC_GENERAL)
-        row_of((int)(blockIdx.y + gridDim.y * blockIdx.z), p.ny, p.nz, p.bc_lo[1], p.bc_hi[1], p.bc_lo[2],
-               p.bc_hi[2], y, z);
     const uint32_t bk = blockIdx.x + gridDim.x * ((uint32_t)y + gridDim.y * (uint32_t)z);
     block_sum4(m0, m1, m2, m3, partials + 4 * (size_t)bk);
 }
@@ -568,8 +577,9 @@ Launch cell_launch(const Params& p, int bx, int cells_per_thread)
 
 template <class L, class S, int PK>
 static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src, void* dst,
-                                    const void* dfield, int bx, hipStream_t s, double* diag, double* rec)
+                                    const void* dfield, int bx, hipStream_t s, double* diag, void* rec_v)
 {
+    auto* rec = static_cast<AdjReal<S>*>(rec_v);
     const Launch l = cell_launch(p, bx);
     auto* a = static_cast<const typename S::T*>(src);
     auto* b = static_cast<typename S::T*>(dst);
@@ -640,7 +650,7 @@ static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src
 template <class L, int PK>
 static hipError_t sweep_dispatch_store(int storage, int bcmode, const Params& p, const void* src,
                                        void* dst, const void* dfield, int bx, hipStream_t s,
-                                       double* diag, double* rec)
+                                       double* diag, void* rec)
 {
     switch (storage) {
     case StoreF64::code: return sweep_dispatch_bc<L, StoreF64, PK>(bcmode, p, src, dst, dfield, bx, s, diag, rec);
@@ -654,7 +664,7 @@ static hipError_t sweep_dispatch_store(int storage, int bcmode, const Params& p,
 
 hipError_t launch_sweep(int q, int storage, int bcmode, int pk, const Params& p, const void* src,
                         void* dst, const void* dfield, int bx, hipStream_t s, double* diag_partials,
-                        double* moment_record)
+                        void* moment_record)
 {
     if (q == 9 && pk == PK_SCALAR)
         return sweep_dispatch_store<D2Q9, PK_SCALAR>(storage, bcmode, p, src, dst, dfield, bx, s, diag_partials,

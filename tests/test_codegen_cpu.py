@@ -99,6 +99,7 @@ def test_no_private_memory_in_sweep_and_moments(asm):
                        **_kernels(asm, "_ZN4hlbm14adjoint_kernel"),
                        **_kernels(asm, "_ZN4hlbm17sweep_pair_kernel"),
                        **_kernels(asm, "_ZN4hlbm19sweep_record_kernel"),
+                       **_kernels(asm, "_ZN4hlbm17sweep_diag_kernel"),
                        **_kernels(asm, "_ZN4hlbm15sweep_aa_kernel"),
                        **_kernels(asm, "_ZN4hlbm20sweep_aa_diag_kernel"),
                        **_kernels(asm, "_ZN4hlbm19adjoint_seed_kernel"),

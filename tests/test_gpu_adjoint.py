@@ -411,6 +411,39 @@ def test_moment_record_tape_equals_replay(H, case, storage):
     assert np.any(out["moments"][0])
 
 
+def test_replay_tape_keeps_the_top_segment_record(H):
+    """A replayed tape: the forward steps of the tape's top segment (the one
+    holding step max_steps) write its moment record themselves, and a reverse
+    sweep from there replays only the segments below.  Gradients equal the
+    moment-record tape's bit for bit: with the top segment recorded whole or in
+    part, not reached, and after a reverse sweep whose replays overwrote its
+    set (the next call replays it)."""
+    shape, kw = (20, 10, 9), dict(tau=0.6, bc_lo=(2, 1, 1), bc_hi=(3, 1, 1), inlet_u=(0.02, 0, 0))
+    nx, ny, nz = shape
+    d = smooth_noise((nz, ny, nx), seed=21).ravel().astype(np.float32)
+    a, b = _cotangents(nx * ny * nz, 19, 5)
+    every, max_steps = 5, 23                      # top segment: steps 21 .. 23
+    for steps in (23, 21, 18):
+        say(f"replay tape, every {every}, max {max_steps}, {steps} forward steps")
+        out = {}
+        for kind in ("replay", "moments"):
+            sim = H.HLBM(19, "f32", shape, **kw)
+            try:
+                sim.set_porosity(d)
+                sim.set_tape_kind(kind)
+                sim.set_tape(every, max_steps)
+                sim.step(steps)
+                out[kind] = [sim.adjoint(steps, a, b).cpu().numpy(),
+                             sim.adjoint(steps, a, b).cpu().numpy(),
+                             sim.adjoint(min(steps, 4), a, b).cpu().numpy()]
+            finally:
+                sim.close()
+        for g_replay, g_moments in zip(out["replay"], out["moments"]):
+            assert np.array_equal(g_replay, g_moments)
+        assert np.array_equal(out["replay"][0], out["replay"][1])
+        assert np.any(out["replay"][0])
+
+
 def test_moment_record_tape_equals_replay_tensor(H):
     """The same for the tensor control (six gradient rows), FP32, channel with
     walls and open faces."""
@@ -454,9 +487,10 @@ def test_tape_kind_rules(H):
         info = sim.tape_info()
         assert info["recorded"] == 0 and info["every"] == 4 and info["max_steps"] == 10
         n = int(np.prod(shape))
-        # 3 checkpoints, no replay states, two FP32 adjoint buffers, 10 steps of 4 FP64 rows
-        assert info["device_bytes"] == 3 * sim.pop_bytes + 2 * 19 * n * 4 + 10 * 4 * n * 8
-        assert replay_bytes == (3 + 4) * sim.pop_bytes + 2 * 19 * n * 4 + 2 * 4 * 4 * n * 8
+        # 3 checkpoints, no replay states, two FP32 adjoint buffers, 10 steps of 4
+        # FP32 rows (the record takes the adjoint's precision)
+        assert info["device_bytes"] == 3 * sim.pop_bytes + 2 * 19 * n * 4 + 10 * 4 * n * 4
+        assert replay_bytes == (3 + 4) * sim.pop_bytes + 2 * 19 * n * 4 + 2 * 4 * 4 * n * 4
         sim.step(10)
         with pytest.raises(H.HLBMError):
             sim.step(1)                         # past max_steps

@@ -110,9 +110,9 @@ def test_padded_rows_adjoint_equal_dense(H, storage):
             sim.set_tape(6, 30)
             pitch = n + pad // elem
             # 6 checkpoints + 4 replay states, two FP32 adjoint buffers, two moment
-            # records of 6 steps (4 FP64 rows of n cells each, dense)
+            # records of 6 steps (4 FP32 rows of n cells each, dense)
             assert sim.tape_info()["device_bytes"] == (10 * 19 * pitch * elem + 2 * 19 * pitch * 4
-                                                       + 2 * 6 * 4 * n * 8)
+                                                       + 2 * 6 * 4 * n * 4)
             sim.step(30)
             grads.append(sim.adjoint(30, a, b).cpu().numpy())
         finally:
