@@ -74,6 +74,31 @@ def test_walls_and_open_faces(H, storage, shape, lo, hi, inu, F, steps):
     assert (dr[~fluid] == 0).all() and (u[:, ~fluid] == 0).all()
 
 
+@pytest.mark.parametrize("storage,shape,lo,hi,inu,F,steps", [
+    ("f64", (70, 20, 1), (2, 1, 0), (3, 1, 0), (0.02, 0, 0), (0, 0, 0), 80),   # D2Q9 channel with open ends
+    ("f32", (66, 17, 1), (1, 2, 0), (1, 3, 0), (0, 0.01, 0), (1e-5, 0, 0), 60),  # x walls, open y faces
+])
+def test_d2q9_walls_and_open_faces(H, storage, shape, lo, hi, inu, F, steps):
+    """D2Q9 with open faces: the plain rows' x-end fix (open x faces) and the
+    x-wall bounce-back fix with open faces on the rows next to them."""
+    nx, ny, nz = shape
+    say(f"D2Q9 {storage} {shape} lo={lo} hi={hi} inlet={inu} {steps} steps")
+    dt = "f64" if storage == "f64" else "f32"
+    d = inputs.round_to(smooth_noise((nz, ny, nx), seed=nx + ny), dt).ravel()
+    kw = dict(tau=0.7, force=F, bc_lo=lo, bc_hi=hi, inlet_u=inu, outlet_rho=1.0)
+    dr, u, tot, _ = gpu_run(H, 9, storage, shape, d.astype(np.float64 if dt == "f64" else np.float32),
+                            steps, **kw)
+    cfg = OracleConfig(q=9, nx=nx, ny=ny, nz=nz, tau=0.7, force=F, bc_lo=lo, bc_hi=hi,
+                       inlet_u=inu, outlet_rho=1.0)
+    g = oracle.run(cfg, d, steps, nthreads=NT)
+    dr_o, u_o = oracle.observe(cfg, g)
+    fluid = ~cfg.solid_mask().ravel()
+    eu, er = rel_l2_u(u, u_o, fluid), rel_l2_drho(dr, dr_o, u_o, fluid)
+    say(f"rel-L2 u {eu:.2e} drho {er:.2e}")
+    assert eu <= TOL[storage] and er <= TOL[storage]
+    assert (dr[~fluid] == 0).all() and (u[:, ~fluid] == 0).all()
+
+
 def test_in_sweep_diagnostics_equal_moment_totals(H):
     """Totals reduced inside the sweep equal hlbm_moments' totals at the same
     time level bit for bit; FP64 mass stays at rounding level; the log drops
