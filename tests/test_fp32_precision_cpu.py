@@ -1,0 +1,126 @@
+"""Why the FP32 form sums its moments in FP64 (CPU only).
+
+A plain float32 emulation (numpy) of the homogenized BGK step -- pull with
+periodic wrap, moments, porosity shift, second-order equilibrium, relaxation
+and Guo source (Sec. 3.2), every operation in FP32 -- on the sphere-array tile
+(32^3, tau = 0.6, F = 1e-6 along x, 200 steps), compared with the FP64 oracle:
+
+* with FP32 moment sums the error in u is already above 1.5e-6 at 200 steps
+  (3.2e-6), and it keeps growing: the same emulation gives 9.8e-6 at 400 steps
+  and 1.7e-5 at 800, past the 1e-5 bar of the FP32 form;
+* summing the same moments in FP64, all else FP32, cuts it by more than half;
+* FP32 weights adjusted so that their exact sum is one do not help: the error
+  is not a bias of the weights' sum.
+
+The GPU form therefore keeps the FP64 moment sums and the balance-law
+correction of the relaxed populations (which this emulation leaves out).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleConfig
+from paper_2310_14746_amd import inputs
+
+F32 = np.float32
+C = np.array([(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+              (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
+              (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)])
+STEPS, TAU, FORCE = 200, 0.6, (1e-6, 0.0, 0.0)
+
+
+def _weights(exact_sum):
+    """D3Q19 weights in FP32: the nearest values of 1/3, 1/18, 1/36, or FP32
+    values near them with w1 = 2 w2 and w0 = 1 - 24 w2 exactly."""
+    from fractions import Fraction
+    if not exact_sum:
+        w0, w1, w2 = F32(1 / 3), F32(1 / 18), F32(1 / 36)
+    else:
+        v = F32(1 / 36)
+        while True:
+            w2f = Fraction(float(v))
+            w0f = 1 - 24 * w2f
+            if Fraction(float(F32(float(w0f)))) == w0f:
+                break
+            v = np.nextafter(v, F32(0), dtype=F32)
+        w2, w1, w0 = v, F32(2 * float(v)), F32(float(w0f))
+        assert Fraction(float(w0)) + 6 * Fraction(float(w1)) + 12 * Fraction(float(w2)) == 1
+    return np.array([w0] + [w1] * 6 + [w2] * 12, dtype=F32)
+
+
+def _pull(g):
+    for i in range(19):
+        g[i] = np.roll(g[i], shift=(C[i, 2], C[i, 1], C[i, 0]), axis=(0, 1, 2))
+
+
+def _emulate(d, f64_sums=False, exact_sum_weights=False):
+    """Shifted populations g = f - w rho0 (rho0 = 1), arrays [i][z][y][x]."""
+    n = d.shape[0]
+    w = _weights(exact_sum_weights)
+    g = np.zeros((19, n, n, n), dtype=F32)
+    dd = d.astype(F32)
+    om, pref = F32(1 / TAU), F32(1 - 0.5 / TAU)
+    F = [F32(v) for v in FORCE]
+    for _ in range(STEPS):
+        _pull(g)
+        if f64_sums:
+            gd = g.astype(np.float64)
+            s = gd.sum(0)
+            j = [(C[:, a, None, None, None] * gd).sum(0) for a in range(3)]
+            rho = 1.0 + s
+            u = [((j[a] + 0.5 * float(F[a])) / rho).astype(F32) for a in range(3)]
+            s, rho = s.astype(F32), rho.astype(F32)
+        else:
+            s = np.zeros_like(g[0])
+            j = [np.zeros_like(g[0]) for _ in range(3)]
+            for i in range(19):
+                s = s + g[i]
+                for a in range(3):
+                    if C[i, a]:
+                        j[a] = j[a] + g[i] if C[i, a] > 0 else j[a] - g[i]
+            rho = F32(1) + s
+            inv = F32(1) / rho
+            u = [(j[a] + F32(0.5) * F[a]) * inv for a in range(3)]
+        shift = F32(1) - dd
+        e = [shift * u[a] for a in range(3)]
+        uu = e[0] * e[0] + e[1] * e[1] + e[2] * e[2]
+        uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2]
+        base = s - F32(1.5) * rho * uu
+        for i in range(19):
+            c = [F32(v) for v in C[i]]
+            ce = c[0] * e[0] + c[1] * e[1] + c[2] * e[2]
+            cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2]
+            cF = c[0] * F[0] + c[1] * F[1] + c[2] * F[2]
+            geq = w[i] * (base + rho * (F32(3) * ce + F32(4.5) * ce * ce))
+            src = pref * w[i] * (F32(3) * (cF - uF) + F32(9) * cu * cF)
+            g[i] = g[i] + (src - om * (g[i] - geq))
+    _pull(g)
+    gd = g.astype(np.float64)
+    s = gd.sum(0)
+    u = np.stack([((C[:, a, None, None, None] * gd).sum(0) + 0.5 * FORCE[a]) / (1 + s) for a in range(3)])
+    return s, u
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def reference():
+    tile = inputs.round_to(inputs.sphere_array_tile(), "f32")
+    cfg = OracleConfig(q=19, nx=32, ny=32, nz=32, tau=TAU, force=FORCE)
+    dr, u = oracle.observe(cfg, oracle.run(cfg, tile.ravel(), STEPS, nthreads=4), nthreads=4)
+    return tile, dr.reshape(32, 32, 32), u.reshape(3, 32, 32, 32)
+
+
+def test_fp32_sums_need_fp64(reference):
+    tile, dr_o, u_o = reference
+    s32, u32 = _emulate(tile)
+    s64, u64 = _emulate(tile, f64_sums=True)
+    sx, ux = _emulate(tile, exact_sum_weights=True)
+    e32, e64, ex = _rel(u32, u_o), _rel(u64, u_o), _rel(ux, u_o)
+    print(f"u rel-L2 at {STEPS} steps: FP32 sums {e32:.2e}, FP64 sums {e64:.2e}, "
+          f"exact-sum weights {ex:.2e}; drho {_rel(s32, dr_o):.2e} / {_rel(s64, dr_o):.2e} / {_rel(sx, dr_o):.2e}")
+    assert e32 > 1.5e-6
+    assert e64 < 0.5 * e32
+    assert ex > e64
