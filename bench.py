@@ -245,6 +245,62 @@ def summarize_profile(path):
     return "\n".join(out)
 
 
+def summarize_backward(path, steps=500):
+    """Timeline of the last replayed backward pass of the differentiation
+    workload (128x64x64) in a rocprofv3 --kernel-trace CSV under `path`: the span from its
+    first to its last reverse step, the reverse steps and replay sweeps inside
+    it, how long the GPU had a kernel running, and how many reverse steps ran
+    beside a replay sweep (the two streams overlapping)."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(path, "**", "*kernel_trace.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            grid = tuple(int(r[k]) for k in ("Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z"))
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"].split("(")[0],
+                         int(r["Queue_Id"]), grid))
+    rows.sort()
+    c4 = (128, 64, 64)
+    rev = [r for r in rows if "adjoint_kernel<" in r[2] and r[4] == c4]
+    if len(rev) < steps:
+        return f"fewer than {steps} reverse steps on 128x64x64 in the trace"
+    # backward passes: consecutive runs of `steps` reverse steps; the last one
+    # with replay sweeps inside its span (a moment-record pass has none)
+    recs = [r for r in rows if "sweep_record_kernel<" in r[2] and r[4] == c4]
+    last = None
+    for k in range(len(rev) // steps):
+        chunk = rev[k * steps:(k + 1) * steps]
+        a, b = chunk[0][0], max(r[1] for r in chunk)
+        if any(r[0] >= a and r[1] <= b for r in recs):
+            last = chunk
+    if last is None:
+        return "no replayed backward pass on 128x64x64 in the trace"
+    t0, t1 = last[0][0], max(r[1] for r in last)
+    inside = [r for r in rows if r[0] >= t0 and r[1] <= t1]
+    rec = [r for r in inside if "sweep_record_kernel<" in r[2] and r[4] == c4]
+    iv = sorted((r[0], r[1]) for r in inside)
+    busy, (cs, ce) = 0, iv[0]
+    for a, b in iv[1:]:
+        if a > ce:
+            busy, cs, ce = busy + ce - cs, a, b
+        else:
+            ce = max(ce, b)
+    busy += ce - cs
+    beside = sum(1 for a in last if any(r[0] < a[1] and r[1] > a[0] for r in rec))
+    def mean_us(v):
+        return sum(r[1] - r[0] for r in v) / max(1, len(v)) / 1e3
+    out = ["| quantity | value |", "|---|---|",
+           f"| span of the reverse steps (first start to last end) | {(t1 - t0) / 1e6:.2f} ms |",
+           f"| reverse steps / mean duration | {len(last)} / {mean_us(last):.1f} us |",
+           f"| replay sweeps inside the span / mean duration | {len(rec)} / {mean_us(rec):.1f} us |",
+           f"| sum of those kernels' durations | {(sum(r[1] - r[0] for r in last) + sum(r[1] - r[0] for r in rec)) / 1e6:.2f} ms |",
+           f"| time with a kernel running | {busy / 1e6:.2f} ms |",
+           f"| reverse steps that ran beside a replay sweep | {beside} of {len(last)} |",
+           f"| queues of the reverse steps / replay sweeps | {sorted(set(r[3] for r in last))} / "
+           f"{sorted(set(r[3] for r in rec))} |"]
+    return "\n".join(out)
+
+
 def sweep_sources_sha256():
     h = hashlib.sha256()
     for f in SWEEP_SRCS:
@@ -751,11 +807,16 @@ def main():
     ap.add_argument("--summarize-counters-all", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="per-kernel HBM traffic against algorithmic bytes from two rocprofv3 --pmc runs "
                          "(the batched step count of those runs: --batched-steps)")
+    ap.add_argument("--summarize-backward", metavar="DIR",
+                    help="timeline of the last replayed backward pass in a rocprofv3 kernel trace, then exit")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="print a per-kernel summary of a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
     if args.summarize_profile:
         print(summarize_profile(args.summarize_profile))
+        return
+    if args.summarize_backward:
+        print(summarize_backward(args.summarize_backward))
         return
     if args.summarize_counters:
         print(summarize_counters(*args.summarize_counters))
