@@ -444,19 +444,8 @@ __device__ __forceinline__ void adjoint_cell(const LamT<S>* __restrict__ lam_in,
     }
 }
 
-// Waves per SIMD that a reverse step kernel asks the register allocator for:
-// in FP32 arithmetic with walls or open faces, 6 (5 with the tensor control's
-// six rows), which fit without spilling to scratch.  Otherwise, and in FP64:
-// no request.
-template <class S, int BC, int PK>
-struct AdjWaves {
-    static constexpr int value =
-        (std::is_same<S, StoreF64>::value || BC == BC_PERIODIC) ? 1 : (PK == PK_TENSOR ? 5 : 6);
-};
-
 template <class L, class S, int BC, int PK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjWaves<S, BC, PK>::value))) void
-adjoint_kernel(const LamT<S>* __restrict__ lam_in,
+__global__ __launch_bounds__(256) void adjoint_kernel(const LamT<S>* __restrict__ lam_in,
                                                        LamT<S>* __restrict__ lam_out,
                                                        const LamT<S>* __restrict__ rec,
                                                        const typename S::D* __restrict__ dfield,
