@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -301,10 +302,20 @@ def summarize_backward(path, steps=500):
     return "\n".join(out)
 
 
-def sweep_sources_sha256():
+def _code_only(text):
+    """Source text without comments and with whitespace collapsed: an edit of
+    a comment does not change the kernel the counters were taken on."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def sweep_sources_sha256(texts=None):
+    """Hash of the sweep's sources (comments stripped): the committed counter
+    record carries it, and bench reports `traffic` only while it matches."""
     h = hashlib.sha256()
-    for f in SWEEP_SRCS:
-        h.update(open(f, "rb").read())
+    for t in (texts if texts is not None else [open(f).read() for f in SWEEP_SRCS]):
+        h.update(_code_only(t).encode())
     return h.hexdigest()
 
 

@@ -84,8 +84,8 @@ struct hlbm_ctx {
     int batch_bpc;       // resident blocks per CU of the persistent kernel
     int max_blocks_per_cu;  // resident blocks of the persistent kernel that fit
     // adjoint tape (hlbm_set_tape): checkpoints of the state every `every`
-    // steps since step `tape_origin`, a replay segment and two FP64 adjoint
-    // population buffers
+    // steps since step `tape_origin`, replay states and segment records, and
+    // two adjoint population buffers (FP64 for the FP64 form, FP32 otherwise)
     int tape_every;
     int tape_max;
     long long tape_origin;
@@ -100,9 +100,10 @@ struct hlbm_ctx {
     // says that the set holds them from the segment's first step on.
     bool tape_top_valid;
     char* tape_lam[2];
-    // HLBM_TAPE_MOMENTS: every recorded step also writes the FP64 pre-collision
-    // moments of each cell (4 rows of N doubles per step), and the reverse
-    // sweep reads them instead of replaying segments (no replay states)
+    // HLBM_TAPE_MOMENTS: every recorded step also writes the pre-collision
+    // moments of each cell (4 rows of N values in the adjoint's precision per
+    // step), and the reverse sweep reads them instead of replaying segments
+    // (no replay states)
     int tape_kind;
     char* tape_rec;
     // The reverse sweep replays the segment below the current one on a second

@@ -639,9 +639,7 @@ static hipError_t sweep_dispatch_bc(int bcmode, const Params& p, const void* src
         }
         hipLaunchKernelGGL((sweep_kernel<L, S, BC_PERIODIC, PK>), l.grid, l.block, 0, s, a, b, d, p);
     } else {
-        // (the interior/shell split that the adjoint uses does not pay here:
-        // the general gather costs the forward sweep little, and the shell's
-        // cells at the row ends load poorly coalesced)
+        // walls or open faces: plain rows and the general rule, chosen per row
         hipLaunchKernelGGL((sweep_kernel<L, S, BC_GENERAL, PK>), l.grid, l.block, 0, s, a, b, d, p);
     }
     return hipGetLastError();
