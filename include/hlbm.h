@@ -339,8 +339,10 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * bytes each, R as above), plus two adjoint buffers of Q rows of P values (P = N +
  * row_pad_bytes divided by the storage's element size, the population row
  * pitch; 8 bytes each for HLBM_F64, else 4).  every = 0
- * frees the tape.  hlbm_step returns EINVAL (and does nothing) if it would
- * take the recorded steps past max_steps.  Waits for the stream. */
+ * frees the tape.  EUNSUPPORTED if one adjoint population row (N values of
+ * 8 bytes for HLBM_F64, else 4) would reach 4 GiB.  hlbm_step returns EINVAL
+ * (and does nothing) if it would take the recorded steps past max_steps.
+ * Waits for the stream. */
 int hlbm_set_tape(hlbm_ctx *ctx, int every, int max_steps);
 
 /* What the tape keeps for the reverse sweep.

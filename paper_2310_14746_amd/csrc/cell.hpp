@@ -19,7 +19,8 @@ namespace hlbm {
 // Element `idx` of a population row addressed by a 32-bit byte offset from a
 // uniform base.  The host guarantees N * sizeof(T) < 2^32 for the rows these
 // helpers index: populations in their storage type, porosity rows (never wider
-// than the storage element) and adjoint population rows.  The offset cannot
+// than the storage element), and adjoint population rows and moment record
+// rows (the adjoint's element type, checked when a tape is set).  The offset cannot
 // wrap, and every access can use the scalar-base + 32-bit vector-offset form
 // of global loads and stores.  Per-cell arrays that may be wider (the link
 // mask under 16-bit storage, the adjoint's FP64 cotangents and gradient, FP64
@@ -156,9 +157,17 @@ __device__ __forceinline__ void collide_plain(R (&g)[L::Q], const Shift& shift, 
     uz_out = uz;
 }
 
+// FP64 moments of the pre-collision populations gathered at one cell:
+// s = sum g*, j = sum c g*, summed in population order.  The adjoint
+// linearizes the collision at them; the forward sweep can record them.
+struct Moms {
+    double s, jx, jy, jz;
+};
+
 template <class L, class R, class Shift, bool Exact = true>
 __device__ __forceinline__ void collide(R (&g)[L::Q], const Shift& shift, R F0, R F1, R F2, R rho0,
-                                        R omega, R pref, R& drho_out, R& ux_out, R& uy_out, R& uz_out)
+                                        R omega, R pref, R& drho_out, R& ux_out, R& uy_out, R& uz_out,
+                                        Moms* sums = nullptr)
 {
     if constexpr (!Exact) {
         collide_plain<L, R, Shift>(g, shift, F0, F1, F2, rho0, omega, pref, drho_out, ux_out, uy_out,
@@ -228,6 +237,9 @@ __device__ __forceinline__ void collide(R (&g)[L::Q], const Shift& shift, R F0, 
     ux_out = ux;
     uy_out = uy;
     uz_out = uz;
+    // the FP64 pre-collision moment sums, as moments_f64 forms them (the
+    // same sums in the same order)
+    if (sums) *sums = Moms{s, jx, jy, jz};
 }
 
 // Moments only (no collision), same definitions as in collide().
@@ -269,12 +281,6 @@ __device__ __forceinline__ void moments_of(const R (&g)[L::Q], R F0, R F1, R F2,
     uz = R((jz + 0.5 * (double)F2) * inv_rho);
 }
 
-// FP64 moments of the pre-collision populations gathered at one cell:
-// s = sum g*, j = sum c g*, summed in population order.  The adjoint
-// linearizes the collision at them; the forward sweep can record them.
-struct Moms {
-    double s, jx, jy, jz;
-};
 
 template <class L, class R>
 __device__ __forceinline__ Moms moments_f64(const R (&g)[L::Q])
@@ -299,21 +305,31 @@ using AdjReal = typename std::conditional<std::is_same<S, StoreF64>::value, doub
 
 // Moment record of one forward step: four rows of N values in the adjoint's
 // precision T (s, jx, jy, jz, rounded from the FP64 sums; cell index
-// x + nx(y + ny z)); rows can pass 4 GiB together: 64-bit offsets.
+// x + nx(y + ny z)).  The four rows together can pass 4 GiB, one row cannot
+// (it has the element type and length of an adjoint population row, which
+// hlbm_set_tape bounds): each row's start is formed in 64 bits and the cell's
+// offset within it in 32.
 template <class T>
 __device__ __forceinline__ void record_moments(T* __restrict__ rec, uint32_t N, uint32_t cell, const Moms& m)
 {
-    rec[cell] = T(m.s);
-    rec[(size_t)N + cell] = T(m.jx);
-    rec[2 * (size_t)N + cell] = T(m.jy);
-    rec[3 * (size_t)N + cell] = T(m.jz);
+    const double v[4] = {m.s, m.jx, m.jy, m.jz};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        T* const row = rec + (size_t)k * N;
+        st(row, cell, T(v[k]));
+    }
 }
 
 template <class T>
 __device__ __forceinline__ Moms recorded_moments(const T* __restrict__ rec, uint32_t N, uint32_t cell)
 {
-    return Moms{double(rec[cell]), double(rec[(size_t)N + cell]), double(rec[2 * (size_t)N + cell]),
-                double(rec[3 * (size_t)N + cell])};
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const T* const row = rec + (size_t)k * N;
+        v[k] = double(ld(row, cell));
+    }
+    return Moms{v[0], v[1], v[2], v[3]};
 }
 
 // ---------------------------------------------------------------------------

@@ -67,11 +67,16 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
         solid = in_wall_layer(b, (int)x, (int)y, (int)z);
     }
     // REC: the FP64 moments of the pulled populations, which the reverse
-    // sweep linearizes the collision at, into this step's moment record
-    if (REC) record_moments(rec, p.N, cell, moments_f64<L, R>(g));
+    // sweep linearizes the collision at, into this step's moment record.  The
+    // forms with FP64 moment sums take them from the collision (the same sums);
+    // the others sum them here.
+    Moms sums;
+    Moms* const want = (REC && S::exact_moments) ? &sums : nullptr;
+    if (REC && !S::exact_moments) record_moments(rec, p.N, cell, moments_f64<L, R>(g));
     if (PK == PK_SCALAR) {
         const ScalarShift<R> sh{S::load_d(ld(dfield, cell))};
-        collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+        collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz,
+                                                      want);
     } else {
         // six rows xx, yy, zz, xy, xz, yz of the symmetric control D
         // (rows P apart, like the population rows)
@@ -81,8 +86,10 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
                                 S::load_d(ld(dfield + 3 * (size_t)P, cell)),
                                 S::load_d(ld(dfield + 4 * (size_t)P, cell)),
                                 S::load_d(ld(dfield + 5 * (size_t)P, cell))};
-        collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz);
+        collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz,
+                                                      want);
     }
+    if (REC && S::exact_moments) record_moments(rec, p.N, cell, sums);
     // The in-place steps use plain stores: the lines they write were read into
     // L2 by the same step, and there the non-temporal hint cost about 3% (FP32,
     // 512^3) where in the two-buffer sweep it gains about 2%.
