@@ -622,11 +622,12 @@ def time_gradient(hlbm, steps=500, every=50, seed=0, reps=4, kind="replay"):
         bwd = float(np.median([b for _, b in times]))
         grad = d.grad.detach().cpu().numpy()
         # a reverse step reads the 16-byte moment record of its forward step;
-        # the replayed tape recomputes the steps below the top segment from the
-        # checkpoints with the recording sweep (156 + 16 bytes per cell), and
-        # the forward steps of the top segment wrote its record themselves
+        # the replayed tape recomputes the steps below the top two segments
+        # from the checkpoints with the recording sweep (156 + 16 bytes per
+        # cell), and the forward steps of the top two segments wrote their
+        # records themselves
         adj = ADJ_BYTES_REC
-        replays = steps - every if kind == "replay" else 0
+        replays = max(0, (steps - 1) // every - 1) * every if kind == "replay" else 0
         moved = cells * (steps * adj + replays * REC_SWEEP_BYTES)
         tape = sim.tape_info()["device_bytes"]
     finally:

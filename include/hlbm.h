@@ -319,10 +319,11 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * replay of the segment below runs on a second stream of the library's own
  * (default priority) while the reverse steps of the current segment run on
  * the context's stream; events order the two, and hlbm_adjoint_step waits
- * for both before it returns.  The forward steps of the tape's top segment
- * (the one that holds step max_steps) write that segment's record
- * themselves, so that a reverse sweep starting there replays only the
- * segments below it.  (HLBM_TAPE_MOMENTS records the moments of every forward
+ * for both before it returns.  The forward steps of the tape's top two
+ * segments (the one that holds step max_steps and the one below it) write
+ * those segments' records themselves, so that a reverse sweep replays only
+ * the segments below them.  A call that replays into a kept record's set
+ * overwrites it; a later call replays that segment too.  (HLBM_TAPE_MOMENTS records the moments of every forward
  * step instead.)  The tape
  * records from the state current when it is set and restarts at the current
  * state whenever the state or the porosity changes otherwise (hlbm_set_state,

@@ -94,11 +94,12 @@ struct hlbm_ctx {
     char* tape_seg;      // replay states: two sets (segments alternate between them) of two
                          // population buffers (the replay's sweeps alternate between them)
     char* tape_segrec;   // the replay's moment records: two sets of `every` steps of 4 rows of N
-    // The forward steps of the tape's top segment (the one holding step
-    // max_steps) also write their moment record, into that segment's set, so
-    // that a reverse sweep from there needs no replay of it: tape_top_valid
-    // says that the set holds them from the segment's first step on.
-    bool tape_top_valid;
+    // The forward steps of the tape's top two segments (the one holding step
+    // max_steps and the one below it, one in each set) also write their moment
+    // records, into their sets, so that a reverse sweep needs no replay of
+    // them: tape_kept[k] says that set k holds the record of its segment
+    // (kept_segment) from the segment's first step on.
+    bool tape_kept[2];
     char* tape_lam[2];
     // HLBM_TAPE_MOMENTS: every recorded step also writes the pre-collision
     // moments of each cell (4 rows of N values in the adjoint's precision per
@@ -389,6 +390,14 @@ size_t record_step_bytes(const hlbm_ctx* c)
     return 4 * (size_t)c->p.N * hlbm::adjoint_elem_bytes(c->cfg.storage);
 }
 
+// The segment whose record the forward steps keep in replay set k: the
+// highest segment of parity k up to the top one, -1 if there is none.
+static long long kept_segment(const hlbm_ctx* c, int k)
+{
+    const long long mtop = (c->tape_max - 1) / c->tape_every;
+    return ((mtop & 1) == k) ? mtop : mtop - 1;
+}
+
 // Bytes of a moment record of `steps` steps.
 size_t tape_record_bytes(const hlbm_ctx* c, int steps) { return (size_t)steps * record_step_bytes(c); }
 
@@ -397,7 +406,7 @@ int tape_restart(hlbm_ctx* c)
 {
     if (!c->tape_every) return HLBM_OK;
     c->tape_origin = c->step;
-    c->tape_top_valid = false;
+    c->tape_kept[0] = c->tape_kept[1] = false;
     hipError_t e = hipMemcpyAsync(c->tape_cps, c->pop[c->cur], c->pop_bytes, hipMemcpyDeviceToDevice,
                                   c->stream);
     if (e != hipSuccess) return hip_fail(e, "tape checkpoint");
@@ -722,13 +731,14 @@ int hlbm_step(hlbm_ctx* c, int nsteps)
             if (c->tape_rec) {
                 mrec = c->tape_rec + (size_t)rel * record_step_bytes(c);
             } else if (c->tape_segrec) {
-                // forward step rel + 1 of the top segment: its moment record,
-                // as the replay would write it (record j = step mtop K + j + 1)
-                const long long K = c->tape_every, mtop = (c->tape_max - 1) / K;
-                if (rel >= mtop * K) {
-                    mrec = c->tape_segrec + ((size_t)(mtop & 1) * (size_t)K + (size_t)(rel - mtop * K)) *
-                                                record_step_bytes(c);
-                    if (rel == mtop * K) c->tape_top_valid = true;
+                // forward step rel + 1 of segment m, one of the top two: its
+                // moment record, as the replay would write it (record j = step
+                // mK + j + 1)
+                const long long K = c->tape_every, m = rel / K;
+                const int k = (int)(m & 1);
+                if (m == kept_segment(c, k)) {
+                    mrec = c->tape_segrec + ((size_t)k * (size_t)K + (size_t)(rel - m * K)) * record_step_bytes(c);
+                    if (rel == m * K) c->tape_kept[k] = true;
                 }
             }
         }
@@ -1159,6 +1169,10 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
         auto thi_of = [&](long long m) { return (R0 < m * K + K) ? R0 : m * K + K; };
         auto replay = [&](long long m) -> hipError_t {
             const int k = (int)(m & 1);
+            // a segment the forward steps kept needs no replay (its record
+            // holds steps mK + 1 .. min(R0, mK + K), all that this call reads)
+            if (c->tape_kept[k] && m == kept_segment(c, k)) return hipEventRecord(c->replayed[k], c->stream);
+            c->tape_kept[k] = false;  // the replay overwrites the kept record
             hipError_t r = hipStreamWaitEvent(c->tape_stream, c->consumed[k], 0);
             const long long jn = thi_of(m) - m * K;
             for (long long j = 0; j < jn && r == hipSuccess; ++j) {
@@ -1175,12 +1189,7 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
         // queued so far (the forward steps that wrote the checkpoints)
         for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventRecord(c->consumed[k], c->stream);
         const long long mhi = (R0 - 1) / K, mlo = tlo / K;
-        // the top segment's record, if the forward steps wrote it, needs no
-        // replay (it holds steps mtop K + 1 .. R0, which is all this call reads)
-        const long long mtop = (c->tape_max - 1) / K;
-        const bool top_recorded = c->tape_top_valid && mhi == mtop;
-        if (e == hipSuccess)
-            e = top_recorded ? hipEventRecord(c->replayed[mhi & 1], c->stream) : replay(mhi);
+        if (e == hipSuccess) e = replay(mhi);
         for (long long m = mhi; e == hipSuccess && m >= mlo; --m) {
             // the segment below replays while this one's reverse steps run
             if (m - 1 >= mlo) e = replay(m - 1);
@@ -1194,8 +1203,6 @@ int hlbm_adjoint_step(hlbm_ctx* c, int nsteps, const double* dJ_drho, const doub
             }
             if (e == hipSuccess) e = hipEventRecord(c->consumed[m & 1], c->stream);
         }
-        // a replay into the top segment's set from another segment overwrote it
-        if (mlo <= mtop - 2) c->tape_top_valid = false;
     }
     if (e == hipSuccess && tmp)
         e = hipMemcpyAsync(dJ_dd, gd, rows * n * sizeof(double), hipMemcpyDeviceToHost, c->stream);

@@ -411,19 +411,20 @@ def test_moment_record_tape_equals_replay(H, case, storage):
     assert np.any(out["moments"][0])
 
 
-def test_replay_tape_keeps_the_top_segment_record(H):
-    """A replayed tape: the forward steps of the tape's top segment (the one
-    holding step max_steps) write its moment record themselves, and a reverse
-    sweep from there replays only the segments below.  Gradients equal the
-    moment-record tape's bit for bit: with the top segment recorded whole or in
-    part, not reached, and after a reverse sweep whose replays overwrote its
-    set (the next call replays it)."""
+def test_replay_tape_keeps_the_top_segment_records(H):
+    """A replayed tape: the forward steps of the tape's top two segments (the
+    one holding step max_steps and the one below it) write their moment
+    records themselves, and a reverse sweep replays only the segments below
+    them.  Gradients equal the moment-record tape's bit for bit: with the top
+    segment recorded whole or in part, the one below it whole, in part or not
+    reached, and after a reverse sweep whose replays overwrote both sets (the
+    next call replays them)."""
     shape, kw = (20, 10, 9), dict(tau=0.6, bc_lo=(2, 1, 1), bc_hi=(3, 1, 1), inlet_u=(0.02, 0, 0))
     nx, ny, nz = shape
     d = smooth_noise((nz, ny, nx), seed=21).ravel().astype(np.float32)
     a, b = _cotangents(nx * ny * nz, 19, 5)
-    every, max_steps = 5, 23                      # top segment: steps 21 .. 23
-    for steps in (23, 21, 18):
+    every, max_steps = 5, 23                      # top segments: steps 16 .. 20 and 21 .. 23
+    for steps in (23, 21, 20, 18, 14):
         say(f"replay tape, every {every}, max {max_steps}, {steps} forward steps")
         out = {}
         for kind in ("replay", "moments"):
@@ -442,6 +443,26 @@ def test_replay_tape_keeps_the_top_segment_record(H):
             assert np.array_equal(g_replay, g_moments)
         assert np.array_equal(out["replay"][0], out["replay"][1])
         assert np.any(out["replay"][0])
+    # forward steps after a reverse sweep: 18 steps, a reverse sweep over the
+    # kept steps 16 .. 18 only (no replay), 5 more forward steps into both
+    # kept segments, then reverse sweeps over all 23 and over 7
+    say("replay tape, every 5, max 23: forward 18, reverse 3, forward 5, reverse 23 and 7")
+    out = {}
+    for kind in ("replay", "moments"):
+        sim = H.HLBM(19, "f32", shape, **kw)
+        try:
+            sim.set_porosity(d)
+            sim.set_tape_kind(kind)
+            sim.set_tape(every, max_steps)
+            sim.step(18)
+            g3 = sim.adjoint(3, a, b).cpu().numpy()
+            sim.step(5)
+            out[kind] = [g3, sim.adjoint(23, a, b).cpu().numpy(), sim.adjoint(7, a, b).cpu().numpy()]
+        finally:
+            sim.close()
+    for g_replay, g_moments in zip(out["replay"], out["moments"]):
+        assert np.array_equal(g_replay, g_moments)
+        assert np.any(g_replay)
 
 
 def test_moment_record_tape_equals_replay_tensor(H):
