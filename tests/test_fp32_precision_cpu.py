@@ -10,7 +10,15 @@ and Guo source (Sec. 3.2), every operation in FP32 -- on the sphere-array tile
   and 1.7e-5 at 800, past the 1e-5 bar of the FP32 form;
 * summing the same moments in FP64, all else FP32, cuts it by more than half;
 * FP32 weights adjusted so that their exact sum is one do not help: the error
-  is not a bias of the weights' sum.
+  is not a bias of the weights' sum;
+* compensated FP32 sums (Neumaier's two-sum per moment, rounded once) do not
+  help either: the rounding of the sums is not what matters;
+* what matters is how u is formed from them.  The FP64 path divides by the
+  unrounded rho = 1 + drho.  In FP32, 1 + drho drops the low digits of drho
+  (~1e-5 here); writing u = J - (J drho) / (1 + drho), so that the rounded
+  1 + drho only scales the small term, brings plain FP32 sums close to the
+  FP64 sums' error.  Over 1000 steps that form still reaches 1.06e-5, against
+  1.97e-5 for plain FP32 and 5.3e-6 for FP64 sums (same emulation).
 
 The GPU form therefore keeps the FP64 moment sums and the balance-law
 correction of the relaxed populations (which this emulation leaves out).
@@ -53,7 +61,18 @@ def _pull(g):
         g[i] = np.roll(g[i], shift=(C[i, 2], C[i, 1], C[i, 0]), axis=(0, 1, 2))
 
 
-def _emulate(d, f64_sums=False, exact_sum_weights=False):
+def _two_sum_total(terms):
+    """Neumaier-compensated FP32 sum: (high part, accumulated low part)."""
+    acc = np.zeros_like(terms[0])
+    low = np.zeros_like(terms[0])
+    for t in terms:
+        total = acc + t
+        low = low + np.where(np.abs(acc) >= np.abs(t), (acc - total) + t, (t - total) + acc)
+        acc = total
+    return acc, low
+
+
+def _emulate(d, f64_sums=False, exact_sum_weights=False, compensated=False, split_division=False):
     """Shifted populations g = f - w rho0 (rho0 = 1), arrays [i][z][y][x]."""
     n = d.shape[0]
     w = _weights(exact_sum_weights)
@@ -70,6 +89,15 @@ def _emulate(d, f64_sums=False, exact_sum_weights=False):
             rho = 1.0 + s
             u = [((j[a] + 0.5 * float(F[a])) / rho).astype(F32) for a in range(3)]
             s, rho = s.astype(F32), rho.astype(F32)
+        elif compensated:
+            hi, lo = _two_sum_total([g[i] for i in range(19)])
+            s = hi + lo
+            rho = (F32(1) + hi) + lo
+            inv = F32(1) / rho
+            u = []
+            for a in range(3):
+                jh, jl = _two_sum_total([g[i] if C[i, a] > 0 else -g[i] for i in range(19) if C[i, a]])
+                u.append(((jh + F32(0.5) * F[a]) + jl) * inv)
         else:
             s = np.zeros_like(g[0])
             j = [np.zeros_like(g[0]) for _ in range(3)]
@@ -80,7 +108,10 @@ def _emulate(d, f64_sums=False, exact_sum_weights=False):
                         j[a] = j[a] + g[i] if C[i, a] > 0 else j[a] - g[i]
             rho = F32(1) + s
             inv = F32(1) / rho
-            u = [(j[a] + F32(0.5) * F[a]) * inv for a in range(3)]
+            if split_division:
+                u = [(j[a] + F32(0.5) * F[a]) - ((j[a] + F32(0.5) * F[a]) * s) * inv for a in range(3)]
+            else:
+                u = [(j[a] + F32(0.5) * F[a]) * inv for a in range(3)]
         shift = F32(1) - dd
         e = [shift * u[a] for a in range(3)]
         uu = e[0] * e[0] + e[1] * e[1] + e[2] * e[2]
@@ -124,3 +155,16 @@ def test_fp32_sums_need_fp64(reference):
     assert e32 > 1.5e-6
     assert e64 < 0.5 * e32
     assert ex > e64
+
+
+def test_fp32_error_comes_from_the_division(reference):
+    tile, dr_o, u_o = reference
+    e32 = _rel(_emulate(tile)[1], u_o)
+    e64 = _rel(_emulate(tile, f64_sums=True)[1], u_o)
+    ec = _rel(_emulate(tile, compensated=True)[1], u_o)
+    ed = _rel(_emulate(tile, split_division=True)[1], u_o)
+    print(f"u rel-L2 at {STEPS} steps: FP32 sums {e32:.2e}, compensated FP32 sums {ec:.2e}, "
+          f"FP32 sums with u = J - J drho / (1 + drho) {ed:.2e}, FP64 sums {e64:.2e}")
+    assert abs(ec - e32) < 0.1 * e32
+    assert ed < 0.5 * e32
+    assert ed < 1.25 * e64
