@@ -36,6 +36,10 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
     const R inv_scale = R(p.inv_scale), scale = R(p.scale);
     const R F0 = R(p.F[0]), F1 = R(p.F[1]), F2 = R(p.F[2]);
     const R rho0 = R(p.rho0), omega = R(p.omega), pref = R(p.pref);
+    // the porosity value is loaded before the gather, so that it is in flight
+    // with the pulled populations (after the gather it would wait behind the
+    // x-end lanes' branch on a plain row)
+    const typename S::D d0 = ld(dfield, cell);
     R g[L::Q];
     bool solid = false;
     if (BC == BC_PERIODIC) {
@@ -74,13 +78,13 @@ __device__ __forceinline__ bool sweep_cell(const typename S::T* src, typename S:
     Moms* const want = (REC && S::exact_moments) ? &sums : nullptr;
     if (REC && !S::exact_moments) record_moments(rec, p.N, cell, moments_f64<L, R>(g));
     if (PK == PK_SCALAR) {
-        const ScalarShift<R> sh{S::load_d(ld(dfield, cell))};
+        const ScalarShift<R> sh{S::load_d(d0)};
         collide<L, R, decltype(sh), S::exact_moments>(g, sh, F0, F1, F2, rho0, omega, pref, drho, ux, uy, uz,
                                                       want);
     } else {
         // six rows xx, yy, zz, xy, xz, yz of the symmetric control D
         // (rows P apart, like the population rows)
-        const TensorShift<R> sh{S::load_d(ld(dfield, cell)),
+        const TensorShift<R> sh{S::load_d(d0),
                                 S::load_d(ld(dfield + (size_t)P, cell)),
                                 S::load_d(ld(dfield + 2 * (size_t)P, cell)),
                                 S::load_d(ld(dfield + 3 * (size_t)P, cell)),
