@@ -318,6 +318,13 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
     const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
     const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};
     const bool first = x0 == 0, last = x0 + 2 == nx;
+    const uint32_t cell = x0 + nx * (y + ny * z);
+    // the two cells' controls as one 32-bit load (16-bit porosity elements),
+    // issued before the gather: after it, it would wait behind the row-end
+    // lanes' patches
+    static_assert(sizeof(typename S::D) == 2, "pair kernel expects 16-bit porosity elements");
+    uint32_t dw;
+    __builtin_memcpy(&dw, reinterpret_cast<const char*>(dfield) + cell * 2u, 4);
     // Each population pair stays packed in one 32-bit word: the low cell is
     // unpacked, collided and its result written back into the low half, then
     // the same for the high cell.  Only one cell's 19 values are live as
@@ -348,14 +355,9 @@ __global__ __launch_bounds__(1024) void sweep_pair_kernel(const typename S::T* _
             w[i] = (w[i] >> 16) | (bits16<S>(ld(row, 0u)) << 16);
         }
     }
-    const uint32_t cell = x0 + nx * (y + ny * z);
     const R F0 = R(p.F[0]), F1 = R(p.F[1]), F2 = R(p.F[2]);
     const R rho0 = R(p.rho0), omega = R(p.omega), pref = R(p.pref);
     R drho, ux, uy, uz;
-    // the two cells' controls as one 32-bit load (16-bit porosity elements)
-    static_assert(sizeof(typename S::D) == 2, "pair kernel expects 16-bit porosity elements");
-    uint32_t dw;
-    __builtin_memcpy(&dw, reinterpret_cast<const char*>(dfield) + cell * 2u, 4);
     typename S::D d_lo, d_hi;
     const uint16_t dl = (uint16_t)(dw & 0xffffu), dh = (uint16_t)(dw >> 16);
     __builtin_memcpy(&d_lo, &dl, 2);
