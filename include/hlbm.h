@@ -323,8 +323,8 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * segments (the one that holds step max_steps and the one below it) write
  * those segments' records themselves, so that a reverse sweep replays only
  * the segments below them.  A call that replays into a kept record's set
- * overwrites it; a later call replays that segment too.  (HLBM_TAPE_MOMENTS records the moments of every forward
- * step instead.)  The tape
+ * overwrites it; a later call replays that segment too.  (HLBM_TAPE_MOMENTS
+ * records the moments of every forward step instead.)  The tape
  * records from the state current when it is set and restarts at the current
  * state whenever the state or the porosity changes otherwise (hlbm_set_state,
  * hlbm_reset, hlbm_set_porosity, hlbm_bind_buffers).
