@@ -463,6 +463,25 @@ def test_replay_tape_keeps_the_top_segment_records(H):
     for g_replay, g_moments in zip(out["replay"], out["moments"]):
         assert np.array_equal(g_replay, g_moments)
         assert np.any(g_replay)
+    # edge cases of the kept segments: one step per segment (the top two
+    # segments are the last two steps), and a tape shorter than one segment
+    # (one segment, kept in set 0; set 1 keeps none)
+    for every_e, max_e, steps_e in ((1, 7, 7), (1, 7, 6), (9, 6, 6), (9, 6, 4)):
+        say(f"replay tape, every {every_e}, max {max_e}, {steps_e} forward steps")
+        out = {}
+        for kind in ("replay", "moments"):
+            sim = H.HLBM(19, "f32", shape, **kw)
+            try:
+                sim.set_porosity(d)
+                sim.set_tape_kind(kind)
+                sim.set_tape(every_e, max_e)
+                sim.step(steps_e)
+                out[kind] = [sim.adjoint(steps_e, a, b).cpu().numpy(), sim.adjoint(2, a, b).cpu().numpy()]
+            finally:
+                sim.close()
+        for g_replay, g_moments in zip(out["replay"], out["moments"]):
+            assert np.array_equal(g_replay, g_moments)
+            assert np.any(g_replay)
 
 
 def test_moment_record_tape_equals_replay_tensor(H):
