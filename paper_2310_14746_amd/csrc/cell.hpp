@@ -632,9 +632,12 @@ __device__ __forceinline__ void aa_odd_target_walls(const Box& b, int x, int y, 
 // ---------------------------------------------------------------------------
 // Pull gather in a periodic box with resolved solid cells: where the source of
 // direction i is solid, halfway bounce-back g*_i(x) = g_opp(i)(x) (the link
-// mask, precomputed per cell, says which sources are solid).  Straight-line:
-// the load address switches to this cell's opposite population.  Returns
-// whether the cell itself is solid.  `base` offsets the box inside the
+// mask, precomputed per cell, says which sources are solid): the load address
+// switches to this cell's opposite population.  Returns whether the cell
+// itself is solid.  A solid cell's result is discarded by every caller (its
+// populations are stored as zeros, its moments reported as zeros), so it
+// loads nothing and gathers zeros: the one branch of this gather, which keeps
+// the memory system to the fluid cells.  `base` offsets the box inside the
 // population rows and the link mask (an item of a batch; 0 otherwise).
 // ---------------------------------------------------------------------------
 template <class L, class S>
@@ -646,18 +649,23 @@ __device__ __forceinline__ bool gather_masked(const typename S::T* __restrict__ 
 {
     const uint32_t cell = base + x + nx * (y + ny * z);
     const uint32_t lm = linkmask[cell];  // 4 B per cell: may pass 4 GiB under 16-bit storage
+    const bool solid = (lm & LINK_SOLID_SELF) != 0u;
     const uint32_t xs[3] = {x + 1 == nx ? 0u : x + 1, x, x == 0 ? nx - 1 : x - 1};
     const uint32_t ys[3] = {y + 1 == ny ? 0u : y + 1, y, y == 0 ? ny - 1 : y - 1};
     const uint32_t zs[3] = {z + 1 == nz ? 0u : z + 1, z, z == 0 ? nz - 1 : z - 1};
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-        const bool back = ((lm >> i) & 1u) != 0u;
-        const uint32_t noff = base + xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
-        const uint32_t row = sel(back, (uint32_t)opposite(i), (uint32_t)i);
-        const uint32_t off = sel(back, cell, noff);
-        g[i] = S::load(ld(src + (size_t)row * P, off), inv_scale);
+    for (int i = 0; i < L::Q; ++i) g[i] = typename S::R(0);
+    if (!solid) {
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const bool back = ((lm >> i) & 1u) != 0u;
+            const uint32_t noff = base + xs[L::cx[i] + 1] + nx * (ys[L::cy[i] + 1] + ny * zs[L::cz[i] + 1]);
+            const uint32_t row = sel(back, (uint32_t)opposite(i), (uint32_t)i);
+            const uint32_t off = sel(back, cell, noff);
+            g[i] = S::load(ld(src + (size_t)row * P, off), inv_scale);
+        }
     }
-    return (lm & LINK_SOLID_SELF) != 0u;
+    return solid;
 }
 
 // ---------------------------------------------------------------------------
