@@ -526,11 +526,13 @@ __device__ __forceinline__ void gather_plain_row(const typename S::T* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Pull gather with walls and open faces (the general rule).  Straight-line
-// code: every address stays inside the box for any cell, solid ones included
-// (the caller discards their result).  The sweep kernels use it on the rows
-// next to a y or z face and gather_plain_row on the others (a choice per
-// row).  Per direction:
+// Pull gather with walls and open faces (the general rule).  The loads of a
+// direction are straight-line selects: every address stays inside the box.
+// A solid cell (wall layer), whose result the caller discards, loads nothing,
+// and the cell's own state is loaded only where a source lies beyond an open
+// face; both are branches on the cell's own classification.  The sweep
+// kernels use it on the rows next to a y or z face and gather_plain_row on
+// the others (a choice per row).  Per direction:
 //   * periodic axes wrap;
 //   * a source in a wall layer -> halfway bounce-back g*_i(x) = g_opp(i)(x)
 //     (takes precedence on edges): the load address switches to this cell's
@@ -549,27 +551,50 @@ __device__ __forceinline__ void gather_general(const typename S::T* __restrict__
     using R = typename S::R;
     const uint32_t cell = (uint32_t)x + (uint32_t)b.nx * ((uint32_t)y + (uint32_t)b.ny * (uint32_t)z);
     const bool px = b.lo0 == 0, py = b.lo1 == 0, pz = b.lo2 == 0;
-    // own post-collision state (used only where a source lies beyond an open face)
-    R rho_b, ubx, uby, ubz;
-    own_state<L, S>(src, P, cell, of.rho0, inv_scale, rho_b, ubx, uby, ubz);
-#pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
+    // Where the source of direction i lies: in the box, in a wall layer or
+    // beyond a face (then that face's kind).
+    auto source = [&](int i, bool& wall, bool& outside, int& kind, uint32_t& noff) {
         const int sx = wrap_source(x, L::cx[i], b.nx, px);
         const int sy = wrap_source(y, L::cy[i], b.ny, py);
         const int sz = wrap_source(z, L::cz[i], b.nz, pz);
-        const bool wall = in_wall_layer(b, sx, sy, sz);
+        wall = in_wall_layer(b, sx, sy, sz);
         const bool out_x = (sx < 0) | (sx >= b.nx);
         const bool out_y = (sy < 0) | (sy >= b.ny);
         const bool out_z = (sz < 0) | (sz >= b.nz);
-        const bool outside = out_x | out_y | out_z;
-        const uint32_t noff = (uint32_t)sx + (uint32_t)b.nx * ((uint32_t)sy + (uint32_t)b.ny * (uint32_t)sz);
-        const uint32_t row = sel(wall, (uint32_t)opposite(i), (uint32_t)i);
-        const uint32_t off = sel(wall | outside, cell, noff);
-        const R loaded = S::load(ld(src + (size_t)row * P, off), inv_scale);
+        outside = out_x | out_y | out_z;
+        noff = (uint32_t)sx + (uint32_t)b.nx * ((uint32_t)sy + (uint32_t)b.ny * (uint32_t)sz);
         const int kx = sel(sx < 0, b.lo0, b.hi0);
         const int ky = sel(sy < 0, b.lo1, b.hi1);
         const int kz = sel(sz < 0, b.lo2, b.hi2);
-        const int kind = sel(out_x, kx, sel(out_y, ky, kz));
+        kind = sel(out_x, kx, sel(out_y, ky, kz));
+    };
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) g[i] = R(0);
+    // A cell in a wall layer is solid: every caller discards its result, so
+    // it loads nothing (two branches in all, on the cell's own classification).
+    if (in_wall_layer(b, x, y, z)) return;
+    // this cell's own post-collision state, loaded only where a source lies
+    // beyond an open face (the only use of it)
+    bool open_face = false;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        bool wall, outside;
+        int kind;
+        uint32_t noff;
+        source(i, wall, outside, kind, noff);
+        open_face |= outside & !wall;
+    }
+    R rho_b = of.rho0, ubx = R(0), uby = R(0), ubz = R(0);
+    if (open_face) own_state<L, S>(src, P, cell, of.rho0, inv_scale, rho_b, ubx, uby, ubz);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        bool wall, outside;
+        int kind;
+        uint32_t noff;
+        source(i, wall, outside, kind, noff);
+        const uint32_t row = sel(wall, (uint32_t)opposite(i), (uint32_t)i);
+        const uint32_t off = sel(wall | outside, cell, noff);
+        const R loaded = S::load(ld(src + (size_t)row * P, off), inv_scale);
         const bool inlet = kind == 2;
         const R e_rho = sel(inlet, rho_b, of.out_rho);
         const R e_ux = sel(inlet, of.in_ux, ubx);

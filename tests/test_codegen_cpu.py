@@ -8,9 +8,11 @@ wall-row path the register holding such an address was never written before a
 load used it.  Boundary rules are now selects over register copies of the
 parameters: the kernels without walls or open faces are straight-line code
 (one guard branch); with walls or open faces a kernel adds only its choice of
-path per row (plain rows or the general rule) and the branch of a plain row's
-x-end lanes; with resolved solid cells, only the branch that skips a solid
-cell's loads.  No kernel keeps operands in private memory or writes through the
+path per row (plain rows or the general rule), the branch of a plain row's
+x-end lanes and the general rule's branches on a cell's own classification
+(a solid cell loads nothing, the own state is loaded only next to an open
+face); with resolved solid cells, only the branch that skips a solid cell's
+loads.  No kernel keeps operands in private memory or writes through the
 scalar cache.
 """
 import os
@@ -54,10 +56,14 @@ def _branches(body):
     return len(re.findall(r"^\s+s_(?:c)?branch", body, flags=re.M))
 
 
-# the guard, the row order's scalar divisions, the choice of path per block
-# and the x-end lanes, each of which the compiler may emit as one or two
-# branches
-GENERAL_BRANCHES = 10
+# the guard, the row order's scalar divisions, the choice of path per block,
+# the x-end lanes, and in the general rule the skipped loads of a solid cell
+# and the own state loaded only next to an open face, each of which the
+# compiler may emit as one or two branches
+GENERAL_BRANCHES = 12
+# the adjoint's seed with walls or open faces: the guard and the general
+# rule's two branches
+SEED_GENERAL_BRANCHES = 4
 # the guard and the skipped loads of a solid cell (one or two branches)
 MASKED_BRANCHES = 3
 
@@ -97,8 +103,11 @@ def test_adjoint_kernels_are_straight_line(asm):
     # seed: 2 lattices x 4 storages x 2 boundary modes
     assert len(kern) == 24 + 16
     for name, body in kern.items():
-        general = "adjoint_kernel" in name and _bc(name) == 1
-        assert _branches(body) <= (GENERAL_BRANCHES if general else 1), (name, _branches(body))
+        if "adjoint_kernel" in name:
+            allowed = GENERAL_BRANCHES if _bc(name) == 1 else 1
+        else:
+            allowed = SEED_GENERAL_BRANCHES if re.search(r"ELi1EEEv", name) else 1
+        assert _branches(body) <= allowed, (name, _branches(body))
 
 
 def test_no_private_memory_in_sweep_and_moments(asm):
