@@ -343,6 +343,8 @@ int hlbm_read_diagnostics(hlbm_ctx *ctx, double *out, int max_records, int *coun
  * frees the tape.  EUNSUPPORTED if one adjoint population row (N values of
  * 8 bytes for HLBM_F64, else 4) would reach 4 GiB.  hlbm_step returns EINVAL
  * (and does nothing) if it would take the recorded steps past max_steps.
+ * Called again with the tape's own every and max_steps (and kind), it keeps
+ * the tape's memory and only restarts recording at the current state.
  * Waits for the stream. */
 int hlbm_set_tape(hlbm_ctx *ctx, int every, int max_steps);
 

@@ -1041,6 +1041,15 @@ int hlbm_set_tape(hlbm_ctx* c, int every, int max_steps)
     if (every < 0 || max_steps < 0) return fail(HLBM_EINVAL, "every and max_steps must be >= 0");
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(e, "set_tape: outstanding work failed");
+    // The tape it already has (same every, max_steps and kind), as in a loop
+    // of forward and reverse sweeps: its memory, stream and events are kept,
+    // and recording restarts at the current state.
+    const bool have = c->tape_kind == HLBM_TAPE_MOMENTS ? c->tape_rec != nullptr : c->tape_segrec != nullptr;
+    if (every != 0 && every == c->tape_every && max_steps == c->tape_max && have) {
+        e = hipStreamSynchronize(c->tape_stream);
+        if (e != hipSuccess) return hip_fail(e, "set_tape: outstanding replays failed");
+        return tape_restart(c);
+    }
     tape_free(c);
     if (every == 0) return HLBM_OK;
     const size_t lam_elem = hlbm::adjoint_elem_bytes(c->cfg.storage);
